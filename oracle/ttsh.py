@@ -1,0 +1,451 @@
+"""FP64 CPU oracle of the damped TTSH time step (test infrastructure only).
+
+What is computed follows the paper's method section (model eqs. (1)-(4),
+computation and mask-generation subsections), Appendix C (Algorithm 1, the
+integration scheme, and the text after it: unitary DFT, the exponential
+multiplier, the k = 0 rule of eq. (7), the 1/2-rule cutoff, the Hermitian
+correction, the stream function) and Appendix D (Algorithm 2, the automatic
+mask generator).
+
+General coefficient form.  The paper writes the model in the dimensionless
+(a, b, lambda, gamma_v, gamma_w) convention, eq. (2)/(4).  The workloads used
+here are quoted in the (alpha, beta, Gamma0, Gamma2, lambda0, lambda1)
+convention of the Toner-Tu/Swift-Hohenberg literature the paper cites.  Both
+are special cases of
+
+    div v = 0,
+    dv/dt + lambda0 (v.grad) v = -grad p + lambda1 grad|v|^2
+                                 - (alpha + beta |v|^2) v
+                                 + Gamma0 lap v - Gamma2 lap^2 v
+                                 - gamma_v K v
+    plus, in the vorticity equation, the extra damping  -gamma_w K omega,
+
+whose linear Fourier symbol is  L(k) = -alpha - Gamma0 k^2 - Gamma2 k^4.
+The paper's a - (1 - k^2)^2 is alpha = 1 - a, Gamma0 = -2, Gamma2 = 1.
+
+Conventions: forward DFT carries e^{-ik.x}
+and is unitary (1/N per 2D transform, Appendix C); a spatial derivative is the
+multiplier +ik, which is what Algorithm 1 and the stream-function relations of
+Appendix A use (the prose sentence after Algorithm 1 has the opposite sign,
+taken as a slip).  Arrays are [component][y][x], component 0 = x; grid node
+(i, j) sits at x = (j - N/2) dx, y = (i - N/2) dx.  Spectra are in FFT order,
+axis -2 = m_y, axis -1 = m_x, k = (2 pi / L) m.
+
+The dealiasing radius is M = N/4: a mode is removed when
+m_x^2 + m_y^2 > M^2 (the 1/2 rule, k^2 > (pi/(2 dx))^2, strict inequality).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import os
+
+import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = os.cpu_count() or 1
+
+
+# ---------------------------------------------------------------------------
+# parameters
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class Params:
+    """Coefficients of the general form above, plus the time step.
+
+    scheme: 'ifeuler' (Algorithm 1: integrating factor + Euler, the default),
+            'etd1'    (exponential Euler with phi_1 weighting of the forcing),
+            'imex'    (linearly implicit Euler on the stiff operator).
+    """
+    alpha: float = -1.0
+    beta: float = 1.0
+    gamma0: float = -1.0
+    gamma2: float = 1.0
+    lambda0: float = 3.0
+    lambda1: float = 0.0
+    gamma_v: float = 100.0
+    gamma_w: float = 0.0
+    dt: float = 0.01
+    scheme: str = "ifeuler"
+
+
+def paper_params(dt: float = 0.01) -> Params:
+    """The paper's preset (a, b, lambda, gamma_v, gamma_w) = (0.5, 1.6, 9, 40, 4)
+    (model subsection; Table I), mapped to the general form."""
+    a, b, lam = 0.5, 1.6, 9.0
+    return Params(alpha=1.0 - a, beta=b, gamma0=-2.0, gamma2=1.0, lambda0=lam,
+                  lambda1=0.0, gamma_v=40.0, gamma_w=4.0, dt=dt)
+
+
+def workload_params(dt: float = 0.01) -> Params:
+    """Gamma0 = -1, Gamma2 = 1, alpha = -1, beta = 1, lambda0 = 3, lambda1 = 0,
+    one penalisation kappa = 100 taken as gamma_v, gamma_w = 0."""
+    return Params(dt=dt)
+
+
+# ---------------------------------------------------------------------------
+# grid and transforms
+# ---------------------------------------------------------------------------
+def mode_index(N: int) -> np.ndarray:
+    """Integer mode numbers in FFT order: 0, 1, ..., N/2-1, -N/2, ..., -1."""
+    return np.fft.fftfreq(N, d=1.0 / N).round().astype(np.int64)
+
+
+def grid(N: int, L: float):
+    """Return (kx, ky, k2, m2) on the full N x N spectrum in FFT order
+    (Table I: k in [-pi/dx, pi/dx]^2, spacing 2 pi / L)."""
+    m = mode_index(N)
+    dk = 2.0 * math.pi / L
+    mx = m[None, :]
+    my = m[:, None]
+    kx = dk * mx * np.ones((N, 1))
+    ky = dk * my * np.ones((1, N))
+    m2 = mx * mx + my * my
+    k2 = kx * kx + ky * ky
+    return kx, ky, k2, m2
+
+
+def dft2(f: np.ndarray) -> np.ndarray:
+    """Unitary forward DFT over the last two axes (Appendix C definition)."""
+    return sfft.fft2(f, axes=(-2, -1), norm="ortho", workers=_WORKERS)
+
+
+def idft2(F: np.ndarray) -> np.ndarray:
+    """Unitary inverse DFT over the last two axes (Appendix C definition)."""
+    return sfft.ifft2(F, axes=(-2, -1), norm="ortho", workers=_WORKERS)
+
+
+def dft2_bruteforce(f: np.ndarray, sign: int = -1) -> np.ndarray:
+    """The Appendix C definition summed term by term, O(N^4): tiny N only.
+
+    sign = -1 is the forward DFT, +1 the inverse; both carry 1/sqrt(N^2).
+    """
+    f = np.asarray(f, dtype=np.complex128)
+    N = f.shape[-1]
+    assert f.shape[-2] == N and N <= 32
+    out = np.zeros_like(f)
+    idx = np.arange(N)
+    for my in range(N):
+        for mx in range(N):
+            phase = np.exp(sign * 2j * math.pi * (my * idx[:, None] + mx * idx[None, :]) / N)
+            out[..., my, mx] = (f * phase).sum(axis=(-2, -1)) / N
+    return out
+
+
+def reflect(F: np.ndarray) -> np.ndarray:
+    """F(-k) in FFT order: index m -> (-m) mod N on both spectral axes."""
+    return np.roll(np.flip(F, axis=(-2, -1)), 1, axis=(-2, -1))
+
+
+# ---------------------------------------------------------------------------
+# linear operator
+# ---------------------------------------------------------------------------
+def linear_symbol(k2: np.ndarray, p: Params) -> np.ndarray:
+    """L(k) = -alpha - Gamma0 k^2 - Gamma2 k^4 (general form; the paper's
+    a - (1 - k^2)^2 of Algorithm 1 is the special case)."""
+    return -p.alpha - p.gamma0 * k2 - p.gamma2 * k2 * k2
+
+
+def linear_factors(k2: np.ndarray, p: Params):
+    """Weights (A, B) of the one-step map  u' = A u + B dt f  for the stiff
+    linear part.
+
+    ifeuler: A = B = exp(L dt)            (Algorithm 1, exponential multiplier)
+    etd1:    A = exp(L dt), B = (exp(L dt) - 1)/(L dt)   (B = 1 at L = 0)
+    imex:    A = B = 1/(1 - L dt)
+    """
+    z = linear_symbol(k2, p) * p.dt
+    if p.scheme == "ifeuler":
+        E = np.exp(z)
+        return E, E
+    if p.scheme == "etd1":
+        E = np.exp(z)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            phi = np.where(z == 0.0, 1.0, np.expm1(z) / np.where(z == 0.0, 1.0, z))
+        return E, phi
+    if p.scheme == "imex":
+        A = 1.0 / (1.0 - z)
+        return A, A
+    raise ValueError(p.scheme)
+
+
+# ---------------------------------------------------------------------------
+# projections
+# ---------------------------------------------------------------------------
+def dealias_keep(N: int) -> np.ndarray:
+    """True where a mode survives the 1/2 rule: m_x^2 + m_y^2 <= (N/4)^2."""
+    _, _, _, m2 = grid(N, 1.0)
+    M = N // 4
+    return m2 <= M * M
+
+
+def hermitian_fix(F: np.ndarray) -> np.ndarray:
+    """F(k) <- (F(k) + F(-k)^*)/2 (Algorithm 1, Hermitian correction of the
+    surviving modes; Appendix C says it is essential for stability)."""
+    return 0.5 * (F + np.conj(reflect(F)))
+
+
+def leray(vhat: np.ndarray, kx: np.ndarray, ky: np.ndarray, k2: np.ndarray) -> np.ndarray:
+    """Divergence-free part, P(k) = I - k k^T / k^2, for k != 0; k = 0 kept."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
+    div = kx * vhat[0] + ky * vhat[1]
+    return np.stack([vhat[0] - kx * div * inv, vhat[1] - ky * div * inv])
+
+
+def project_field(v0: np.ndarray, L: float) -> np.ndarray:
+    """Initial projection of an arbitrary real field onto the state space of
+    the scheme: DFT, 1/2-rule cutoff, Leray (k != 0), Hermitian fix.  Returns
+    the full unitary spectrum v_hat [2][N][N]."""
+    N = v0.shape[-1]
+    kx, ky, k2, _ = grid(N, L)
+    vh = dft2(np.asarray(v0, dtype=np.float64))
+    vh = vh * dealias_keep(N)
+    vh = leray(vh, kx, ky, k2)
+    return hermitian_fix(vh)
+
+
+def vorticity_hat(vhat: np.ndarray, kx: np.ndarray, ky: np.ndarray) -> np.ndarray:
+    """omega_hat = i (k_x v_y - k_y v_x) (omega = d_x v_y - d_y v_x, model subsection)."""
+    return 1j * (kx * vhat[1] - ky * vhat[0])
+
+
+def velocity_from_vorticity(w_hat: np.ndarray, kx, ky, k2) -> np.ndarray:
+    """Stream function psi_hat = omega_hat / k^2, v = (i k_y psi, -i k_x psi)
+    (Algorithm 1, stream-function step; Appendix A: lap psi = -omega, v_x = d_y psi,
+    v_y = -d_x psi).  The k = 0 entry is returned as 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        psi = np.where(k2 > 0, w_hat / np.where(k2 > 0, k2, 1.0), 0.0)
+    return np.stack([1j * ky * psi, -1j * kx * psi])
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1, as printed (vorticity form, convective advection)
+# ---------------------------------------------------------------------------
+def alg1_init(v0: np.ndarray, L: float):
+    """Consistent Algorithm 1 state (v, omega_hat) from an arbitrary field."""
+    N = v0.shape[-1]
+    kx, ky, _, _ = grid(N, L)
+    vh = project_field(v0, L)
+    return idft2(vh).real, vorticity_hat(vh, kx, ky)
+
+
+def alg1_step(v: np.ndarray, w_hat: np.ndarray, K: np.ndarray, p: Params, L: float):
+    """One step of Algorithm 1 in the general coefficient form.
+
+    REQUIRE (v(t), omega_hat(t)); ENSURE (v(t+dt), omega_hat(t+dt)).
+    """
+    N = v.shape[-1]
+    M = N // 4
+    kx, ky, k2, m2 = grid(N, L)
+    vx, vy = v[0], v[1]
+    # real-space forcing: rhs_1 = -b |v|^2 v - gamma_v K v
+    vsq = vx * vx + vy * vy
+    rhs1 = np.stack([-p.beta * vsq * vx - p.gamma_v * K * vx,
+                     -p.beta * vsq * vy - p.gamma_v * K * vy])
+    # convective term: rhs_2 = -lambda v . iDFT[i k omega_hat] - gamma_w K omega
+    w = idft2(w_hat).real
+    dwx = idft2(1j * kx * w_hat).real
+    dwy = idft2(1j * ky * w_hat).real
+    rhs2 = -p.lambda0 * (vx * dwx + vy * dwy) - p.gamma_w * K * w
+    # curl in k-space: rhs_hat = i k x DFT[rhs_1] + DFT[rhs_2]
+    r1 = dft2(rhs1)
+    rhs_hat = 1j * (kx * r1[1] - ky * r1[0]) + dft2(rhs2)
+    # Euler step with exponential multiplier: exp(L dt)(omega_hat + dt rhs_hat)
+    A, B = linear_factors(k2, p)
+    w_naive = A * w_hat + B * p.dt * rhs_hat
+    # per-k post-processing
+    w_new = hermitian_fix(w_naive)                       # Hermitian correction
+    cut = m2 > M * M
+    w_new[cut] = 0.0                                     # 1/2-rule cutoff
+    w_new[0, 0] = 0.0                                    # omega_hat(0) = 0
+    vh_new = velocity_from_vorticity(w_new, kx, ky, k2)  # stream function; cut modes stay 0
+    # mean flow from the averaged equation (7): exp(L(0) dt) DFT[v + dt rhs_1](0)
+    A0, B0 = A[0, 0], B[0, 0]
+    vh0 = dft2(v)[:, 0, 0]
+    vh_new[:, 0, 0] = A0 * vh0 + B0 * p.dt * r1[:, 0, 0]
+    v_new = idft2(vh_new).real
+    return v_new, w_new
+
+
+# ---------------------------------------------------------------------------
+# velocity / Leray form (independent formulation, the one the GPU evolves)
+# ---------------------------------------------------------------------------
+def velocity_rhs(vhat: np.ndarray, K: np.ndarray, p: Params, L: float):
+    """Real-space forcing of the velocity form, transformed.
+
+    Uses (v.grad) v = grad(|v|^2/2) + omega v_perp, v_perp = (-v_y, v_x); the
+    gradient part (and lambda1 grad|v|^2) is removed by the projection, but it
+    is kept here so that the test of its removal is meaningful.
+
+    Returns (N_hat, rhs1_hat, G_hat): the full forcing, the part from
+    -beta|v|^2 v - gamma_v K v alone (what the k = 0 rule uses) and the
+    vorticity source -gamma_w K omega.
+    """
+    N = vhat.shape[-1]
+    kx, ky, _, _ = grid(N, L)
+    v = idft2(vhat).real
+    w_hat = vorticity_hat(vhat, kx, ky)
+    w = idft2(w_hat).real
+    vx, vy = v[0], v[1]
+    vsq = vx * vx + vy * vy
+    rhs1 = np.stack([-(p.beta * vsq + p.gamma_v * K) * vx,
+                     -(p.beta * vsq + p.gamma_v * K) * vy])
+    adv = -p.lambda0 * np.stack([w * (-vy), w * vx])
+    grad_half = -p.lambda0 * 0.5 * vsq          # -lambda0 grad(|v|^2/2)
+    r1 = dft2(rhs1)
+    gh = dft2(grad_half + p.lambda1 * vsq)
+    N_hat = r1 + dft2(adv) + np.stack([1j * kx * gh, 1j * ky * gh])
+    G_hat = dft2(-p.gamma_w * K * w)
+    return N_hat, r1, G_hat
+
+
+def velocity_step(vhat: np.ndarray, K: np.ndarray, p: Params, L: float) -> np.ndarray:
+    """One step on the spectral velocity v_hat (full unitary spectrum).
+
+    v_hat' = A v_hat + B dt [P(k) N_hat + (i k_y, -i k_x) G_hat / k^2]  for
+    0 < m^2 <= M^2;  v_hat'(0) = A(0) v_hat(0) + B(0) dt rhs1_hat(0);  0 for
+    m^2 > M^2;  then the Hermitian correction.  Its curl is Algorithm 1's
+    omega update (identical up to rounding), which the tests check.
+    """
+    N = vhat.shape[-1]
+    M = N // 4
+    kx, ky, k2, m2 = grid(N, L)
+    N_hat, r1, G_hat = velocity_rhs(vhat, K, p, L)
+    A, B = linear_factors(k2, p)
+    forcing = leray(N_hat, kx, ky, k2) + velocity_from_vorticity(G_hat, kx, ky, k2)
+    out = A * vhat + B * p.dt * forcing
+    out[:, 0, 0] = A[0, 0] * vhat[:, 0, 0] + B[0, 0] * p.dt * r1[:, 0, 0]
+    out = out * (m2 <= M * M)
+    return hermitian_fix(out)
+
+
+def run_velocity(vhat: np.ndarray, K: np.ndarray, p: Params, L: float, nsteps: int) -> np.ndarray:
+    for _ in range(nsteps):
+        vhat = velocity_step(vhat, K, p, L)
+    return vhat
+
+
+def field(vhat: np.ndarray) -> np.ndarray:
+    """Real velocity field from its unitary spectrum."""
+    return idft2(vhat).real
+
+
+# ---------------------------------------------------------------------------
+# masks (method section "mask generation"; Appendix D)
+# ---------------------------------------------------------------------------
+def node_coords(N: int, L: float):
+    """Physical coordinates (x, y) of the nodes: x = (j - N/2) dx, y = (i - N/2) dx."""
+    dx = L / N
+    c = (np.arange(N, dtype=np.float64) - N / 2) * dx
+    return c[None, :] * np.ones((N, 1)), c[:, None] * np.ones((1, N))
+
+
+def mask_tanh(N: int, L: float, centers, radii, xi: float) -> np.ndarray:
+    """Smoothed wall K = 1/2 [1 + tanh((r - R)/xi)] for one circle; for several
+    circles the product of their outsides (the smooth AND of the outsides)."""
+    x, y = node_coords(N, L)
+    K = np.ones((N, N))
+    for (cx, cy), R in zip(centers, radii):
+        r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+        K = K * (0.5 * (1.0 + np.tanh((r - R) / xi)))
+    return K
+
+
+def mask_alg2(K_naive: np.ndarray) -> np.ndarray:
+    """Algorithm 2: DFT of the binary mask, zero every mode with
+    k^2 > (pi/(4 dx))^2 (m_x^2 + m_y^2 > (N/8)^2), inverse DFT, square.
+    No optional modification.  The real part is taken before squaring."""
+    N = K_naive.shape[-1]
+    _, _, _, m2 = grid(N, 1.0)
+    Kh = dft2(np.asarray(K_naive, dtype=np.float64))
+    Kh[m2 > (N // 8) ** 2] = 0.0
+    return idft2(Kh).real ** 2
+
+
+# ---------------------------------------------------------------------------
+# compact half spectrum (the library's state layout, for comparisons)
+# ---------------------------------------------------------------------------
+def to_compact(vhat: np.ndarray) -> np.ndarray:
+    """Full FFT-order spectrum [..., N, N] -> compact [..., 2M+1, M+1] holding
+    m_y = -M..M (row m_y + M) and m_x = 0..M."""
+    N = vhat.shape[-1]
+    M = N // 4
+    rows = np.arange(-M, M + 1) % N
+    return vhat[..., rows, :][..., : M + 1]
+
+
+def from_compact(c: np.ndarray, N: int) -> np.ndarray:
+    """Inverse of to_compact, filling m_x < 0 by Hermitian symmetry."""
+    M = N // 4
+    shape = c.shape[:-2] + (N, N)
+    out = np.zeros(shape, dtype=np.complex128)
+    my = np.arange(-M, M + 1)
+    for mx in range(M + 1):
+        out[..., my % N, mx] = c[..., :, mx]
+        if mx > 0:
+            out[..., (-my) % N, (-mx) % N] = np.conj(c[..., :, mx])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# diagnostics
+# ---------------------------------------------------------------------------
+def norms(vhat: np.ndarray, L: float):
+    """(sum_x |v|^2, <v_x>, <v_y>, max |k . v_hat|) in FP64 (Parseval for the first)."""
+    N = vhat.shape[-1]
+    kx, ky, _, _ = grid(N, L)
+    e = float(np.sum(np.abs(vhat) ** 2))
+    mean = vhat[:, 0, 0].real / N
+    div = float(np.max(np.abs(kx * vhat[0] + ky * vhat[1])))
+    return e, float(mean[0]), float(mean[1]), div
+
+
+def vortex_order(v: np.ndarray, L: float, center=(0.0, 0.0)) -> float:
+    """Vortex order parameter Psi (circle section, transition subsection):
+    [sum |e_theta . v| / sum |v| - 2/pi] / (1 - 2/pi)."""
+    N = v.shape[-1]
+    x, y = node_coords(N, L)
+    x = x - center[0]
+    y = y - center[1]
+    r = np.sqrt(x * x + y * y)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        etx = np.where(r > 0, -y / np.where(r > 0, r, 1.0), 0.0)
+        ety = np.where(r > 0, x / np.where(r > 0, r, 1.0), 0.0)
+    num = np.sum(np.abs(etx * v[0] + ety * v[1]))
+    den = np.sum(np.sqrt(v[0] ** 2 + v[1] ** 2))
+    return float((num / den - 2.0 / math.pi) / (1.0 - 2.0 / math.pi))
+
+
+def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
+    """||a - b||_2 / ||b||_2 over all entries, FP64 sums."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.sqrt(np.sum((a - b) ** 2)) / np.sqrt(np.sum(b * b)))
+
+
+# ---------------------------------------------------------------------------
+# D4 actions on a vector field about the node (N/2, N/2)
+# ---------------------------------------------------------------------------
+def rotate90(v: np.ndarray) -> np.ndarray:
+    """Counter-clockwise quarter turn about the centre node, acting on a vector
+    field [2][y][x]: v'(x) = R v(R^-1 x), R (a, b) = (-b, a)."""
+    N = v.shape[-1]
+    I, J = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    # destination node (i', j') takes the source node ((N - j') mod N, i')
+    src_i, src_j = (N - J) % N, I
+    vx = v[0][src_i, src_j]
+    vy = v[1][src_i, src_j]
+    return np.stack([-vy, vx])
+
+
+def reflect_x(v: np.ndarray) -> np.ndarray:
+    """Mirror x -> -x about the centre node: v'(x, y) = (-v_x, v_y)(-x, y)."""
+    N = v.shape[-1]
+    j = (N - np.arange(N)) % N
+    return np.stack([-v[0][:, j], v[1][:, j]])
+
+
+def transpose_xy(v: np.ndarray) -> np.ndarray:
+    """Mirror about the diagonal x <-> y: v'(x, y) = (v_y, v_x)(y, x)."""
+    return np.stack([v[1].T, v[0].T])

@@ -1,0 +1,57 @@
+"""Write the oracle reference states used by the long GPU parity tests.
+
+Calls only the FP64 CPU oracle (Algorithm 1 as printed) and the seeded input
+generators; nothing here reads GPU output.  Each case is stepped 1000 times
+from its seeded FP32-rounded initial field and stored as the compact spectrum
+[2][2M+1][M+1] (complex64 storage; FP32 rounding of the reference is 6e-8,
+far below the 1e-5 tolerance it is used with).
+
+    python tests/golden/make_reference_states.py [case ...]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import ttsh as O  # noqa: E402
+from paper_2304_03306_amd import workloads as W  # noqa: E402
+
+STEPS = 1000
+
+
+def cases():
+    c1 = W.circle_fp32_512().instances[0]
+    sweep = W.radius_sweep().instances
+    db = W.dumbbells().instances
+    return {
+        "circle512": c1,
+        "sweep_R8_128": sweep[0],      # radius 8, upward ramp, 128^2
+        "sweep_R24_256": sweep[14],    # radius 8 + 72*7/31 = 24.26, 256^2
+        "sweep_R80_512": sweep[62],    # radius 80, 512^2
+        "dumbbell_d40_1024": db[0],
+    }
+
+
+def run(name, inst):
+    p = O.workload_params()
+    K = O.mask_tanh(inst.N, inst.L, inst.centers, inst.radii, inst.xi)
+    v0 = W.uniform_field(inst.seed, inst.N, 0.01, 32)
+    v, w = O.alg1_init(v0, inst.L)
+    t0 = time.time()
+    for s in range(STEPS):
+        v, w = O.alg1_step(v, w, K, p, inst.L)
+    vh = O.dft2(v)
+    c = O.to_compact(vh).astype(np.complex64)
+    np.savez_compressed(os.path.join(HERE, f"ref_{name}_step{STEPS}.npz"), state=c,
+                        N=inst.N, L=inst.L, seed=inst.seed, steps=STEPS)
+    print(name, inst.N, f"{time.time() - t0:.1f}s", flush=True)
+
+
+if __name__ == "__main__":
+    want = sys.argv[1:] or list(cases())
+    for n in want:
+        run(n, cases()[n])
