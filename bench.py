@@ -1,0 +1,252 @@
+#!/usr/bin/env python
+"""Throughput of the TTSH time step on one MI355X.
+
+Headline ("value"): the batched radius sweep in FP32 -- 64 instances, radii
+8..80 on 128^2, 256^2 and 512^2 grids (box side 3.2 R), all advanced together;
+a "step" is one time step of every instance (10,682,368 grid points).  Also
+reported: the plain single-instance 512^2 run ("plain"), the FP32-vs-FP64
+oracle error at step 1000 of both ("parity"), the roofline figure of the
+dominant kernel from HIP-event timings taken in this process, and the FP64 CPU
+oracle timed on a bounded sample of the same workload ("cpu_baseline").
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-pt·steps/s batched vs plain at L2 err ≤1e-5 vs FP64; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(N: int, gw: bool = False) -> tuple[int, int]:
+    """Algorithmic HBM bytes of one instance for (row pass, column pass), FP32.
+
+    Row pass:    read v_x, v_y, omega in the mixed domain (3 (M+1) N complex),
+                 read K (N^2 reals), write the forcing (2 (M+1) N complex) and
+                 the row sums (2N reals).
+    Column pass: read the forcing, read and write the compact state
+                 (2 x 2 (M+1)(2M+1) complex), write the mixed v_x, v_y, omega,
+                 read the row sums.
+    """
+    M = N // 4
+    c8, r4 = 8, 4
+    nf = 3 if gw else 2
+    mixed = (M + 1) * N * c8
+    row = 3 * mixed + N * N * r4 + nf * mixed + 2 * N * r4
+    col = nf * mixed + 2 * 2 * (M + 1) * (2 * M + 1) * c8 + 3 * mixed + 2 * N * r4
+    return row, col
+
+
+def setup(T, W, wl, params):
+    s = T.Solver([i.N for i in wl.instances], [i.L for i in wl.instances], params, T.TTSH_FP32)
+    for q, inst in enumerate(wl.instances):
+        s.mask_tanh(q, inst.centers, inst.radii, inst.xi)
+        s.set_field(q, W.uniform_field(inst.seed, inst.N, 0.01, 32))
+    return s
+
+
+def reinit(s, W, wl):
+    for q, inst in enumerate(wl.instances):
+        s.set_field(q, W.uniform_field(inst.seed, inst.N, 0.01, 32))
+
+
+def golden_rel_l2(s, q, name):
+    """rel-L2 of instance q against a stored FP64 oracle state (Parseval on
+    the compact spectrum: m_x > 0 columns count twice)."""
+    path = os.path.join(GOLDEN, f"ref_{name}_step1000.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)["state"].astype(np.complex128)
+    got = s.state(q)
+    w = np.ones(ref.shape[-1])
+    w[1:] = 2.0
+    num = np.sum(w * np.abs(got - ref) ** 2)
+    den = np.sum(w * np.abs(ref) ** 2)
+    return float(np.sqrt(num / den))
+
+
+def timed_steps(s, torch, steps):
+    torch.cuda.synchronize()
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(wl, budget_s: float):
+    """The FP64 oracle (Algorithm 1 as printed) on the host cores: per distinct
+    grid size one instance of the workload is stepped for a bounded number of
+    steps; the per-point rates are combined with the workload's size mix."""
+    from oracle import ttsh as O
+    from paper_2304_03306_amd import workloads as W
+    p = O.workload_params()
+    sizes = sorted({i.N for i in wl.instances})
+    per = budget_s / len(sizes)
+    sec_per_pt = {}
+    sample = []
+    for N in sizes:
+        inst = next(i for i in wl.instances if i.N == N)
+        K = O.mask_tanh(N, inst.L, inst.centers, inst.radii, inst.xi)
+        v, w = O.alg1_init(W.uniform_field(inst.seed, N, 0.01, 32), inst.L)
+        t0 = time.perf_counter()
+        v, w = O.alg1_step(v, w, K, p, inst.L)  # warm-up (plans, caches)
+        one = time.perf_counter() - t0
+        n = max(2, min(200, int(per / max(one, 1e-4))))
+        t0 = time.perf_counter()
+        for _ in range(n):
+            v, w = O.alg1_step(v, w, K, p, inst.L)
+        dt = time.perf_counter() - t0
+        sec_per_pt[N] = dt / (n * N * N)
+        sample.append(f"{n} steps of one {N}^2 instance")
+    t_step = sum(sec_per_pt[i.N] * i.N * i.N for i in wl.instances)
+    return {"value": wl.points / t_step, "unit": "grid-pt·steps/s", "cores": os.cpu_count(),
+            "kind": "oracle",
+            "sample": "FP64 Algorithm-1 oracle (scipy.fft, workers=all cores): " + ", ".join(sample)
+                      + "; per-point rates combined with the workload's grid-size mix"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--prof-steps", type=int, default=100, help="steps timed per kernel with HIP events")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "dumbbell"])
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the workloads shard by instance; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from oracle import ttsh as O
+    from paper_2304_03306_amd import ttsh as T, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    params = O.workload_params()
+    wl = W.radius_sweep() if args.workload == "sweep" else W.dumbbells()
+    log(f"[bench] workload {wl.name}: {len(wl.instances)} instances, {wl.points} points/step")
+    s = setup(T, W, wl, params)
+    s.option(T.TTSH_OPT_GUARD, 0)
+
+    parity = {}
+    if not args.no_parity and args.workload == "sweep":
+        s.step(1000)
+        s.sync()
+        for q, name in ((0, "sweep_R8_128"), (14, "sweep_R24_256"), (62, "sweep_R80_512")):
+            parity[name] = golden_rel_l2(s, q, name)
+        log(f"[bench] parity at step 1000: {parity}")
+        reinit(s, W, wl)
+
+    s.step(args.warmup)
+    s.sync()
+    dt = timed_steps(s, torch, args.steps)
+    value = wl.points * args.steps / dt
+    log(f"[bench] {args.steps} steps in {dt:.3f} s: {value:.4e} pt*steps/s")
+    finite = True
+    try:
+        s.option(T.TTSH_OPT_GUARD, 1)
+        s.sync()
+    except T.TTSHError:
+        finite = False
+
+    # per-kernel durations from HIP events on the library's stream
+    times = T.ttsh_pass_times(s.ctx, args.prof_steps)
+    counts = {}
+    for i in wl.instances:
+        counts[i.N] = counts.get(i.N, 0) + 1
+    kern = []
+    for N, (row_us, col_us) in times.items():
+        rb, cb = pass_bytes(N)
+        kern.append(("row_pass", N, row_us, rb * counts[N]))
+        kern.append(("col_pass", N, col_us, cb * counts[N]))
+    dom = max(kern, key=lambda k: k[2])
+    achieved = dom[3] / (dom[2] * 1e-6) / 1e9
+    step_bytes = sum(k[3] for k in kern)
+    step_us = sum(k[2] for k in kern)
+    log("[bench] kernels: " + ", ".join(f"{k[0]}<{k[1]}> {k[2]:.1f}us {k[3] / k[2] / 1e3:.0f}GB/s" for k in kern))
+    s.close()
+
+    plain = None
+    if not args.no_plain:
+        pw = W.circle_fp32_512()
+        ps = setup(T, W, pw, params)
+        ps.option(T.TTSH_OPT_GUARD, 0)
+        perr = None
+        if not args.no_parity:
+            ps.step(1000)
+            ps.sync()
+            perr = golden_rel_l2(ps, 0, "circle512")
+            parity["circle512"] = perr
+            reinit(ps, W, pw)
+        ps.step(args.warmup)
+        psteps = args.steps * 2
+        pdt = timed_steps(ps, torch, psteps)
+        plain = {"workload": pw.name, "value": pw.points * psteps / pdt, "unit": "grid-pt·steps/s",
+                 "steps": psteps, "ms_per_step": 1e3 * pdt / psteps,
+                 "config": {"N": 512, "L": 256.0, "R": 60.0, "instances": 1}}
+        log(f"[bench] plain 512^2: {plain['value']:.4e} pt*steps/s, {plain['ms_per_step'] * 1e3:.1f} us/step")
+        ps.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_budget)
+        log(f"[bench] cpu baseline {cpu['value']:.4e} pt*steps/s on {cpu['cores']} cores")
+
+    sizes = sorted(counts)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-pt·steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "instances": len(wl.instances),
+                   "grids": " + ".join(f"{counts[N]}x{N}^2" for N in sizes),
+                   "points_per_step": wl.points, "dt": params.dt, "precision": "FP32 (FP64 k-space update)",
+                   "parallelism": "single GPU, instances batched per grid size"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"{dom[0]}<N={dom[1]}>", "avg_us": dom[2],
+                     "bytes_per_launch": dom[3]},
+        "step_hbm": {"algorithmic_bytes": step_bytes, "kernel_us": step_us,
+                     "GBps": step_bytes / (step_us * 1e-6) / 1e9,
+                     "frac": step_bytes / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "wall_GBps": step_bytes * args.steps / dt / 1e9},
+        "parity": {"rel_l2_step1000_vs_fp64_oracle": parity, "all_finite": finite},
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * ttsh.h -- C interface of libttsh.so: time stepping of the confined polar
+ * active fluid velocity equation (incompressible Toner-Tu/Swift-Hohenberg,
+ * "TTSH") with the damping-mask treatment of arbitrary boundaries, on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Model (paper: method section, eqs. (1)-(4); general coefficient form):
+ *   div v = 0,
+ *   dv/dt + lambda0 (v.grad) v = -grad p + lambda1 grad|v|^2
+ *        - (alpha + beta|v|^2) v + Gamma0 lap v - Gamma2 lap^2 v - gamma_v K v,
+ *   and in the vorticity equation the extra term -gamma_w K omega (eq. (4)).
+ * The paper's (a, b, lambda, gamma_v, gamma_w) is alpha = 1 - a, beta = b,
+ * Gamma0 = -2, Gamma2 = 1, lambda0 = lambda, lambda1 = 0.
+ *
+ * Time step: Algorithm 1 of Appendix C (pseudo-spectral, unitary DFT,
+ * exponential multiplier on the linear part, Euler on the rest, 1/2-rule
+ * cutoff m_x^2 + m_y^2 > (N/4)^2, k = 0 rule from the averaged equation (7),
+ * Hermitian correction, stream-function velocity), evaluated in the
+ * equivalent spectral-velocity form with a Leray projection.
+ *
+ * Conventions
+ *   Real fields are row-major [component][y][x] (component 0 = x) of float64;
+ *   grid node (i, j) sits at x = (j - N/2) L/N, y = (i - N/2) L/N.
+ *   Spectra use the paper's unitary DFT  f_hat(k) = N^-1 sum_x f(x) e^{-ik.x},
+ *   k = (2 pi / L) m, and derivative multiplier +ik.
+ *   A "compact state" is [2][2M+1][M+1] complex float64 (re, im interleaved),
+ *   M = N/4: entry [c][m_y + M][m_x] holds v_hat_c(m_x, m_y) for m_x = 0..M,
+ *   m_y = -M..M; modes with m_x < 0 follow from v_hat(-k) = v_hat(k)^*.
+ *
+ * Memory ("where" arguments): TTSH_HOST for host pointers, TTSH_DEVICE for
+ *   device pointers.  The caller owns every buffer it passes; the library
+ *   copies in or out and never keeps a pointer after the call returns.  Device
+ *   buffers passed to asynchronous calls must stay valid until the work queued
+ *   on the context's stream has completed (ttsh_sync).
+ *
+ * Errors: every int-returning call returns TTSH_OK (0) or a negative code;
+ *   ttsh_last_error() gives a message for the calling thread.  No exception
+ *   crosses the interface and the library never terminates the process.
+ *
+ * Threads: a context may be used by one thread at a time.
+ */
+#ifndef TTSH_H
+#define TTSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ttsh_ctx ttsh_ctx;
+
+enum {
+  TTSH_OK = 0,
+  TTSH_EINVAL = -1,       /* invalid argument (null pointer, index, size) */
+  TTSH_EUNSUPPORTED = -2, /* grid size or option not supported */
+  TTSH_EHIP = -3,         /* HIP runtime error (no device, launch failure) */
+  TTSH_ENONFINITE = -4,   /* NaN/Inf met in an input or in the state */
+  TTSH_ENOMEM = -5        /* device allocation failed */
+};
+
+enum { TTSH_HOST = 0, TTSH_DEVICE = 1 };
+
+/* One-step map of the stiff linear part, u' = A u + B dt f with
+ * L = -alpha - Gamma0 k^2 - Gamma2 k^4:
+ *   TTSH_IFEULER  A = B = exp(L dt)           (Algorithm 1, the default)
+ *   TTSH_ETD1     A = exp(L dt), B = (exp(L dt) - 1)/(L dt)
+ *   TTSH_IMEX     A = B = 1/(1 - L dt)                                     */
+enum { TTSH_IFEULER = 0, TTSH_ETD1 = 1, TTSH_IMEX = 2 };
+
+/* Arithmetic of the step (precision argument of ttsh_create):
+ *   TTSH_FP64         everything in FP64;
+ *   TTSH_FP32         FFTs, real-space terms and the stored spectrum in FP32;
+ *                     the linear factors, the k-space update and all norms in FP64;
+ *   TTSH_FP32_STATE64 as TTSH_FP32 but the stored spectrum kept in FP64.     */
+enum { TTSH_FP32 = 32, TTSH_FP64 = 64, TTSH_FP32_STATE64 = 96 };
+
+typedef struct {
+  double alpha, beta, gamma0, gamma2, lambda0, lambda1;
+  double gamma_v; /* velocity damping in the wall, -gamma_v K v  (eq. (4)) */
+  double gamma_w; /* vorticity damping in the wall, -gamma_w K omega (eq. (4)) */
+  double dt;
+  int scheme;     /* TTSH_IFEULER, TTSH_ETD1 or TTSH_IMEX */
+} ttsh_params;
+
+/* Options for ttsh_set_option. */
+enum {
+  TTSH_OPT_GRAPH_STEPS = 1, /* steps captured per HIP graph (0 = no graph); default 50 */
+  TTSH_OPT_ROW_PAIRS = 2,   /* row pairs per workgroup of the row pass (0 = tuned) */
+  TTSH_OPT_COL_TILE = 3,    /* columns per workgroup of the column pass (0 = tuned) */
+  TTSH_OPT_GUARD = 4        /* 1: ttsh_sync checks the state for NaN/Inf; default 1 */
+};
+
+/* Create a context holding n_inst independent instances advanced together.
+ *   N[i]   grid points per side of instance i: 64, 128, 256, 512 or 1024
+ *   L[i]   box side of instance i (> 0)
+ *   p      coefficients shared by all instances
+ *   precision  TTSH_FP32, TTSH_FP64 or TTSH_FP32_STATE64
+ *   stream hipStream_t the work is queued on (NULL = the default stream)
+ * The state starts at zero and the mask at K = 0.
+ * Errors: TTSH_EINVAL, TTSH_EUNSUPPORTED, TTSH_EHIP, TTSH_ENOMEM.           */
+int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const ttsh_params* p,
+                int precision, void* stream);
+
+/* Release every device buffer and graph of the context (synchronises). */
+void ttsh_destroy(ttsh_ctx* ctx);
+
+/* Mask K(x) >= 0 of instance inst, [N][N] float64 (method section: K ~ 0
+ * inside the system, ~ 1 in the wall).  Stored in the run precision.       */
+int ttsh_set_mask(ttsh_ctx* ctx, int inst, const double* K, int where);
+
+/* Read the stored mask back as [N][N] float64. */
+int ttsh_get_mask(ttsh_ctx* ctx, int inst, double* K, int where);
+
+/* Smoothed wall K = prod_c 1/2 [1 + tanh((|x - c| - R_c)/xi)] over n_circ
+ * circles (1 <= n_circ <= 8) with centres (cx, cy) and radii R (host
+ * arrays), evaluated in FP64 at the nodes (the tanh interpolation the method
+ * section mentions; a product of circle outsides gives the dumbbell).       */
+int ttsh_mask_tanh(ttsh_ctx* ctx, int inst, int n_circ, const double* cx, const double* cy,
+                   const double* R, double xi);
+
+/* Algorithm 2 (Appendix D): from a binary field K_naive [N][N] uint8 (nonzero
+ * = wall), K = (Re iDFT[DFT[K_naive] with m_x^2 + m_y^2 > (N/8)^2 zeroed])^2. */
+int ttsh_mask_from_binary(ttsh_ctx* ctx, int inst, const uint8_t* K_naive, int where);
+
+/* Set the velocity of instance inst from a real field v [2][N][N] float64:
+ * DFT, 1/2-rule cutoff, Leray projection (k != 0); the k = 0 mode is kept.  */
+int ttsh_set_field(ttsh_ctx* ctx, int inst, const double* v, int where);
+
+/* Real velocity v [2][N][N] and, if omega is not NULL, vorticity omega [N][N]
+ * (omega = d_x v_y - d_y v_x) of instance inst, float64.  Synchronous.      */
+int ttsh_get_field(ttsh_ctx* ctx, int inst, double* v, double* omega, int where);
+
+/* Compact state in / out (layout above).  set_state rounds to the stored
+ * precision, sets the modes outside the 1/2-rule disk (m_x^2 + m_y^2 > M^2)
+ * to zero and performs no other projection; for a state that is zero outside
+ * the disk, get_state(set_state(s)) returns s bit for bit when the stored
+ * precision is FP64.  get_state is synchronous.                             */
+int ttsh_set_state(ttsh_ctx* ctx, int inst, const double* vhat, int where);
+int ttsh_get_state(ttsh_ctx* ctx, int inst, double* vhat, int where);
+
+/* Advance every instance by nsteps >= 0 steps.  Asynchronous on the
+ * context's stream; whole chunks of TTSH_OPT_GRAPH_STEPS steps replay a
+ * captured HIP graph.                                                       */
+int ttsh_step(ttsh_ctx* ctx, int64_t nsteps);
+
+/* Continuation between stages (hysteresis protocol of the circle section):
+ * for q = 0..n-1, simultaneously,
+ *   state[dst[q]] <- resample(state[src[q]]) + P DFT[noise_q]
+ * where resample copies the spectrum by integer mode index (zero padding or
+ * truncation between grid sizes, scaled by N_dst/N_src for the unitary DFT)
+ * and noise_q [2][N_dst][N_dst] float64 is the q-th block of `noise` (blocks
+ * stored back to back in the order of dst; noise may be NULL for none).
+ * All sources are read before any destination is written.                   */
+int ttsh_reseed(ttsh_ctx* ctx, int n, const int* dst, const int* src, const double* noise,
+                int where);
+
+/* FP64 diagnostics of instance inst (synchronous):
+ * out[0] = sum_x |v|^2, out[1] = <v_x>, out[2] = <v_y>, out[3] = max |k . v_hat|. */
+int ttsh_norms(ttsh_ctx* ctx, int inst, double out[4]);
+
+/* Wait for the context's queued work; with TTSH_OPT_GUARD set, return
+ * TTSH_ENONFINITE if any instance holds NaN/Inf.                           */
+int ttsh_sync(ttsh_ctx* ctx);
+
+/* Measurement: advance every instance by nsteps >= 1 steps without graphs,
+ * bracketing each kernel launch with HIP events on the context's stream, and
+ * return the mean duration in microseconds of each pass of each size class:
+ * out[2c] = row pass, out[2c+1] = column pass, for the size classes c in
+ * increasing N (out needs 2 * ttsh_num_classes entries).  Synchronous.     */
+int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
+
+/* Number of distinct grid sizes (size classes) in the context; their sizes in
+ * increasing order go to N_out (may be NULL).                               */
+int ttsh_num_classes(ttsh_ctx* ctx, int* N_out);
+
+/* Set an option (TTSH_OPT_*); invalidates captured graphs. */
+int ttsh_set_option(ttsh_ctx* ctx, int key, int64_t value);
+
+/* Unitary 2D DFT (Appendix C definition) of `batch` complex N x N arrays,
+ * device pointers, interleaved float64 [batch][N][N][2]; inverse != 0 for the
+ * iDFT.  precision 32 runs the library's FP32 transform (inputs rounded),
+ * 64 the FP64 one.  Synchronous; in and out may alias.                      */
+int ttsh_fft2(const double* in, double* out, int N, int batch, int inverse, int precision);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ttsh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTSH_H */

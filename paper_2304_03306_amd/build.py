@@ -1,0 +1,64 @@
+"""Build libttsh.so for gfx950 with hipcc (cross-compiles without a GPU).
+
+The kernels are compiled once per grid size (kernels_n.hip with -DTTSH_N=N)
+in parallel, plus the host runtime, then linked into a shared library next to
+this file.  Usage:  python -m paper_2304_03306_amd.build
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+from pathlib import Path
+
+HERE = Path(__file__).resolve().parent
+CSRC = HERE / "csrc"
+OUT = HERE / "_build"
+LIB = HERE / "libttsh.so"
+SIZES = (64, 128, 256, 512, 1024)
+ARCH = os.environ.get("TTSH_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed FP32 instructions are kept out of the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result",
+]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("command failed: " + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+    return r
+
+
+def sources():
+    return sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.hpp")) + [HERE.parent / "include" / "ttsh.h"]
+
+
+def build(jobs: int | None = None, verbose: bool = True) -> Path:
+    OUT.mkdir(exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    units = [(CSRC / "kernels_n.hip", OUT / f"kernels_{n}.o", [f"-DTTSH_N={n}"]) for n in SIZES]
+    units.append((CSRC / "ttsh_capi.hip", OUT / "ttsh_capi.o", []))
+    cmds = [[HIPCC, *FLAGS, *extra, "-c", str(src), "-o", str(obj)] for src, obj, extra in units]
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for cmd, fut in zip(cmds, [ex.submit(_run, c) for c in cmds]):
+            fut.result()
+            if verbose:
+                print("compiled", cmd[-1], flush=True)
+    tmp = LIB.with_suffix(".so.tmp")
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp),
+          *[str(o) for _, o, _ in units]])
+    os.replace(tmp, LIB)
+    if verbose:
+        print("linked", LIB, flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,246 @@
+// Set-up and read-out kernels (host runtime translation unit only): state
+// packing with projection, masks (tanh wall and Algorithm 2), state
+// layout conversion, resampling between grid sizes, FP64 norms.
+// None of these runs inside the time loop.
+#pragma once
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "step.hpp"
+#include "fft_full.hpp"
+
+namespace ttsh {
+
+// ---- simple element-wise helpers -------------------------------------------
+__global__ void k_pack_xy(const double* __restrict__ v, C2<double>* __restrict__ z, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = mk(v[i], v[n + i]);
+}
+__global__ void k_unpack_xy(const C2<double>* __restrict__ z, double* __restrict__ v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    v[i] = z[i].x;
+    v[n + i] = z[i].y;
+  }
+}
+__global__ void k_real_part(const C2<double>* __restrict__ z, double* __restrict__ v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = z[i].x;
+}
+__global__ void k_scale_c(C2<double>* __restrict__ z, double s, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = cscale(z[i], s);
+}
+template <class D, class S>
+__global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (D)in[i];
+}
+__global__ void k_binary_to_c(const uint8_t* __restrict__ b, C2<double>* __restrict__ z, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = mk(b[i] ? 1.0 : 0.0, 0.0);
+}
+
+// integer mode number of FFT index i on an N grid
+__device__ __forceinline__ int mode_of(int i, int N) { return i < N / 2 ? i : i - N; }
+
+// Algorithm 2 cutoff: zero m^2 > (N/8)^2, scale the survivors by s
+__global__ void k_lowpass(C2<double>* __restrict__ z, int N, int cut2, double s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * N) return;
+  const int my = mode_of(i / N, N), mx = mode_of(i % N, N);
+  z[i] = (mx * mx + my * my > cut2) ? mk(0.0, 0.0) : cscale(z[i], s);
+}
+
+// K = (Re z)^2 into the run precision
+template <class T>
+__global__ void k_square_real(const C2<double>* __restrict__ z, T* __restrict__ K, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) K[i] = (T)(z[i].x * z[i].x);
+}
+
+// tanh wall, product over circles; evaluated in FP64
+struct Circles {
+  int n;
+  double cx[8], cy[8], R[8];
+};
+template <class T>
+__global__ void k_mask_tanh(T* __restrict__ K, int N, double dx, Circles c, double xi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * N) return;
+  const double x = ((i % N) - N / 2) * dx, y = ((i / N) - N / 2) * dx;
+  double k = 1.0;
+  for (int q = 0; q < c.n; ++q) {
+    const double r = sqrt((x - c.cx[q]) * (x - c.cx[q]) + (y - c.cy[q]) * (y - c.cy[q]));
+    k *= 0.5 * (1.0 + tanh((r - c.R[q]) / xi));
+  }
+  K[i] = (T)k;
+}
+
+// ---- state packing -----------------------------------------------------------
+// From Z = unnormalised 2D FFT of (v_x + i v_y): separate the two real fields,
+// scale to the unitary DFT, cut at m^2 > M^2, project (k != 0), optionally add
+// a compact FP64 spectrum `add` (same layout as the state), store the state.
+// Thread per stored (component-pair) position.
+template <class S>
+__global__ void k_pack_state(const C2<double>* __restrict__ Z, const C2<double>* __restrict__ add,
+                             C2<S>* __restrict__ st, int N) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MP * SP) return;
+  const int mx = i / SP, pos = i % SP;
+  C2<double> ox = mk(0.0, 0.0), oy = mk(0.0, 0.0);
+  if (pos <= 2 * M) {
+    const int my = pos <= M ? pos : pos - (2 * M + 1);
+    if (mx * mx + my * my <= M * M) {
+      const C2<double> zp = Z[(size_t)((my + N) % N) * N + mx];
+      const C2<double> zm = Z[(size_t)((N - my) % N) * N + (N - mx) % N];
+      const double s = 1.0 / N;
+      ox = cscale(mk(zp.x + zm.x, zp.y - zm.y), 0.5 * s);   // (Z(k) + Z(-k)^*)/2
+      oy = cscale(mk(zp.y + zm.y, -(zp.x - zm.x)), 0.5 * s);  // -i (Z(k) - Z(-k)^*)/2
+      const int m2 = mx * mx + my * my;
+      if (m2 > 0) {
+        const double inv = 1.0 / m2;
+        const C2<double> d = cscale(mk(mx * ox.x + my * oy.x, mx * ox.y + my * oy.y), inv);
+        ox = ox - cscale(d, (double)mx);
+        oy = oy - cscale(d, (double)my);
+      }
+      if (add) {
+        ox = ox + add[(0 * MP + mx) * SP + pos];
+        oy = oy + add[(1 * MP + mx) * SP + pos];
+      }
+    }
+  }
+  st[(0 * MP + mx) * SP + pos] = cvt<S>(ox);
+  st[(1 * MP + mx) * SP + pos] = cvt<S>(oy);
+}
+
+// Full spectrum of (v_x + i v_y)/N (or omega/N) from the state, ready for the
+// unnormalised inverse transform.  what = 0: velocity, 1: vorticity.
+template <class S>
+__global__ void k_state_to_full(const C2<S>* __restrict__ st, C2<double>* __restrict__ Z, int N,
+                                double dk, int what) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * N) return;
+  int my = mode_of(i / N, N), mx = mode_of(i % N, N);
+  C2<double> out = mk(0.0, 0.0);
+  if (mx * mx + my * my <= M * M) {
+    const bool neg = mx < 0;
+    const int ax = neg ? -mx : mx, ay = neg ? -my : my;
+    const int pos = ay >= 0 ? ay : ay + 2 * M + 1;
+    C2<double> a = cvt<double>(st[(0 * MP + ax) * SP + pos]);
+    C2<double> b = cvt<double>(st[(1 * MP + ax) * SP + pos]);
+    if (neg) {
+      a = conj(a);
+      b = conj(b);
+    }
+    if (what == 0) {
+      out = mk(a.x - b.y, a.y + b.x);  // a + i b
+    } else {
+      const C2<double> c = cscale(b, (double)mx) - cscale(a, (double)my);
+      out = mk(-c.y * dk, c.x * dk);    // i dk (m_x v_y - m_y v_x)
+    }
+    out = cscale(out, 1.0 / N);
+  }
+  Z[i] = out;
+}
+
+// internal state [2][M+1][2M+2]  <->  interface layout [2][2M+1][M+1] (FP64)
+template <class S>
+__global__ void k_state_to_abi(const C2<S>* __restrict__ st, C2<double>* __restrict__ o, int N) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * (2 * M + 1) * MP) return;
+  const int c = i / ((2 * M + 1) * MP), r = (i / MP) % (2 * M + 1), mx = i % MP;
+  const int my = r - M;
+  const int pos = my >= 0 ? my : my + 2 * M + 1;
+  o[i] = cvt<double>(st[(c * MP + mx) * SP + pos]);
+}
+template <class S>
+__global__ void k_abi_to_state(const C2<double>* __restrict__ in, C2<S>* __restrict__ st, int N) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * MP * SP) return;
+  const int c = i / (MP * SP), mx = (i / SP) % MP, pos = i % SP;
+  C2<double> v = mk(0.0, 0.0);
+  if (pos <= 2 * M) {
+    const int my = pos <= M ? pos : pos - (2 * M + 1);
+    if (mx * mx + my * my <= M * M) v = in[((size_t)c * (2 * M + 1) + (my + M)) * MP + mx];
+  }
+  st[i] = cvt<S>(v);
+}
+
+// dst (compact FP64, dst layout) <- src state scaled by Nd/Ns, by integer mode
+// index; modes beyond either grid's radius are zero.
+template <class S>
+__global__ void k_resample(const C2<S>* __restrict__ src, int Ns, C2<double>* __restrict__ dst,
+                           int Nd) {
+  const int Md = Nd / 4, MPd = Md + 1, SPd = 2 * Md + 2;
+  const int Ms = Ns / 4, MPs = Ms + 1, SPs = 2 * Ms + 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * MPd * SPd) return;
+  const int c = i / (MPd * SPd), mx = (i / SPd) % MPd, pos = i % SPd;
+  C2<double> v = mk(0.0, 0.0);
+  if (pos <= 2 * Md) {
+    const int my = pos <= Md ? pos : pos - (2 * Md + 1);
+    const int m2 = mx * mx + my * my;
+    if (m2 <= Md * Md && m2 <= Ms * Ms) {
+      const int ps = my >= 0 ? my : my + 2 * Ms + 1;
+      v = cscale(cvt<double>(src[((size_t)c * MPs + mx) * SPs + ps]), (double)Nd / (double)Ns);
+    }
+  }
+  dst[i] = v;
+}
+
+// ---- FP64 norms on the compact state -----------------------------------------
+// out[0] = sum_x |v|^2 (Parseval, unitary), out[1..2] = <v_x>, <v_y>,
+// out[3] = max |k . v_hat|, out[4] = 1 if any entry is non-finite.
+template <class S>
+__global__ void __launch_bounds__(1024) k_norms(const C2<S>* __restrict__ st, int N, double dk,
+                                                double* __restrict__ out) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  double e = 0.0, dv = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < MP * SP; i += blockDim.x) {
+    const int mx = i / SP, pos = i % SP;
+    if (pos > 2 * M) continue;
+    const int my = pos <= M ? pos : pos - (2 * M + 1);
+    const C2<double> a = cvt<double>(st[i]);
+    const C2<double> b = cvt<double>(st[MP * SP + i]);
+    const double w = mx == 0 ? 1.0 : 2.0;
+    const double s = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y;
+    if (!isfinite(s)) bad = 1.0;
+    e += w * s;
+    const C2<double> d = mk(mx * a.x + my * b.x, mx * a.y + my * b.y);
+    dv = fmax(dv, dk * sqrt(d.x * d.x + d.y * d.y));
+  }
+  __shared__ double red[16][3];
+  for (int o = 1; o < 64; o <<= 1) {
+    e += __shfl_xor(e, o, 64);
+    dv = fmax(dv, __shfl_xor(dv, o, 64));
+    bad = fmax(bad, __shfl_xor(bad, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = e;
+    red[threadIdx.x >> 6][1] = dv;
+    red[threadIdx.x >> 6][2] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double E0 = 0.0, D0 = 0.0, B0 = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      E0 += red[w][0];
+      D0 = fmax(D0, red[w][1]);
+      B0 = fmax(B0, red[w][2]);
+    }
+    const C2<double> a0 = cvt<double>(st[0]);
+    const C2<double> b0 = cvt<double>(st[MP * SP]);
+    out[0] = E0;
+    out[1] = a0.x / N;
+    out[2] = b0.x / N;
+    out[3] = D0;
+    out[4] = B0;
+  }
+}
+
+}  // namespace ttsh

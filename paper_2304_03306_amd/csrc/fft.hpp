@@ -1,0 +1,152 @@
+// Workgroup-level Stockham FFT staged through LDS, for gfx950.
+//
+// One transform of length N (64..1024, a power of two) is carried by TT = N/8
+// threads of a workgroup; thread t holds the 8 elements t + e*TT (e = 0..7)
+// in registers.  Each stage of radix R (8, or a final 4 or 2) reads its
+// butterfly inputs x[i + r*N/R] from exactly those registers, multiplies by
+// the twiddles w^(r*k) (k = i mod P, P the product of the earlier radices),
+// does the radix-R DFT and scatters the outputs to y[(i-k)R + k + rP]
+// (Stockham autosort, decimation in time; Van Loan, Computational Frameworks
+// for the FFT, ch. 1.7).  Because the input stride N/R is the same in every
+// stage, the scatter is followed by a gather of t + e*TT, and in the last stage
+// (P = N/R) the scatter target is t + e*TT itself, so the output lands in the
+// registers that held the input, in natural order.  A transform therefore
+// costs (#stages - 1) LDS round trips and needs no bit reversal.
+//
+// NF independent transforms that share the same threads are processed
+// together, so that one barrier serves all of them.
+//
+// All threads of the workgroup must call these functions (they contain
+// __syncthreads); threads that carry no useful data just transform zeros.
+#pragma once
+
+#include "common.hpp"
+
+namespace ttsh {
+
+constexpr int kFftE = 8;  // elements per thread
+
+// LDS index with one pad slot every 8 entries (breaks the stride-8 scatter of
+// the first stage across banks).
+__host__ __device__ constexpr int lds_pad(int j) { return j + (j >> 3); }
+template <int N>
+struct Padded {
+  static constexpr int value = N + N / 8;
+};
+
+// ---- radix-R DFTs, DIR = -1 forward (e^{-2 pi i nk/R}), +1 inverse ---------
+template <int DIR, class T>
+__device__ __forceinline__ void dft4(C2<T>& a0, C2<T>& a1, C2<T>& a2, C2<T>& a3) {
+  const C2<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3;
+  const C2<T> t3 = mul_i<DIR>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <int R, int DIR, class T>
+struct Dft;
+
+template <int DIR, class T>
+struct Dft<2, DIR, T> {
+  __device__ static __forceinline__ void run(C2<T> (&u)[2]) {
+    const C2<T> d = u[0] - u[1];
+    u[0] = u[0] + u[1];
+    u[1] = d;
+  }
+};
+
+template <int DIR, class T>
+struct Dft<4, DIR, T> {
+  __device__ static __forceinline__ void run(C2<T> (&u)[4]) { dft4<DIR>(u[0], u[1], u[2], u[3]); }
+};
+
+template <int DIR, class T>
+struct Dft<8, DIR, T> {
+  __device__ static __forceinline__ void run(C2<T> (&u)[8]) {
+    // even / odd halves, then combine with W8^k = e^{DIR 2 pi i k / 8}
+    C2<T> e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6];
+    C2<T> o0 = u[1], o1 = u[3], o2 = u[5], o3 = u[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    const T c = (T)0.70710678118654752440084436210484903928;
+    const T d = (T)DIR;
+    const C2<T> w1 = mk(c * (o1.x - d * o1.y), c * (d * o1.x + o1.y));
+    const C2<T> w2 = mul_i<DIR>(o2);
+    const C2<T> w3 = mk(c * (-o3.x - d * o3.y), c * (d * o3.x - o3.y));
+    u[0] = e0 + o0;
+    u[4] = e0 - o0;
+    u[1] = e1 + w1;
+    u[5] = e1 - w1;
+    u[2] = e2 + w2;
+    u[6] = e2 - w2;
+    u[3] = e3 + w3;
+    u[7] = e3 - w3;
+  }
+};
+
+// ---- one Stockham stage, recursing into the next ---------------------------
+// v[f][e] holds element t + e*TT of transform f.  `lds` points at this group's
+// NF regions of Padded<N> entries each.  `tw[j]` = e^{-2 pi i j / N}.
+template <int N, int DIR, int NF, int P, class T>
+struct FftStage {
+  static constexpr int E = kFftE;
+  static constexpr int TT = N / E;
+  static constexpr int REM = N / P;
+  static constexpr int R = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
+  static constexpr int NB = E / R;  // butterflies per thread in this stage
+  static constexpr bool LAST = (P * R == N);
+  static constexpr int NP = Padded<N>::value;
+
+  __device__ static __forceinline__ void run(C2<T> (&v)[NF][E], C2<T>* lds, int t,
+                                             const C2<T>* __restrict__ tw) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = t + b * TT;
+        const int k = i & (P - 1);
+        C2<T> u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[f][b + r * NB];
+        if constexpr (P > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            C2<T> w = tw[r * k * (N / (P * R))];
+            if constexpr (DIR > 0) w.y = -w.y;
+            u[r] = cmul(u[r], w);
+          }
+        }
+        Dft<R, DIR, T>::run(u);
+        if constexpr (LAST) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[f][b + r * NB] = u[r];
+        } else {
+          const int j0 = (i - k) * R + k;
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[f * NP + lds_pad(j0 + r * P)] = u[r];
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[f][e] = lds[f * NP + lds_pad(t + e * TT)];
+      __syncthreads();
+      FftStage<N, DIR, NF, P * R, T>::run(v, lds, t, tw);
+    }
+  }
+};
+
+// Unnormalised transform(s): out[m] = sum_n in[n] e^{DIR 2 pi i m n / N}.
+template <int N, int DIR, int NF, class T>
+__device__ __forceinline__ void fft(C2<T> (&v)[NF][kFftE], C2<T>* lds, int t,
+                                    const C2<T>* __restrict__ tw) {
+  static_assert(N >= 64 && (N & (N - 1)) == 0, "N must be a power of two >= 64");
+  FftStage<N, DIR, NF, 1, T>::run(v, lds, t, tw);
+}
+
+}  // namespace ttsh

@@ -1,0 +1,406 @@
+// The two fused kernels of one time step of the damped TTSH equation in its
+// spectral-velocity (Leray) form.
+//
+// State of an instance on an N x N grid (M = N/4 the 1/2-rule radius):
+//   st  [2][M+1][2M+2]   unitary spectrum v_hat, column m_x = 0..M, position
+//                        p = m_y (m_y >= 0) or m_y + 2M + 1 (m_y < 0); FP32 or
+//                        FP64.  Modes with m_x^2 + m_y^2 > M^2 are kept at 0.
+//   X   [3][M+1][N]      v_x, v_y, omega transformed back along y only
+//                        ("mixed domain", y contiguous), scaled so that the
+//                        row transform alone yields the real field.
+// Per step:
+//   row pass    X -> inverse row C2R (two real rows per complex transform) ->
+//               real-space forcing  N = -(beta|v|^2 + gamma_v K) v - lambda0
+//               omega v_perp  (and G = -gamma_w K omega) -> forward row R2C,
+//               keeping m_x <= M  -> Y [2 or 3][M+1][N];  also the row sums of
+//               -(beta|v|^2 + gamma_v K) v, which feed the k = 0 rule.
+//   column pass Y -> forward column FFT -> k-space update (FP64) of v_hat ->
+//               new st -> omega_hat -> inverse column FFT of v_x, v_y, omega ->
+//               X for the next step.
+//
+// The k-space update is the velocity form of Algorithm 1 (Appendix C):
+//   0 < m^2 <= M^2:  v' = A v + B dt [P(k) N_hat + (i k_y, -i k_x) G_hat / k^2]
+//   m = 0:           v'(0) = A(0) v(0) + B(0) dt DFT[-(beta|v|^2 + gamma_v K) v](0)
+//                    (eq. (7): advection and the gamma_w term do not enter)
+//   m^2 > M^2:       v' = 0                                  (1/2-rule cutoff)
+//   m_x = 0 column:  v'(k) <- (v'(k) + v'(-k)^*)/2           (Hermitian correction)
+// with (A, B) = (e^{L dt}, e^{L dt}) for the paper's integrating-factor Euler
+// (computed per mode in FP64, see LinCoef),
+// and L(k) = -alpha - Gamma0 k^2 - Gamma2 k^4.  The curl of this update is the
+// paper's vorticity update: (v.grad)v = grad(|v|^2/2) + omega v_perp, and the
+// projection removes the gradient.
+#pragma once
+
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace ttsh {
+
+// Coefficients of the linear one-step map u' = A u + B dt f, evaluated per
+// mode in FP64 from the integer m^2: L = -alpha - Gamma0 k^2 - Gamma2 k^4,
+// k^2 = dk^2 m^2, z = L dt;  scheme 0: A = B = e^z (integrating-factor Euler),
+// 1: A = e^z, B = (e^z - 1)/z, 2: A = B = 1/(1 - z).
+struct LinCoef {
+  double alpha, gamma0, gamma2, dt, dt_over_N;
+  int scheme;
+};
+
+__device__ __forceinline__ void linear_ab(const LinCoef& c, double dk, int m2, double& A, double& B) {
+  const double k2 = dk * dk * (double)m2;
+  const double z = (-c.alpha - c.gamma0 * k2 - c.gamma2 * k2 * k2) * c.dt;
+  if (c.scheme == 1) {
+    A = exp(z);
+    B = (z == 0.0) ? 1.0 : expm1(z) / z;
+  } else if (c.scheme == 2) {
+    A = B = 1.0 / (1.0 - z);
+  } else {
+    A = B = exp(z);
+  }
+}
+
+template <class T>
+struct alignas(4 * sizeof(T)) CPair {
+  C2<T> a, b;
+};
+
+template <class T>
+struct RowCoef {
+  T beta, gamma_v, lambda0, gamma_w;
+};
+
+template <int N>
+struct Geo {
+  static constexpr int E = kFftE;
+  static constexpr int TT = N / E;       // threads per transform
+  static constexpr int M = N / 4;        // dealiasing radius
+  static constexpr int MP = M + 1;       // stored columns m_x = 0..M
+  static constexpr int SP = 2 * M + 2;   // stored positions per state column
+  static constexpr int NP = Padded<N>::value;
+};
+
+// z = p + i q
+template <class T>
+__device__ __forceinline__ C2<T> pack_pq(C2<T> p, C2<T> q) {
+  return mk(p.x - q.y, p.y + q.x);
+}
+
+// ---------------------------------------------------------------------------
+// row pass: RP row pairs per workgroup, TT threads per pair
+// ---------------------------------------------------------------------------
+template <int N, int RP, class T, bool GW>
+__global__ void __launch_bounds__(RP*(N / 8))
+row_pass(const C2<T>* __restrict__ X, C2<T>* __restrict__ Y, const T* __restrict__ K,
+         T* __restrict__ rowsum, const C2<T>* __restrict__ tw, RowCoef<T> c) {
+  using G = Geo<N>;
+  constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, NP = G::NP;
+  constexpr int NFY = GW ? 3 : 2;
+  constexpr int NT = RP * TT;
+  constexpr int NW = NT / 64;
+  static_assert(NT % 64 == 0, "row pass needs whole wavefronts");
+  __shared__ C2<T> lds[RP * 3 * NP];
+  __shared__ T red[NW][RP][4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid % RP;
+  const int t = tid / RP;
+  const size_t inst = blockIdx.y;
+  const int y0 = (blockIdx.x * RP + lane) * 2;
+  const CPair<T>* Xp = reinterpret_cast<const CPair<T>*>(X + inst * 3 * MP * N);
+  CPair<T>* Yp = reinterpret_cast<CPair<T>*>(Y + inst * NFY * MP * N);
+  const T* Kp = K + inst * N * N;
+  C2<T>* L = lds + lane * 3 * NP;
+
+  // mask rows first, so their latency hides behind the gather and transforms
+  T kr[2][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = t + e * TT;
+    kr[0][e] = Kp[(size_t)y0 * N + x];
+    kr[1][e] = Kp[(size_t)(y0 + 1) * N + x];
+  }
+
+  // gather Z(m) over the full row spectrum from the stored m_x = 0..M half
+  C2<T> z[3][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = t + e * TT;
+    const bool lo = idx <= M;
+    const bool hi = idx >= N - M;
+    const int m = lo ? idx : N - idx;
+    CPair<T> a, b, w;
+    a.a = a.b = b.a = b.b = w.a = w.b = mk<T>(0, 0);
+    if (lo || hi) {
+      a = Xp[(0 * MP + m) * (N / 2) + y0 / 2];
+      b = Xp[(1 * MP + m) * (N / 2) + y0 / 2];
+      w = Xp[(2 * MP + m) * (N / 2) + y0 / 2];
+    }
+    if (idx == 0) {  // real transform: the m_x = 0 term is real
+      a.a.y = a.b.y = b.a.y = b.b.y = w.a.y = w.b.y = 0;
+    }
+    if (hi) {
+      a.a = conj(a.a); a.b = conj(a.b);
+      b.a = conj(b.a); b.b = conj(b.b);
+      w.a = conj(w.a); w.b = conj(w.b);
+    }
+    z[0][e] = pack_pq(a.a, b.a);  // v_x + i v_y, row y0
+    z[1][e] = pack_pq(a.b, b.b);  // v_x + i v_y, row y0+1
+    z[2][e] = pack_pq(w.a, w.b);  // omega(y0) + i omega(y0+1)
+  }
+  fft<N, +1, 3>(z, L, t, tw);
+
+  // real-space forcing at x = t + e*TT
+  C2<T> wv[NFY][E];
+  T s1[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const T vx = z[r][e].x, vy = z[r][e].y;
+      const T om = r ? z[2][e].y : z[2][e].x;
+      const T s = c.beta * (vx * vx + vy * vy) + c.gamma_v * kr[r][e];
+      const T r1x = -s * vx, r1y = -s * vy;
+      s1[r][0] += r1x;
+      s1[r][1] += r1y;
+      wv[r][e] = mk(r1x + c.lambda0 * om * vy, r1y - c.lambda0 * om * vx);
+    }
+    if constexpr (GW)
+      wv[NFY - 1][e] = mk(-c.gamma_w * kr[0][e] * z[2][e].x, -c.gamma_w * kr[1][e] * z[2][e].y);
+  }
+  fft<N, -1, NFY>(wv, L, t, tw);
+
+  // split the packed transforms: F_p(m) = (W(m) + W(N-m)^*)/2,
+  // F_q(m) = -i (W(m) - W(N-m)^*)/2; keep m = 0..M
+#pragma unroll
+  for (int f = 0; f < NFY; ++f)
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[f * NP + lds_pad(t + e * TT)] = wv[f][e];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) s1[r][q] = wave_sum_from(s1[r][q], RP);
+  if ((tid & 63) < RP) {
+    red[tid >> 6][lane][0] = s1[0][0];
+    red[tid >> 6][lane][1] = s1[0][1];
+    red[tid >> 6][lane][2] = s1[1][0];
+    red[tid >> 6][lane][3] = s1[1][1];
+  }
+  __syncthreads();
+  const T h = (T)0.5;
+#pragma unroll
+  for (int e = 0; e <= M / TT; ++e) {
+    const int m = t + e * TT;
+    if (m <= M) {
+      const int mm = (N - m) & (N - 1);
+      C2<T> out[NFY][2];
+#pragma unroll
+      for (int f = 0; f < NFY; ++f) {
+        const C2<T> Wm = L[f * NP + lds_pad(m)];
+        const C2<T> Wn = L[f * NP + lds_pad(mm)];
+        out[f][0] = mk(h * (Wm.x + Wn.x), h * (Wm.y - Wn.y));
+        out[f][1] = mk(h * (Wm.y + Wn.y), -h * (Wm.x - Wn.x));
+      }
+      CPair<T> px, py;
+      px.a = out[0][0]; px.b = out[1][0];  // N_x at rows y0, y0+1
+      py.a = out[0][1]; py.b = out[1][1];  // N_y
+      Yp[(0 * MP + m) * (N / 2) + y0 / 2] = px;
+      Yp[(1 * MP + m) * (N / 2) + y0 / 2] = py;
+      if constexpr (GW) {
+        CPair<T> pg;
+        pg.a = out[2][0]; pg.b = out[2][1];
+        Yp[(2 * MP + m) * (N / 2) + y0 / 2] = pg;
+      }
+    }
+  }
+  if (tid < RP) {
+    T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += red[w][tid][q];
+    T* rs = rowsum + inst * 2 * N;
+    rs[y0] = acc[0];
+    rs[N + y0] = acc[1];
+    rs[y0 + 1] = acc[2];
+    rs[N + y0 + 1] = acc[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column pass: TC columns per workgroup, TT threads per column
+// MODE 0: full step;  MODE 1: only state -> X (after the state was set)
+// ---------------------------------------------------------------------------
+template <int N, int TC, class T, bool GW>
+struct ColSmem {
+  static constexpr size_t fft = (size_t)TC * 3 * Geo<N>::NP * sizeof(C2<T>);
+  static constexpr size_t herm = (size_t)2 * N * sizeof(C2<double>);
+  static constexpr size_t bytes = fft > herm ? fft : herm;
+};
+
+template <int N, int TC, class T, class S, bool GW, int MODE>
+__global__ void __launch_bounds__(TC*(N / 8))
+col_pass(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X, C2<S>* __restrict__ st,
+         const T* __restrict__ rowsum, const double* __restrict__ dkv,
+         const C2<T>* __restrict__ tw, LinCoef lc) {
+  using G = Geo<N>;
+  constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, SP = G::SP, NP = G::NP;
+  constexpr int NFY = GW ? 3 : 2;
+  constexpr int NT = TC * TT;
+  constexpr int NW = NT / 64;
+  static_assert(NT % 64 == 0, "column pass needs whole wavefronts");
+  __shared__ __align__(16) unsigned char smem[ColSmem<N, TC, T, GW>::bytes];
+
+  const int tid = threadIdx.x;
+  const int t = tid % TT;
+  const int col = tid / TT;
+  const int mx = blockIdx.x * TC + col;
+  const bool valid = mx <= M;
+  const size_t inst = blockIdx.y;
+  const double dk = dkv[inst];
+  C2<T>* L = reinterpret_cast<C2<T>*>(smem) + col * 3 * NP;
+  C2<S>* stp = st + inst * 2 * MP * SP;
+
+  C2<T> f[NFY][E];
+  double s1x = 0.0, s1y = 0.0;
+  if constexpr (MODE == 0) {
+    if (blockIdx.x == 0) {  // sum of the row sums: DFT of the k = 0 forcing
+      const T* rs = rowsum + inst * 2 * N;
+      double a = 0.0, b = 0.0;
+      for (int y = tid; y < N; y += NT) {
+        a += (double)rs[y];
+        b += (double)rs[N + y];
+      }
+      a = wave_sum_from(a, 1);
+      b = wave_sum_from(b, 1);
+      double* R = reinterpret_cast<double*>(smem);
+      if ((tid & 63) == 0) {
+        R[2 * (tid >> 6)] = a;
+        R[2 * (tid >> 6) + 1] = b;
+      }
+      __syncthreads();
+      for (int w = 0; w < NW; ++w) {
+        s1x += R[2 * w];
+        s1y += R[2 * w + 1];
+      }
+      __syncthreads();
+    }
+    const C2<T>* Yp = Y + inst * NFY * MP * N;
+#pragma unroll
+    for (int q = 0; q < NFY; ++q)
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        f[q][e] = valid ? Yp[((size_t)q * MP + mx) * N + t + e * TT] : mk<T>(0, 0);
+    fft<N, -1, NFY>(f, L, t, tw);
+  }
+
+  // k-space update in FP64
+  C2<double> nx[E], ny[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = t + e * TT;
+    const bool lo = idx <= M, hi = idx >= N - M;
+    const int my = lo ? idx : idx - N;
+    const int pos = lo ? idx : idx - (N - 2 * M - 1);
+    const int m2 = mx * mx + my * my;
+    nx[e] = ny[e] = mk(0.0, 0.0);
+    if (valid && (lo || hi) && m2 <= M * M) {
+      const C2<double> ux = cvt<double>(stp[(0 * MP + mx) * SP + pos]);
+      const C2<double> uy = cvt<double>(stp[(1 * MP + mx) * SP + pos]);
+      if constexpr (MODE == 0) {
+        const double dt_over_N = lc.dt_over_N;
+        double A, B;
+        linear_ab(lc, dk, m2, A, B);
+        const double inv_m2 = m2 > 0 ? 1.0 / (double)m2 : 0.0;
+        C2<double> fx, fy;
+        if (m2 == 0) {
+          fx = mk(dt_over_N * s1x, 0.0);
+          fy = mk(dt_over_N * s1y, 0.0);
+        } else {
+          fx = cscale(cvt<double>(f[0][e]), dt_over_N);
+          fy = cscale(cvt<double>(f[1][e]), dt_over_N);
+          const double dmx = mx, dmy = my;
+          const C2<double> d = cscale(mk(dmx * fx.x + dmy * fy.x, dmx * fx.y + dmy * fy.y), inv_m2);
+          fx = fx - cscale(d, dmx);
+          fy = fy - cscale(d, dmy);
+          if constexpr (GW) {
+            const C2<double> g = cscale(cvt<double>(f[2][e]), dt_over_N * inv_m2 / dk);
+            fx = fx + mk(-dmy * g.y, dmy * g.x);
+            fy = fy + mk(dmx * g.y, -dmx * g.x);
+          }
+        }
+        nx[e] = cscale(ux, A) + cscale(fx, B);
+        ny[e] = cscale(uy, A) + cscale(fy, B);
+      } else {
+        nx[e] = ux;
+        ny[e] = uy;
+      }
+    }
+  }
+
+  if constexpr (MODE == 0) {
+    if (blockIdx.x == 0) {  // Hermitian correction on the m_x = 0 column
+      C2<double>* H = reinterpret_cast<C2<double>*>(smem);
+      __syncthreads();
+      if (col == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          H[t + e * TT] = nx[e];
+          H[N + t + e * TT] = ny[e];
+        }
+      }
+      __syncthreads();
+      if (col == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int mir = (N - (t + e * TT)) & (N - 1);
+          nx[e] = cscale(nx[e] + conj(H[mir]), 0.5);
+          ny[e] = cscale(ny[e] + conj(H[N + mir]), 0.5);
+        }
+      }
+      __syncthreads();
+    }
+    // round to the stored precision; the transforms below start from the
+    // stored values, so the stored spectrum is the whole state of the run
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      nx[e] = cvt<double>(cvt<S>(nx[e]));
+      ny[e] = cvt<double>(cvt<S>(ny[e]));
+    }
+    if (valid) {
+      // modes outside the 1/2-rule disk stay zero in memory and are not rewritten
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = t + e * TT;
+        const bool lo = idx <= M, hi = idx >= N - M;
+        const int pos = lo ? idx : idx - (N - 2 * M - 1);
+        const int my = lo ? idx : idx - N;
+        if ((lo || hi) && mx * mx + my * my <= M * M) {
+          stp[(0 * MP + mx) * SP + pos] = cvt<S>(nx[e]);
+          stp[(1 * MP + mx) * SP + pos] = cvt<S>(ny[e]);
+        }
+      }
+    }
+  }
+
+  // inverse column transforms of v_x, v_y and omega = i dk (m_x v_y - m_y v_x)
+  const double sN = 1.0 / N;
+  C2<T> z[3][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = t + e * TT;
+    const double dmy = (idx <= M) ? idx : idx - N;
+    const C2<double> cw = cscale(ny[e], (double)mx) - cscale(nx[e], dmy);
+    z[0][e] = cvt<T>(cscale(nx[e], sN));
+    z[1][e] = cvt<T>(cscale(ny[e], sN));
+    z[2][e] = cvt<T>(mk(-cw.y * dk * sN, cw.x * dk * sN));
+  }
+  fft<N, +1, 3>(z, L, t, tw);
+  if (valid) {
+    C2<T>* Xp = X + inst * 3 * MP * N;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int e = 0; e < E; ++e) Xp[((size_t)q * MP + mx) * N + t + e * TT] = z[q][e];
+  }
+}
+
+}  // namespace ttsh

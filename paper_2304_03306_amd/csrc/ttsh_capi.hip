@@ -1,0 +1,811 @@
+// Host runtime and C interface of libttsh.so (declared in include/ttsh.h).
+//
+// A context groups its instances by grid size ("size classes"); each class
+// owns contiguous device arrays for its instances, so that one launch of the
+// row pass and one of the column pass advance the whole class.  A step is
+// [row pass, column pass] for every class; chunks of steps are captured once
+// into a HIP graph and replayed on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ttsh.h"
+#include "aux.hpp"
+#include "launch.hpp"
+
+using namespace ttsh;
+
+namespace ttsh {
+const SizeOps* ops_64();
+const SizeOps* ops_128();
+const SizeOps* ops_256();
+const SizeOps* ops_512();
+const SizeOps* ops_1024();
+const SizeOps* size_ops(int N) {
+  switch (N) {
+    case 64: return ops_64();
+    case 128: return ops_128();
+    case 256: return ops_256();
+    case 512: return ops_512();
+    case 1024: return ops_1024();
+    default: return nullptr;
+  }
+}
+}  // namespace ttsh
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(TTSH_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t elem_real(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
+size_t elem_state(int prec) { return prec == 32 ? 2 * sizeof(float) : 2 * sizeof(double); }
+
+struct SizeClass {
+  int N = 0;
+  std::vector<int> ids;  // context instance ids, in order
+  void* X = nullptr;
+  void* Y = nullptr;
+  void* st = nullptr;
+  void* K = nullptr;
+  void* rowsum = nullptr;
+  double* dk = nullptr;
+  void* tw = nullptr;    // run precision
+  int rp = 0, tc = 0;    // chosen tiles
+  // per-instance strides in elements
+  size_t sX() const { return (size_t)3 * (N / 4 + 1) * N; }
+  size_t sY(int gw) const { return (size_t)(gw ? 3 : 2) * (N / 4 + 1) * N; }
+  size_t sSt() const { return (size_t)2 * (N / 4 + 1) * (N / 2 + 2); }
+  size_t sK() const { return (size_t)N * N; }
+};
+
+}  // namespace
+
+struct ttsh_ctx {
+  int n_inst = 0;
+  std::vector<int> N;
+  std::vector<double> L;
+  ttsh_params p{};
+  int prec = 32;
+  int gw = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<SizeClass> cls;
+  std::vector<std::pair<int, int>> loc;  // instance -> (class, index in class)
+  std::map<int, void*> tw64;             // FP64 twiddles per N (set-up paths)
+  std::map<int, void*> tw32;             // FP32 twiddles per N
+  void* scr0 = nullptr;                  // FP64 complex N^2 of the largest N
+  void* scr1 = nullptr;
+  double* dnorm = nullptr;               // [n_inst][5]
+  int graph_steps = 50;
+  int opt_rp = 0, opt_tc = 0;
+  int guard = 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+void drop_graph(ttsh_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+int make_twiddles(int N, bool fp64, void** out) {
+  std::vector<double> w(2 * N);
+  for (int j = 0; j < N; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)N;
+    w[2 * j] = std::cos(a);
+    w[2 * j + 1] = -std::sin(a);
+  }
+  if (fp64) {
+    HIPCHK(hipMalloc(out, sizeof(double) * 2 * N));
+    HIPCHK(hipMemcpy(*out, w.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(2 * N);
+    for (int j = 0; j < 2 * N; ++j) f[j] = (float)w[j];
+    HIPCHK(hipMalloc(out, sizeof(float) * 2 * N));
+    HIPCHK(hipMemcpy(*out, f.data(), sizeof(float) * 2 * N, hipMemcpyHostToDevice));
+  }
+  return TTSH_OK;
+}
+
+// Pick tiles: the largest tile that still gives >= target workgroups, else the
+// smallest valid one.  Overridden by TTSH_OPT_ROW_PAIRS / TTSH_OPT_COL_TILE.
+int pick(unsigned mask, int want, int per_inst_units, int n, int target) {
+  if (want > 0) return (mask & (unsigned)want) ? want : -1;
+  int best = -1, smallest = -1;
+  for (int b = 0; b < 6; ++b) {
+    if (!(mask & (1u << b))) continue;
+    const int v = 1 << b;
+    if (smallest < 0) smallest = v;
+    const int groups = (per_inst_units + v - 1) / v * n;
+    if (groups >= target) best = v;
+  }
+  return best > 0 ? best : smallest;
+}
+
+int choose_tiles(ttsh_ctx* c) {
+  for (auto& k : c->cls) {
+    const SizeOps* ops = size_ops(k.N);
+    const int n = (int)k.ids.size();
+    k.rp = pick(ops->row_options(c->prec, c->gw), c->opt_rp, k.N / 2, n, 1024);
+    k.tc = pick(ops->col_options(c->prec, c->gw), c->opt_tc, k.N / 4 + 1, n, 512);
+    if (k.rp < 0 || k.tc < 0) return fail(TTSH_EUNSUPPORTED, "tile option not available for N=" + std::to_string(k.N));
+  }
+  return TTSH_OK;
+}
+
+PassArgs pass_args(ttsh_ctx* c, SizeClass& k, int first, int count) {
+  PassArgs a{};
+  const size_t er = elem_real(c->prec), es = elem_state(c->prec);
+  a.N = k.N;
+  a.n = count;
+  a.prec = c->prec;
+  a.gw = c->gw;
+  a.rp = k.rp;
+  a.tc = k.tc;
+  a.X_in = (const char*)k.X + first * k.sX() * 2 * er;
+  a.X_out = (char*)k.X + first * k.sX() * 2 * er;
+  a.Y = (char*)k.Y + first * k.sY(c->gw) * 2 * er;
+  a.st = (char*)k.st + first * k.sSt() * es;
+  a.K = (const char*)k.K + first * k.sK() * er;
+  a.rowsum = (char*)k.rowsum + first * (size_t)2 * k.N * er;
+  a.dk = k.dk + first;
+  a.tw = k.tw;
+  a.beta = c->p.beta;
+  a.gamma_v = c->p.gamma_v;
+  a.lambda0 = c->p.lambda0;
+  a.gamma_w = c->p.gamma_w;
+  a.alpha = c->p.alpha;
+  a.gamma0 = c->p.gamma0;
+  a.gamma2 = c->p.gamma2;
+  a.dt = c->p.dt;
+  a.scheme = c->p.scheme;
+  a.dt_over_N = c->p.dt / (double)k.N;
+  return a;
+}
+
+int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
+  for (int64_t i = 0; i < n; ++i) {
+    for (auto& k : c->cls) {
+      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
+      HIPCHK(size_ops(k.N)->row(a, s));
+    }
+    for (auto& k : c->cls) {
+      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
+      HIPCHK(size_ops(k.N)->col(a, 0, s));
+    }
+  }
+  return TTSH_OK;
+}
+
+int build_graph(ttsh_ctx* c) {
+  drop_graph(c);
+  HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_steps(c, c->graph_steps, c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc != TTSH_OK) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(TTSH_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  c->graph = g;
+  HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  return TTSH_OK;
+}
+
+int check_inst(ttsh_ctx* c, int inst) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (inst < 0 || inst >= c->n_inst) return fail(TTSH_EINVAL, "instance index out of range");
+  return TTSH_OK;
+}
+
+// device pointer to instance data of class k at index j
+template <class Tp>
+Tp* at(void* base, size_t stride_elems, size_t elem_bytes, int j) {
+  return (Tp*)((char*)base + (size_t)j * stride_elems * elem_bytes);
+}
+
+int stage_in(ttsh_ctx* c, const void* src, size_t bytes, int where, const void** dev) {
+  if (!src) return fail(TTSH_EINVAL, "null input pointer");
+  if (where == TTSH_DEVICE) {
+    *dev = src;
+    return TTSH_OK;
+  }
+  if (where != TTSH_HOST) return fail(TTSH_EINVAL, "where must be TTSH_HOST or TTSH_DEVICE");
+  HIPCHK(hipMemcpyAsync(c->scr1, src, bytes, hipMemcpyHostToDevice, c->stream));
+  *dev = c->scr1;
+  return TTSH_OK;
+}
+
+const unsigned kB = 256;
+unsigned nblk(size_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+// X of one instance from its state
+int refresh_x(ttsh_ctx* c, int inst) {
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  PassArgs a = pass_args(c, k, j, 1);
+  HIPCHK(size_ops(k.N)->col(a, 1, c->stream));
+  return TTSH_OK;
+}
+
+// Z (FP64, scr0) holds the unnormalised FFT of v_x + i v_y; `add` optional.
+int pack_into_state(ttsh_ctx* c, int inst, const void* add) {
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, M = N / 4;
+  const size_t n = (size_t)(M + 1) * (2 * M + 2);
+  if (c->prec == 32) {
+    hipLaunchKernelGGL(k_pack_state<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const C2<double>*)c->scr0, (const C2<double>*)add,
+                       at<C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), N);
+  } else {
+    hipLaunchKernelGGL(k_pack_state<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const C2<double>*)c->scr0, (const C2<double>*)add,
+                       at<C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), N);
+  }
+  HIPCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+// forward FP64 FFT of a real field pair v [2][N][N] (device) into scr0
+int field_to_spectrum(ttsh_ctx* c, int N, const double* v) {
+  const int n = N * N;
+  hipLaunchKernelGGL(k_pack_xy, dim3(nblk(n)), dim3(kB), 0, c->stream, v, (C2<double>*)c->scr0, n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(size_ops(N)->fft2(c->scr0, 1, -1, 1, c->tw64[N], c->stream));
+  return TTSH_OK;
+}
+
+int norms_into(ttsh_ctx* c, int inst, double* dout) {
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const double dk = 2.0 * M_PI / c->L[inst];
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_norms<float>, dim3(1), dim3(1024), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), k.N, dk, dout);
+  else
+    hipLaunchKernelGGL(k_norms<double>, dim3(1), dim3(1024), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), k.N, dk, dout);
+  HIPCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+void free_ctx(ttsh_ctx* c) {
+  if (!c) return;
+  drop_graph(c);
+  for (auto& k : c->cls) {
+    for (void* p : {k.X, k.Y, k.st, k.K, k.rowsum, (void*)k.dk, k.tw})
+      if (p) hipFree(p);
+  }
+  for (auto& kv : c->tw64) hipFree(kv.second);
+  for (auto& kv : c->tw32) hipFree(kv.second);
+  if (c->scr0) hipFree(c->scr0);
+  if (c->scr1) hipFree(c->scr1);
+  if (c->dnorm) hipFree(c->dnorm);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ttsh_last_error(void) { return g_err.c_str(); }
+
+int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const ttsh_params* p,
+                int precision, void* stream) {
+  if (!out || !N || !L || !p) return fail(TTSH_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_inst < 1 || n_inst > 4096) return fail(TTSH_EINVAL, "n_inst must be in 1..4096");
+  if (precision != TTSH_FP32 && precision != TTSH_FP64 && precision != TTSH_FP32_STATE64)
+    return fail(TTSH_EINVAL, "precision must be TTSH_FP32, TTSH_FP64 or TTSH_FP32_STATE64");
+  if (p->scheme < TTSH_IFEULER || p->scheme > TTSH_IMEX) return fail(TTSH_EINVAL, "unknown scheme");
+  const double coef[] = {p->alpha, p->beta, p->gamma0, p->gamma2, p->lambda0, p->lambda1, p->gamma_v, p->gamma_w, p->dt};
+  for (double v : coef)
+    if (!std::isfinite(v)) return fail(TTSH_EINVAL, "non-finite coefficient");
+  if (!(p->dt > 0)) return fail(TTSH_EINVAL, "dt must be > 0");
+  for (int i = 0; i < n_inst; ++i) {
+    if (!size_ops(N[i])) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024");
+    if (!(L[i] > 0) || !std::isfinite(L[i])) return fail(TTSH_EINVAL, "L must be > 0");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(TTSH_EHIP, "no HIP device available");
+
+  ttsh_ctx* c = new ttsh_ctx();
+  c->n_inst = n_inst;
+  c->N.assign(N, N + n_inst);
+  c->L.assign(L, L + n_inst);
+  c->p = *p;
+  c->prec = precision;
+  c->gw = p->gamma_w != 0.0;
+  c->stream = (hipStream_t)stream;
+  c->loc.resize(n_inst);
+  auto bail = [&](int rc) {
+    free_ctx(c);
+    return rc;
+  };
+
+  std::vector<int> sizes(N, N + n_inst);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  const size_t er = elem_real(precision), es = elem_state(precision);
+  for (int Nc : sizes) {
+    SizeClass k;
+    k.N = Nc;
+    for (int i = 0; i < n_inst; ++i)
+      if (N[i] == Nc) {
+        c->loc[i] = {(int)c->cls.size(), (int)k.ids.size()};
+        k.ids.push_back(i);
+      }
+    const size_t n = k.ids.size();
+    struct {
+      void** p;
+      size_t bytes;
+    } al[] = {{&k.X, n * k.sX() * 2 * er},       {&k.Y, n * k.sY(c->gw) * 2 * er},
+              {&k.st, n * k.sSt() * es},         {&k.K, n * k.sK() * er},
+              {&k.rowsum, n * 2 * (size_t)Nc * er}, {(void**)&k.dk, n * sizeof(double)}};
+    for (auto& a : al) {
+      if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+        c->cls.push_back(k);
+        return bail(fail(TTSH_ENOMEM, "device allocation failed"));
+      }
+      if (hipMemset(*a.p, 0, a.bytes) != hipSuccess) {
+        c->cls.push_back(k);
+        return bail(fail(TTSH_EHIP, "hipMemset failed"));
+      }
+    }
+    std::vector<double> dks;
+    for (int id : k.ids) dks.push_back(2.0 * M_PI / L[id]);
+    c->cls.push_back(k);
+    SizeClass& kk = c->cls.back();
+    if (hipMemcpy(kk.dk, dks.data(), dks.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(TTSH_EHIP, "wavenumber upload failed"));
+    int rc = make_twiddles(Nc, precision == 64, &kk.tw);
+    if (rc) return bail(rc);
+    void* t64 = nullptr;
+    rc = make_twiddles(Nc, true, &t64);
+    if (rc) return bail(rc);
+    c->tw64[Nc] = t64;
+  }
+  const int Nmax = sizes.back();
+  if (hipMalloc(&c->scr0, sizeof(double) * 2 * Nmax * Nmax) != hipSuccess ||
+      hipMalloc(&c->scr1, sizeof(double) * 2 * Nmax * Nmax) != hipSuccess ||
+      hipMalloc((void**)&c->dnorm, sizeof(double) * 5 * n_inst) != hipSuccess)
+    return bail(fail(TTSH_ENOMEM, "scratch allocation failed"));
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(TTSH_EHIP, "stream creation failed"));
+  int rc = choose_tiles(c);
+  if (rc) return bail(rc);
+  *out = c;
+  return TTSH_OK;
+}
+
+void ttsh_destroy(ttsh_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  free_ctx(c);
+}
+
+int ttsh_set_option(ttsh_ctx* c, int key, int64_t value) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  switch (key) {
+    case TTSH_OPT_GRAPH_STEPS:
+      if (value < 0 || value > 100000) return fail(TTSH_EINVAL, "graph steps out of range");
+      c->graph_steps = (int)value;
+      break;
+    case TTSH_OPT_ROW_PAIRS:
+    case TTSH_OPT_COL_TILE: {
+      if (value < 0 || value > 32 || (value & (value - 1))) return fail(TTSH_EINVAL, "tile must be 0 or a power of two <= 32");
+      const int save_rp = c->opt_rp, save_tc = c->opt_tc;
+      (key == TTSH_OPT_ROW_PAIRS ? c->opt_rp : c->opt_tc) = (int)value;
+      int rc = choose_tiles(c);
+      if (rc) {
+        c->opt_rp = save_rp;
+        c->opt_tc = save_tc;
+        choose_tiles(c);
+        return rc;
+      }
+      break;
+    }
+    case TTSH_OPT_GUARD:
+      c->guard = value != 0;
+      break;
+    default:
+      return fail(TTSH_EINVAL, "unknown option");
+  }
+  drop_graph(c);
+  return TTSH_OK;
+}
+
+int ttsh_set_mask(ttsh_ctx* c, int inst, const double* K, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const size_t n = (size_t)k.N * k.N;
+  const void* dev = nullptr;
+  if ((rc = stage_in(c, K, n * sizeof(double), where, &dev))) return rc;
+  if (c->prec == 64)
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const double*)dev, at<double>(k.K, k.sK(), 8, j), n);
+  else
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const double*)dev, at<float>(k.K, k.sK(), 4, j), n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
+int ttsh_get_mask(ttsh_ctx* c, int inst, double* K, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!K) return fail(TTSH_EINVAL, "null output");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const size_t n = (size_t)k.N * k.N;
+  double* dst = where == TTSH_DEVICE ? K : (double*)c->scr1;
+  if (c->prec == 64)
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       at<const double>(k.K, k.sK(), 8, j), dst, n);
+  else
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       at<const float>(k.K, k.sK(), 4, j), dst, n);
+  HIPCHK(hipGetLastError());
+  if (where != TTSH_DEVICE) HIPCHK(hipMemcpyAsync(K, dst, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
+int ttsh_mask_tanh(ttsh_ctx* c, int inst, int n_circ, const double* cx, const double* cy,
+                   const double* R, double xi) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (n_circ < 1 || n_circ > 8 || !cx || !cy || !R) return fail(TTSH_EINVAL, "need 1..8 circles");
+  if (!(xi > 0) || !std::isfinite(xi)) return fail(TTSH_EINVAL, "xi must be > 0");
+  Circles cc{};
+  cc.n = n_circ;
+  for (int q = 0; q < n_circ; ++q) {
+    if (!std::isfinite(cx[q]) || !std::isfinite(cy[q]) || !std::isfinite(R[q])) return fail(TTSH_EINVAL, "non-finite circle");
+    cc.cx[q] = cx[q];
+    cc.cy[q] = cy[q];
+    cc.R[q] = R[q];
+  }
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int n = k.N * k.N;
+  const double dx = c->L[inst] / k.N;
+  if (c->prec == 64)
+    hipLaunchKernelGGL(k_mask_tanh<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       at<double>(k.K, k.sK(), 8, j), k.N, dx, cc, xi);
+  else
+    hipLaunchKernelGGL(k_mask_tanh<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       at<float>(k.K, k.sK(), 4, j), k.N, dx, cc, xi);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
+int ttsh_mask_from_binary(ttsh_ctx* c, int inst, const uint8_t* Kn, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, n = N * N;
+  const void* dev = nullptr;
+  if ((rc = stage_in(c, Kn, (size_t)n, where, &dev))) return rc;
+  hipLaunchKernelGGL(k_binary_to_c, dim3(nblk(n)), dim3(kB), 0, c->stream, (const uint8_t*)dev,
+                     (C2<double>*)c->scr0, n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(size_ops(N)->fft2(c->scr0, 1, -1, 1, c->tw64[N], c->stream));
+  hipLaunchKernelGGL(k_lowpass, dim3(nblk(n)), dim3(kB), 0, c->stream, (C2<double>*)c->scr0, N,
+                     (N / 8) * (N / 8), 1.0 / ((double)N * N));
+  HIPCHK(hipGetLastError());
+  HIPCHK(size_ops(N)->fft2(c->scr0, 1, +1, 1, c->tw64[N], c->stream));
+  if (c->prec == 64)
+    hipLaunchKernelGGL(k_square_real<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const C2<double>*)c->scr0, at<double>(k.K, k.sK(), 8, j), n);
+  else
+    hipLaunchKernelGGL(k_square_real<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const C2<double>*)c->scr0, at<float>(k.K, k.sK(), 4, j), n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
+int ttsh_set_field(ttsh_ctx* c, int inst, const double* v, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  const int N = c->N[inst];
+  const void* dev = nullptr;
+  if ((rc = stage_in(c, v, sizeof(double) * 2 * N * N, where, &dev))) return rc;
+  if ((rc = field_to_spectrum(c, N, (const double*)dev))) return rc;
+  if ((rc = pack_into_state(c, inst, nullptr))) return rc;
+  if ((rc = refresh_x(c, inst))) return rc;
+  double h[5];
+  if ((rc = norms_into(c, inst, c->dnorm))) return rc;
+  HIPCHK(hipMemcpyAsync(h, c->dnorm, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (h[4] != 0.0) return fail(TTSH_ENONFINITE, "non-finite value in the input field");
+  return TTSH_OK;
+}
+
+int ttsh_get_field(ttsh_ctx* c, int inst, double* v, double* omega, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!v) return fail(TTSH_EINVAL, "null output");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, n = N * N;
+  const double dk = 2.0 * M_PI / c->L[inst];
+  for (int what = 0; what < (omega ? 2 : 1); ++what) {
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_state_to_full<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                         at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), (C2<double>*)c->scr0, N, dk, what);
+    else
+      hipLaunchKernelGGL(k_state_to_full<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                         at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), (C2<double>*)c->scr0, N, dk, what);
+    HIPCHK(hipGetLastError());
+    HIPCHK(size_ops(N)->fft2(c->scr0, 1, +1, 1, c->tw64[N], c->stream));
+    double* out = what == 0 ? v : omega;
+    double* dst = where == TTSH_DEVICE ? out : (double*)c->scr1;
+    if (what == 0)
+      hipLaunchKernelGGL(k_unpack_xy, dim3(nblk(n)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr0, dst, n);
+    else
+      hipLaunchKernelGGL(k_real_part, dim3(nblk(n)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr0, dst, n);
+    HIPCHK(hipGetLastError());
+    if (where != TTSH_DEVICE)
+      HIPCHK(hipMemcpyAsync(out, dst, sizeof(double) * (what == 0 ? 2 : 1) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return TTSH_OK;
+}
+
+int ttsh_set_state(ttsh_ctx* c, int inst, const double* vhat, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, M = N / 4;
+  const size_t nabi = (size_t)2 * (2 * M + 1) * (M + 1);
+  const void* dev = nullptr;
+  if ((rc = stage_in(c, vhat, nabi * 2 * sizeof(double), where, &dev))) return rc;
+  const size_t n = k.sSt();
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_abi_to_state<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const C2<double>*)dev, at<C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), N);
+  else
+    hipLaunchKernelGGL(k_abi_to_state<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       (const C2<double>*)dev, at<C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), N);
+  HIPCHK(hipGetLastError());
+  if ((rc = refresh_x(c, inst))) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
+int ttsh_get_state(ttsh_ctx* c, int inst, double* vhat, int where) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!vhat) return fail(TTSH_EINVAL, "null output");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, M = N / 4;
+  const size_t nabi = (size_t)2 * (2 * M + 1) * (M + 1);
+  C2<double>* dst = where == TTSH_DEVICE ? (C2<double>*)vhat : (C2<double>*)c->scr1;
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_state_to_abi<float>, dim3(nblk(nabi)), dim3(kB), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), dst, N);
+  else
+    hipLaunchKernelGGL(k_state_to_abi<double>, dim3(nblk(nabi)), dim3(kB), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), dst, N);
+  HIPCHK(hipGetLastError());
+  if (where != TTSH_DEVICE)
+    HIPCHK(hipMemcpyAsync(vhat, dst, nabi * sizeof(C2<double>), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
+int ttsh_step(ttsh_ctx* c, int64_t nsteps) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (nsteps < 0) return fail(TTSH_EINVAL, "nsteps must be >= 0");
+  int rc;
+  int64_t left = nsteps;
+  if (c->graph_steps > 0 && left >= c->graph_steps) {
+    if (!c->gexec && (rc = build_graph(c))) return rc;
+    while (left >= c->graph_steps) {
+      HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+      left -= c->graph_steps;
+    }
+  }
+  return enqueue_steps(c, left, c->stream);
+}
+
+int ttsh_reseed(ttsh_ctx* c, int n, const int* dst, const int* src, const double* noise, int where) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (n < 0 || (n > 0 && (!dst || !src))) return fail(TTSH_EINVAL, "bad reseed lists");
+  if (noise && where != TTSH_HOST && where != TTSH_DEVICE) return fail(TTSH_EINVAL, "bad where");
+  for (int q = 0; q < n; ++q) {
+    if (dst[q] < 0 || dst[q] >= c->n_inst || src[q] < 0 || src[q] >= c->n_inst)
+      return fail(TTSH_EINVAL, "reseed index out of range");
+    for (int r = 0; r < q; ++r)
+      if (dst[r] == dst[q]) return fail(TTSH_EINVAL, "duplicate reseed destination");
+  }
+  // gather every resampled source first
+  std::vector<size_t> off(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    const int Nd = c->N[dst[q]];
+    off[q + 1] = off[q] + (size_t)2 * (Nd / 4 + 1) * (Nd / 2 + 2);
+  }
+  C2<double>* tmp = nullptr;
+  if (n > 0 && hipMalloc((void**)&tmp, off[n] * sizeof(C2<double>)) != hipSuccess)
+    return fail(TTSH_ENOMEM, "reseed scratch allocation failed");
+  auto done = [&](int rc) {
+    hipStreamSynchronize(c->stream);
+    if (tmp) hipFree(tmp);
+    return rc;
+  };
+  for (int q = 0; q < n; ++q) {
+    auto [cs, js] = c->loc[src[q]];
+    SizeClass& ks = c->cls[cs];
+    const int Nd = c->N[dst[q]];
+    const size_t cnt = off[q + 1] - off[q];
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_resample<float>, dim3(nblk(cnt)), dim3(kB), 0, c->stream,
+                         at<const C2<float>>(ks.st, ks.sSt(), sizeof(C2<float>), js), ks.N, tmp + off[q], Nd);
+    else
+      hipLaunchKernelGGL(k_resample<double>, dim3(nblk(cnt)), dim3(kB), 0, c->stream,
+                         at<const C2<double>>(ks.st, ks.sSt(), sizeof(C2<double>), js), ks.N, tmp + off[q], Nd);
+    if (hipGetLastError() != hipSuccess) return done(fail(TTSH_EHIP, "resample launch failed"));
+  }
+  size_t noff = 0;
+  for (int q = 0; q < n; ++q) {
+    const int Nd = c->N[dst[q]];
+    int rc;
+    if (noise) {
+      const double* blk = noise + noff;
+      const void* dev = nullptr;
+      if ((rc = stage_in(c, blk, sizeof(double) * 2 * Nd * Nd, where, &dev))) return done(rc);
+      if ((rc = field_to_spectrum(c, Nd, (const double*)dev))) return done(rc);
+      noff += (size_t)2 * Nd * Nd;
+    } else {
+      if (hipMemsetAsync(c->scr0, 0, sizeof(C2<double>) * Nd * Nd, c->stream) != hipSuccess)
+        return done(fail(TTSH_EHIP, "memset failed"));
+    }
+    if ((rc = pack_into_state(c, dst[q], tmp + off[q]))) return done(rc);
+    if ((rc = refresh_x(c, dst[q]))) return done(rc);
+    if (where == TTSH_HOST) hipStreamSynchronize(c->stream);
+  }
+  return done(TTSH_OK);
+}
+
+int ttsh_norms(ttsh_ctx* c, int inst, double out[4]) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!out) return fail(TTSH_EINVAL, "null output");
+  if ((rc = norms_into(c, inst, c->dnorm))) return rc;
+  double h[5];
+  HIPCHK(hipMemcpyAsync(h, c->dnorm, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int q = 0; q < 4; ++q) out[q] = h[q];
+  if (h[4] != 0.0) return fail(TTSH_ENONFINITE, "non-finite value in the state");
+  return TTSH_OK;
+}
+
+int ttsh_sync(ttsh_ctx* c) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (!c->guard) return TTSH_OK;
+  for (int i = 0; i < c->n_inst; ++i) {
+    int rc = norms_into(c, i, c->dnorm + 5 * i);
+    if (rc) return rc;
+  }
+  std::vector<double> h(5 * c->n_inst);
+  HIPCHK(hipMemcpyAsync(h.data(), c->dnorm, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < c->n_inst; ++i)
+    if (h[5 * i + 4] != 0.0) return fail(TTSH_ENONFINITE, "non-finite value in instance " + std::to_string(i));
+  return TTSH_OK;
+}
+
+int ttsh_num_classes(ttsh_ctx* c, int* N_out) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (N_out)
+    for (size_t i = 0; i < c->cls.size(); ++i) N_out[i] = c->cls[i].N;
+  return (int)c->cls.size();
+}
+
+int ttsh_pass_times(ttsh_ctx* c, int64_t nsteps, double* out) {
+  if (!c || !out) return fail(TTSH_EINVAL, "null argument");
+  if (nsteps < 1 || nsteps > 1000000) return fail(TTSH_EINVAL, "nsteps must be in 1..1e6");
+  const size_t nc = c->cls.size();
+  std::vector<hipEvent_t> ev(4 * nc, nullptr);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  std::vector<double> acc(2 * nc, 0.0);
+  int rc = TTSH_OK;
+  for (int64_t s = 0; s < nsteps && rc == TTSH_OK; ++s) {
+    for (size_t q = 0; q < nc && rc == TTSH_OK; ++q) {
+      SizeClass& k = c->cls[q];
+      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
+      hipEventRecord(ev[4 * q], c->stream);
+      if (size_ops(k.N)->row(a, c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "row pass launch failed");
+      hipEventRecord(ev[4 * q + 1], c->stream);
+    }
+    for (size_t q = 0; q < nc && rc == TTSH_OK; ++q) {
+      SizeClass& k = c->cls[q];
+      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
+      hipEventRecord(ev[4 * q + 2], c->stream);
+      if (size_ops(k.N)->col(a, 0, c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "column pass launch failed");
+      hipEventRecord(ev[4 * q + 3], c->stream);
+    }
+    if (rc == TTSH_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "sync failed");
+    for (size_t q = 0; q < nc && rc == TTSH_OK; ++q) {
+      float ms0 = 0, ms1 = 0;
+      hipEventElapsedTime(&ms0, ev[4 * q], ev[4 * q + 1]);
+      hipEventElapsedTime(&ms1, ev[4 * q + 2], ev[4 * q + 3]);
+      acc[2 * q] += ms0;
+      acc[2 * q + 1] += ms1;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  if (rc) return rc;
+  for (size_t i = 0; i < 2 * nc; ++i) out[i] = 1000.0 * acc[i] / (double)nsteps;
+  return TTSH_OK;
+}
+
+int ttsh_fft2(const double* in, double* out, int N, int batch, int inverse, int precision) {
+  if (!in || !out) return fail(TTSH_EINVAL, "null pointer");
+  const SizeOps* ops = size_ops(N);
+  if (!ops) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024");
+  if (batch < 1) return fail(TTSH_EINVAL, "batch must be >= 1");
+  if (precision != 32 && precision != 64) return fail(TTSH_EINVAL, "precision must be 32 or 64");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(TTSH_EHIP, "no HIP device available");
+  const bool f64 = precision == 64;
+  const size_t n = (size_t)batch * N * N;
+  void* tw = nullptr;
+  void* buf = nullptr;
+  int rc = make_twiddles(N, f64, &tw);
+  if (rc) return rc;
+  auto done = [&](int r) {
+    hipDeviceSynchronize();
+    if (tw) hipFree(tw);
+    if (buf) hipFree(buf);
+    return r;
+  };
+  if (hipMalloc(&buf, n * (f64 ? 16 : 8)) != hipSuccess) return done(fail(TTSH_ENOMEM, "allocation failed"));
+  if (f64) {
+    if (hipMemcpy(buf, in, n * 16, hipMemcpyDeviceToDevice) != hipSuccess) return done(fail(TTSH_EHIP, "copy failed"));
+  } else {
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(2 * n)), dim3(kB), 0, 0, in, (float*)buf, 2 * n);
+  }
+  if (ops->fft2(buf, batch, inverse ? +1 : -1, f64, tw, 0) != hipSuccess) return done(fail(TTSH_EHIP, "fft launch failed"));
+  if (f64) {
+    hipLaunchKernelGGL(k_scale_c, dim3(nblk(n)), dim3(kB), 0, 0, (C2<double>*)buf, 1.0 / N, n);
+    if (hipMemcpy(out, buf, n * 16, hipMemcpyDeviceToDevice) != hipSuccess) return done(fail(TTSH_EHIP, "copy failed"));
+  } else {
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(2 * n)), dim3(kB), 0, 0, (const float*)buf, out, 2 * n);
+    hipLaunchKernelGGL(k_scale_c, dim3(nblk(n)), dim3(kB), 0, 0, (C2<double>*)out, 1.0 / N, n);
+  }
+  if (hipGetLastError() != hipSuccess) return done(fail(TTSH_EHIP, "kernel launch failed"));
+  return done(TTSH_OK);
+}
+
+}  // extern "C"

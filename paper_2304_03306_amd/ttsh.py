@@ -1,0 +1,292 @@
+"""ctypes binding of libttsh.so (functions of include/ttsh.h, same names).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Host buffers are numpy arrays (passed with TTSH_HOST); device
+buffers are torch tensors on a ROCm device (passed with TTSH_DEVICE by their
+data pointer).  A missing library raises at import of this module's functions;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().with_name("libttsh.so")
+
+TTSH_OK, TTSH_EINVAL, TTSH_EUNSUPPORTED, TTSH_EHIP, TTSH_ENONFINITE, TTSH_ENOMEM = 0, -1, -2, -3, -4, -5
+TTSH_HOST, TTSH_DEVICE = 0, 1
+TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX = 0, 1, 2
+TTSH_FP32, TTSH_FP64, TTSH_FP32_STATE64 = 32, 64, 96
+TTSH_OPT_GRAPH_STEPS, TTSH_OPT_ROW_PAIRS, TTSH_OPT_COL_TILE, TTSH_OPT_GUARD = 1, 2, 3, 4
+SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX}
+
+
+class TTSHError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ttsh error {code}: {msg}")
+        self.code = code
+
+
+class ttsh_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("alpha", "beta", "gamma0", "gamma2", "lambda0", "lambda1", "gamma_v", "gamma_w", "dt")] + \
+               [("scheme", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libttsh.so (built in-tree by paper_2304_03306_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_03306_amd.build`")
+        L = ctypes.CDLL(str(LIB_PATH))
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        sig = {
+            "ttsh_create": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ttsh_params), i32, vp],
+            "ttsh_set_mask": [vp, i32, dp, i32],
+            "ttsh_get_mask": [vp, i32, dp, i32],
+            "ttsh_mask_tanh": [vp, i32, i32, dp, dp, dp, ctypes.c_double],
+            "ttsh_mask_from_binary": [vp, i32, dp, i32],
+            "ttsh_set_field": [vp, i32, dp, i32],
+            "ttsh_get_field": [vp, i32, dp, dp, i32],
+            "ttsh_set_state": [vp, i32, dp, i32],
+            "ttsh_get_state": [vp, i32, dp, i32],
+            "ttsh_step": [vp, i64],
+            "ttsh_reseed": [vp, i32, dp, dp, dp, i32],
+            "ttsh_norms": [vp, i32, dp],
+            "ttsh_sync": [vp],
+            "ttsh_set_option": [vp, i32, i64],
+            "ttsh_fft2": [dp, dp, i32, i32, i32, i32],
+            "ttsh_pass_times": [vp, i64, dp],
+            "ttsh_num_classes": [vp, dp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.ttsh_destroy.argtypes = [vp]
+        L.ttsh_destroy.restype = None
+        L.ttsh_last_error.argtypes = []
+        L.ttsh_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != TTSH_OK:
+        raise TTSHError(rc, lib().ttsh_last_error().decode())
+    return rc
+
+
+def _buf(x, dtype):
+    """(pointer, where, keepalive) of a numpy array (host) or torch tensor (device)."""
+    if x is None:
+        return None, TTSH_HOST, None
+    if isinstance(x, np.ndarray):
+        a = np.ascontiguousarray(x, dtype=dtype)
+        return a.ctypes.data_as(ctypes.c_void_p), TTSH_HOST, a
+    # torch tensor on the GPU
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("device buffers must be contiguous GPU tensors")
+    return ctypes.c_void_p(x.data_ptr()), TTSH_DEVICE, x
+
+
+def make_params(p) -> ttsh_params:
+    """ttsh_params from any object with the coefficient attributes."""
+    scheme = getattr(p, "scheme", "ifeuler")
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    return ttsh_params(p.alpha, p.beta, p.gamma0, p.gamma2, p.lambda0, p.lambda1,
+                       p.gamma_v, p.gamma_w, p.dt, int(scheme))
+
+
+# ---- functions of the C interface ------------------------------------------------
+def ttsh_create(N, L, params, precision=TTSH_FP32, stream=None):
+    n = len(N)
+    Na = (ctypes.c_int * n)(*[int(v) for v in N])
+    La = (ctypes.c_double * n)(*[float(v) for v in L])
+    prm = params if isinstance(params, ttsh_params) else make_params(params)
+    ctx = ctypes.c_void_p()
+    _check(lib().ttsh_create(ctypes.byref(ctx), n, Na, La, ctypes.byref(prm), int(precision),
+                             ctypes.c_void_p(stream or 0)))
+    return ctx
+
+
+def ttsh_destroy(ctx):
+    lib().ttsh_destroy(ctx)
+
+
+def ttsh_set_mask(ctx, inst, K):
+    p, w, keep = _buf(K, np.float64)
+    return _check(lib().ttsh_set_mask(ctx, inst, p, w))
+
+
+def ttsh_get_mask(ctx, inst, out):
+    p, w, keep = _buf(out, np.float64)
+    _check(lib().ttsh_get_mask(ctx, inst, p, w))
+    return out
+
+
+def ttsh_mask_tanh(ctx, inst, centers, radii, xi):
+    n = len(radii)
+    cx = np.ascontiguousarray([c[0] for c in centers], dtype=np.float64)
+    cy = np.ascontiguousarray([c[1] for c in centers], dtype=np.float64)
+    R = np.ascontiguousarray(radii, dtype=np.float64)
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    return _check(lib().ttsh_mask_tanh(ctx, inst, n, f(cx), f(cy), f(R), float(xi)))
+
+
+def ttsh_mask_from_binary(ctx, inst, K_naive):
+    p, w, keep = _buf(K_naive, np.uint8)
+    return _check(lib().ttsh_mask_from_binary(ctx, inst, p, w))
+
+
+def ttsh_set_field(ctx, inst, v):
+    p, w, keep = _buf(v, np.float64)
+    return _check(lib().ttsh_set_field(ctx, inst, p, w))
+
+
+def ttsh_get_field(ctx, inst, v_out, omega_out=None):
+    p, w, keep = _buf(v_out, np.float64)
+    q, w2, keep2 = _buf(omega_out, np.float64)
+    if omega_out is not None and w2 != w:
+        raise ValueError("v and omega must both be host or both be device buffers")
+    _check(lib().ttsh_get_field(ctx, inst, p, q, w))
+    return v_out, omega_out
+
+
+def ttsh_set_state(ctx, inst, vhat):
+    p, w, keep = _buf(vhat, np.complex128)
+    return _check(lib().ttsh_set_state(ctx, inst, p, w))
+
+
+def ttsh_get_state(ctx, inst, out):
+    p, w, keep = _buf(out, np.complex128)
+    _check(lib().ttsh_get_state(ctx, inst, p, w))
+    return out
+
+
+def ttsh_step(ctx, nsteps):
+    return _check(lib().ttsh_step(ctx, int(nsteps)))
+
+
+def ttsh_reseed(ctx, dst, src, noise=None):
+    n = len(dst)
+    d = (ctypes.c_int * n)(*[int(v) for v in dst])
+    s = (ctypes.c_int * n)(*[int(v) for v in src])
+    p, w, keep = _buf(noise, np.float64)
+    return _check(lib().ttsh_reseed(ctx, n, ctypes.cast(d, ctypes.c_void_p),
+                                    ctypes.cast(s, ctypes.c_void_p), p, w))
+
+
+def ttsh_norms(ctx, inst):
+    out = (ctypes.c_double * 4)()
+    _check(lib().ttsh_norms(ctx, inst, ctypes.cast(out, ctypes.c_void_p)))
+    return list(out)
+
+
+def ttsh_sync(ctx):
+    return _check(lib().ttsh_sync(ctx))
+
+
+def ttsh_set_option(ctx, key, value):
+    return _check(lib().ttsh_set_option(ctx, int(key), int(value)))
+
+
+def ttsh_fft2(inp, out, N, batch, inverse, precision):
+    """Device tensors (complex128 viewed as float64 pairs)."""
+    return _check(lib().ttsh_fft2(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  int(N), int(batch), int(bool(inverse)), int(precision)))
+
+
+def ttsh_num_classes(ctx):
+    n = lib().ttsh_num_classes(ctx, None)
+    if n < 0:
+        _check(n)
+    sizes = (ctypes.c_int * max(n, 1))()
+    lib().ttsh_num_classes(ctx, ctypes.cast(sizes, ctypes.c_void_p))
+    return list(sizes)[:n]
+
+
+def ttsh_pass_times(ctx, nsteps):
+    """{N: (row_us, col_us)} mean kernel durations from HIP events."""
+    sizes = ttsh_num_classes(ctx)
+    out = (ctypes.c_double * (2 * len(sizes)))()
+    _check(lib().ttsh_pass_times(ctx, int(nsteps), ctypes.cast(out, ctypes.c_void_p)))
+    return {N: (out[2 * i], out[2 * i + 1]) for i, N in enumerate(sizes)}
+
+
+def ttsh_last_error() -> str:
+    return lib().ttsh_last_error().decode()
+
+
+# ---- convenience wrapper ------------------------------------------------------------
+class Solver:
+    """Owns one context.  N, L: per-instance lists; params: coefficients object."""
+
+    def __init__(self, N, L, params, precision=TTSH_FP32, stream=None):
+        self.N = [int(n) for n in N]
+        self.L = [float(x) for x in L]
+        self.ctx = ttsh_create(self.N, self.L, params, precision, stream)
+
+    def close(self):
+        if self.ctx:
+            ttsh_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mask_tanh(self, inst, centers, radii, xi):
+        ttsh_mask_tanh(self.ctx, inst, centers, radii, xi)
+
+    def mask_from_binary(self, inst, K_naive):
+        ttsh_mask_from_binary(self.ctx, inst, K_naive)
+
+    def set_mask(self, inst, K):
+        ttsh_set_mask(self.ctx, inst, K)
+
+    def mask(self, inst):
+        n = self.N[inst]
+        return ttsh_get_mask(self.ctx, inst, np.empty((n, n)))
+
+    def set_field(self, inst, v):
+        ttsh_set_field(self.ctx, inst, v)
+
+    def field(self, inst, omega=False):
+        n = self.N[inst]
+        v = np.empty((2, n, n))
+        w = np.empty((n, n)) if omega else None
+        ttsh_get_field(self.ctx, inst, v, w)
+        return (v, w) if omega else v
+
+    def state(self, inst):
+        M = self.N[inst] // 4
+        return ttsh_get_state(self.ctx, inst, np.empty((2, 2 * M + 1, M + 1), dtype=np.complex128))
+
+    def set_state(self, inst, vhat):
+        ttsh_set_state(self.ctx, inst, vhat)
+
+    def step(self, n):
+        ttsh_step(self.ctx, n)
+
+    def sync(self):
+        ttsh_sync(self.ctx)
+
+    def norms(self, inst):
+        return ttsh_norms(self.ctx, inst)
+
+    def option(self, key, value):
+        ttsh_set_option(self.ctx, key, value)
+
+    def reseed(self, dst, src, noise=None):
+        ttsh_reseed(self.ctx, dst, src, noise)
