@@ -303,18 +303,24 @@ def velocity_rhs(vhat: np.ndarray, K: np.ndarray, p: Params, L: float):
 def velocity_step(vhat: np.ndarray, K: np.ndarray, p: Params, L: float) -> np.ndarray:
     """One step on the spectral velocity v_hat (full unitary spectrum).
 
-    v_hat' = A v_hat + B dt [P(k) N_hat + (i k_y, -i k_x) G_hat / k^2]  for
-    0 < m^2 <= M^2;  v_hat'(0) = A(0) v_hat(0) + B(0) dt rhs1_hat(0);  0 for
-    m^2 > M^2;  then the Hermitian correction.  Its curl is Algorithm 1's
+    v_hat' = P(k)[A v_hat + B dt N_hat] + B dt (i k_y, -i k_x) G_hat / k^2
+    for 0 < m^2 <= M^2;  v_hat'(0) = A(0) v_hat(0) + B(0) dt rhs1_hat(0);
+    0 for m^2 > M^2;  then the Hermitian correction.  Its curl is Algorithm 1's
     omega update (identical up to rounding), which the tests check.
+
+    The projection acts on the whole update, not on the forcing alone:
+    Algorithm 1 rebuilds v from the stream function of the new omega every
+    step, so v is divergence-free after every step.  Projecting only the
+    forcing would leave the rounding error's divergent part to be multiplied
+    by e^{L dt} each step, which grows wherever L(k) > 0.
     """
     N = vhat.shape[-1]
     M = N // 4
     kx, ky, k2, m2 = grid(N, L)
     N_hat, r1, G_hat = velocity_rhs(vhat, K, p, L)
     A, B = linear_factors(k2, p)
-    forcing = leray(N_hat, kx, ky, k2) + velocity_from_vorticity(G_hat, kx, ky, k2)
-    out = A * vhat + B * p.dt * forcing
+    out = leray(A * vhat + B * p.dt * N_hat, kx, ky, k2) \
+        + B * p.dt * velocity_from_vorticity(G_hat, kx, ky, k2)
     out[:, 0, 0] = A[0, 0] * vhat[:, 0, 0] + B[0, 0] * p.dt * r1[:, 0, 0]
     out = out * (m2 <= M * M)
     return hermitian_fix(out)

@@ -19,7 +19,7 @@
 //               X for the next step.
 //
 // The k-space update is the velocity form of Algorithm 1 (Appendix C):
-//   0 < m^2 <= M^2:  v' = A v + B dt [P(k) N_hat + (i k_y, -i k_x) G_hat / k^2]
+//   0 < m^2 <= M^2:  v' = P(k)[A v + B dt N_hat] + B dt (i k_y, -i k_x) G_hat / k^2
 //   m = 0:           v'(0) = A(0) v(0) + B(0) dt DFT[-(beta|v|^2 + gamma_v K) v](0)
 //                    (eq. (7): advection and the gamma_w term do not enter)
 //   m^2 > M^2:       v' = 0                                  (1/2-rule cutoff)
@@ -310,25 +310,27 @@ col_pass(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X, C2<S>* __restrict__
         double A, B;
         linear_ab(lc, dk, m2, A, B);
         const double inv_m2 = m2 > 0 ? 1.0 / (double)m2 : 0.0;
-        C2<double> fx, fy;
         if (m2 == 0) {
-          fx = mk(dt_over_N * s1x, 0.0);
-          fy = mk(dt_over_N * s1y, 0.0);
+          nx[e] = cscale(ux, A) + mk(B * dt_over_N * s1x, 0.0);
+          ny[e] = cscale(uy, A) + mk(B * dt_over_N * s1y, 0.0);
         } else {
-          fx = cscale(cvt<double>(f[0][e]), dt_over_N);
-          fy = cscale(cvt<double>(f[1][e]), dt_over_N);
+          // project the whole update (state and forcing), so that rounding
+          // never leaves a divergent part for e^{L dt} to amplify
+          const double bs = B * dt_over_N;
+          C2<double> qx = cscale(ux, A) + cscale(cvt<double>(f[0][e]), bs);
+          C2<double> qy = cscale(uy, A) + cscale(cvt<double>(f[1][e]), bs);
           const double dmx = mx, dmy = my;
-          const C2<double> d = cscale(mk(dmx * fx.x + dmy * fy.x, dmx * fx.y + dmy * fy.y), inv_m2);
-          fx = fx - cscale(d, dmx);
-          fy = fy - cscale(d, dmy);
+          const C2<double> d = cscale(mk(dmx * qx.x + dmy * qy.x, dmx * qx.y + dmy * qy.y), inv_m2);
+          qx = qx - cscale(d, dmx);
+          qy = qy - cscale(d, dmy);
           if constexpr (GW) {
-            const C2<double> g = cscale(cvt<double>(f[2][e]), dt_over_N * inv_m2 / dk);
-            fx = fx + mk(-dmy * g.y, dmy * g.x);
-            fy = fy + mk(dmx * g.y, -dmx * g.x);
+            const C2<double> g = cscale(cvt<double>(f[2][e]), bs * inv_m2 / dk);
+            qx = qx + mk(-dmy * g.y, dmy * g.x);
+            qy = qy + mk(dmx * g.y, -dmx * g.x);
           }
+          nx[e] = qx;
+          ny[e] = qy;
         }
-        nx[e] = cscale(ux, A) + cscale(fx, B);
-        ny[e] = cscale(uy, A) + cscale(fy, B);
       } else {
         nx[e] = ux;
         ny[e] = uy;

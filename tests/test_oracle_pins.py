@@ -220,6 +220,20 @@ def test_divergence_free_real_and_mean_vorticity():
     assert np.abs(O.idft2(w).imag).max() < 1e-15 * np.abs(w).max() * N
 
 
+def test_velocity_form_stays_divergence_free():
+    """Algorithm 1 derives v from the stream function every step, so the
+    velocity must stay divergence-free over long runs even where L(k) > 0
+    would amplify any divergent rounding error by e^{L t} (here e^{1.25 * 30})."""
+    N, L = 32, 32.0
+    K = O.mask_tanh(N, L, [(0, 0)], [10.0], 0.5)
+    p = O.workload_params()
+    vh = O.project_field(W.uniform_field(13, N, 0.01), L)
+    kx, ky, _, _ = O.grid(N, L)
+    for _ in range(3000):
+        vh = O.velocity_step(vh, K, p, L)
+    assert np.abs(kx * vh[0] + ky * vh[1]).max() < 1e-13 * np.abs(vh).max()
+
+
 def test_projection_idempotent_and_gradient_free():
     N, L = 32, 16.0
     kx, ky, k2, _ = O.grid(N, L)
