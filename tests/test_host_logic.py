@@ -1,0 +1,79 @@
+"""Host-side logic that needs no GPU: workload definitions, the sweep's chain
+map, the algorithmic-byte model used for the roofline, and the binding's
+refusal to run without the HIP library."""
+import importlib
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2304_03306_amd import workloads as W
+
+
+def test_radius_sweep_definition():
+    wl = W.radius_sweep()
+    assert len(wl.instances) == 64
+    radii = sorted({i.radii[0] for i in wl.instances})
+    assert len(radii) == 32 and radii[0] == 8.0 and radii[-1] == 80.0
+    for i in wl.instances:
+        assert abs(i.L - 3.2 * i.radii[0]) < 1e-12
+        assert i.L / i.N <= 0.5 + 1e-12
+        assert i.N == 128 or i.L / (i.N // 2) > 0.5  # smallest admissible grid
+    counts = {N: sum(1 for i in wl.instances if i.N == N) for N in (128, 256, 512)}
+    assert counts == {128: 12, 256: 16, 512: 36}
+    assert wl.points == 12 * 128 ** 2 + 16 * 256 ** 2 + 36 * 512 ** 2 == 10_682_368
+
+
+def test_sweep_chain_map():
+    src = W.sweep_chain(32)
+    assert len(src) == 64
+    for j in range(32):
+        up, down = 2 * j, 2 * j + 1
+        assert src[up] == (2 * (j - 1) if j else up)          # up ramp takes radius j-1
+        assert src[down] == (2 * (j + 1) + 1 if j < 31 else down)  # down ramp takes radius j+1
+    # every source is on the same ramp as its destination
+    assert all(s % 2 == d % 2 for d, s in enumerate(src))
+
+
+def test_dumbbell_definition():
+    wl = W.dumbbells()
+    assert len(wl.instances) == 16
+    d = [i.centers[1][0] - i.centers[0][0] for i in wl.instances]
+    assert abs(d[0] - 40) < 1e-12 and abs(d[-1] - 80) < 1e-12
+    assert all(i.N == 1024 and i.L == 256.0 and i.radii == [40.0, 40.0] for i in wl.instances)
+
+
+def test_uniform_field_is_seeded_and_rounded():
+    a = W.uniform_field(3, 16, 0.01, 32)
+    b = W.uniform_field(3, 16, 0.01, 32)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
+    assert np.abs(a).max() <= 0.01 and a.shape == (2, 16, 16)
+    assert not np.array_equal(a, W.uniform_field(4, 16, 0.01, 32))
+
+
+def test_binary_outside():
+    N, L = 32, 32.0
+    b = W.binary_outside(N, L, [(0.0, 0.0)], [8.0])
+    assert b.dtype == np.uint8
+    assert b[N // 2, N // 2] == 0 and b[0, 0] == 1
+    assert b[N // 2, N // 2 + 8] == 1  # ||x|| >= R is wall
+
+
+def test_algorithmic_bytes_model():
+    import bench
+    # kept modes of the half disk for M = 128
+    M = 128
+    brute = sum(1 for mx in range(M + 1) for my in range(-M, M + 1) if mx * mx + my * my <= M * M)
+    assert bench.kept_modes(512) == brute
+    row, col = bench.pass_bytes(512, 8)
+    assert abs((row + col) / 512 ** 2 - 26.5) < 1.0  # ~ 28 B/pt with the full rectangle
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    from paper_2304_03306_amd import ttsh
+    monkeypatch.setattr(ttsh, "LIB_PATH", tmp_path / "missing.so")
+    monkeypatch.setattr(ttsh, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        ttsh.lib()
