@@ -33,27 +33,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pass_bytes(N: int, gw: bool = False) -> tuple[int, int]:
-    """Algorithmic HBM bytes of one instance for (row pass, column pass), FP32.
+def kept_modes(N: int) -> int:
+    """Stored modes per component that the 1/2 rule keeps: m_x = 0..M,
+    m_y = -M..M with m_x^2 + m_y^2 <= M^2 (M = N/4)."""
+    M = N // 4
+    return sum(2 * int(np.floor(np.sqrt(M * M - mx * mx))) + 1 for mx in range(M + 1))
+
+
+def pass_bytes(N: int, state_bytes: int = 8, gw: bool = False) -> tuple[int, int]:
+    """Algorithmic HBM bytes of one instance for (row pass, column pass);
+    FP32 transforms, `state_bytes` per stored complex mode.
 
     Row pass:    read v_x, v_y, omega in the mixed domain (3 (M+1) N complex),
                  read K (N^2 reals), write the forcing (2 (M+1) N complex) and
                  the row sums (2N reals).
-    Column pass: read the forcing, read and write the compact state
-                 (2 x 2 (M+1)(2M+1) complex), write the mixed v_x, v_y, omega,
-                 read the row sums.
+    Column pass: read the forcing, read and write the kept modes of the state
+                 (2 components), write the mixed v_x, v_y, omega, read the row
+                 sums.
     """
     M = N // 4
     c8, r4 = 8, 4
     nf = 3 if gw else 2
     mixed = (M + 1) * N * c8
     row = 3 * mixed + N * N * r4 + nf * mixed + 2 * N * r4
-    col = nf * mixed + 2 * 2 * (M + 1) * (2 * M + 1) * c8 + 3 * mixed + 2 * N * r4
+    col = nf * mixed + 2 * 2 * kept_modes(N) * state_bytes + 3 * mixed + 2 * N * r4
     return row, col
 
 
-def setup(T, W, wl, params):
-    s = T.Solver([i.N for i in wl.instances], [i.L for i in wl.instances], params, T.TTSH_FP32)
+def setup(T, W, wl, params, prec):
+    s = T.Solver([i.N for i in wl.instances], [i.L for i in wl.instances], params, prec)
     for q, inst in enumerate(wl.instances):
         s.mask_tanh(q, inst.centers, inst.radii, inst.xi)
         s.set_field(q, W.uniform_field(inst.seed, inst.N, 0.01, 32))
@@ -133,6 +141,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--workload", default="sweep", choices=["sweep", "dumbbell"])
+    ap.add_argument("--precision", type=int, default=32, choices=[32, 96],
+                    help="32: FP32 state; 96: FP64 state (FP32 transforms in both)")
+    ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = autotuned)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -148,8 +159,15 @@ def main():
     params = O.workload_params()
     wl = W.radius_sweep() if args.workload == "sweep" else W.dumbbells()
     log(f"[bench] workload {wl.name}: {len(wl.instances)} instances, {wl.points} points/step")
-    s = setup(T, W, wl, params)
+    state_bytes = 8 if args.precision == 32 else 16
+    s = setup(T, W, wl, params, args.precision)
     s.option(T.TTSH_OPT_GUARD, 0)
+    if args.block:
+        s.option(T.TTSH_OPT_BLOCK, args.block)
+        block = args.block
+    else:
+        block, tuned_us = s.tune(20)
+        log(f"[bench] autotuned workgroup size {block} ({tuned_us:.1f} us/step)")
 
     parity = {}
     if not args.no_parity and args.workload == "sweep":
@@ -173,27 +191,26 @@ def main():
         finite = False
 
     # per-kernel durations from HIP events on the library's stream
-    times = T.ttsh_pass_times(s.ctx, args.prof_steps)
+    row_us, col_us = T.ttsh_pass_times(s.ctx, args.prof_steps)
     counts = {}
     for i in wl.instances:
         counts[i.N] = counts.get(i.N, 0) + 1
-    kern = []
-    for N, (row_us, col_us) in times.items():
-        rb, cb = pass_bytes(N)
-        kern.append(("row_pass", N, row_us, rb * counts[N]))
-        kern.append(("col_pass", N, col_us, cb * counts[N]))
-    dom = max(kern, key=lambda k: k[2])
-    achieved = dom[3] / (dom[2] * 1e-6) / 1e9
-    step_bytes = sum(k[3] for k in kern)
-    step_us = sum(k[2] for k in kern)
-    log("[bench] kernels: " + ", ".join(f"{k[0]}<{k[1]}> {k[2]:.1f}us {k[3] / k[2] / 1e3:.0f}GB/s" for k in kern))
+    row_b = sum(pass_bytes(N, state_bytes)[0] * n for N, n in counts.items())
+    col_b = sum(pass_bytes(N, state_bytes)[1] * n for N, n in counts.items())
+    kern = [("row_multi", row_us, row_b), ("col_multi", col_us, col_b)]
+    dom = max(kern, key=lambda k: k[1])
+    achieved = dom[2] / (dom[1] * 1e-6) / 1e9
+    step_bytes = row_b + col_b
+    step_us = row_us + col_us
+    log("[bench] kernels: " + ", ".join(f"{k[0]} {k[1]:.1f}us {k[2] / k[1] / 1e3:.0f}GB/s" for k in kern))
     s.close()
 
     plain = None
     if not args.no_plain:
         pw = W.circle_fp32_512()
-        ps = setup(T, W, pw, params)
+        ps = setup(T, W, pw, params, args.precision)
         ps.option(T.TTSH_OPT_GUARD, 0)
+        pblock, _ = ps.tune(20)
         perr = None
         if not args.no_parity:
             ps.step(1000)
@@ -206,7 +223,7 @@ def main():
         pdt = timed_steps(ps, torch, psteps)
         plain = {"workload": pw.name, "value": pw.points * psteps / pdt, "unit": "grid-pt·steps/s",
                  "steps": psteps, "ms_per_step": 1e3 * pdt / psteps,
-                 "config": {"N": 512, "L": 256.0, "R": 60.0, "instances": 1}}
+                 "config": {"N": 512, "L": 256.0, "R": 60.0, "instances": 1, "block": pblock}}
         log(f"[bench] plain 512^2: {plain['value']:.4e} pt*steps/s, {plain['ms_per_step'] * 1e3:.1f} us/step")
         ps.close()
 
@@ -227,16 +244,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == 32 else "f32 (f64 state)",
         "data": "synthetic",
         "config": {"workload": wl.name, "instances": len(wl.instances),
                    "grids": " + ".join(f"{counts[N]}x{N}^2" for N in sizes),
-                   "points_per_step": wl.points, "dt": params.dt, "precision": "FP32 (FP64 k-space update)",
+                   "points_per_step": wl.points, "dt": params.dt, "block": block,
+                   "precision": ("FP32 transforms and state" if args.precision == 32 else
+                                 "FP32 transforms, FP64 state") + ", FP64 k-space update",
                    "parallelism": "single GPU, instances batched per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"{dom[0]}<N={dom[1]}>", "avg_us": dom[2],
-                     "bytes_per_launch": dom[3]},
+                     "kernel": dom[0], "avg_us": dom[1], "bytes_per_launch": dom[2]},
         "step_hbm": {"algorithmic_bytes": step_bytes, "kernel_us": step_us,
                      "GBps": step_bytes / (step_us * 1e-6) / 1e9,
                      "frac": step_bytes / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,

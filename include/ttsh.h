@@ -86,8 +86,8 @@ typedef struct {
 /* Options for ttsh_set_option. */
 enum {
   TTSH_OPT_GRAPH_STEPS = 1, /* steps captured per HIP graph (0 = no graph); default 50 */
-  TTSH_OPT_ROW_PAIRS = 2,   /* row pairs per workgroup of the row pass (0 = tuned) */
-  TTSH_OPT_COL_TILE = 3,    /* columns per workgroup of the column pass (0 = tuned) */
+  TTSH_OPT_BLOCK = 2,       /* workgroup size of the step kernels: 64, 128 or 256
+                               (8 x size >= largest N), 0 = chosen from the batch */
   TTSH_OPT_GUARD = 4        /* 1: ttsh_sync checks the state for NaN/Inf; default 1 */
 };
 
@@ -164,11 +164,17 @@ int ttsh_norms(ttsh_ctx* ctx, int inst, double out[4]);
 int ttsh_sync(ttsh_ctx* ctx);
 
 /* Measurement: advance every instance by nsteps >= 1 steps without graphs,
- * bracketing each kernel launch with HIP events on the context's stream, and
- * return the mean duration in microseconds of each pass of each size class:
- * out[2c] = row pass, out[2c+1] = column pass, for the size classes c in
- * increasing N (out needs 2 * ttsh_num_classes entries).  Synchronous.     */
+ * bracketing each of the two kernel launches of a step (row pass, column
+ * pass; each covers every instance) with HIP events on the context's stream,
+ * and return their mean durations in microseconds: out[0] = row pass,
+ * out[1] = column pass.  Synchronous.                                      */
 int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
+
+/* Autotuner: time nsteps steps with every usable workgroup size (HIP events,
+ * after two warm-up steps), keep the fastest, and restore the state the
+ * context had before the call.  Writes the chosen size and its microseconds
+ * per step (either pointer may be NULL).  Synchronous.                      */
+int ttsh_tune(ttsh_ctx* ctx, int64_t nsteps, int* bs_out, double* us_out);
 
 /* Number of distinct grid sizes (size classes) in the context; their sizes in
  * increasing order go to N_out (may be NULL).                               */

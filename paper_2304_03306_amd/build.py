@@ -17,6 +17,8 @@ CSRC = HERE / "csrc"
 OUT = HERE / "_build"
 LIB = HERE / "libttsh.so"
 SIZES = (64, 128, 256, 512, 1024)
+PRECS = (32, 64, 96)
+BLOCKS = (64, 128, 256)
 ARCH = os.environ.get("TTSH_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -43,6 +45,8 @@ def build(jobs: int | None = None, verbose: bool = True) -> Path:
     OUT.mkdir(exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     units = [(CSRC / "kernels_n.hip", OUT / f"kernels_{n}.o", [f"-DTTSH_N={n}"]) for n in SIZES]
+    units += [(CSRC / "step_multi.hip", OUT / f"step_{p}_{b}.o", [f"-DTTSH_PREC={p}", f"-DTTSH_BS={b}"])
+              for p in PRECS for b in BLOCKS]
     units.append((CSRC / "ttsh_capi.hip", OUT / "ttsh_capi.o", []))
     cmds = [[HIPCC, *FLAGS, *extra, "-c", str(src), "-o", str(obj)] for src, obj, extra in units]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

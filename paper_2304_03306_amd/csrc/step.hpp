@@ -85,26 +85,33 @@ __device__ __forceinline__ C2<T> pack_pq(C2<T> p, C2<T> q) {
 }
 
 // ---------------------------------------------------------------------------
-// row pass: RP row pairs per workgroup, TT threads per pair
+// row pass: RP row pairs per workgroup, TT threads per pair; `tile` selects
+// rows 2 RP tile .. 2 RP (tile + 1) - 1 of instance `inst`
 // ---------------------------------------------------------------------------
+template <int N, int RP, class T>
+struct RowSmem {
+  static constexpr size_t lds = (size_t)RP * 3 * Geo<N>::NP * sizeof(C2<T>);
+  static constexpr size_t bytes = lds + (size_t)(RP * Geo<N>::TT / 64) * RP * 4 * sizeof(T);
+};
+
 template <int N, int RP, class T, bool GW>
-__global__ void __launch_bounds__(RP*(N / 8))
-row_pass(const C2<T>* __restrict__ X, C2<T>* __restrict__ Y, const T* __restrict__ K,
-         T* __restrict__ rowsum, const C2<T>* __restrict__ tw, RowCoef<T> c) {
+__device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
+                                         const T* __restrict__ K, T* __restrict__ rowsum,
+                                         const C2<T>* __restrict__ tw, const RowCoef<T>& c,
+                                         size_t inst, int tile, unsigned char* smem) {
   using G = Geo<N>;
   constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, NP = G::NP;
   constexpr int NFY = GW ? 3 : 2;
   constexpr int NT = RP * TT;
   constexpr int NW = NT / 64;
   static_assert(NT % 64 == 0, "row pass needs whole wavefronts");
-  __shared__ C2<T> lds[RP * 3 * NP];
-  __shared__ T red[NW][RP][4];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem);
+  T(*red)[RP][4] = reinterpret_cast<T(*)[RP][4]>(smem + RowSmem<N, RP, T>::lds);
 
   const int tid = threadIdx.x;
   const int lane = tid % RP;
   const int t = tid / RP;
-  const size_t inst = blockIdx.y;
-  const int y0 = (blockIdx.x * RP + lane) * 2;
+  const int y0 = (tile * RP + lane) * 2;
   const CPair<T>* Xp = reinterpret_cast<const CPair<T>*>(X + inst * 3 * MP * N);
   CPair<T>* Yp = reinterpret_cast<CPair<T>*>(Y + inst * NFY * MP * N);
   const T* Kp = K + inst * N * N;
@@ -237,24 +244,23 @@ struct ColSmem {
 };
 
 template <int N, int TC, class T, class S, bool GW, int MODE>
-__global__ void __launch_bounds__(TC*(N / 8))
-col_pass(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X, C2<S>* __restrict__ st,
-         const T* __restrict__ rowsum, const double* __restrict__ dkv,
-         const C2<T>* __restrict__ tw, LinCoef lc) {
+__device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X,
+                                         C2<S>* __restrict__ st, const T* __restrict__ rowsum,
+                                         const double* __restrict__ dkv,
+                                         const C2<T>* __restrict__ tw, const LinCoef& lc,
+                                         size_t inst, int tile, unsigned char* smem) {
   using G = Geo<N>;
   constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, SP = G::SP, NP = G::NP;
   constexpr int NFY = GW ? 3 : 2;
   constexpr int NT = TC * TT;
   constexpr int NW = NT / 64;
   static_assert(NT % 64 == 0, "column pass needs whole wavefronts");
-  __shared__ __align__(16) unsigned char smem[ColSmem<N, TC, T, GW>::bytes];
 
   const int tid = threadIdx.x;
   const int t = tid % TT;
   const int col = tid / TT;
-  const int mx = blockIdx.x * TC + col;
+  const int mx = tile * TC + col;
   const bool valid = mx <= M;
-  const size_t inst = blockIdx.y;
   const double dk = dkv[inst];
   C2<T>* L = reinterpret_cast<C2<T>*>(smem) + col * 3 * NP;
   C2<S>* stp = st + inst * 2 * MP * SP;
@@ -262,7 +268,7 @@ col_pass(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X, C2<S>* __restrict__
   C2<T> f[NFY][E];
   double s1x = 0.0, s1y = 0.0;
   if constexpr (MODE == 0) {
-    if (blockIdx.x == 0) {  // sum of the row sums: DFT of the k = 0 forcing
+    if (tile == 0) {  // sum of the row sums: DFT of the k = 0 forcing
       const T* rs = rowsum + inst * 2 * N;
       double a = 0.0, b = 0.0;
       for (int y = tid; y < N; y += NT) {
@@ -339,7 +345,7 @@ col_pass(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X, C2<S>* __restrict__
   }
 
   if constexpr (MODE == 0) {
-    if (blockIdx.x == 0) {  // Hermitian correction on the m_x = 0 column
+    if (tile == 0) {  // Hermitian correction on the m_x = 0 column
       C2<double>* H = reinterpret_cast<C2<double>*>(smem);
       __syncthreads();
       if (col == 0) {

@@ -1,0 +1,63 @@
+// Launchers of the multi-size step kernels for one arithmetic (TTSH_PREC =
+// 32: FP32 with FP32 state, 64: FP64, 96: FP32 with FP64 state) and one
+// workgroup size (TTSH_BS = 64, 128 or 256), both set on the compiler command
+// line.  The row pass does not depend on the state type, so the FP32-state
+// build also serves the FP64-state one.
+#include "launch.hpp"
+#include "step_multi.hpp"
+
+#if !defined(TTSH_PREC) || !defined(TTSH_BS)
+#error "define TTSH_PREC and TTSH_BS"
+#endif
+
+namespace ttsh {
+namespace {
+
+#if TTSH_PREC == 64
+using T = double;
+using S = double;
+#elif TTSH_PREC == 96
+using T = float;
+using S = double;
+#else
+using T = float;
+using S = float;
+#endif
+constexpr int BS = TTSH_BS;
+
+#if TTSH_PREC != 96
+hipError_t row(const MultiArgs& a, int gw, hipStream_t s) {
+  const int grid = a.start[a.ncls];
+  if (gw)
+    hipLaunchKernelGGL((row_multi<T, true, BS>), dim3(grid), dim3(BS), 0, s, a);
+  else
+    hipLaunchKernelGGL((row_multi<T, false, BS>), dim3(grid), dim3(BS), 0, s, a);
+  return hipGetLastError();
+}
+#endif
+
+hipError_t col(const MultiArgs& a, int gw, int mode, hipStream_t s) {
+  const int grid = a.start[a.ncls];
+  if (mode == 1)
+    hipLaunchKernelGGL((col_multi<T, S, false, 1, BS>), dim3(grid), dim3(BS), 0, s, a);
+  else if (gw)
+    hipLaunchKernelGGL((col_multi<T, S, true, 0, BS>), dim3(grid), dim3(BS), 0, s, a);
+  else
+    hipLaunchKernelGGL((col_multi<T, S, false, 0, BS>), dim3(grid), dim3(BS), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define TTSH_CAT4(a, b, c, d) a##b##c##d
+#define TTSH_NAME(p, b) TTSH_CAT4(multi_ops_, p, _, b)
+const MultiOps* TTSH_NAME(TTSH_PREC, TTSH_BS)() {
+#if TTSH_PREC != 96
+  static const MultiOps ops = {row, col};
+#else
+  static const MultiOps ops = {nullptr, col};
+#endif
+  return &ops;
+}
+
+}  // namespace ttsh

@@ -1,0 +1,137 @@
+// One launch per pass for every instance of a context, whatever its mix of
+// grid sizes.  Workgroups have a fixed size BS; an instance of size N is cut
+// into tiles of BS threads: RP = BS/(N/8) row pairs per row-pass tile and
+// TC = BS/(N/8) columns per column-pass tile, so every tile carries the same
+// amount of data (16 BS grid points of the row pass, 8 BS of the column pass)
+// and the LDS footprint is the same for every N.  Workgroup b finds its size
+// class from prefix sums of the per-class tile counts, then its instance and
+// tile; the class test is uniform across the workgroup.
+#pragma once
+
+#include "step.hpp"
+
+namespace ttsh {
+
+constexpr int kMaxClasses = 5;
+
+struct ClassArgs {
+  int N;       // grid points per side
+  int n;       // instances in the class (contiguous in every array below)
+  int tiles;   // tiles per instance in this pass
+  const void* X_in;
+  void* X_out;
+  void* Y;
+  void* st;
+  const void* K;
+  void* rowsum;
+  const double* dk;
+  const void* tw;
+};
+
+struct MultiArgs {
+  int ncls;
+  int start[kMaxClasses + 1];  // first workgroup of each class; start[ncls] = grid size
+  ClassArgs c[kMaxClasses];
+  double beta, gamma_v, lambda0, gamma_w;
+  LinCoef lc;
+};
+
+template <int N, int BS>
+struct TileOf {
+  static constexpr int TT = N / 8;
+  static constexpr int R = BS / TT;  // row pairs (row pass) or columns (column pass)
+  static constexpr bool ok = BS % TT == 0 && R >= 1;
+};
+
+template <class T, int BS, int N>
+constexpr size_t row_smem_n() {
+  if constexpr (TileOf<N, BS>::ok) return RowSmem<N, TileOf<N, BS>::R, T>::bytes;
+  else return 0;
+}
+template <class T, int BS, int N>
+constexpr size_t col_smem_n() {
+  if constexpr (TileOf<N, BS>::ok) return ColSmem<N, TileOf<N, BS>::R, T, true>::bytes;
+  else return 0;
+}
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+template <class T, int BS>
+constexpr size_t row_smem() {
+  return cmax(cmax(cmax(row_smem_n<T, BS, 64>(), row_smem_n<T, BS, 128>()),
+                   cmax(row_smem_n<T, BS, 256>(), row_smem_n<T, BS, 512>())),
+              row_smem_n<T, BS, 1024>());
+}
+template <class T, int BS>
+constexpr size_t col_smem() {
+  return cmax(cmax(cmax(col_smem_n<T, BS, 64>(), col_smem_n<T, BS, 128>()),
+                   cmax(col_smem_n<T, BS, 256>(), col_smem_n<T, BS, 512>())),
+              col_smem_n<T, BS, 1024>());
+}
+
+__device__ __forceinline__ int class_of(const MultiArgs& a, int b) {
+  int ci = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxClasses; ++q)
+    if (q < a.ncls && b >= a.start[q]) ci = q;
+  return ci;
+}
+
+template <int N, class T, bool GW, int BS>
+__device__ __forceinline__ void row_go(const ClassArgs& d, const RowCoef<T>& c, int inst, int tile,
+                                       unsigned char* smem) {
+  if constexpr (TileOf<N, BS>::ok)
+    row_body<N, TileOf<N, BS>::R, T, GW>((const C2<T>*)d.X_in, (C2<T>*)d.Y, (const T*)d.K,
+                                         (T*)d.rowsum, (const C2<T>*)d.tw, c, inst, tile, smem);
+}
+
+template <class T, bool GW, int BS>
+__global__ void __launch_bounds__(BS) row_multi(MultiArgs a) {
+  __shared__ __align__(16) unsigned char smem[row_smem<T, BS>()];
+  const int b = blockIdx.x;
+  const int ci = class_of(a, b);
+  const ClassArgs& d = a.c[ci];
+  const int local = b - a.start[ci];
+  const int inst = local / d.tiles;
+  const int tile = local - inst * d.tiles;
+  const RowCoef<T> c{(T)a.beta, (T)a.gamma_v, (T)a.lambda0, (T)a.gamma_w};
+  switch (d.N) {
+    case 64: row_go<64, T, GW, BS>(d, c, inst, tile, smem); break;
+    case 128: row_go<128, T, GW, BS>(d, c, inst, tile, smem); break;
+    case 256: row_go<256, T, GW, BS>(d, c, inst, tile, smem); break;
+    case 512: row_go<512, T, GW, BS>(d, c, inst, tile, smem); break;
+    case 1024: row_go<1024, T, GW, BS>(d, c, inst, tile, smem); break;
+    default: break;
+  }
+}
+
+template <int N, class T, class S, bool GW, int MODE, int BS>
+__device__ __forceinline__ void col_go(const ClassArgs& d, const LinCoef& lc, int inst, int tile,
+                                       unsigned char* smem) {
+  if constexpr (TileOf<N, BS>::ok) {
+    LinCoef l = lc;
+    l.dt_over_N = lc.dt / N;  // the unnormalised forward FFT carries N x the unitary DFT
+    col_body<N, TileOf<N, BS>::R, T, S, GW, MODE>((const C2<T>*)d.Y, (C2<T>*)d.X_out, (C2<S>*)d.st,
+                                                  (const T*)d.rowsum, d.dk, (const C2<T>*)d.tw, l,
+                                                  inst, tile, smem);
+  }
+}
+
+template <class T, class S, bool GW, int MODE, int BS>
+__global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
+  __shared__ __align__(16) unsigned char smem[col_smem<T, BS>()];
+  const int b = blockIdx.x;
+  const int ci = class_of(a, b);
+  const ClassArgs& d = a.c[ci];
+  const int local = b - a.start[ci];
+  const int inst = local / d.tiles;
+  const int tile = local - inst * d.tiles;
+  switch (d.N) {
+    case 64: col_go<64, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
+    case 128: col_go<128, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
+    case 256: col_go<256, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
+    case 512: col_go<512, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
+    case 1024: col_go<1024, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
+    default: break;
+  }
+}
+
+}  // namespace ttsh

@@ -15,6 +15,7 @@
 #include "../../include/ttsh.h"
 #include "aux.hpp"
 #include "launch.hpp"
+#include "step_multi.hpp"
 
 using namespace ttsh;
 
@@ -31,6 +32,28 @@ const SizeOps* size_ops(int N) {
     case 256: return ops_256();
     case 512: return ops_512();
     case 1024: return ops_1024();
+    default: return nullptr;
+  }
+}
+#define TTSH_DECL(p)                   \
+  const MultiOps* multi_ops_##p##_64();  \
+  const MultiOps* multi_ops_##p##_128(); \
+  const MultiOps* multi_ops_##p##_256();
+TTSH_DECL(32)
+TTSH_DECL(64)
+TTSH_DECL(96)
+#undef TTSH_DECL
+const MultiOps* multi_ops(int prec, int bs) {
+  switch (prec * 1000 + bs) {
+    case 32064: return multi_ops_32_64();
+    case 32128: return multi_ops_32_128();
+    case 32256: return multi_ops_32_256();
+    case 64064: return multi_ops_64_64();
+    case 64128: return multi_ops_64_128();
+    case 64256: return multi_ops_64_256();
+    case 96064: return multi_ops_96_64();
+    case 96128: return multi_ops_96_128();
+    case 96256: return multi_ops_96_256();
     default: return nullptr;
   }
 }
@@ -64,7 +87,6 @@ struct SizeClass {
   void* rowsum = nullptr;
   double* dk = nullptr;
   void* tw = nullptr;    // run precision
-  int rp = 0, tc = 0;    // chosen tiles
   // per-instance strides in elements
   size_t sX() const { return (size_t)3 * (N / 4 + 1) * N; }
   size_t sY(int gw) const { return (size_t)(gw ? 3 : 2) * (N / 4 + 1) * N; }
@@ -91,7 +113,8 @@ struct ttsh_ctx {
   void* scr1 = nullptr;
   double* dnorm = nullptr;               // [n_inst][5]
   int graph_steps = 50;
-  int opt_rp = 0, opt_tc = 0;
+  int bs = 0;       // workgroup size of the step kernels in use
+  int opt_bs = 0;   // requested by TTSH_OPT_BLOCK (0 = chosen)
   int guard = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -125,41 +148,45 @@ int make_twiddles(int N, bool fp64, void** out) {
   return TTSH_OK;
 }
 
-// Pick tiles: the largest tile that still gives >= target workgroups, else the
-// smallest valid one.  Overridden by TTSH_OPT_ROW_PAIRS / TTSH_OPT_COL_TILE.
-int pick(unsigned mask, int want, int per_inst_units, int n, int target) {
-  if (want > 0) return (mask & (unsigned)want) ? want : -1;
-  int best = -1, smallest = -1;
-  for (int b = 0; b < 6; ++b) {
-    if (!(mask & (1u << b))) continue;
-    const int v = 1 << b;
-    if (smallest < 0) smallest = v;
-    const int groups = (per_inst_units + v - 1) / v * n;
-    if (groups >= target) best = v;
-  }
-  return best > 0 ? best : smallest;
+int max_N(const ttsh_ctx* c) {
+  int m = 0;
+  for (auto& k : c->cls) m = std::max(m, k.N);
+  return m;
 }
 
-int choose_tiles(ttsh_ctx* c) {
-  for (auto& k : c->cls) {
-    const SizeOps* ops = size_ops(k.N);
-    const int n = (int)k.ids.size();
-    k.rp = pick(ops->row_options(c->prec, c->gw), c->opt_rp, k.N / 2, n, 1024);
-    k.tc = pick(ops->col_options(c->prec, c->gw), c->opt_tc, k.N / 4 + 1, n, 512);
-    if (k.rp < 0 || k.tc < 0) return fail(TTSH_EUNSUPPORTED, "tile option not available for N=" + std::to_string(k.N));
+// A workgroup of bs threads carries one transform of length N with N/8
+// threads, so bs is usable when 8 bs >= N for every size class.
+bool bs_valid(const ttsh_ctx* c, int bs) {
+  return (bs == 64 || bs == 128 || bs == 256) && 8 * bs >= max_N(c);
+}
+
+// Default workgroup size: the largest one that still gives >= 2048 row-pass
+// workgroups (8 per compute unit), else the smallest usable one.
+int choose_bs(ttsh_ctx* c) {
+  if (c->opt_bs) {
+    if (!bs_valid(c, c->opt_bs)) return fail(TTSH_EUNSUPPORTED, "workgroup size not usable for this context");
+    c->bs = c->opt_bs;
+    return TTSH_OK;
   }
+  long pts = 0;
+  for (size_t i = 0; i < c->N.size(); ++i) pts += (long)c->N[i] * c->N[i];
+  int best = 0;
+  for (int bs : {64, 128, 256}) {
+    if (!bs_valid(c, bs)) continue;
+    if (!best || pts / (16L * bs) >= 2048) best = bs;
+  }
+  if (!best) return fail(TTSH_EUNSUPPORTED, "no workgroup size fits N");
+  c->bs = best;
   return TTSH_OK;
 }
 
-PassArgs pass_args(ttsh_ctx* c, SizeClass& k, int first, int count) {
-  PassArgs a{};
+ClassArgs class_args(ttsh_ctx* c, SizeClass& k, int first, int count, int row) {
+  ClassArgs a{};
   const size_t er = elem_real(c->prec), es = elem_state(c->prec);
+  const int R = c->bs / (k.N / 8);
   a.N = k.N;
   a.n = count;
-  a.prec = c->prec;
-  a.gw = c->gw;
-  a.rp = k.rp;
-  a.tc = k.tc;
+  a.tiles = row ? k.N / (2 * R) : (k.N / 4 + 1 + R - 1) / R;
   a.X_in = (const char*)k.X + first * k.sX() * 2 * er;
   a.X_out = (char*)k.X + first * k.sX() * 2 * er;
   a.Y = (char*)k.Y + first * k.sY(c->gw) * 2 * er;
@@ -168,29 +195,47 @@ PassArgs pass_args(ttsh_ctx* c, SizeClass& k, int first, int count) {
   a.rowsum = (char*)k.rowsum + first * (size_t)2 * k.N * er;
   a.dk = k.dk + first;
   a.tw = k.tw;
-  a.beta = c->p.beta;
-  a.gamma_v = c->p.gamma_v;
-  a.lambda0 = c->p.lambda0;
-  a.gamma_w = c->p.gamma_w;
-  a.alpha = c->p.alpha;
-  a.gamma0 = c->p.gamma0;
-  a.gamma2 = c->p.gamma2;
-  a.dt = c->p.dt;
-  a.scheme = c->p.scheme;
-  a.dt_over_N = c->p.dt / (double)k.N;
   return a;
 }
 
+// Launch arguments of one pass: all instances (inst < 0) or one instance.
+MultiArgs multi_args(ttsh_ctx* c, int row, int inst) {
+  MultiArgs m{};
+  m.beta = c->p.beta;
+  m.gamma_v = c->p.gamma_v;
+  m.lambda0 = c->p.lambda0;
+  m.gamma_w = c->p.gamma_w;
+  m.lc = LinCoef{c->p.alpha, c->p.gamma0, c->p.gamma2, c->p.dt, 0.0, c->p.scheme};
+  int blocks = 0;
+  auto add = [&](SizeClass& k, int first, int count) {
+    ClassArgs a = class_args(c, k, first, count, row);
+    m.start[m.ncls] = blocks;
+    m.c[m.ncls++] = a;
+    blocks += a.tiles * count;
+  };
+  if (inst < 0) {
+    for (auto& k : c->cls) add(k, 0, (int)k.ids.size());
+  } else {
+    auto [ci, j] = c->loc[inst];
+    add(c->cls[ci], j, 1);
+  }
+  m.start[m.ncls] = blocks;
+  return m;
+}
+
+hipError_t launch_row(ttsh_ctx* c, const MultiArgs& m, hipStream_t s) {
+  return multi_ops(c->prec == 64 ? 64 : 32, c->bs)->row(m, c->gw, s);
+}
+hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) {
+  return multi_ops(c->prec, c->bs)->col(m, c->gw, mode, s);
+}
+
 int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
+  if (n <= 0) return TTSH_OK;
+  const MultiArgs r = multi_args(c, 1, -1), q = multi_args(c, 0, -1);
   for (int64_t i = 0; i < n; ++i) {
-    for (auto& k : c->cls) {
-      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
-      HIPCHK(size_ops(k.N)->row(a, s));
-    }
-    for (auto& k : c->cls) {
-      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
-      HIPCHK(size_ops(k.N)->col(a, 0, s));
-    }
+    HIPCHK(launch_row(c, r, s));
+    HIPCHK(launch_col(c, q, 0, s));
   }
   return TTSH_OK;
 }
@@ -240,10 +285,7 @@ unsigned nblk(size_t n) { return (unsigned)((n + kB - 1) / kB); }
 
 // X of one instance from its state
 int refresh_x(ttsh_ctx* c, int inst) {
-  auto [ci, j] = c->loc[inst];
-  SizeClass& k = c->cls[ci];
-  PassArgs a = pass_args(c, k, j, 1);
-  HIPCHK(size_ops(k.N)->col(a, 1, c->stream));
+  HIPCHK(launch_col(c, multi_args(c, 0, inst), 1, c->stream));
   return TTSH_OK;
 }
 
@@ -393,7 +435,8 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
     return bail(fail(TTSH_ENOMEM, "scratch allocation failed"));
   if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(TTSH_EHIP, "stream creation failed"));
-  int rc = choose_tiles(c);
+  if (sizes.size() > (size_t)kMaxClasses) return bail(fail(TTSH_EUNSUPPORTED, "too many grid sizes"));
+  int rc = choose_bs(c);
   if (rc) return bail(rc);
   *out = c;
   return TTSH_OK;
@@ -412,18 +455,11 @@ int ttsh_set_option(ttsh_ctx* c, int key, int64_t value) {
       if (value < 0 || value > 100000) return fail(TTSH_EINVAL, "graph steps out of range");
       c->graph_steps = (int)value;
       break;
-    case TTSH_OPT_ROW_PAIRS:
-    case TTSH_OPT_COL_TILE: {
-      if (value < 0 || value > 32 || (value & (value - 1))) return fail(TTSH_EINVAL, "tile must be 0 or a power of two <= 32");
-      const int save_rp = c->opt_rp, save_tc = c->opt_tc;
-      (key == TTSH_OPT_ROW_PAIRS ? c->opt_rp : c->opt_tc) = (int)value;
-      int rc = choose_tiles(c);
-      if (rc) {
-        c->opt_rp = save_rp;
-        c->opt_tc = save_tc;
-        choose_tiles(c);
-        return rc;
-      }
+    case TTSH_OPT_BLOCK: {
+      if (value != 0 && !bs_valid(c, (int)value)) return fail(TTSH_EINVAL, "workgroup size must be 0, 64, 128 or 256 with 8 x size >= N");
+      c->opt_bs = (int)value;
+      int rc = choose_bs(c);
+      if (rc) return rc;
       break;
     }
     case TTSH_OPT_GUARD:
@@ -735,38 +771,87 @@ int ttsh_num_classes(ttsh_ctx* c, int* N_out) {
 int ttsh_pass_times(ttsh_ctx* c, int64_t nsteps, double* out) {
   if (!c || !out) return fail(TTSH_EINVAL, "null argument");
   if (nsteps < 1 || nsteps > 1000000) return fail(TTSH_EINVAL, "nsteps must be in 1..1e6");
-  const size_t nc = c->cls.size();
-  std::vector<hipEvent_t> ev(4 * nc, nullptr);
+  hipEvent_t ev[3];
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  std::vector<double> acc(2 * nc, 0.0);
+  const MultiArgs r = multi_args(c, 1, -1), q = multi_args(c, 0, -1);
+  double acc[2] = {0.0, 0.0};
   int rc = TTSH_OK;
   for (int64_t s = 0; s < nsteps && rc == TTSH_OK; ++s) {
-    for (size_t q = 0; q < nc && rc == TTSH_OK; ++q) {
-      SizeClass& k = c->cls[q];
-      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
-      hipEventRecord(ev[4 * q], c->stream);
-      if (size_ops(k.N)->row(a, c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "row pass launch failed");
-      hipEventRecord(ev[4 * q + 1], c->stream);
+    hipEventRecord(ev[0], c->stream);
+    if (launch_row(c, r, c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "row pass launch failed");
+    hipEventRecord(ev[1], c->stream);
+    if (rc == TTSH_OK && launch_col(c, q, 0, c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "column pass launch failed");
+    hipEventRecord(ev[2], c->stream);
+    if (rc == TTSH_OK && hipEventSynchronize(ev[2]) != hipSuccess) rc = fail(TTSH_EHIP, "sync failed");
+    float m0 = 0, m1 = 0;
+    if (rc == TTSH_OK) {
+      hipEventElapsedTime(&m0, ev[0], ev[1]);
+      hipEventElapsedTime(&m1, ev[1], ev[2]);
     }
-    for (size_t q = 0; q < nc && rc == TTSH_OK; ++q) {
-      SizeClass& k = c->cls[q];
-      PassArgs a = pass_args(c, k, 0, (int)k.ids.size());
-      hipEventRecord(ev[4 * q + 2], c->stream);
-      if (size_ops(k.N)->col(a, 0, c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "column pass launch failed");
-      hipEventRecord(ev[4 * q + 3], c->stream);
-    }
-    if (rc == TTSH_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(TTSH_EHIP, "sync failed");
-    for (size_t q = 0; q < nc && rc == TTSH_OK; ++q) {
-      float ms0 = 0, ms1 = 0;
-      hipEventElapsedTime(&ms0, ev[4 * q], ev[4 * q + 1]);
-      hipEventElapsedTime(&ms1, ev[4 * q + 2], ev[4 * q + 3]);
-      acc[2 * q] += ms0;
-      acc[2 * q + 1] += ms1;
-    }
+    acc[0] += m0;
+    acc[1] += m1;
   }
   for (auto& e : ev) hipEventDestroy(e);
   if (rc) return rc;
-  for (size_t i = 0; i < 2 * nc; ++i) out[i] = 1000.0 * acc[i] / (double)nsteps;
+  out[0] = 1000.0 * acc[0] / (double)nsteps;
+  out[1] = 1000.0 * acc[1] / (double)nsteps;
+  return TTSH_OK;
+}
+
+int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* bs_out, double* us_out) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (nsteps < 1 || nsteps > 100000) return fail(TTSH_EINVAL, "nsteps must be in 1..1e5");
+  // save the state and the mixed-domain v, omega of every class
+  std::vector<void*> save;
+  size_t bytes_total = 0;
+  const size_t er = elem_real(c->prec), es = elem_state(c->prec);
+  for (auto& k : c->cls) bytes_total += k.ids.size() * (k.sSt() * es + k.sX() * 2 * er);
+  void* buf = nullptr;
+  if (hipMalloc(&buf, bytes_total) != hipSuccess) return fail(TTSH_ENOMEM, "tuner scratch allocation failed");
+  auto copy_all = [&](bool to_buf) -> hipError_t {
+    char* p = (char*)buf;
+    for (auto& k : c->cls) {
+      const size_t bs_ = k.ids.size() * k.sSt() * es, bx = k.ids.size() * k.sX() * 2 * er;
+      hipError_t e = to_buf ? hipMemcpyAsync(p, k.st, bs_, hipMemcpyDeviceToDevice, c->stream)
+                            : hipMemcpyAsync(k.st, p, bs_, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+      p += bs_;
+      e = to_buf ? hipMemcpyAsync(p, k.X, bx, hipMemcpyDeviceToDevice, c->stream)
+                 : hipMemcpyAsync(k.X, p, bx, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+      p += bx;
+    }
+    return hipSuccess;
+  };
+  int rc = TTSH_OK;
+  if (copy_all(true) != hipSuccess) rc = fail(TTSH_EHIP, "tuner save failed");
+  const int keep_bs = c->bs, keep_opt = c->opt_bs;
+  int best = 0;
+  double best_us = 0.0;
+  for (int bs : {64, 128, 256}) {
+    if (rc != TTSH_OK || !bs_valid(c, bs)) continue;
+    c->bs = bs;
+    double t[2];
+    if (enqueue_steps(c, 2, c->stream) != TTSH_OK) { rc = TTSH_EHIP; break; }  // warm-up
+    if ((rc = ttsh_pass_times(c, nsteps, t)) != TTSH_OK) break;
+    if (!best || t[0] + t[1] < best_us) {
+      best = bs;
+      best_us = t[0] + t[1];
+    }
+  }
+  if (copy_all(false) != hipSuccess && rc == TTSH_OK) rc = fail(TTSH_EHIP, "tuner restore failed");
+  hipStreamSynchronize(c->stream);
+  hipFree(buf);
+  if (rc != TTSH_OK || !best) {
+    c->bs = keep_bs;
+    return rc ? rc : fail(TTSH_EUNSUPPORTED, "no workgroup size to tune");
+  }
+  (void)keep_opt;
+  c->bs = best;
+  c->opt_bs = best;  // keep the tuned size across later option changes
+  drop_graph(c);
+  if (bs_out) *bs_out = best;
+  if (us_out) *us_out = best_us;
   return TTSH_OK;
 }
 

@@ -19,7 +19,7 @@ TTSH_OK, TTSH_EINVAL, TTSH_EUNSUPPORTED, TTSH_EHIP, TTSH_ENONFINITE, TTSH_ENOMEM
 TTSH_HOST, TTSH_DEVICE = 0, 1
 TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX = 0, 1, 2
 TTSH_FP32, TTSH_FP64, TTSH_FP32_STATE64 = 32, 64, 96
-TTSH_OPT_GRAPH_STEPS, TTSH_OPT_ROW_PAIRS, TTSH_OPT_COL_TILE, TTSH_OPT_GUARD = 1, 2, 3, 4
+TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD = 1, 2, 4
 SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX}
 
 
@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_set_option": [vp, i32, i64],
             "ttsh_fft2": [dp, dp, i32, i32, i32, i32],
             "ttsh_pass_times": [vp, i64, dp],
+            "ttsh_tune": [vp, i64, dp, dp],
             "ttsh_num_classes": [vp, dp],
         }
         for name, args in sig.items():
@@ -215,11 +216,20 @@ def ttsh_num_classes(ctx):
 
 
 def ttsh_pass_times(ctx, nsteps):
-    """{N: (row_us, col_us)} mean kernel durations from HIP events."""
-    sizes = ttsh_num_classes(ctx)
-    out = (ctypes.c_double * (2 * len(sizes)))()
+    """(row_us, col_us): mean durations of the two launches of a step, from
+    HIP events."""
+    out = (ctypes.c_double * 2)()
     _check(lib().ttsh_pass_times(ctx, int(nsteps), ctypes.cast(out, ctypes.c_void_p)))
-    return {N: (out[2 * i], out[2 * i + 1]) for i, N in enumerate(sizes)}
+    return out[0], out[1]
+
+
+def ttsh_tune(ctx, nsteps):
+    """Pick the fastest workgroup size; returns (size, us_per_step)."""
+    bs = ctypes.c_int()
+    us = ctypes.c_double()
+    _check(lib().ttsh_tune(ctx, int(nsteps), ctypes.cast(ctypes.byref(bs), ctypes.c_void_p),
+                           ctypes.cast(ctypes.byref(us), ctypes.c_void_p)))
+    return bs.value, us.value
 
 
 def ttsh_last_error() -> str:
@@ -290,3 +300,9 @@ class Solver:
 
     def reseed(self, dst, src, noise=None):
         ttsh_reseed(self.ctx, dst, src, noise)
+
+    def tune(self, nsteps=20):
+        return ttsh_tune(self.ctx, nsteps)
+
+    def pass_times(self, nsteps=50):
+        return ttsh_pass_times(self.ctx, nsteps)

@@ -247,3 +247,31 @@ def test_norms(gpu):
     assert abs(got[0] - ref[0]) < 1e-12 * ref[0]
     assert abs(got[1] - ref[1]) < 1e-15 and abs(got[2] - ref[2]) < 1e-15
     assert got[3] < 1e-12
+
+
+def test_block_sizes_agree_and_tuner_restores_state(gpu):
+    """The workgroup size only changes how rows and columns are grouped (and
+    the order of the k = 0 row-sum reduction); the tuner leaves the state as
+    it found it."""
+    say("block sizes / tuner")
+    p = O.workload_params()
+    Ns, Ls = [256, 128, 512], [100.0, 64.0, 256.0]
+    out = {}
+    for bs in (64, 128, 256):
+        s = gpu.Solver(Ns, Ls, p, 32)
+        s.option(gpu.TTSH_OPT_BLOCK, bs)
+        for i, (N, L) in enumerate(zip(Ns, Ls)):
+            s.mask_tanh(i, [(0.0, 0.0)], [L / 4], 0.5)
+            s.set_field(i, W.uniform_field(40 + i, N, 0.2, 32))
+        if bs == 128:
+            before = [s.state(i) for i in range(3)]
+            chosen, us = s.tune(3)
+            assert chosen in (64, 128, 256) and us > 0
+            for i in range(3):
+                assert np.array_equal(s.state(i), before[i])
+        s.step(20)
+        s.sync()
+        out[bs] = [s.state(i) for i in range(3)]
+    for bs in (64, 128):
+        for a, b in zip(out[bs], out[256]):
+            assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
