@@ -144,7 +144,19 @@ def main():
     ap.add_argument("--precision", type=int, default=32, choices=[32, 96],
                     help="32: FP32 state; 96: FP64 state (FP32 transforms in both)")
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = autotuned)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 10 times (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration} MiB 10 times")
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -5,14 +5,19 @@
 //   st  [2][M+1][2M+2]   unitary spectrum v_hat, column m_x = 0..M, position
 //                        p = m_y (m_y >= 0) or m_y + 2M + 1 (m_y < 0); FP32 or
 //                        FP64.  Modes with m_x^2 + m_y^2 > M^2 are kept at 0.
-//   X   [3][M+1][N]      v_x, v_y, omega transformed back along y only
-//                        ("mixed domain", y contiguous), scaled so that the
-//                        row transform alone yields the real field.
+//   X   [3][MP4/4][N][4] v_x, v_y, omega transformed back along y only
+//                        ("mixed domain"), scaled so that the row transform
+//                        alone yields the real field; columns m_x = 0..M are
+//                        interleaved by groups of four (MP4 = M+1 rounded up to
+//                        a multiple of 4): entry (m_x, y) sits at
+//                        (m_x/4) 4N + 4y + m_x%4.  The column pass reads and
+//                        writes whole 4-column slabs; the row pass reads runs
+//                        of (rows per workgroup) x 32 bytes.
 // Per step:
 //   row pass    X -> inverse row C2R (two real rows per complex transform) ->
 //               real-space forcing  N = -(beta|v|^2 + gamma_v K) v - lambda0
 //               omega v_perp  (and G = -gamma_w K omega) -> forward row R2C,
-//               keeping m_x <= M  -> Y [2 or 3][M+1][N];  also the row sums of
+//               keeping m_x <= M  -> Y [2 or 3][MP4/4][N][4];  also the row sums of
 //               -(beta|v|^2 + gamma_v K) v, which feed the k = 0 rule.
 //   column pass Y -> forward column FFT -> k-space update (FP64) of v_hat ->
 //               new st -> omega_hat -> inverse column FFT of v_x, v_y, omega ->
@@ -76,7 +81,16 @@ struct Geo {
   static constexpr int MP = M + 1;       // stored columns m_x = 0..M
   static constexpr int SP = 2 * M + 2;   // stored positions per state column
   static constexpr int NP = Padded<N>::value;
+  static constexpr int MP4 = (MP + 3) / 4 * 4;  // mixed-domain columns, padded
+  static constexpr int LS = 3 * NP + 8;  // LDS stride between transform groups
+                                         // (16 banks apart for FP32)
 };
+
+// index of mixed-domain entry (field f, column m, row y)
+template <int N>
+__device__ __forceinline__ size_t mix_idx(int f, int m, int y) {
+  return (size_t)f * Geo<N>::MP4 * N + (size_t)(m >> 2) * (4 * N) + 4 * y + (m & 3);
+}
 
 // z = p + i q
 template <class T>
@@ -90,7 +104,7 @@ __device__ __forceinline__ C2<T> pack_pq(C2<T> p, C2<T> q) {
 // ---------------------------------------------------------------------------
 template <int N, int RP, class T>
 struct RowSmem {
-  static constexpr size_t lds = (size_t)RP * 3 * Geo<N>::NP * sizeof(C2<T>);
+  static constexpr size_t lds = (size_t)RP * Geo<N>::LS * sizeof(C2<T>);
   static constexpr size_t bytes = lds + (size_t)(RP * Geo<N>::TT / 64) * RP * 4 * sizeof(T);
 };
 
@@ -112,10 +126,11 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
   const int lane = tid % RP;
   const int t = tid / RP;
   const int y0 = (tile * RP + lane) * 2;
-  const CPair<T>* Xp = reinterpret_cast<const CPair<T>*>(X + inst * 3 * MP * N);
-  CPair<T>* Yp = reinterpret_cast<CPair<T>*>(Y + inst * NFY * MP * N);
+  constexpr int MP4 = G::MP4;
+  const C2<T>* Xp = X + inst * 3 * MP4 * N;
+  C2<T>* Yp = Y + inst * NFY * MP4 * N;
   const T* Kp = K + inst * N * N;
-  C2<T>* L = lds + lane * 3 * NP;
+  C2<T>* L = lds + lane * G::LS;
 
   // mask rows first, so their latency hides behind the gather and transforms
   T kr[2][E];
@@ -137,9 +152,12 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     CPair<T> a, b, w;
     a.a = a.b = b.a = b.b = w.a = w.b = mk<T>(0, 0);
     if (lo || hi) {
-      a = Xp[(0 * MP + m) * (N / 2) + y0 / 2];
-      b = Xp[(1 * MP + m) * (N / 2) + y0 / 2];
-      w = Xp[(2 * MP + m) * (N / 2) + y0 / 2];
+      a.a = Xp[mix_idx<N>(0, m, y0)];
+      a.b = Xp[mix_idx<N>(0, m, y0 + 1)];
+      b.a = Xp[mix_idx<N>(1, m, y0)];
+      b.b = Xp[mix_idx<N>(1, m, y0 + 1)];
+      w.a = Xp[mix_idx<N>(2, m, y0)];
+      w.b = Xp[mix_idx<N>(2, m, y0 + 1)];
     }
     if (idx == 0) {  // real transform: the m_x = 0 term is real
       a.a.y = a.b.y = b.a.y = b.b.y = w.a.y = w.b.y = 0;
@@ -206,15 +224,13 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
         out[f][0] = mk(h * (Wm.x + Wn.x), h * (Wm.y - Wn.y));
         out[f][1] = mk(h * (Wm.y + Wn.y), -h * (Wm.x - Wn.x));
       }
-      CPair<T> px, py;
-      px.a = out[0][0]; px.b = out[1][0];  // N_x at rows y0, y0+1
-      py.a = out[0][1]; py.b = out[1][1];  // N_y
-      Yp[(0 * MP + m) * (N / 2) + y0 / 2] = px;
-      Yp[(1 * MP + m) * (N / 2) + y0 / 2] = py;
+      Yp[mix_idx<N>(0, m, y0)] = out[0][0];  // N_x, row y0
+      Yp[mix_idx<N>(0, m, y0 + 1)] = out[1][0];
+      Yp[mix_idx<N>(1, m, y0)] = out[0][1];  // N_y
+      Yp[mix_idx<N>(1, m, y0 + 1)] = out[1][1];
       if constexpr (GW) {
-        CPair<T> pg;
-        pg.a = out[2][0]; pg.b = out[2][1];
-        Yp[(2 * MP + m) * (N / 2) + y0 / 2] = pg;
+        Yp[mix_idx<N>(2, m, y0)] = out[2][0];
+        Yp[mix_idx<N>(2, m, y0 + 1)] = out[2][1];
       }
     }
   }
@@ -238,7 +254,7 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
 // ---------------------------------------------------------------------------
 template <int N, int TC, class T, bool GW>
 struct ColSmem {
-  static constexpr size_t fft = (size_t)TC * 3 * Geo<N>::NP * sizeof(C2<T>);
+  static constexpr size_t fft = (size_t)TC * Geo<N>::LS * sizeof(C2<T>);
   static constexpr size_t herm = (size_t)2 * N * sizeof(C2<double>);
   static constexpr size_t bytes = fft > herm ? fft : herm;
 };
@@ -256,13 +272,17 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
   constexpr int NW = NT / 64;
   static_assert(NT % 64 == 0, "column pass needs whole wavefronts");
 
+  // up to four columns share a wavefront (consecutive threads walk the
+  // columns of one 4-column slab, then the rows), so that each load or store
+  // instruction covers a contiguous run of the interleaved layout
+  constexpr int CI = TC < 4 ? TC : 4;
   const int tid = threadIdx.x;
-  const int t = tid % TT;
-  const int col = tid / TT;
+  const int t = (tid / CI) % TT;
+  const int col = (tid / (CI * TT)) * CI + tid % CI;
   const int mx = tile * TC + col;
   const bool valid = mx <= M;
   const double dk = dkv[inst];
-  C2<T>* L = reinterpret_cast<C2<T>*>(smem) + col * 3 * NP;
+  C2<T>* L = reinterpret_cast<C2<T>*>(smem) + col * G::LS;
   C2<S>* stp = st + inst * 2 * MP * SP;
 
   C2<T> f[NFY][E];
@@ -289,12 +309,12 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       }
       __syncthreads();
     }
-    const C2<T>* Yp = Y + inst * NFY * MP * N;
+    const C2<T>* Yp = Y + inst * NFY * G::MP4 * N;
 #pragma unroll
     for (int q = 0; q < NFY; ++q)
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        f[q][e] = valid ? Yp[((size_t)q * MP + mx) * N + t + e * TT] : mk<T>(0, 0);
+        f[q][e] = valid ? Yp[mix_idx<N>(q, mx, t + e * TT)] : mk<T>(0, 0);
     fft<N, -1, NFY>(f, L, t, tw);
   }
 
@@ -403,11 +423,11 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
   }
   fft<N, +1, 3>(z, L, t, tw);
   if (valid) {
-    C2<T>* Xp = X + inst * 3 * MP * N;
+    C2<T>* Xp = X + inst * 3 * G::MP4 * N;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
-      for (int e = 0; e < E; ++e) Xp[((size_t)q * MP + mx) * N + t + e * TT] = z[q][e];
+      for (int e = 0; e < E; ++e) Xp[mix_idx<N>(q, mx, t + e * TT)] = z[q][e];
   }
 }
 

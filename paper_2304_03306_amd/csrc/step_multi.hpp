@@ -67,6 +67,15 @@ constexpr size_t col_smem() {
               col_smem_n<T, BS, 1024>());
 }
 
+// Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
+// XCD b % 8).  Map them so that each XCD receives one contiguous range of
+// tiles: neighbouring row tiles share cache lines of the interleaved
+// mixed-domain arrays, and this keeps those lines in one XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int x = b & 7, j = b >> 3, q = G >> 3, r = G & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
+}
+
 __device__ __forceinline__ int class_of(const MultiArgs& a, int b) {
   int ci = 0;
 #pragma unroll
@@ -86,7 +95,7 @@ __device__ __forceinline__ void row_go(const ClassArgs& d, const RowCoef<T>& c, 
 template <class T, bool GW, int BS>
 __global__ void __launch_bounds__(BS) row_multi(MultiArgs a) {
   __shared__ __align__(16) unsigned char smem[row_smem<T, BS>()];
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int ci = class_of(a, b);
   const ClassArgs& d = a.c[ci];
   const int local = b - a.start[ci];
@@ -118,7 +127,7 @@ __device__ __forceinline__ void col_go(const ClassArgs& d, const LinCoef& lc, in
 template <class T, class S, bool GW, int MODE, int BS>
 __global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
   __shared__ __align__(16) unsigned char smem[col_smem<T, BS>()];
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int ci = class_of(a, b);
   const ClassArgs& d = a.c[ci];
   const int local = b - a.start[ci];

@@ -88,8 +88,10 @@ struct SizeClass {
   double* dk = nullptr;
   void* tw = nullptr;    // run precision
   // per-instance strides in elements
-  size_t sX() const { return (size_t)3 * (N / 4 + 1) * N; }
-  size_t sY(int gw) const { return (size_t)(gw ? 3 : 2) * (N / 4 + 1) * N; }
+  // mixed-domain arrays hold M+1 columns padded to a multiple of 4
+  size_t mp4() const { return (size_t)((N / 4 + 1 + 3) / 4 * 4); }
+  size_t sX() const { return (size_t)3 * mp4() * N; }
+  size_t sY(int gw) const { return (size_t)(gw ? 3 : 2) * mp4() * N; }
   size_t sSt() const { return (size_t)2 * (N / 4 + 1) * (N / 2 + 2); }
   size_t sK() const { return (size_t)N * N; }
 };
