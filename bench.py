@@ -176,10 +176,10 @@ def main():
     s.option(T.TTSH_OPT_GUARD, 0)
     if args.block:
         s.option(T.TTSH_OPT_BLOCK, args.block)
-        block = args.block
+        block = (args.block, args.block)
     else:
         block, tuned_us = s.tune(20)
-        log(f"[bench] autotuned workgroup size {block} ({tuned_us:.1f} us/step)")
+        log(f"[bench] autotuned workgroup sizes (row, column) {block} ({tuned_us:.1f} us/step)")
 
     parity = {}
     if not args.no_parity and args.workload == "sweep":

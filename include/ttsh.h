@@ -171,9 +171,11 @@ int ttsh_sync(ttsh_ctx* ctx);
 int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
 
 /* Autotuner: time nsteps steps with every usable workgroup size (HIP events,
- * after two warm-up steps), keep the fastest, and restore the state the
- * context had before the call.  Writes the chosen size and its microseconds
- * per step (either pointer may be NULL).  Synchronous.                      */
+ * after two warm-up steps), keep the fastest size for each of the two passes
+ * independently, and restore the state the context had before the call.
+ * Writes 1000 x (row-pass size) + (column-pass size) and the microseconds per
+ * step of that choice (either pointer may be NULL).  A later
+ * TTSH_OPT_BLOCK sets both passes again.  Synchronous.                     */
 int ttsh_tune(ttsh_ctx* ctx, int64_t nsteps, int* bs_out, double* us_out);
 
 /* Number of distinct grid sizes (size classes) in the context; their sizes in

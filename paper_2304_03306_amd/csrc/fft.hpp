@@ -26,12 +26,16 @@ namespace ttsh {
 
 constexpr int kFftE = 8;  // elements per thread
 
-// LDS index with one pad slot every 8 entries (breaks the stride-8 scatter of
-// the first stage across banks).
-__host__ __device__ constexpr int lds_pad(int j) { return j + (j >> 3); }
+// LDS index with one pad slot every 2^TTSH_PAD_SHIFT entries (breaks the
+// strided scatter of the first stage across banks).  One slot per 16 was the
+// fastest of 1 per 4..64 in measurements of both step passes on gfx950.
+#ifndef TTSH_PAD_SHIFT
+#define TTSH_PAD_SHIFT 4
+#endif
+__host__ __device__ constexpr int lds_pad(int j) { return j + (j >> TTSH_PAD_SHIFT); }
 template <int N>
 struct Padded {
-  static constexpr int value = N + N / 8;
+  static constexpr int value = N + (N >> TTSH_PAD_SHIFT);
 };
 
 // ---- radix-R DFTs, DIR = -1 forward (e^{-2 pi i nk/R}), +1 inverse ---------

@@ -16,8 +16,9 @@
 // Per step:
 //   row pass    X -> inverse row C2R (two real rows per complex transform) ->
 //               real-space forcing  N = -(beta|v|^2 + gamma_v K) v - lambda0
-//               omega v_perp  (and G = -gamma_w K omega) -> forward row R2C,
-//               keeping m_x <= M  -> Y [2 or 3][MP4/4][N][4];  also the row sums of
+//               omega v_perp  (and G = -gamma_w K omega) -> forward row
+//               transform of N_x + i N_y, values at m_x and N - m_x for
+//               m_x <= M -> Y [2 or 3][MP4/4][N][4];  also the row sums of
 //               -(beta|v|^2 + gamma_v K) v, which feed the k = 0 rule.
 //   column pass Y -> forward column FFT -> k-space update (FP64) of v_hat ->
 //               new st -> omega_hat -> inverse column FFT of v_x, v_y, omega ->
@@ -38,6 +39,10 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+
+#ifndef TTSH_LDS_OFF
+#define TTSH_LDS_OFF 8
+#endif
 
 namespace ttsh {
 
@@ -82,8 +87,10 @@ struct Geo {
   static constexpr int SP = 2 * M + 2;   // stored positions per state column
   static constexpr int NP = Padded<N>::value;
   static constexpr int MP4 = (MP + 3) / 4 * 4;  // mixed-domain columns, padded
-  static constexpr int LS = 3 * NP + 8;  // LDS stride between transform groups
-                                         // (16 banks apart for FP32)
+  // LDS stride between transform groups that share a wavefront: TTSH_LDS_OFF
+  // complex entries off a multiple of 32 (chosen by measuring LDS bank
+  // conflicts on gfx950).
+  static constexpr int LS = (3 * NP + 31) / 32 * 32 + TTSH_LDS_OFF;
 };
 
 // index of mixed-domain entry (field f, column m, row y)
@@ -125,6 +132,9 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
   const int tid = threadIdx.x;
   const int lane = tid % RP;
   const int t = tid / RP;
+  // lets the compiler drop the zero band of the pruned inverse transforms and
+  // the unused outputs of the pruned forward ones
+  __builtin_assume(t >= 0 && t < TT);
   const int y0 = (tile * RP + lane) * 2;
   constexpr int MP4 = G::MP4;
   const C2<T>* Xp = X + inst * 3 * MP4 * N;
@@ -193,12 +203,23 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
   }
   fft<N, -1, NFY>(wv, L, t, tw);
 
-  // split the packed transforms: F_p(m) = (W(m) + W(N-m)^*)/2,
-  // F_q(m) = -i (W(m) - W(N-m)^*)/2; keep m = 0..M
+  // Outputs.  The forcing rows are stored unsplit, straight from registers:
+  // Y[0][m][y] = W_y(m) and Y[1][m][y] = W_y(N - m) (m = 0..M) with
+  // W_y = FFT(N_x + i N_y) of row y; the column pass, whose thread loads both,
+  // separates N_x_hat = (W(m) + W(N-m)^*)/2, N_y_hat = -i (W(m) - W(N-m)^*)/2.
 #pragma unroll
-  for (int f = 0; f < NFY; ++f)
-#pragma unroll
-    for (int e = 0; e < E; ++e) L[f * NP + lds_pad(t + e * TT)] = wv[f][e];
+  for (int e = 0; e < E; ++e) {
+    const int idx = t + e * TT;
+    if (idx <= M) {
+      Yp[mix_idx<N>(0, idx, y0)] = wv[0][e];
+      Yp[mix_idx<N>(0, idx, y0 + 1)] = wv[1][e];
+    }
+    if (idx == 0 || idx >= N - M) {
+      const int m = (N - idx) & (N - 1);
+      Yp[mix_idx<N>(1, m, y0)] = wv[0][e];
+      Yp[mix_idx<N>(1, m, y0 + 1)] = wv[1][e];
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -209,28 +230,26 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     red[tid >> 6][lane][2] = s1[1][0];
     red[tid >> 6][lane][3] = s1[1][1];
   }
+  if constexpr (GW) {
+    // G of the two rows shares one transform: split it through LDS,
+    // G_y0(m) = (W(m) + W(N-m)^*)/2, G_y1(m) = -i (W(m) - W(N-m)^*)/2
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = t + e * TT;
+      if (idx <= M || idx >= N - M) L[lds_pad(idx)] = wv[2][e];
+    }
+  }
   __syncthreads();
-  const T h = (T)0.5;
+  if constexpr (GW) {
+    const T h = (T)0.5;
 #pragma unroll
-  for (int e = 0; e <= M / TT; ++e) {
-    const int m = t + e * TT;
-    if (m <= M) {
-      const int mm = (N - m) & (N - 1);
-      C2<T> out[NFY][2];
-#pragma unroll
-      for (int f = 0; f < NFY; ++f) {
-        const C2<T> Wm = L[f * NP + lds_pad(m)];
-        const C2<T> Wn = L[f * NP + lds_pad(mm)];
-        out[f][0] = mk(h * (Wm.x + Wn.x), h * (Wm.y - Wn.y));
-        out[f][1] = mk(h * (Wm.y + Wn.y), -h * (Wm.x - Wn.x));
-      }
-      Yp[mix_idx<N>(0, m, y0)] = out[0][0];  // N_x, row y0
-      Yp[mix_idx<N>(0, m, y0 + 1)] = out[1][0];
-      Yp[mix_idx<N>(1, m, y0)] = out[0][1];  // N_y
-      Yp[mix_idx<N>(1, m, y0 + 1)] = out[1][1];
-      if constexpr (GW) {
-        Yp[mix_idx<N>(2, m, y0)] = out[2][0];
-        Yp[mix_idx<N>(2, m, y0 + 1)] = out[2][1];
+    for (int e = 0; e <= M / TT; ++e) {
+      const int m = t + e * TT;
+      if (m <= M) {
+        const C2<T> Wm = L[lds_pad(m)];
+        const C2<T> Wn = L[lds_pad((N - m) & (N - 1))];
+        Yp[mix_idx<N>(2, m, y0)] = mk(h * (Wm.x + Wn.x), h * (Wm.y - Wn.y));
+        Yp[mix_idx<N>(2, m, y0 + 1)] = mk(h * (Wm.y + Wn.y), -h * (Wm.x - Wn.x));
       }
     }
   }
@@ -279,6 +298,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
   const int tid = threadIdx.x;
   const int t = (tid / CI) % TT;
   const int col = (tid / (CI * TT)) * CI + tid % CI;
+  __builtin_assume(t >= 0 && t < TT);
   const int mx = tile * TC + col;
   const bool valid = mx <= M;
   const double dk = dkv[inst];
@@ -310,11 +330,18 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       __syncthreads();
     }
     const C2<T>* Yp = Y + inst * NFY * G::MP4 * N;
+    const T h = (T)0.5;
 #pragma unroll
-    for (int q = 0; q < NFY; ++q)
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-        f[q][e] = valid ? Yp[mix_idx<N>(q, mx, t + e * TT)] : mk<T>(0, 0);
+    for (int e = 0; e < E; ++e) {
+      C2<T> w0 = mk<T>(0, 0), w1 = mk<T>(0, 0);
+      if (valid) {
+        w0 = Yp[mix_idx<N>(0, mx, t + e * TT)];  // W(m_x) of row y
+        w1 = Yp[mix_idx<N>(1, mx, t + e * TT)];  // W(N - m_x) of row y
+      }
+      f[0][e] = mk(h * (w0.x + w1.x), h * (w0.y - w1.y));   // row transform of N_x
+      f[1][e] = mk(h * (w0.y + w1.y), -h * (w0.x - w1.x));  // row transform of N_y
+      if constexpr (GW) f[2][e] = valid ? Yp[mix_idx<N>(2, mx, t + e * TT)] : mk<T>(0, 0);
+    }
     fft<N, -1, NFY>(f, L, t, tw);
   }
 
@@ -335,7 +362,17 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
         const double dt_over_N = lc.dt_over_N;
         double A, B;
         linear_ab(lc, dk, m2, A, B);
-        const double inv_m2 = m2 > 0 ? 1.0 / (double)m2 : 0.0;
+        // 1/m^2: FP32 reciprocal refined by two Newton steps in FP64
+        // (m^2 <= 2^16, so the result is the correctly rounded FP64 value to
+        // within an ulp)
+        double inv_m2 = 0.0;
+        if (m2 > 0) {
+          const double dm = (double)m2;
+          double r = (double)__frcp_rn((float)m2);
+          r = r * (2.0 - dm * r);
+          r = r * (2.0 - dm * r);
+          inv_m2 = r;
+        }
         if (m2 == 0) {
           nx[e] = cscale(ux, A) + mk(B * dt_over_N * s1x, 0.0);
           ny[e] = cscale(uy, A) + mk(B * dt_over_N * s1y, 0.0);

@@ -115,7 +115,8 @@ struct ttsh_ctx {
   void* scr1 = nullptr;
   double* dnorm = nullptr;               // [n_inst][5]
   int graph_steps = 50;
-  int bs = 0;       // workgroup size of the step kernels in use
+  int bs = 0;       // workgroup size of the column pass in use
+  int bs_row = 0;   // workgroup size of the row pass in use
   int opt_bs = 0;   // requested by TTSH_OPT_BLOCK (0 = chosen)
   int guard = 1;
   hipGraph_t graph = nullptr;
@@ -167,7 +168,7 @@ bool bs_valid(const ttsh_ctx* c, int bs) {
 int choose_bs(ttsh_ctx* c) {
   if (c->opt_bs) {
     if (!bs_valid(c, c->opt_bs)) return fail(TTSH_EUNSUPPORTED, "workgroup size not usable for this context");
-    c->bs = c->opt_bs;
+    c->bs = c->bs_row = c->opt_bs;
     return TTSH_OK;
   }
   long pts = 0;
@@ -178,14 +179,14 @@ int choose_bs(ttsh_ctx* c) {
     if (!best || pts / (16L * bs) >= 2048) best = bs;
   }
   if (!best) return fail(TTSH_EUNSUPPORTED, "no workgroup size fits N");
-  c->bs = best;
+  c->bs = c->bs_row = best;
   return TTSH_OK;
 }
 
 ClassArgs class_args(ttsh_ctx* c, SizeClass& k, int first, int count, int row) {
   ClassArgs a{};
   const size_t er = elem_real(c->prec), es = elem_state(c->prec);
-  const int R = c->bs / (k.N / 8);
+  const int R = (row ? c->bs_row : c->bs) / (k.N / 8);
   a.N = k.N;
   a.n = count;
   a.tiles = row ? k.N / (2 * R) : (k.N / 4 + 1 + R - 1) / R;
@@ -226,7 +227,7 @@ MultiArgs multi_args(ttsh_ctx* c, int row, int inst) {
 }
 
 hipError_t launch_row(ttsh_ctx* c, const MultiArgs& m, hipStream_t s) {
-  return multi_ops(c->prec == 64 ? 64 : 32, c->bs)->row(m, c->gw, s);
+  return multi_ops(c->prec == 64 ? 64 : 32, c->bs_row)->row(m, c->gw, s);
 }
 hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) {
   return multi_ops(c->prec, c->bs)->col(m, c->gw, mode, s);
@@ -827,32 +828,35 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* bs_out, double* us_out) {
   };
   int rc = TTSH_OK;
   if (copy_all(true) != hipSuccess) rc = fail(TTSH_EHIP, "tuner save failed");
-  const int keep_bs = c->bs, keep_opt = c->opt_bs;
-  int best = 0;
-  double best_us = 0.0;
+  const int keep_bs = c->bs, keep_row = c->bs_row;
+  int best_row = 0, best_col = 0;
+  double row_us = 0.0, col_us = 0.0;
   for (int bs : {64, 128, 256}) {
     if (rc != TTSH_OK || !bs_valid(c, bs)) continue;
-    c->bs = bs;
+    c->bs = c->bs_row = bs;
     double t[2];
     if (enqueue_steps(c, 2, c->stream) != TTSH_OK) { rc = TTSH_EHIP; break; }  // warm-up
     if ((rc = ttsh_pass_times(c, nsteps, t)) != TTSH_OK) break;
-    if (!best || t[0] + t[1] < best_us) {
-      best = bs;
-      best_us = t[0] + t[1];
-    }
+    if (!best_row || t[0] < row_us) { best_row = bs; row_us = t[0]; }
+    if (!best_col || t[1] < col_us) { best_col = bs; col_us = t[1]; }
   }
   if (copy_all(false) != hipSuccess && rc == TTSH_OK) rc = fail(TTSH_EHIP, "tuner restore failed");
   hipStreamSynchronize(c->stream);
   hipFree(buf);
-  if (rc != TTSH_OK || !best) {
+  if (rc != TTSH_OK || !best_row) {
     c->bs = keep_bs;
+    c->bs_row = keep_row;
     return rc ? rc : fail(TTSH_EUNSUPPORTED, "no workgroup size to tune");
   }
-  (void)keep_opt;
-  c->bs = best;
-  c->opt_bs = best;  // keep the tuned size across later option changes
+  // the two passes are tuned independently (the data layout does not depend
+  // on the workgroup size)
+  c->bs_row = best_row;
+  c->bs = best_col;
+  c->opt_bs = 0;
   drop_graph(c);
-  if (bs_out) *bs_out = best;
+  const int best = best_col;
+  const double best_us = row_us + col_us;
+  if (bs_out) *bs_out = best_row * 1000 + best;
   if (us_out) *us_out = best_us;
   return TTSH_OK;
 }

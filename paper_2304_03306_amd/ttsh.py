@@ -224,12 +224,12 @@ def ttsh_pass_times(ctx, nsteps):
 
 
 def ttsh_tune(ctx, nsteps):
-    """Pick the fastest workgroup size; returns (size, us_per_step)."""
+    """Pick the fastest workgroup sizes; returns ((row_size, col_size), us_per_step)."""
     bs = ctypes.c_int()
     us = ctypes.c_double()
     _check(lib().ttsh_tune(ctx, int(nsteps), ctypes.cast(ctypes.byref(bs), ctypes.c_void_p),
                            ctypes.cast(ctypes.byref(us), ctypes.c_void_p)))
-    return bs.value, us.value
+    return (bs.value // 1000, bs.value % 1000), us.value
 
 
 def ttsh_last_error() -> str:

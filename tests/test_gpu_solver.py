@@ -265,8 +265,8 @@ def test_block_sizes_agree_and_tuner_restores_state(gpu):
             s.set_field(i, W.uniform_field(40 + i, N, 0.2, 32))
         if bs == 128:
             before = [s.state(i) for i in range(3)]
-            chosen, us = s.tune(3)
-            assert chosen in (64, 128, 256) and us > 0
+            (brow, bcol), us = s.tune(3)
+            assert brow in (64, 128, 256) and bcol in (64, 128, 256) and us > 0
             for i in range(3):
                 assert np.array_equal(s.state(i), before[i])
         s.step(20)
