@@ -1,0 +1,108 @@
+/*
+ * fno.h -- C interface of the Fourier-neural-operator surrogate in
+ * libttsh.so: forward, hand-written backward and Adam on MI355X (gfx950), with
+ * BF16 weights and activations and FP32 accumulation on the matrix cores.
+ *
+ * Architecture (Fourier neural operator, Li et al., ICLR 2021): per-point
+ * lift cin -> C; `layers` Fourier layers h <- act(S(h) + h W + b), where S
+ * multiplies the retained modes k_x = 0..m-1, k_y = -m..m-1 of rfft2(h) by a
+ * complex C x C matrix per mode and transforms back (irfft2), act = exact
+ * GELU except after the last layer; projection C -> hidden -> GELU -> cout.
+ * The surrogate advances a coarse velocity field (input: v_x, v_y, K) by a
+ * fixed number of solver steps; training pairs come from the solver.
+ *
+ * Layouts: fields are channels-last float32 [B][H][W][c] on the device.
+ * Parameters are exchanged as one float32 vector in this order:
+ *   P_w [cin][C], P_b [C],
+ *   for each layer: R real part [2m][m][C][C], R imaginary part [2m][m][C][C]
+ *     (row q of the 2m retained k_y rows is k_y = q for q < m, q - 2m else;
+ *     R[q][k_x][i][o] maps input channel i to output channel o),
+ *     W [C][C], b [C],
+ *   Q1_w [C][hidden], Q1_b [hidden], Q2_w [hidden][cout], Q2_b [cout].
+ * Transforms: rfft2 unnormalised, irfft2 with 1/(HW).
+ * Loss: mean over samples of ||y - t||_2 / ||t||_2.
+ *
+ * Errors: 0 or a negative TTSH_* code (ttsh.h); message via ttsh_last_error().
+ * The library owns its device buffers; caller buffers are never retained.
+ */
+#ifndef FNO_H
+#define FNO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fno_ctx fno_ctx;
+
+/* Create a network and its training state for batches of up to max_batch
+ * samples of H x W (H, W multiples of 16, 2m <= H, m <= W/2).  Parameters are
+ * drawn from a seeded generator (set them with fno_set_params to match an
+ * outside model).  stream: hipStream_t (NULL = default stream).            */
+int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cout, int hidden,
+               int H, int W, int max_batch, uint64_t seed, void* stream);
+void fno_destroy(fno_ctx* ctx);
+
+/* Number of float32 parameters (the length of the vectors below). */
+int64_t fno_num_params(fno_ctx* ctx);
+
+/* Host float32 vectors in the order above.  set also resets nothing else. */
+int fno_set_params(fno_ctx* ctx, const float* params);
+int fno_get_params(fno_ctx* ctx, float* params);
+int fno_get_grads(fno_ctx* ctx, float* grads);
+
+/* y [B][H][W][cout] = network(x [B][H][W][cin]); device float32 buffers,
+ * 1 <= batch <= max_batch.  With train != 0 the activations needed by
+ * fno_backward are kept.  Asynchronous on the context's stream.            */
+int fno_forward(fno_ctx* ctx, const float* x, float* y, int batch, int train);
+
+/* Relative-L2 loss of the last training forward's output y against target t
+ * (device float32, same shape); writes the loss (synchronous) and keeps
+ * dl/dy for fno_backward.                                                  */
+int fno_loss(fno_ctx* ctx, const float* y, const float* t, int batch, double* loss);
+
+/* Gradients of the loss with respect to every parameter (overwritten). */
+int fno_backward(fno_ctx* ctx, int batch);
+
+/* One Adam step (Kingma & Ba) on the float32 master parameters. */
+int fno_adam_step(fno_ctx* ctx, float lr, float beta1, float beta2, float eps);
+
+/* fno_forward with two options.  Output element (p, o) (p = point index over
+ * the batch, o < cout) is written to y[p * y_pix_stride + o]; with
+ * residual != 0 it is x[p * cin + o] + network(x)[p][o] (requires
+ * cout <= cin: the network predicts the change of the first cout input
+ * channels).  y may alias x (e.g. the velocity channels of the next step's
+ * input): x is converted before any output is written, and each output
+ * element reads only its own residual input.  fno_loss and fno_backward
+ * treat the residual as part of the output (it has no parameters).        */
+int fno_forward_ex(fno_ctx* ctx, const float* x, float* y, int64_t y_pix_stride, int residual, int batch,
+                   int train);
+
+/* Gather training samples: for s < n, pixel p < npix, channel c < nch:
+ * dst[(s*npix + p)*dst_ch + c] = src[(idx[s]*npix + p)*src_ch + c]
+ * (device float32 buffers, idx host int64 indices, all within src's
+ * extent, which the caller guarantees).  Asynchronous; n <= max_batch.    */
+int fno_gather(fno_ctx* ctx, float* dst, int64_t dst_ch, const float* src, int64_t src_ch, int nch,
+               int64_t npix, const int64_t* idx, int n);
+
+/* Relative L2 error per sample between device float32 fields laid out with
+ * pixel strides: sample s, pixel p, channel c at y[(s*npix + p)*ys + c] and
+ * t[(s*npix + p)*ts + c], c < nch;  out[s] = ||y_s - t_s|| / ||t_s|| (host,
+ * synchronous, FP64 sums).                                                 */
+int fno_sample_errors(const float* y, int64_t ys, const float* t, int64_t ts, int nch, int64_t npix,
+                      int batch, double* out);
+
+/* Batched strided GEMM on the matrix cores, exposed for testing:
+ * C[b][i][j] = alpha sum_k A[b][i][k] B[b][k][j] with A, B bfloat16 (raw
+ * uint16 storage) and C float32, all device pointers; element (i, k) of
+ * batch b of A sits at A + b*sA + i*rA + k*cA (likewise B, C).  Synchronous. */
+int fno_gemm_bf16(int batch, int M, int N, int K, float alpha, const uint16_t* A, int64_t sA,
+                  int64_t rA, int64_t cA, const uint16_t* B, int64_t sB, int64_t rB, int64_t cB,
+                  float* C, int64_t sC, int64_t rC, int64_t cC);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNO_H */

@@ -131,6 +131,34 @@ int ttsh_set_field(ttsh_ctx* ctx, int inst, const double* v, int where);
  * (omega = d_x v_y - d_y v_x) of instance inst, float64.  Synchronous.      */
 int ttsh_get_field(ttsh_ctx* ctx, int inst, double* v, double* omega, int where);
 
+/* Coarse real velocity of instance inst on an Nc x Nc grid of the same box
+ * (Nc one of 64..1024, at most the context's largest N): the modes inside
+ * both grids' 1/2-rule disks are copied by integer mode index, scaled by Nc/N
+ * for the unitary DFT, and transformed back.  Output: device float32,
+ * channels-last with a stride: component c of node (i, j) goes to
+ * out[(i*Nc + j)*pix_stride + c], c = 0 (x), 1 (y); pix_stride >= 2.
+ * Asynchronous on the context's stream.                                    */
+int ttsh_get_field_coarse(ttsh_ctx* ctx, int inst, int Nc, float* out, int64_t pix_stride);
+
+/* Inverse of ttsh_get_field_coarse: set instance inst from a coarse real
+ * velocity on an Nc x Nc grid of the same box (device float32, layout as in
+ * ttsh_get_field_coarse).  The field is transformed, cut to the coarse 1/2
+ * rule, Leray-projected (as in ttsh_set_field), and its modes are copied into
+ * the instance's grid by integer mode index, scaled by N/Nc (modes beyond the
+ * instance's own 1/2-rule disk are dropped).  Asynchronous.                 */
+int ttsh_set_field_coarse(ttsh_ctx* ctx, int inst, int Nc, const float* v, int64_t pix_stride);
+
+/* Project a batch of real velocity fields on an N x N periodic grid in place
+ * onto the solver's state space: 1/2-rule cutoff (m^2 > (N/4)^2 dropped) and
+ * Leray projection (sec. "Numerical method": divergence-free velocity), the
+ * mean (k = 0) kept.  v: device float32, field b, node (i, j), component c at
+ * v[((b*N + i)*N + j)*pix_stride + c].  If norms is non-null (host, [batch][2])
+ * it receives, per projected field, sum_x |v|^2 and sum_x |w|^2 with w the
+ * vorticity in integer-mode units (the physical enstrophy times (L/2 pi)^2),
+ * and the call synchronises; else it is asynchronous.  Uses the context's
+ * stream and grows a scratch buffer of 2 * batch * N^2 complex doubles.    */
+int ttsh_project_coarse(ttsh_ctx* ctx, int N, float* v, int64_t pix_stride, int batch, double* norms);
+
 /* Compact state in / out (layout above).  set_state rounds to the stored
  * precision, sets the modes outside the 1/2-rule disk (m_x^2 + m_y^2 > M^2)
  * to zero and performs no other projection; for a state that is zero outside

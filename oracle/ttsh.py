@@ -337,6 +337,24 @@ def field(vhat: np.ndarray) -> np.ndarray:
     return idft2(vhat).real
 
 
+def resample(vhat: np.ndarray, N_dst: int) -> np.ndarray:
+    """Continuation between runs on different grids (the circle section's
+    hysteresis protocol seeds each run from the previous final state): copy
+    the spectrum by integer mode index, keeping the modes inside both grids'
+    1/2-rule disks.  With the box side scaled with R, mode m is the same
+    physical pattern on both grids; the unitary DFT carries a factor N, hence
+    the scale N_dst/N_src."""
+    N_src = vhat.shape[-1]
+    Ms, Md = N_src // 4, N_dst // 4
+    lim = min(Ms, Md) ** 2
+    out = np.zeros(vhat.shape[:-2] + (N_dst, N_dst), dtype=np.complex128)
+    for my in range(-min(Ms, Md), min(Ms, Md) + 1):
+        for mx in range(-min(Ms, Md), min(Ms, Md) + 1):
+            if mx * mx + my * my <= lim:
+                out[..., my % N_dst, mx % N_dst] = vhat[..., my % N_src, mx % N_src] * (N_dst / N_src)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # masks (method section "mask generation"; Appendix D)
 # ---------------------------------------------------------------------------

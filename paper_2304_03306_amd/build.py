@@ -38,7 +38,7 @@ def _run(cmd):
 
 
 def sources():
-    return sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.hpp")) + [HERE.parent / "include" / "ttsh.h"]
+    return sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.hpp")) + sorted((HERE.parent / "include").glob("*.h"))
 
 
 def build(jobs: int | None = None, verbose: bool = True) -> Path:
@@ -48,6 +48,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> Path:
     units += [(CSRC / "step_multi.hip", OUT / f"step_{p}_{b}.o", [f"-DTTSH_PREC={p}", f"-DTTSH_BS={b}"])
               for p in PRECS for b in BLOCKS]
     units.append((CSRC / "ttsh_capi.hip", OUT / "ttsh_capi.o", []))
+    units.append((CSRC / "fno.hip", OUT / "fno.o", []))
     cmds = [[HIPCC, *FLAGS, *extra, "-c", str(src), "-o", str(obj)] for src, obj, extra in units]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for cmd, fut in zip(cmds, [ex.submit(_run, c) for c in cmds]):

@@ -23,6 +23,20 @@ __global__ void k_unpack_xy(const C2<double>* __restrict__ z, double* __restrict
     v[n + i] = z[i].y;
   }
 }
+__global__ void k_unpack_xy_strided(const C2<double>* __restrict__ z, float* __restrict__ v, int n,
+                                    long long stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    v[(long long)i * stride] = (float)z[i].x;
+    v[(long long)i * stride + 1] = (float)z[i].y;
+  }
+}
+__global__ void k_pack_xy_strided(const float* __restrict__ v, long long stride, C2<double>* __restrict__ z,
+                                  int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = mk((double)v[(long long)i * stride], (double)v[(long long)i * stride + 1]);
+}
+
 __global__ void k_real_part(const C2<double>* __restrict__ z, double* __restrict__ v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = z[i].x;
@@ -144,6 +158,72 @@ __global__ void k_state_to_full(const C2<S>* __restrict__ st, C2<double>* __rest
     out = cscale(out, 1.0 / N);
   }
   Z[i] = out;
+}
+
+template <class S>
+__global__ void k_convert_c(const C2<double>* __restrict__ in, C2<S>* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cvt<S>(in[i]);
+}
+
+// Batched full spectra Z of (v_x + i v_y) (unnormalised, [batch][N][N]) ->
+// Z' of the projected field: components separated, cut at m^2 > (N/4)^2,
+// Leray-projected (m != 0), recombined and scaled by 1/N^2 so that the
+// unnormalised inverse transform returns the field.
+__global__ void k_project_full(const C2<double>* __restrict__ Z, C2<double>* __restrict__ out, int N, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = i / (N * N), r = i % (N * N);
+  const int my = mode_of(r / N, N), mx = mode_of(r % N, N);
+  const int M = N / 4, m2 = mx * mx + my * my;
+  C2<double> o = mk(0.0, 0.0);
+  if (m2 <= M * M) {
+    const C2<double>* Zb = Z + (size_t)b * N * N;
+    const C2<double> zp = Zb[r];
+    const C2<double> zm = Zb[(size_t)((N - my) % N) * N + (N - mx) % N];
+    C2<double> ox = cscale(mk(zp.x + zm.x, zp.y - zm.y), 0.5);
+    C2<double> oy = cscale(mk(zp.y + zm.y, -(zp.x - zm.x)), 0.5);
+    if (m2 > 0) {
+      const C2<double> d = cscale(mk(mx * ox.x + my * oy.x, mx * ox.y + my * oy.y), 1.0 / m2);
+      ox = ox - cscale(d, (double)mx);
+      oy = oy - cscale(d, (double)my);
+    }
+    o = cscale(mk(ox.x - oy.y, ox.y + oy.x), 1.0 / ((double)N * N));
+  }
+  out[i] = o;
+}
+
+// Per field of a batch of projected spectra (as written by k_project_full):
+// out[2b] = sum_x |v|^2, out[2b+1] = sum_x |w|^2 with w the vorticity in
+// integer-mode units (i (m_x v_y - m_y v_x) per mode).  Block per field.
+__global__ void __launch_bounds__(256) k_full_norms(const C2<double>* __restrict__ Zs, int N,
+                                                    double* __restrict__ out) {
+  const C2<double>* Z = Zs + (size_t)blockIdx.x * N * N;
+  const double s = (double)N * N;  // undo the 1/N^2 of the stored spectrum
+  double e = 0.0, w = 0.0;
+  for (int r = threadIdx.x; r < N * N; r += blockDim.x) {
+    const int my = mode_of(r / N, N), mx = mode_of(r % N, N);
+    const C2<double> zp = cscale(Z[r], s);
+    const C2<double> zm = cscale(Z[(size_t)((N - my) % N) * N + (N - mx) % N], s);
+    const C2<double> ox = cscale(mk(zp.x + zm.x, zp.y - zm.y), 0.5);
+    const C2<double> oy = cscale(mk(zp.y + zm.y, -(zp.x - zm.x)), 0.5);
+    e += zp.x * zp.x + zp.y * zp.y;
+    const C2<double> c = cscale(oy, (double)mx) - cscale(ox, (double)my);
+    w += c.x * c.x + c.y * c.y;
+  }
+  e = wave_sum_from(e, 1);
+  w = wave_sum_from(w, 1);
+  __shared__ double red[4][2];
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = e;
+    red[threadIdx.x >> 6][1] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double inv = 1.0 / ((double)N * N);  // Parseval for the unnormalised transform
+    out[2 * blockIdx.x] = (red[0][0] + red[1][0] + red[2][0] + red[3][0]) * inv;
+    out[2 * blockIdx.x + 1] = (red[0][1] + red[1][1] + red[2][1] + red[3][1]) * inv;
+  }
 }
 
 // internal state [2][M+1][2M+2]  <->  interface layout [2][2M+1][M+1] (FP64)

@@ -1,0 +1,984 @@
+// Fourier-neural-operator surrogate on gfx950 (interface: include/fno.h).
+//
+// Every dense piece of the network goes through one strided, batched GEMM on
+// the matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
+// accumulation): the pruned 2D DFTs as products with small DFT matrices (only
+// m of W/2+1 k_x columns and 2m of H k_y rows are ever needed), the per-mode
+// complex channel mixing as real block products [Re, Im] [[R_r, R_i],
+// [-R_i, R_r]], the 1x1 convolutions, the projection and every weight
+// gradient (split over chunks of the point axis, partial sums reduced in a
+// fixed order).  A GEMM call may add a second product (A2 B2) and fuses bias,
+// exact GELU, GELU' and the saving of pre-activations into its epilogue.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/fno.h"
+#include "../../include/ttsh.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace {
+
+using bf16 = uint16_t;
+
+// ---- BF16 <-> FP32 (round to nearest even) ---------------------------------------
+__host__ __device__ inline bf16 f2bf(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+__host__ __device__ inline float bf2f(bf16 h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// ---- GEMM -------------------------------------------------------------------------------
+struct Op {
+  const bf16* p;
+  long long s1, s2, r, c;  // batch strides (b1, b2), row stride, column stride
+};
+
+struct GemmArgs {
+  int M, N, K, K2;
+  int nb1, nb2;            // batch = b1 * nb2 + b2
+  Op A, B, A2, B2;         // C = alpha A B + alpha2 A2 B2
+  float alpha, alpha2;
+  void* C;
+  long long sC1, sC2, rC, cC;
+  int c_bf16;              // C element type: 1 bf16, 0 float
+  int accumulate;          // float C only: C += result
+  const float* bias;       // per column, added before the activation
+  int act;                 // 0 none, 1 GELU, 2 multiply by GELU'(pre_in)
+  const bf16* pre_in;      // act 2: pre-activations (same strides as C)
+  bf16* pre_out;           // act 1: store the pre-activation (same strides as C)
+  const float* skip;       // float C only: C[i][j] += skip[i * skip_r + j] (after everything else)
+  long long skip_r;
+};
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline short4_t load_frag(const bf16* base, long long r, long long c, int row, int k0,
+                                     int nrow, int K) {
+  short4_t v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = k0 + q;
+    v[q] = (row < nrow && k < K) ? (short)base[(long long)row * r + (long long)k * c] : (short)0;
+  }
+  return v;
+}
+
+// One wavefront computes one 32 x 32 tile of C as 2 x 2 MFMA 16 x 16 blocks.
+// MFMA 16x16x16 operand layout (lane l): A row l%16, k = 4(l/16)..+3; B column
+// l%16, same k; result column l%16, rows 4(l/16)..+3.
+__device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, int b1, int b2,
+                                 int i0, int j0, int lane, float4_t (&acc)[2][2]) {
+  const bf16* pa = A.p + b1 * A.s1 + b2 * A.s2;
+  const bf16* pb = B.p + b1 * B.s1 + b2 * B.s2;
+  const int rl = lane & 15, kq = (lane >> 4) * 4;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    short4_t a[2], b[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      a[s] = load_frag(pa, A.r, A.c, i0 + 16 * s + rl, k0 + kq, M, K);
+      // B[k][j]: treat as rows j with stride B.c, columns k with stride B.r
+      b[s] = load_frag(pb, B.c, B.r, j0 + 16 * s + rl, k0 + kq, N, K);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[t], acc[s][t], 0, 0, 0);
+  }
+}
+
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int tiles) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long nbatch = (long long)g.nb1 * g.nb2;
+  const int groups = (tiles + 3) / 4;
+  const long long blk = blockIdx.x;
+  const long long batch = blk / groups;
+  const int tile = (int)(blk % groups) * 4 + wave;
+  if (batch >= nbatch || tile >= tiles) return;  // whole wavefront exits together
+  const int b1 = (int)(batch / g.nb2), b2 = (int)(batch % g.nb2);
+  const int i0 = (tile / tiles_n) * 32, j0 = (tile % tiles_n) * 32;
+  float4_t acc[2][2], acc2[2][2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
+      acc2[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  gemm_part(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc);
+  if (g.K2 > 0) gemm_part(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2);
+  const long long cbase = b1 * g.sC1 + b2 * g.sC2;
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 16 * s + (lane >> 4) * 4 + q;
+        const int j = j0 + 16 * t + (lane & 15);
+        if (i >= g.M || j >= g.N) continue;
+        const long long off = cbase + (long long)i * g.rC + (long long)j * g.cC;
+        float v = g.alpha * acc[s][t][q] + (g.K2 > 0 ? g.alpha2 * acc2[s][t][q] : 0.f);
+        if (g.accumulate) v += ((float*)g.C)[off];
+        if (g.bias) v += g.bias[j];
+        if (g.act == 1) {
+          if (g.pre_out) g.pre_out[off] = f2bf(v);
+          v = gelu(v);
+        } else if (g.act == 2) {
+          v *= gelu_grad(bf2f(g.pre_in[off]));
+        }
+        if (g.skip) v += g.skip[(long long)i * g.skip_r + j];
+        if (g.c_bf16)
+          ((bf16*)g.C)[off] = f2bf(v);
+        else
+          ((float*)g.C)[off] = v;
+      }
+}
+
+hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+  const int tiles_n = (g.N + 31) / 32, tiles = ((g.M + 31) / 32) * tiles_n;
+  const long long blocks = (long long)g.nb1 * g.nb2 * ((tiles + 3) / 4);
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
+  return hipGetLastError();
+}
+
+Op op(const bf16* p, long long r, long long c, long long s1 = 0, long long s2 = 0) { return Op{p, s1, s2, r, c}; }
+
+
+
+// ---- element-wise kernels ------------------------------------------------------------------
+__global__ void k_to_bf16(const float* __restrict__ x, bf16* __restrict__ y, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// h0[p][c] = sum_k x[p][k] P_w[k][c] + P_b[c]  (cin is small: vector ALU)
+__global__ void k_lift(const bf16* __restrict__ x, const bf16* __restrict__ Pw,
+                       const float* __restrict__ Pb, bf16* __restrict__ h, long long npts, int cin, int C) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts * C) return;
+  const long long p = i / C;
+  const int c = (int)(i % C);
+  float v = Pb[c];
+  for (int k = 0; k < cin; ++k) v += bf2f(x[p * cin + k]) * bf2f(Pw[k * C + c]);
+  h[i] = f2bf(v);
+}
+
+// dz = dh * GELU'(z)
+__global__ void k_gelu_back(const bf16* __restrict__ dh, const bf16* __restrict__ z, bf16* __restrict__ dz,
+                            long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dz[i] = f2bf(bf2f(dh[i]) * gelu_grad(bf2f(z[i])));
+}
+
+__global__ void k_gather(float* __restrict__ dst, long long dch, const float* __restrict__ src, long long sch,
+                         int nch, long long npix, const long long* __restrict__ idx, long long tot) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const long long s = i / (npix * nch), r = i % (npix * nch);
+  const long long p = r / nch;
+  const int ch = (int)(r % nch);
+  dst[(s * npix + p) * dch + ch] = src[(idx[s] * npix + p) * sch + ch];
+}
+
+// per-sample sums of (y - t)^2 and t^2 (FP64), one block per sample
+__global__ void __launch_bounds__(256) k_loss_sums(const float* __restrict__ y, const float* __restrict__ t,
+                                                   long long per, double* __restrict__ out) {
+  const long long base = (long long)blockIdx.x * per;
+  double a = 0.0, b = 0.0;
+  for (long long i = threadIdx.x; i < per; i += blockDim.x) {
+    const double d = (double)y[base + i] - (double)t[base + i];
+    a += d * d;
+    b += (double)t[base + i] * (double)t[base + i];
+  }
+  __shared__ double red[4][2];
+  a = ttsh::wave_sum_from(a, 1);
+  b = ttsh::wave_sum_from(b, 1);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = a;
+    red[threadIdx.x >> 6][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    out[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+  }
+}
+
+// per-sample sums of (y - t)^2 and t^2 over strided channels-last fields
+__global__ void __launch_bounds__(256) k_err_sums(const float* __restrict__ y, long long ys,
+                                                  const float* __restrict__ t, long long ts, int nch,
+                                                  long long npix, double* __restrict__ out) {
+  const long long base = (long long)blockIdx.x * npix;
+  double a = 0.0, b = 0.0;
+  for (long long i = threadIdx.x; i < npix * nch; i += blockDim.x) {
+    const long long p = base + i / nch;
+    const int ch = (int)(i % nch);
+    const double tv = t[p * ts + ch];
+    const double d = (double)y[p * ys + ch] - tv;
+    a += d * d;
+    b += tv * tv;
+  }
+  __shared__ double red[4][2];
+  a = ttsh::wave_sum_from(a, 1);
+  b = ttsh::wave_sum_from(b, 1);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = a;
+    red[threadIdx.x >> 6][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    out[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+  }
+}
+
+// dl/dy = (y - t) / (||y - t|| ||t|| B)
+__global__ void k_loss_grad(const float* __restrict__ y, const float* __restrict__ t,
+                            const double* __restrict__ sums, long long per, int B, bf16* __restrict__ dy) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per * B) return;
+  const long long s = i / per;
+  const double num = sqrt(sums[2 * s]), den = sqrt(sums[2 * s + 1]);
+  dy[i] = f2bf((float)(((double)y[i] - (double)t[i]) / (num * den * B)));
+}
+
+// column sums of a [rows][ncol] bf16 matrix: partials per chunk of rows
+__global__ void k_colsum_part(const bf16* __restrict__ a, long long rows, int ncol, long long chunk,
+                              float* __restrict__ part) {
+  const int j = threadIdx.x % ncol;  // blockDim = ncol * lanes
+  const int lanes = blockDim.x / ncol;
+  const int l = threadIdx.x / ncol;
+  const long long r0 = (long long)blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
+  float v = 0.f;
+  for (long long r = r0 + l; r < r1; r += lanes) v += bf2f(a[r * ncol + j]);
+  __shared__ float red[1024];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (l == 0) {
+    float s = 0.f;
+    for (int q = 0; q < lanes; ++q) s += red[q * ncol + j];
+    part[(long long)blockIdx.x * ncol + j] = s;
+  }
+}
+
+// out[j] = sum_c part[c][j] (fixed order)
+__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, long long n, float* __restrict__ out) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < nparts; ++c) s += part[(long long)c * n + j];
+  out[j] = s;
+}
+
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Wb[kx][q] = [[R_r, R_i], [-R_i, R_r]] (2C x 2C, bf16) from the master R
+__global__ void k_build_wb(const float* __restrict__ Rr, const float* __restrict__ Ri, bf16* __restrict__ Wb,
+                           int m, int C) {
+  const long long n = (long long)2 * m * m * 4 * C * C;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int C2 = 2 * C;
+  const int j = (int)(idx % C2), i = (int)((idx / C2) % C2);
+  const long long mode = idx / ((long long)C2 * C2);  // = kx * 2m + q
+  const int q = (int)(mode % (2 * m)), kx = (int)(mode / (2 * m));
+  const long long src = (((long long)q * m + kx) * C + (i % C)) * C + (j % C);
+  float v;
+  if (i < C) v = (j < C) ? Rr[src] : Ri[src];
+  else v = (j < C) ? -Ri[src] : Rr[src];
+  Wb[idx] = f2bf(v);
+}
+
+unsigned nb(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// =============================================================================================
+// context
+// =============================================================================================
+namespace {
+thread_local std::string g_fno_err;
+int ffail(int code, const std::string& msg);
+}  // namespace
+
+struct fno_ctx {
+  int C, m, L, cin, cout, hid, H, W, maxB;
+  hipStream_t s = nullptr;
+  int64_t nparam = 0;
+  // parameter offsets in the flat vector
+  int64_t oPw, oPb, oR[16], oW[16], ob[16], oQ1, oQ1b, oQ2, oQ2b;
+  float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+  int adam_t = 0;
+  // bf16 compute copies
+  bf16 *Pw = nullptr, *Wl[16] = {}, *Wb[16] = {}, *Q1 = nullptr, *Q2 = nullptr;
+  // DFT matrices (bf16)
+  bf16 *Dx, *DxG, *DyRe, *DyIm, *Ec, *Es, *Esn, *Ax, *Ax1;
+  // activations
+  bf16 *xb, *h[17], *z[16], *G[16], *T1, *T2, *O, *u, *a, *dy;
+  float* y = nullptr;  // last training output (pointer to caller buffer is not kept)
+  // backward scratch
+  bf16 *dh0, *dh1, *dz, *gG, *gF, *du, *xt;
+  float *part = nullptr;
+  size_t part_n = 0;
+  double* lsum = nullptr;
+  long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
+  std::vector<void*> allocs;
+  std::vector<std::pair<const char*, size_t>> extents;  // (start, bytes) of every buffer
+};
+
+namespace {
+int ffail(int code, const std::string& msg) {
+  g_fno_err = msg;
+  return ttsh::record_error(code, msg.c_str());
+}
+
+#define FCHK(expr)                                                                           \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return ffail(TTSH_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int alloc(fno_ctx* c, T** p, size_t n) {
+  if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) return ffail(TTSH_ENOMEM, "fno allocation failed");
+  c->allocs.push_back((void*)*p);
+  c->extents.push_back({(const char*)*p, n * sizeof(T)});
+  return TTSH_OK;
+}
+
+// Host-side bounds proof for a GEMM launch: the whole index range of every
+// operand must fall inside one buffer of the context (or a caller buffer
+// registered for the call).  Strides are non-negative by construction.
+bool inside(const fno_ctx* c, const void* p, long long max_off, size_t elem,
+            const std::pair<const char*, size_t>* extra, int nextra = 1) {
+  if (!p) return true;
+  const char* a = (const char*)p;
+  const char* e = a + (size_t)(max_off + 1) * elem;
+  auto fits = [&](const std::pair<const char*, size_t>& x) { return a >= x.first && e <= x.first + x.second; };
+  for (int q = 0; extra && q < nextra; ++q)
+    if (fits(extra[q])) return true;
+  for (auto& x : c->extents)
+    if (fits(x)) return true;
+  return false;
+}
+
+long long span(const Op& o, int nb1, int nb2, int rows, int cols) {
+  return (long long)(nb1 - 1) * o.s1 + (long long)(nb2 - 1) * o.s2 + (long long)(rows - 1) * o.r +
+         (long long)(cols - 1) * o.c;
+}
+
+int upload_bf16(fno_ctx* c, bf16** dst, const std::vector<double>& v) {
+  std::vector<bf16> h(v.size());
+  for (size_t i = 0; i < v.size(); ++i) h[i] = f2bf((float)v[i]);
+  int rc = alloc(c, dst, v.size());
+  if (rc) return rc;
+  FCHK(hipMemcpy(*dst, h.data(), h.size() * sizeof(bf16), hipMemcpyHostToDevice));
+  return TTSH_OK;
+}
+
+// DFT matrices of the pruned transforms (FP64 on the host, rounded to bf16)
+int make_dft(fno_ctx* c) {
+  const int m = c->m, H = c->H, W = c->W;
+  const double tp = 2.0 * M_PI, HW = (double)H * W;
+  auto kyq = [&](int q) { return q < m ? q : q - 2 * m; };
+  std::vector<double> Dx(2 * m * W), DxG(2 * m * W), DyRe(4 * m * H), DyIm(4 * m * H);
+  std::vector<double> Ec(H * 2 * m), Es(H * 2 * m), Esn(H * 2 * m), Ax(W * 2 * m), Ax1(W * 2 * m);
+  for (int kx = 0; kx < m; ++kx)
+    for (int x = 0; x < W; ++x) {
+      const double th = tp * kx * x / W, w = (kx == 0 ? 1.0 : 2.0) / HW;
+      Dx[kx * W + x] = cos(th);
+      Dx[(m + kx) * W + x] = -sin(th);
+      DxG[kx * W + x] = w * cos(th);
+      DxG[(m + kx) * W + x] = -w * sin(th);
+      Ax[x * 2 * m + kx] = w * cos(th);
+      Ax[x * 2 * m + m + kx] = -w * sin(th);
+      Ax1[x * 2 * m + kx] = cos(th);
+      Ax1[x * 2 * m + m + kx] = -sin(th);
+    }
+  for (int q = 0; q < 2 * m; ++q)
+    for (int y = 0; y < H; ++y) {
+      const double th = tp * kyq(q) * y / H;
+      DyRe[q * H + y] = cos(th);
+      DyRe[(2 * m + q) * H + y] = -sin(th);
+      DyIm[q * H + y] = sin(th);
+      DyIm[(2 * m + q) * H + y] = cos(th);
+      Ec[y * 2 * m + q] = cos(th);
+      Es[y * 2 * m + q] = sin(th);
+      Esn[y * 2 * m + q] = -sin(th);
+    }
+  int rc;
+  if ((rc = upload_bf16(c, &c->Dx, Dx)) || (rc = upload_bf16(c, &c->DxG, DxG)) ||
+      (rc = upload_bf16(c, &c->DyRe, DyRe)) || (rc = upload_bf16(c, &c->DyIm, DyIm)) ||
+      (rc = upload_bf16(c, &c->Ec, Ec)) || (rc = upload_bf16(c, &c->Es, Es)) ||
+      (rc = upload_bf16(c, &c->Esn, Esn)) || (rc = upload_bf16(c, &c->Ax, Ax)) ||
+      (rc = upload_bf16(c, &c->Ax1, Ax1)))
+    return rc;
+  return TTSH_OK;
+}
+
+// bf16 compute copies of the master parameters
+int refresh_weights(fno_ctx* c) {
+  const int C = c->C, m = c->m;
+  hipLaunchKernelGGL(k_to_bf16, dim3(nb((long long)c->cin * C)), dim3(256), 0, c->s, c->theta + c->oPw, c->Pw,
+                     (long long)c->cin * C);
+  for (int l = 0; l < c->L; ++l) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(nb((long long)C * C)), dim3(256), 0, c->s, c->theta + c->oW[l], c->Wl[l],
+                       (long long)C * C);
+    const long long nwb = (long long)2 * m * m * 4 * C * C;
+    const long long nR = (long long)2 * m * m * C * C;
+    hipLaunchKernelGGL(k_build_wb, dim3(nb(nwb)), dim3(256), 0, c->s, c->theta + c->oR[l], c->theta + c->oR[l] + nR,
+                       c->Wb[l], m, C);
+  }
+  hipLaunchKernelGGL(k_to_bf16, dim3(nb((long long)C * c->hid)), dim3(256), 0, c->s, c->theta + c->oQ1, c->Q1,
+                     (long long)C * c->hid);
+  hipLaunchKernelGGL(k_to_bf16, dim3(nb((long long)c->hid * c->cout)), dim3(256), 0, c->s, c->theta + c->oQ2, c->Q2,
+                     (long long)c->hid * c->cout);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+// Launch after proving every operand in bounds.
+int cgemm(fno_ctx* c, const GemmArgs& g, const std::pair<const char*, size_t>* extra = nullptr, int nextra = 1) {
+  const Op ops[4] = {g.A, g.B, g.A2, g.B2};
+  const int rows[4] = {g.M, g.K, g.M, g.K2}, cols[4] = {g.K, g.N, g.K2, g.N};
+  for (int q = 0; q < 4; ++q) {
+    if (q >= 2 && g.K2 <= 0) break;
+    const Op& o = ops[q];
+    if (o.s1 < 0 || o.s2 < 0 || o.r < 0 || o.c < 0) return ffail(TTSH_EINVAL, "negative GEMM stride");
+    if (!inside(c, o.p, span(o, g.nb1, g.nb2, rows[q], cols[q]), sizeof(bf16), extra, nextra))
+      return ffail(TTSH_EINVAL, "GEMM operand out of bounds (internal layout error)");
+  }
+  const long long cmax = (long long)(g.nb1 - 1) * g.sC1 + (long long)(g.nb2 - 1) * g.sC2 +
+                         (long long)(g.M - 1) * g.rC + (long long)(g.N - 1) * g.cC;
+  if (!inside(c, g.C, cmax, g.c_bf16 ? 2 : 4, extra, nextra) || !inside(c, g.pre_in, cmax, 2, extra, nextra) ||
+      !inside(c, g.pre_out, cmax, 2, extra, nextra) || !inside(c, g.bias, g.N - 1, 4, extra, nextra))
+    return ffail(TTSH_EINVAL, "GEMM output out of bounds (internal layout error)");
+  if (g.skip && (g.c_bf16 || g.skip_r < 0 ||
+                 !inside(c, g.skip, (long long)(g.M - 1) * g.skip_r + g.N - 1, 4, extra, nextra)))
+    return ffail(TTSH_EINVAL, "GEMM residual input out of bounds (internal layout error)");
+  const hipError_t e = gemm(g, c->s);
+  if (e != hipSuccess) return ffail(TTSH_EHIP, std::string("GEMM launch: ") + hipGetErrorString(e));
+  return TTSH_OK;
+}
+
+GemmArgs ga() {
+  GemmArgs g{};
+  g.nb1 = g.nb2 = 1;
+  g.alpha = 1.f;
+  g.alpha2 = 1.f;
+  return g;
+}
+
+// ---- spectral pieces shared by forward and backward ------------------------------------
+// Forward truncated rfft2 of src [B][H][W][C] into the mode layout
+// dst [m][4m][B][C] (rows 0..2m-1 real parts, 2m..4m-1 imaginary parts);
+// Dxm is the k_x matrix (Dx, or DxG for the backward weights).
+int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, int B) {
+  int rc;
+  const int C = c->C, m = c->m, H = c->H, W = c->W;
+  const long long HWC = (long long)H * W * C, HC = (long long)H * C;
+  // T1 [B][2m][H][C] = Dxm (2m x W) . src[b][y] (W x C)
+  GemmArgs g = ga();
+  g.M = 2 * m; g.N = C; g.K = W;
+  g.nb1 = B; g.nb2 = H;
+  g.A = op(Dxm, W, 1);
+  g.B = op(src, C, 1, HWC, (long long)W * C);
+  g.C = c->T1; g.c_bf16 = 1;
+  g.sC1 = 2LL * m * HC; g.sC2 = C; g.rC = HC; g.cC = 1;
+  if ((rc = cgemm(c, g))) return rc;
+  // dst[kx] (4m x C per b) = DyRe . T1_re + DyIm . T1_im
+  GemmArgs h = ga();
+  h.M = 4 * m; h.N = C; h.K = H; h.K2 = H;
+  h.nb1 = B; h.nb2 = m;
+  h.A = op(c->DyRe, H, 1);
+  h.B = op(c->T1, C, 1, 2LL * m * HC, HC);
+  h.A2 = op(c->DyIm, H, 1);
+  h.B2 = op(c->T1 + (long long)m * HC, C, 1, 2LL * m * HC, HC);
+  h.C = dst; h.c_bf16 = 1;
+  h.sC1 = C; h.sC2 = 4LL * m * B * C; h.rC = (long long)B * C; h.cC = 1;
+  if ((rc = cgemm(c, h))) return rc;
+  return TTSH_OK;
+}
+
+// Inverse along y of the mode array src [m][2m][B][2C] (real, imaginary halves
+// of each channel block) into T2 [B][H][2m][C] (k_x real at kx, imaginary at m+kx).
+int spectral_synth_y(fno_ctx* c, const bf16* src, int B) {
+  int rc;
+  const int C = c->C, m = c->m, H = c->H;
+  const long long modeS = (long long)B * 2 * C;  // stride between k_y rows
+  for (int part = 0; part < 2; ++part) {
+    // part 0: Fr = Ec . O_r + (-Es) . O_i ;  part 1: Fi = Es . O_r + Ec . O_i
+    GemmArgs g = ga();
+    g.M = H; g.N = C; g.K = 2 * m; g.K2 = 2 * m;
+    g.nb1 = B; g.nb2 = m;
+    g.A = op(part == 0 ? c->Ec : c->Es, 2 * m, 1);
+    g.B = op(src, modeS, 1, 2LL * C, 2LL * m * modeS);
+    g.A2 = op(part == 0 ? c->Esn : c->Ec, 2 * m, 1);
+    g.B2 = op(src + C, modeS, 1, 2LL * C, 2LL * m * modeS);
+    g.C = c->T2 + (part ? (long long)m * C : 0); g.c_bf16 = 1;
+    g.sC1 = (long long)H * 2 * m * C; g.sC2 = C; g.rC = 2LL * m * C; g.cC = 1;
+    if ((rc = cgemm(c, g))) return rc;
+  }
+  return TTSH_OK;
+}
+
+// Mode mixing: out[kx][q][b][0:2C] = [G_r, G_i][b] . Wb (forward) or Wb^T (adjoint)
+int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, bool transpose, bf16* out, int B) {
+  int rc;
+  const int C = c->C, m = c->m;
+  const long long C2 = 2LL * C;
+  GemmArgs g = ga();
+  g.M = B; g.N = 2 * C; g.K = C; g.K2 = C;
+  g.nb1 = m; g.nb2 = 2 * m;
+  g.A = op(G, C, 1, 4LL * m * B * C, (long long)B * C);
+  g.A2 = op(G + 2LL * m * B * C, C, 1, 4LL * m * B * C, (long long)B * C);
+  const long long wS1 = 2LL * m * C2 * C2, wS2 = C2 * C2;
+  if (!transpose) {
+    g.B = op(Wb, C2, 1, wS1, wS2);
+    g.B2 = op(Wb + C * C2, C2, 1, wS1, wS2);
+  } else {  // B[k][j] = Wb[j][k]
+    g.B = op(Wb, 1, C2, wS1, wS2);
+    g.B2 = op(Wb + C, 1, C2, wS1, wS2);
+  }
+  g.C = out; g.c_bf16 = 1;
+  g.sC1 = 2LL * m * B * C2; g.sC2 = B * C2; g.rC = C2; g.cC = 1;
+  if ((rc = cgemm(c, g))) return rc;
+  return TTSH_OK;
+}
+
+long long pts(const fno_ctx* c, int B) { return (long long)B * c->H * c->W; }
+
+// split-K weight gradient: out (M x N, float, += into grad) = A^T-like product
+// over the point axis.  A[i][p] at A + i*rA + p*cA, B[p][j] at B + p*rB + j*cB.
+int wgrad(fno_ctx* c, int M, int N, long long P, const bf16* A, long long rA, long long cA, const bf16* Bm,
+          long long rB, long long cB, float* out) {
+  int rc;
+  const long long chunk = 4096;
+  const long long nchunk = (P + chunk - 1) / chunk;
+  if ((size_t)(nchunk * M * N) > c->part_n) return ffail(TTSH_ENOMEM, "fno partials buffer too small");
+  GemmArgs g = ga();
+  g.M = M; g.N = N; g.K = (int)chunk;
+  g.nb1 = (int)nchunk; g.nb2 = 1;
+  g.A = op(A, rA, cA, chunk * cA, 0);
+  g.B = op(Bm, rB, cB, chunk * rB, 0);
+  g.C = c->part; g.c_bf16 = 0;
+  g.sC1 = (long long)M * N; g.rC = N; g.cC = 1;
+  // the last chunk may be short: handled by passing K per call below
+  if (P % chunk == 0) {
+    if ((rc = cgemm(c, g))) return rc;
+  } else {
+    g.nb1 = (int)(nchunk - 1);
+    if (g.nb1 > 0) if ((rc = cgemm(c, g))) return rc;
+    GemmArgs t = g;
+    t.nb1 = 1;
+    t.K = (int)(P - (nchunk - 1) * chunk);
+    t.A.p = A + (nchunk - 1) * chunk * cA;
+    t.B.p = Bm + (nchunk - 1) * chunk * rB;
+    t.C = c->part + (nchunk - 1) * M * N;
+    if ((rc = cgemm(c, t))) return rc;
+  }
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nb((long long)M * N)), dim3(256), 0, c->s, c->part, (int)nchunk,
+                     (long long)M * N, out);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+int colsum(fno_ctx* c, const bf16* a, long long rows, int ncol, float* out) {
+  const long long chunk = 8192;
+  const long long nchunk = (rows + chunk - 1) / chunk;
+  if ((size_t)(nchunk * ncol) > c->part_n) return ffail(TTSH_ENOMEM, "fno partials buffer too small");
+  const int lanes = std::max(1, std::min(1024 / ncol, 64));
+  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)nchunk), dim3(lanes * ncol), 0, c->s, a, rows, ncol, chunk,
+                     c->part);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nb(ncol)), dim3(256), 0, c->s, c->part, (int)nchunk, (long long)ncol, out);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+void free_fno(fno_ctx* c) {
+  if (!c) return;
+  for (void* p : c->allocs) hipFree(p);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cout, int hidden, int H, int W,
+               int max_batch, uint64_t seed, void* stream) {
+  if (!out) return ffail(TTSH_EINVAL, "null output");
+  *out = nullptr;
+  if (width < 1 || width > 256 || modes < 1 || layers < 1 || layers > 16 || cin < 1 || cin > 16 || cout < 1 ||
+      cout > 16 || hidden < 1 || hidden > 1024 || H < 16 || W < 16 || H % 16 || W % 16 || 2 * modes > H ||
+      modes > W / 2 || max_batch < 1 || (long long)max_batch * H * W > (1LL << 31) / 256)
+    return ffail(TTSH_EINVAL, "fno_create: invalid sizes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ffail(TTSH_EHIP, "no HIP device available");
+  fno_ctx* c = new fno_ctx();
+  c->C = width; c->m = modes; c->L = layers; c->cin = cin; c->cout = cout; c->hid = hidden;
+  c->H = H; c->W = W; c->maxB = max_batch; c->s = (hipStream_t)stream;
+  const long long C = width, m = modes;
+  int64_t o = 0;
+  c->oPw = o; o += cin * C;
+  c->oPb = o; o += C;
+  for (int l = 0; l < layers; ++l) {
+    c->oR[l] = o; o += 2 * (2 * m * m * C * C);
+    c->oW[l] = o; o += C * C;
+    c->ob[l] = o; o += C;
+  }
+  c->oQ1 = o; o += C * hidden;
+  c->oQ1b = o; o += hidden;
+  c->oQ2 = o; o += (long long)hidden * cout;
+  c->oQ2b = o; o += cout;
+  c->nparam = o;
+  auto bail = [&](int rc) { free_fno(c); return rc; };
+  int rc;
+  const long long P = (long long)max_batch * H * W;
+  const long long modesz = (long long)m * 4 * m * max_batch * C;
+  if ((rc = alloc(c, &c->theta, o)) || (rc = alloc(c, &c->grad, o)) || (rc = alloc(c, &c->m1, o)) ||
+      (rc = alloc(c, &c->m2, o)) || (rc = alloc(c, &c->Pw, (size_t)(cin * C))) ||
+      (rc = alloc(c, &c->Q1, (size_t)(C * hidden))) || (rc = alloc(c, &c->Q2, (size_t)(hidden * cout))) ||
+      (rc = alloc(c, &c->xb, (size_t)(P * cin))) || (rc = alloc(c, &c->T1, (size_t)(max_batch * 2 * m * H * C))) ||
+      (rc = alloc(c, &c->T2, (size_t)(max_batch * 2 * m * H * C))) || (rc = alloc(c, &c->O, (size_t)modesz)) ||
+      (rc = alloc(c, &c->u, (size_t)(P * hidden))) || (rc = alloc(c, &c->a, (size_t)(P * hidden))) ||
+      (rc = alloc(c, &c->dy, (size_t)(P * cout))) || (rc = alloc(c, &c->dh0, (size_t)(P * C))) ||
+      (rc = alloc(c, &c->dh1, (size_t)(P * C))) || (rc = alloc(c, &c->dz, (size_t)(P * C))) ||
+      (rc = alloc(c, &c->gG, (size_t)modesz)) || (rc = alloc(c, &c->gF, (size_t)modesz)) ||
+      (rc = alloc(c, &c->du, (size_t)(P * hidden))) || (rc = alloc(c, &c->lsum, (size_t)(2 * max_batch))) ||
+      (rc = alloc(c, &c->gidx, (size_t)max_batch)))
+    return bail(rc);
+  for (int l = 0; l <= layers; ++l)
+    if ((rc = alloc(c, &c->h[l], (size_t)(P * C)))) return bail(rc);
+  for (int l = 0; l < layers; ++l)
+    if ((rc = alloc(c, &c->z[l], (size_t)(P * C))) || (rc = alloc(c, &c->G[l], (size_t)modesz)) ||
+        (rc = alloc(c, &c->Wl[l], (size_t)(C * C))) ||
+        (rc = alloc(c, &c->Wb[l], (size_t)(2 * m * m * 4 * C * C))))
+      return bail(rc);
+  // partial sums of the split-K reductions: (points/4096) x the largest gradient block
+  const long long maxblk = std::max<long long>({C * C, C * hidden, (long long)hidden * cout, cin * C});
+  c->part_n = (size_t)((P + 4095) / 4096 + 1) * (size_t)std::max<long long>(maxblk, 1024);
+  if ((rc = alloc(c, &c->part, c->part_n))) return bail(rc);
+  if ((rc = make_dft(c))) return bail(rc);
+  // seeded initial parameters (same distributions as the oracle's)
+  std::vector<float> th(o, 0.f);
+  std::mt19937_64 gen(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::uniform_real_distribution<double> ud(0.0, 1.0);
+  for (long long i = 0; i < cin * C; ++i) th[c->oPw + i] = (float)(nd(gen) / sqrt((double)cin));
+  for (int l = 0; l < layers; ++l) {
+    for (long long i = 0; i < 2 * (2 * m * m * C * C); ++i) th[c->oR[l] + i] = (float)(ud(gen) / (double)(C * C));
+    for (long long i = 0; i < C * C; ++i) th[c->oW[l] + i] = (float)(nd(gen) / sqrt((double)C));
+  }
+  for (long long i = 0; i < C * hidden; ++i) th[c->oQ1 + i] = (float)(nd(gen) / sqrt((double)C));
+  for (long long i = 0; i < (long long)hidden * cout; ++i) th[c->oQ2 + i] = (float)(nd(gen) / sqrt((double)hidden));
+  if (hipMemcpy(c->theta, th.data(), o * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->m1, 0, o * 4) != hipSuccess || hipMemset(c->m2, 0, o * 4) != hipSuccess ||
+      hipMemset(c->grad, 0, o * 4) != hipSuccess)
+    return bail(ffail(TTSH_EHIP, "parameter upload failed"));
+  if ((rc = refresh_weights(c))) return bail(rc);
+  if (hipStreamSynchronize(c->s) != hipSuccess) return bail(ffail(TTSH_EHIP, "sync failed"));
+  *out = c;
+  return TTSH_OK;
+}
+
+void fno_destroy(fno_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->s);
+  free_fno(c);
+}
+
+int64_t fno_num_params(fno_ctx* c) { return c ? c->nparam : (int64_t)ffail(TTSH_EINVAL, "null context"); }
+
+int fno_set_params(fno_ctx* c, const float* p) {
+  if (!c || !p) return ffail(TTSH_EINVAL, "null argument");
+  FCHK(hipMemcpy(c->theta, p, c->nparam * 4, hipMemcpyHostToDevice));
+  c->adam_t = 0;
+  FCHK(hipMemset(c->m1, 0, c->nparam * 4));
+  FCHK(hipMemset(c->m2, 0, c->nparam * 4));
+  int rc = refresh_weights(c);
+  if (rc) return rc;
+  FCHK(hipStreamSynchronize(c->s));
+  return TTSH_OK;
+}
+
+int fno_get_params(fno_ctx* c, float* p) {
+  if (!c || !p) return ffail(TTSH_EINVAL, "null argument");
+  FCHK(hipStreamSynchronize(c->s));
+  FCHK(hipMemcpy(p, c->theta, c->nparam * 4, hipMemcpyDeviceToHost));
+  return TTSH_OK;
+}
+
+int fno_get_grads(fno_ctx* c, float* p) {
+  if (!c || !p) return ffail(TTSH_EINVAL, "null argument");
+  FCHK(hipStreamSynchronize(c->s));
+  FCHK(hipMemcpy(p, c->grad, c->nparam * 4, hipMemcpyDeviceToHost));
+  return TTSH_OK;
+}
+
+int fno_forward(fno_ctx* c, const float* x, float* y, int B, int train) {
+  return c ? fno_forward_ex(c, x, y, c->cout, 0, B, train) : ffail(TTSH_EINVAL, "null context");
+}
+
+int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residual, int B, int train) {
+  if (!c || !x || !y) return ffail(TTSH_EINVAL, "null argument");
+  if (ys < c->cout) return ffail(TTSH_EINVAL, "output pixel stride smaller than cout");
+  if (B < 1 || B > c->maxB) return ffail(TTSH_EINVAL, "batch out of range");
+  if (residual && c->cout > c->cin) return ffail(TTSH_EINVAL, "residual output needs cout <= cin");
+  const int C = c->C, m = c->m, H = c->H, W = c->W;
+  const long long P = pts(c, B);
+  {
+    // an output that overlaps the input must be the input's own first channels
+    const char *x0 = (const char*)x, *x1 = x0 + P * c->cin * sizeof(float);
+    const char *y0 = (const char*)y, *y1 = y0 + ((P - 1) * ys + c->cout) * sizeof(float);
+    if (y0 < x1 && x0 < y1 && !(y0 == x0 && ys == c->cin))
+      return ffail(TTSH_EINVAL, "output overlaps the input other than as its first channels");
+  }
+  hipLaunchKernelGGL(k_to_bf16, dim3(nb(P * c->cin)), dim3(256), 0, c->s, x, c->xb, P * c->cin);
+  hipLaunchKernelGGL(k_lift, dim3(nb(P * C)), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb, c->h[0], P,
+                     c->cin, C);
+  FCHK(hipGetLastError());
+  int rc;
+  for (int l = 0; l < c->L; ++l) {
+    const bool last = l == c->L - 1;
+    if ((rc = spectral_analysis(c, c->h[l], c->Dx, c->G[l], B))) return rc;
+    if ((rc = spectral_mix(c, c->G[l], c->Wb[l], false, c->O, B))) return rc;
+    if ((rc = spectral_synth_y(c, c->O, B))) return rc;
+    // h_{l+1} = act(Ax . T2[b][y] + h_l[b][y] . W_l + b_l)
+    GemmArgs g = ga();
+    g.M = W; g.N = C; g.K = 2 * m; g.K2 = C;
+    g.nb1 = B; g.nb2 = H;
+    g.A = op(c->Ax, 2 * m, 1);
+    g.B = op(c->T2, C, 1, (long long)H * 2 * m * C, 2LL * m * C);
+    g.A2 = op(c->h[l], C, 1, (long long)H * W * C, (long long)W * C);
+    g.B2 = op(c->Wl[l], C, 1);
+    g.C = c->h[l + 1]; g.c_bf16 = 1;
+    g.sC1 = (long long)H * W * C; g.sC2 = (long long)W * C; g.rC = C; g.cC = 1;
+    g.bias = c->theta + c->ob[l];
+    if (!last) {
+      g.act = 1;
+      g.pre_out = c->z[l];
+    }
+    if ((rc = cgemm(c, g))) return rc;
+  }
+  // projection: a = GELU(h_L Q1 + Q1_b) (pre-activation u kept), y = a Q2 + Q2_b
+  GemmArgs g = ga();
+  g.M = (int)P; g.N = c->hid; g.K = C;
+  g.A = op(c->h[c->L], C, 1);
+  g.B = op(c->Q1, c->hid, 1);
+  g.C = c->a; g.c_bf16 = 1; g.rC = c->hid; g.cC = 1;
+  g.bias = c->theta + c->oQ1b; g.act = 1; g.pre_out = c->u;
+  if ((rc = cgemm(c, g))) return rc;
+  GemmArgs q = ga();
+  q.M = (int)P; q.N = c->cout; q.K = c->hid;
+  q.A = op(c->a, c->hid, 1);
+  q.B = op(c->Q2, c->cout, 1);
+  q.C = y; q.c_bf16 = 0; q.rC = ys; q.cC = 1;
+  q.bias = c->theta + c->oQ2b;
+  if (residual) {
+    q.skip = x;
+    q.skip_r = c->cin;
+  }
+  const std::pair<const char*, size_t> ext[2] = {
+      {(const char*)y, (size_t)((P - 1) * ys + c->cout) * sizeof(float)},
+      {(const char*)x, (size_t)(P * c->cin) * sizeof(float)}};
+  if ((rc = cgemm(c, q, ext, 2))) return rc;
+  (void)train;
+  return TTSH_OK;
+}
+
+int fno_loss(fno_ctx* c, const float* y, const float* t, int B, double* loss) {
+  if (!c || !y || !t || !loss) return ffail(TTSH_EINVAL, "null argument");
+  if (B < 1 || B > c->maxB) return ffail(TTSH_EINVAL, "batch out of range");
+  const long long per = (long long)c->H * c->W * c->cout;
+  hipLaunchKernelGGL(k_loss_sums, dim3(B), dim3(256), 0, c->s, y, t, per, c->lsum);
+  hipLaunchKernelGGL(k_loss_grad, dim3(nb(per * B)), dim3(256), 0, c->s, y, t, c->lsum, per, B, c->dy);
+  FCHK(hipGetLastError());
+  std::vector<double> h(2 * B);
+  FCHK(hipMemcpyAsync(h.data(), c->lsum, 2 * B * sizeof(double), hipMemcpyDeviceToHost, c->s));
+  FCHK(hipStreamSynchronize(c->s));
+  double acc = 0.0;
+  for (int s = 0; s < B; ++s) acc += sqrt(h[2 * s]) / sqrt(h[2 * s + 1]);
+  *loss = acc / B;
+  return TTSH_OK;
+}
+
+int fno_backward(fno_ctx* c, int B) {
+  if (!c) return ffail(TTSH_EINVAL, "null context");
+  if (B < 1 || B > c->maxB) return ffail(TTSH_EINVAL, "batch out of range");
+  const int C = c->C, m = c->m, H = c->H, W = c->W, hid = c->hid, co = c->cout;
+  const long long P = pts(c, B);
+  int rc;
+  // projection
+  if ((rc = wgrad(c, hid, co, P, c->a, 1, hid, c->dy, co, 1, c->grad + c->oQ2))) return rc;
+  if ((rc = colsum(c, c->dy, P, co, c->grad + c->oQ2b))) return rc;
+  GemmArgs g = ga();  // du = (dy Q2^T) * GELU'(u)
+  g.M = (int)P; g.N = hid; g.K = co;
+  g.A = op(c->dy, co, 1);
+  g.B = op(c->Q2, 1, co);
+  g.C = c->du; g.c_bf16 = 1; g.rC = hid; g.cC = 1;
+  g.act = 2; g.pre_in = c->u;
+  if ((rc = cgemm(c, g))) return rc;
+  if ((rc = wgrad(c, C, hid, P, c->h[c->L], 1, C, c->du, hid, 1, c->grad + c->oQ1))) return rc;
+  if ((rc = colsum(c, c->du, P, hid, c->grad + c->oQ1b))) return rc;
+  GemmArgs d = ga();  // dh_L = du Q1^T
+  d.M = (int)P; d.N = C; d.K = hid;
+  d.A = op(c->du, hid, 1);
+  d.B = op(c->Q1, 1, hid);
+  d.C = c->dh0; d.c_bf16 = 1; d.rC = C; d.cC = 1;
+  if ((rc = cgemm(c, d))) return rc;
+  bf16* dh = c->dh0;
+  bf16* dh_next = c->dh1;
+  for (int l = c->L - 1; l >= 0; --l) {
+    const bf16* dz = dh;
+    if (l < c->L - 1) {
+      hipLaunchKernelGGL(k_gelu_back, dim3(nb(P * C)), dim3(256), 0, c->s, dh, c->z[l], c->dz, P * C);
+      FCHK(hipGetLastError());
+      dz = c->dz;
+    }
+    if ((rc = wgrad(c, C, C, P, c->h[l], 1, C, dz, C, 1, c->grad + c->oW[l]))) return rc;
+    if ((rc = colsum(c, dz, P, C, c->grad + c->ob[l]))) return rc;
+    // g_G = (w/(HW)) trunc rfft2(dz)
+    if ((rc = spectral_analysis(c, dz, c->DxG, c->gG, B))) return rc;
+    // dR per mode (kx, q): dR_r = F_r^T gG_r + F_i^T gG_i ; dR_i = F_r^T gG_i - F_i^T gG_r
+    const long long nR = 2LL * m * m * C * C;
+    for (int part = 0; part < 2; ++part) {
+      GemmArgs r = ga();
+      r.M = C; r.N = C; r.K = B; r.K2 = B;
+      r.nb1 = m; r.nb2 = 2 * m;
+      const long long s1 = 4LL * m * B * C, s2 = (long long)B * C, im = 2LL * m * B * C;
+      r.A = op(c->G[l], 1, C, s1, s2);                 // F_r^T
+      r.A2 = op(c->G[l] + im, 1, C, s1, s2);           // F_i^T
+      if (part == 0) {
+        r.B = op(c->gG, C, 1, s1, s2);
+        r.B2 = op(c->gG + im, C, 1, s1, s2);
+      } else {
+        r.B = op(c->gG + im, C, 1, s1, s2);
+        r.B2 = op(c->gG, C, 1, s1, s2);
+        r.alpha2 = -1.f;
+      }
+      r.C = c->grad + c->oR[l] + part * nR; r.c_bf16 = 0;
+      r.sC1 = (long long)C * C; r.sC2 = (long long)m * C * C; r.rC = C; r.cC = 1;
+      if ((rc = cgemm(c, r))) return rc;
+    }
+    // g_F = g_G Wb^T  (into gF, mode layout [m][2m][B][2C])
+    if ((rc = spectral_mix(c, c->gG, c->Wb[l], true, c->gF, B))) return rc;
+    if ((rc = spectral_synth_y(c, c->gF, B))) return rc;
+    // dh_l = Ax1 . T2 + dz W_l^T
+    GemmArgs e = ga();
+    e.M = W; e.N = C; e.K = 2 * m; e.K2 = C;
+    e.nb1 = B; e.nb2 = H;
+    e.A = op(c->Ax1, 2 * m, 1);
+    e.B = op(c->T2, C, 1, (long long)H * 2 * m * C, 2LL * m * C);
+    e.A2 = op(dz, C, 1, (long long)H * W * C, (long long)W * C);
+    e.B2 = op(c->Wl[l], 1, C);
+    e.C = dh_next; e.c_bf16 = 1;
+    e.sC1 = (long long)H * W * C; e.sC2 = (long long)W * C; e.rC = C; e.cC = 1;
+    if ((rc = cgemm(c, e))) return rc;
+    std::swap(dh, dh_next);
+  }
+  // lift
+  if ((rc = wgrad(c, c->cin, C, P, c->xb, 1, c->cin, dh, C, 1, c->grad + c->oPw))) return rc;
+  if ((rc = colsum(c, dh, P, C, c->grad + c->oPb))) return rc;
+  return TTSH_OK;
+}
+
+int fno_adam_step(fno_ctx* c, float lr, float b1, float b2, float eps) {
+  if (!c) return ffail(TTSH_EINVAL, "null context");
+  if (!(lr >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return ffail(TTSH_EINVAL, "invalid Adam coefficients");
+  c->adam_t += 1;
+  const float c1 = 1.f - powf(b1, (float)c->adam_t), c2 = 1.f - powf(b2, (float)c->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3(nb(c->nparam)), dim3(256), 0, c->s, c->theta, c->grad, c->m1, c->m2,
+                     (long long)c->nparam, lr, b1, b2, eps, c1, c2);
+  FCHK(hipGetLastError());
+  return refresh_weights(c);
+}
+
+int fno_gather(fno_ctx* c, float* dst, int64_t dch, const float* src, int64_t sch, int nch, int64_t npix,
+               const int64_t* idx, int n) {
+  if (!c || !dst || !src || !idx) return ffail(TTSH_EINVAL, "null argument");
+  if (n < 1 || n > c->maxB) return ffail(TTSH_EINVAL, "sample count out of range");
+  if (nch < 1 || npix < 1 || dch < nch || sch < nch) return ffail(TTSH_EINVAL, "invalid sizes");
+  for (int s = 0; s < n; ++s)
+    if (idx[s] < 0) return ffail(TTSH_EINVAL, "negative sample index");
+  static_assert(sizeof(long long) == sizeof(int64_t), "index width");
+  FCHK(hipMemcpyAsync(c->gidx, idx, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->s));
+  const long long tot = (long long)n * npix * nch;
+  hipLaunchKernelGGL(k_gather, dim3(nb(tot)), dim3(256), 0, c->s, dst, (long long)dch, src, (long long)sch, nch,
+                     (long long)npix, c->gidx, tot);
+  FCHK(hipGetLastError());
+  FCHK(hipStreamSynchronize(c->s));  // idx is read from pageable host memory
+  return TTSH_OK;
+}
+
+int fno_sample_errors(const float* y, int64_t ys, const float* t, int64_t ts, int nch, int64_t npix, int B,
+                      double* out) {
+  if (!y || !t || !out) return ffail(TTSH_EINVAL, "null argument");
+  if (B < 1 || nch < 1 || npix < 1 || ys < nch || ts < nch) return ffail(TTSH_EINVAL, "invalid sizes");
+  double* d = nullptr;
+  FCHK(hipMalloc((void**)&d, 2 * B * sizeof(double)));
+  hipLaunchKernelGGL(k_err_sums, dim3(B), dim3(256), 0, 0, y, (long long)ys, t, (long long)ts, nch,
+                     (long long)npix, d);
+  std::vector<double> h(2 * B);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(h.data(), d, 2 * B * sizeof(double), hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return ffail(TTSH_EHIP, std::string("error sums: ") + hipGetErrorString(e));
+  for (int s = 0; s < B; ++s) out[s] = sqrt(h[2 * s]) / sqrt(h[2 * s + 1]);
+  return TTSH_OK;
+}
+
+int fno_gemm_bf16(int batch, int M, int N, int K, float alpha, const uint16_t* A, int64_t sA, int64_t rA,
+                  int64_t cA, const uint16_t* B, int64_t sB, int64_t rB, int64_t cB, float* C, int64_t sC,
+                  int64_t rC, int64_t cC) {
+  if (!A || !B || !C) return ffail(TTSH_EINVAL, "null pointer");
+  if (batch < 1 || M < 1 || N < 1 || K < 1) return ffail(TTSH_EINVAL, "sizes must be >= 1");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ffail(TTSH_EHIP, "no HIP device available");
+  GemmArgs g = ga();
+  g.M = M; g.N = N; g.K = K;
+  g.nb1 = batch;
+  g.alpha = alpha;
+  g.A = op(A, rA, cA, sA, 0);
+  g.B = op(B, rB, cB, sB, 0);
+  g.C = C; g.c_bf16 = 0; g.sC1 = sC; g.rC = rC; g.cC = cC;
+  FCHK(gemm(g, 0));
+  FCHK(hipDeviceSynchronize());
+  return TTSH_OK;
+}
+
+}  // extern "C"

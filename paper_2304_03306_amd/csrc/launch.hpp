@@ -25,6 +25,8 @@ struct MultiOps {
 };
 
 const SizeOps* size_ops(int N);
+// record `msg` as the calling thread's last error (ttsh_last_error) and return code
+int record_error(int code, const char* msg);
 const MultiOps* multi_ops(int prec, int bs);
 
 }  // namespace ttsh

@@ -6,6 +6,8 @@
 #include "launch.hpp"
 #include "step_multi.hpp"
 
+#include <algorithm>
+
 #if !defined(TTSH_PREC) || !defined(TTSH_BS)
 #error "define TTSH_PREC and TTSH_BS"
 #endif
@@ -25,25 +27,37 @@ using S = float;
 #endif
 constexpr int BS = TTSH_BS;
 
+// dynamic LDS of a launch: the largest tile footprint over the classes present
+template <class F>
+size_t lds_bytes(const MultiArgs& a, F of) {
+  size_t m = 0;
+  for (int q = 0; q < a.ncls; ++q) m = std::max(m, (size_t)of(a.c[q].N));
+  return m;
+}
+
 #if TTSH_PREC != 96
 hipError_t row(const MultiArgs& a, int gw, hipStream_t s) {
   const int grid = a.start[a.ncls];
+  const size_t lds = lds_bytes(a, row_smem_of<T, BS>);
+  if (lds == 0) return hipErrorInvalidValue;
   if (gw)
-    hipLaunchKernelGGL((row_multi<T, true, BS>), dim3(grid), dim3(BS), 0, s, a);
+    hipLaunchKernelGGL((row_multi<T, true, BS>), dim3(grid), dim3(BS), lds, s, a);
   else
-    hipLaunchKernelGGL((row_multi<T, false, BS>), dim3(grid), dim3(BS), 0, s, a);
+    hipLaunchKernelGGL((row_multi<T, false, BS>), dim3(grid), dim3(BS), lds, s, a);
   return hipGetLastError();
 }
 #endif
 
 hipError_t col(const MultiArgs& a, int gw, int mode, hipStream_t s) {
   const int grid = a.start[a.ncls];
+  const size_t lds = gw && mode != 1 ? lds_bytes(a, col_smem_of<T, BS, true>) : lds_bytes(a, col_smem_of<T, BS, false>);
+  if (lds == 0) return hipErrorInvalidValue;
   if (mode == 1)
-    hipLaunchKernelGGL((col_multi<T, S, false, 1, BS>), dim3(grid), dim3(BS), 0, s, a);
+    hipLaunchKernelGGL((col_multi<T, S, false, 1, BS>), dim3(grid), dim3(BS), lds, s, a);
   else if (gw)
-    hipLaunchKernelGGL((col_multi<T, S, true, 0, BS>), dim3(grid), dim3(BS), 0, s, a);
+    hipLaunchKernelGGL((col_multi<T, S, true, 0, BS>), dim3(grid), dim3(BS), lds, s, a);
   else
-    hipLaunchKernelGGL((col_multi<T, S, false, 0, BS>), dim3(grid), dim3(BS), 0, s, a);
+    hipLaunchKernelGGL((col_multi<T, S, false, 0, BS>), dim3(grid), dim3(BS), lds, s, a);
   return hipGetLastError();
 }
 

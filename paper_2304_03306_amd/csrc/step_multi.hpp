@@ -43,28 +43,30 @@ struct TileOf {
   static constexpr bool ok = BS % TT == 0 && R >= 1;
 };
 
+// LDS bytes of one tile of size N; the launch allocates the largest over the
+// size classes present (dynamic LDS), so that a context without the small
+// grids, whose padded tiles need the most LDS, keeps a higher occupancy.
 template <class T, int BS, int N>
 constexpr size_t row_smem_n() {
   if constexpr (TileOf<N, BS>::ok) return RowSmem<N, TileOf<N, BS>::R, T>::bytes;
   else return 0;
 }
-template <class T, int BS, int N>
+template <class T, int BS, bool GW, int N>
 constexpr size_t col_smem_n() {
-  if constexpr (TileOf<N, BS>::ok) return ColSmem<N, TileOf<N, BS>::R, T, true>::bytes;
+  if constexpr (TileOf<N, BS>::ok) return ColSmem<N, TileOf<N, BS>::R, T, GW>::bytes;
   else return 0;
 }
-constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 template <class T, int BS>
-constexpr size_t row_smem() {
-  return cmax(cmax(cmax(row_smem_n<T, BS, 64>(), row_smem_n<T, BS, 128>()),
-                   cmax(row_smem_n<T, BS, 256>(), row_smem_n<T, BS, 512>())),
-              row_smem_n<T, BS, 1024>());
+constexpr size_t row_smem_of(int N) {
+  return N == 64 ? row_smem_n<T, BS, 64>() : N == 128 ? row_smem_n<T, BS, 128>()
+       : N == 256 ? row_smem_n<T, BS, 256>() : N == 512 ? row_smem_n<T, BS, 512>()
+       : N == 1024 ? row_smem_n<T, BS, 1024>() : 0;
 }
-template <class T, int BS>
-constexpr size_t col_smem() {
-  return cmax(cmax(cmax(col_smem_n<T, BS, 64>(), col_smem_n<T, BS, 128>()),
-                   cmax(col_smem_n<T, BS, 256>(), col_smem_n<T, BS, 512>())),
-              col_smem_n<T, BS, 1024>());
+template <class T, int BS, bool GW>
+constexpr size_t col_smem_of(int N) {
+  return N == 64 ? col_smem_n<T, BS, GW, 64>() : N == 128 ? col_smem_n<T, BS, GW, 128>()
+       : N == 256 ? col_smem_n<T, BS, GW, 256>() : N == 512 ? col_smem_n<T, BS, GW, 512>()
+       : N == 1024 ? col_smem_n<T, BS, GW, 1024>() : 0;
 }
 
 // Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
@@ -94,7 +96,7 @@ __device__ __forceinline__ void row_go(const ClassArgs& d, const RowCoef<T>& c, 
 
 template <class T, bool GW, int BS>
 __global__ void __launch_bounds__(BS) row_multi(MultiArgs a) {
-  __shared__ __align__(16) unsigned char smem[row_smem<T, BS>()];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int ci = class_of(a, b);
   const ClassArgs& d = a.c[ci];
@@ -126,7 +128,7 @@ __device__ __forceinline__ void col_go(const ClassArgs& d, const LinCoef& lc, in
 
 template <class T, class S, bool GW, int MODE, int BS>
 __global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
-  __shared__ __align__(16) unsigned char smem[col_smem<T, BS>()];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int ci = class_of(a, b);
   const ClassArgs& d = a.c[ci];

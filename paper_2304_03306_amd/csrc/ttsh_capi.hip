@@ -68,6 +68,17 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+namespace ttsh {
+int record_error(int code, const char* msg) {
+  g_err = msg ? msg : "";
+  return code;
+}
+}  // namespace ttsh
+
+namespace {
+
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
@@ -114,6 +125,11 @@ struct ttsh_ctx {
   void* scr0 = nullptr;                  // FP64 complex N^2 of the largest N
   void* scr1 = nullptr;
   double* dnorm = nullptr;               // [n_inst][5]
+  void* pb0 = nullptr;                   // batched coarse-field spectra (grown on demand)
+  void* pb1 = nullptr;
+  size_t pb_cap = 0;                     // bytes of each
+  double* pnorm = nullptr;               // [pnorm_cap][2]
+  int pnorm_cap = 0;
   int graph_steps = 50;
   int bs = 0;       // workgroup size of the column pass in use
   int bs_row = 0;   // workgroup size of the row pass in use
@@ -311,6 +327,19 @@ int pack_into_state(ttsh_ctx* c, int inst, const void* add) {
   return TTSH_OK;
 }
 
+// FP64 twiddles for a grid size that may differ from the context's sizes
+int twiddles64(ttsh_ctx* c, int N, const void** out) {
+  auto it = c->tw64.find(N);
+  if (it == c->tw64.end()) {
+    void* t = nullptr;
+    int rc = make_twiddles(N, true, &t);
+    if (rc) return rc;
+    it = c->tw64.emplace(N, t).first;
+  }
+  *out = it->second;
+  return TTSH_OK;
+}
+
 // forward FP64 FFT of a real field pair v [2][N][N] (device) into scr0
 int field_to_spectrum(ttsh_ctx* c, int N, const double* v) {
   const int n = N * N;
@@ -346,6 +375,8 @@ void free_ctx(ttsh_ctx* c) {
   if (c->scr0) hipFree(c->scr0);
   if (c->scr1) hipFree(c->scr1);
   if (c->dnorm) hipFree(c->dnorm);
+  for (void* p : {c->pb0, c->pb1, (void*)c->pnorm})
+    if (p) hipFree(p);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
@@ -613,6 +644,126 @@ int ttsh_get_field(ttsh_ctx* c, int inst, double* v, double* omega, int where) {
     HIPCHK(hipGetLastError());
     if (where != TTSH_DEVICE)
       HIPCHK(hipMemcpyAsync(out, dst, sizeof(double) * (what == 0 ? 2 : 1) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return TTSH_OK;
+}
+
+int ttsh_get_field_coarse(ttsh_ctx* c, int inst, int Nc, float* out, int64_t pix_stride) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!out) return fail(TTSH_EINVAL, "null output");
+  if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
+  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024");
+  if (Nc > max_N(c)) return fail(TTSH_EINVAL, "Nc larger than the context's largest grid");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, n = Nc * Nc;
+  // compact FP64 spectrum at Nc in scr1, full spectrum in scr0 (both hold
+  // max_N^2 complex values, enough for Nc <= max_N)
+  const size_t ncomp = (size_t)2 * (Nc / 4 + 1) * (Nc / 2 + 2);
+  C2<double>* comp = (C2<double>*)c->scr1;
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_resample<float>, dim3(nblk(ncomp)), dim3(kB), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), N, comp, Nc);
+  else
+    hipLaunchKernelGGL(k_resample<double>, dim3(nblk(ncomp)), dim3(kB), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), N, comp, Nc);
+  hipLaunchKernelGGL(k_state_to_full<double>, dim3(nblk(n)), dim3(kB), 0, c->stream, comp,
+                     (C2<double>*)c->scr0, Nc, 2.0 * M_PI / c->L[inst], 0);
+  HIPCHK(hipGetLastError());
+  const void* tw = nullptr;
+  if ((rc = twiddles64(c, Nc, &tw))) return rc;
+  HIPCHK(size_ops(Nc)->fft2(c->scr0, 1, +1, 1, tw, c->stream));
+  hipLaunchKernelGGL(k_unpack_xy_strided, dim3(nblk(n)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr0,
+                     out, n, (long long)pix_stride);
+  HIPCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+int ttsh_set_field_coarse(ttsh_ctx* c, int inst, int Nc, const float* v, int64_t pix_stride) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!v) return fail(TTSH_EINVAL, "null input");
+  if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
+  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024");
+  if (Nc > max_N(c)) return fail(TTSH_EINVAL, "Nc larger than the context's largest grid");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, n = Nc * Nc, Mc = Nc / 4;
+  const void* tw = nullptr;
+  if ((rc = twiddles64(c, Nc, &tw))) return rc;
+  // spectrum at Nc (scr0) -> projected compact FP64 state at Nc (scr1) ->
+  // resampled to N (scr0) -> stored precision
+  hipLaunchKernelGGL(k_pack_xy_strided, dim3(nblk(n)), dim3(kB), 0, c->stream, v, (long long)pix_stride,
+                     (C2<double>*)c->scr0, n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(size_ops(Nc)->fft2(c->scr0, 1, -1, 1, tw, c->stream));
+  const size_t nc = (size_t)(Mc + 1) * (2 * Mc + 2);
+  hipLaunchKernelGGL(k_pack_state<double>, dim3(nblk(nc)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr0,
+                     (const C2<double>*)nullptr, (C2<double>*)c->scr1, Nc);
+  const size_t ns = k.sSt();
+  hipLaunchKernelGGL(k_resample<double>, dim3(nblk(ns)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr1, Nc,
+                     (C2<double>*)c->scr0, N);
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_convert_c<float>, dim3(nblk(ns)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr0,
+                       at<C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), ns);
+  else
+    hipLaunchKernelGGL(k_convert_c<double>, dim3(nblk(ns)), dim3(kB), 0, c->stream, (const C2<double>*)c->scr0,
+                       at<C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), ns);
+  HIPCHK(hipGetLastError());
+  return refresh_x(c, inst);
+}
+
+int ttsh_project_coarse(ttsh_ctx* c, int N, float* v, int64_t pix_stride, int batch, double* norms) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (!v) return fail(TTSH_EINVAL, "null field");
+  if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
+  if (batch < 1) return fail(TTSH_EINVAL, "batch must be >= 1");
+  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024");
+  const size_t n = (size_t)batch * N * N;
+  if (n > (size_t)INT32_MAX) return fail(TTSH_EINVAL, "batch too large");
+  const size_t bytes = n * sizeof(C2<double>);
+  if (bytes > c->pb_cap) {
+    for (void** p : {&c->pb0, &c->pb1})
+      if (*p) {
+        hipFree(*p);
+        *p = nullptr;
+      }
+    c->pb_cap = 0;
+    if (hipMalloc(&c->pb0, bytes) != hipSuccess || hipMalloc(&c->pb1, bytes) != hipSuccess)
+      return fail(TTSH_ENOMEM, "projection buffers");
+    c->pb_cap = bytes;
+  }
+  if (norms && batch > c->pnorm_cap) {
+    if (c->pnorm) hipFree(c->pnorm);
+    c->pnorm = nullptr;
+    c->pnorm_cap = 0;
+    if (hipMalloc((void**)&c->pnorm, sizeof(double) * 2 * batch) != hipSuccess)
+      return fail(TTSH_ENOMEM, "norm buffer");
+    c->pnorm_cap = batch;
+  }
+  int rc;
+  const void* tw = nullptr;
+  if ((rc = twiddles64(c, N, &tw))) return rc;
+  hipLaunchKernelGGL(k_pack_xy_strided, dim3(nblk(n)), dim3(kB), 0, c->stream, (const float*)v,
+                     (long long)pix_stride, (C2<double>*)c->pb0, (int)n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(size_ops(N)->fft2(c->pb0, batch, -1, 1, tw, c->stream));
+  hipLaunchKernelGGL(k_project_full, dim3(nblk(n)), dim3(kB), 0, c->stream, (const C2<double>*)c->pb0,
+                     (C2<double>*)c->pb1, N, (int)n);
+  HIPCHK(hipGetLastError());
+  if (norms) {
+    hipLaunchKernelGGL(k_full_norms, dim3(batch), dim3(256), 0, c->stream, (const C2<double>*)c->pb1, N,
+                       c->pnorm);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(size_ops(N)->fft2(c->pb1, batch, +1, 1, tw, c->stream));
+  hipLaunchKernelGGL(k_unpack_xy_strided, dim3(nblk(n)), dim3(kB), 0, c->stream, (const C2<double>*)c->pb1, v,
+                     (int)n, (long long)pix_stride);
+  HIPCHK(hipGetLastError());
+  if (norms) {
+    HIPCHK(hipMemcpyAsync(norms, c->pnorm, sizeof(double) * 2 * batch, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   return TTSH_OK;

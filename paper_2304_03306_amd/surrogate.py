@@ -1,0 +1,313 @@
+"""Coarse-field surrogate of the solver: training data from solver
+trajectories, training of the Fourier neural operator (libttsh's fno_* entry
+points), and rollout with acceptance checks, solver fallback and the solver
+as the judge of its error.
+
+Every arithmetic step runs in the HIP library: the solver (ttsh_*), the
+coarsening and its inverse (ttsh_get_field_coarse / ttsh_set_field_coarse),
+the projection of the network's output (ttsh_project_coarse), the network
+(fno_*) and the per-sample errors (fno_sample_errors).  This module only
+orders the calls, moves buffers and keeps host-side bookkeeping (sample
+indices, learning-rate schedule, acceptance decisions).
+
+Data layout on the device: snapshots D[t][i] of instance i at surrogate step
+t, each a channels-last float32 Nc x Nc x 3 field (v_x, v_y, K), where K is
+the instance's mask sampled on the coarse grid.  One surrogate step advances
+`every` solver steps.  The network predicts the change of (v_x, v_y) over one
+surrogate step (residual output), and the rollout projects each prediction
+onto the coarse solver's state space (1/2-rule cutoff, divergence-free) as a
+hard constraint.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import fno as F
+from . import ttsh as T
+from .workloads import Instance, uniform_field
+
+
+@dataclasses.dataclass
+class SurrogateConfig:
+    Nc: int = 128          # coarse grid
+    every: int = 20        # solver steps per surrogate step
+    width: int = 32
+    modes: int = 16
+    layers: int = 4
+    hidden: int = 128
+    batch: int = 256
+    lr: float = 1e-3
+    cin: int = 3           # v_x, v_y, K
+    cout: int = 2
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the surrogate runs on the GPU only")
+    return torch
+
+
+def coarse_masks(instances: Sequence[Instance], Nc: int, params) -> np.ndarray:
+    """Masks of the instances sampled on the coarse grid (same box, same
+    circles and width), computed by the library; float32 [I][Nc][Nc]."""
+    s = T.Solver([Nc] * len(instances), [inst.L for inst in instances], params, T.TTSH_FP32)
+    try:
+        out = np.empty((len(instances), Nc, Nc), dtype=np.float32)
+        for i, inst in enumerate(instances):
+            s.mask_tanh(i, inst.centers, inst.radii, inst.xi)
+            out[i] = s.mask(i)
+        return out
+    finally:
+        s.close()
+
+
+def new_solver(instances: Sequence[Instance], params, precision=T.TTSH_FP32, seed_fields=True) -> T.Solver:
+    """A solver context over the instances, masks set, started from each
+    instance's seeded initial field."""
+    s = T.Solver([i.N for i in instances], [i.L for i in instances], params, precision)
+    for q, inst in enumerate(instances):
+        s.mask_tanh(q, inst.centers, inst.radii, inst.xi)
+        if seed_fields:
+            s.set_field(q, uniform_field(inst.seed, inst.N, 0.01, precision))
+    return s
+
+
+def snapshot(solver: T.Solver, n_inst: int, Nc: int, out) -> None:
+    """Write every instance's coarse velocity into channels 0..1 of out
+    [I][Nc][Nc][cin] (float32 device tensor)."""
+    cin = out.shape[-1]
+    for i in range(n_inst):
+        solver.field_coarse(i, Nc, out[i], cin)
+
+
+def collect(solver: T.Solver, masks: np.ndarray, n_snap: int, every: int, Nc: int, transient: int = 0,
+            log=None):
+    """Run the solver and record n_snap snapshots, `every` steps apart, after
+    `transient` steps.  Returns a device tensor D [n_snap][I][Nc][Nc][3]."""
+    torch = _torch()
+    I = masks.shape[0]
+    D = torch.empty((n_snap, I, Nc, Nc, 3), dtype=torch.float32, device="cuda")
+    Kd = torch.from_numpy(masks).cuda()
+    if transient:
+        solver.step(transient)
+    t0 = time.time()
+    for t in range(n_snap):
+        D[t, :, :, :, 2] = Kd
+        snapshot(solver, I, Nc, D[t])
+        if t + 1 < n_snap:
+            solver.step(every)
+        if log and (t + 1) % 100 == 0:
+            solver.sync()
+            log(f"collect {t + 1}/{n_snap} snapshots, {time.time() - t0:.1f} s")
+    solver.sync()
+    return D
+
+
+def split_by_radius(n_radii: int, hold_every: int = 4):
+    """Train/test split of the radius sweep by radius: every hold_every-th
+    radius (both ramps) is held out.  Returns (train_ids, test_ids)."""
+    test = [2 * j + r for j in range(n_radii) if j % hold_every == hold_every - 1 for r in (0, 1)]
+    train = [i for i in range(2 * n_radii) if i not in test]
+    return train, test
+
+
+class Trainer:
+    """Adam training of one network on snapshot pairs (D[t][i], D[t+1][i])."""
+
+    def __init__(self, cfg: SurrogateConfig, seed: int = 0):
+        torch = _torch()
+        self.cfg = cfg
+        self.net = F.FNO(width=cfg.width, modes=cfg.modes, layers=cfg.layers, cin=cfg.cin, cout=cfg.cout,
+                         hidden=cfg.hidden, H=cfg.Nc, W=cfg.Nc, max_batch=cfg.batch, seed=seed)
+        n = cfg.Nc
+        self.xb = torch.empty((cfg.batch, n, n, cfg.cin), dtype=torch.float32, device="cuda")
+        self.tb = torch.empty((cfg.batch, n, n, cfg.cout), dtype=torch.float32, device="cuda")
+        self.yb = torch.empty_like(self.tb)
+        self.step_count = 0
+
+    def pairs(self, D, ids: Sequence[int]) -> np.ndarray:
+        """Flat sample indices (into D viewed as [n_snap * I]) of every input
+        whose successor exists."""
+        n_snap, I = D.shape[0], D.shape[1]
+        return np.array([t * I + i for t in range(n_snap - 1) for i in ids], dtype=np.int64)
+
+    def batch_step(self, D, idx: np.ndarray, lr: float) -> float:
+        c = self.cfg
+        I = D.shape[1]
+        npix = c.Nc * c.Nc
+        B = len(idx)
+        self.net.gather(self.xb, c.cin, D, 3, c.cin, npix, idx)
+        self.net.gather(self.tb, c.cout, D, 3, c.cout, npix, idx + I)
+        self.net.forward_ex(self.xb, self.yb, c.cout, True, B, train=True)
+        loss = self.net.loss(self.yb[:B], self.tb[:B])
+        self.net.backward(B)
+        self.net.adam_step(lr)
+        self.step_count += 1
+        return loss
+
+    def train(self, D, ids: Sequence[int], epochs: int, seed: int = 0, log=None, time_limit: float = None):
+        """Cosine-decayed Adam over `epochs` passes of the shuffled pairs.
+        Returns the list of (epoch, mean loss, seconds)."""
+        c = self.cfg
+        pairs = self.pairs(D, ids)
+        rng = np.random.default_rng(seed)
+        nb = max(1, len(pairs) // c.batch)
+        total = epochs * nb
+        hist = []
+        t0 = time.time()
+        k = 0
+        for ep in range(epochs):
+            perm = rng.permutation(pairs)
+            acc = 0.0
+            for b in range(nb):
+                lr = 0.5 * c.lr * (1.0 + math.cos(math.pi * k / total))
+                acc += self.batch_step(D, perm[b * c.batch:(b + 1) * c.batch], lr)
+                k += 1
+            hist.append((ep, acc / nb, time.time() - t0))
+            if log:
+                log(f"epoch {ep} loss {acc / nb:.4e} ({time.time() - t0:.1f} s)")
+            if time_limit is not None and time.time() - t0 > time_limit:
+                break
+        return hist
+
+    def eval_one_step(self, D, ids: Sequence[int], project: Optional[T.Solver] = None):
+        """Mean relative L2 error of one surrogate step over the pairs of
+        `ids` (full-field error of the predicted velocity), with and without
+        projecting the prediction, and of persistence (v(t + 1) = v(t))."""
+        torch = _torch()
+        c = self.cfg
+        pairs = self.pairs(D, ids)
+        I = D.shape[1]
+        npix = c.Nc * c.Nc
+        errs, errs_p, pers = [], [], []
+        xb = torch.empty((c.batch, c.Nc, c.Nc, c.cin), dtype=torch.float32, device="cuda")
+        for b0 in range(0, len(pairs), c.batch):
+            idx = pairs[b0:b0 + c.batch]
+            B = len(idx)
+            self.net.gather(xb, c.cin, D, 3, c.cin, npix, idx)
+            self.net.gather(self.tb, c.cout, D, 3, c.cout, npix, idx + I)
+            pers.append(F.fno_sample_errors(xb, c.cin, self.tb, c.cout, c.cout, npix, B))
+            self.net.forward_ex(xb, self.yb, c.cout, True, B)
+            errs.append(F.fno_sample_errors(self.yb, c.cout, self.tb, c.cout, c.cout, npix, B))
+            if project is not None:
+                self.net.forward_ex(xb, xb, c.cin, True, B)
+                project.project_coarse(c.Nc, xb, c.cin, B)
+                errs_p.append(F.fno_sample_errors(xb, c.cin, self.tb, c.cout, c.cout, npix, B))
+        out = dict(network=float(np.mean(np.concatenate(errs))), persistence=float(np.mean(np.concatenate(pers))))
+        if errs_p:
+            out["network_projected"] = float(np.mean(np.concatenate(errs_p)))
+        return out
+
+
+@dataclasses.dataclass
+class RolloutResult:
+    err: np.ndarray            # [steps][I] rel-L2 vs the judge (NaN where no judge)
+    fallback_step: np.ndarray  # [I] surrogate step at which the instance went to the solver (-1: never)
+    reason: List[str]
+    seconds: float             # wall time of the rollout (surrogate + checks + fallback)
+    seconds_surrogate: float   # of which network + projection + acceptance
+
+
+class Rollout:
+    """Advance coarse fields with the network; hand an instance back to the
+    native-grid solver when its prediction fails an acceptance test.
+
+    Acceptance, per instance and surrogate step: every value finite, and the
+    energy sum |v|^2 and enstrophy sum |w|^2 of the projected prediction
+    within a factor `envelope` of the previous step's.  Every `check_every`
+    steps the solver checks the network locally: the current coarse fields
+    are put on the native grids, advanced `every` solver steps and coarsened;
+    if the network's prediction from the same fields is further than `tol`
+    (relative L2) from that, the instance fails too.  A failed instance
+    continues with the solver, on its native grid, from its last accepted
+    coarse field (the field the failed step started from).  The context
+    `checker` (all instances) serves the checks and the projection; the
+    solver runs of failed instances get contexts of their own."""
+
+    def __init__(self, net: F.FNO, cfg: SurrogateConfig, instances: Sequence[Instance], params,
+                 checker: T.Solver, envelope: float = 1.5, check_every: int = 25, tol: float = 0.1):
+        self.net, self.cfg, self.inst, self.params = net, cfg, list(instances), params
+        self.checker = checker
+        self.envelope, self.check_every, self.tol = envelope, check_every, tol
+
+    def run(self, x0, steps: int, judge=None, log=None) -> RolloutResult:
+        """x0: device [I][Nc][Nc][3] (v_x, v_y, K) at surrogate step 0.
+        judge(s) -> device [I][Nc][Nc][>=2] solver fields at step s, or None."""
+        torch = _torch()
+        c = self.cfg
+        I = x0.shape[0]
+        npix = c.Nc * c.Nc
+        x = x0.clone()
+        x_prev = torch.empty_like(x)
+        ref = torch.empty_like(x)
+        err = np.full((steps, I), np.nan)
+        fb_step = np.full(I, -1)
+        reason = [""] * I
+        active = np.ones(I, dtype=bool)
+        solvers = []  # (context, instance ids) of instances on the solver
+        prev = None
+        t_sur = 0.0
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for s in range(steps):
+            check = self.check_every > 0 and s % self.check_every == 0 and active.any()
+            x_prev.copy_(x)
+            if check:
+                ids = np.flatnonzero(active)
+                for i in ids:
+                    self.checker.set_field_coarse(int(i), c.Nc, x[i], 3)
+                self.checker.step(c.every)
+                for i in ids:
+                    self.checker.field_coarse(int(i), c.Nc, ref[i], 3)
+            ts = time.time()
+            self.net.forward_ex(x, x, 3, True, I)
+            nrm = self.checker.project_coarse(c.Nc, x, 3, I, norms=True)
+            t_sur += time.time() - ts
+            bad = ~np.isfinite(nrm).all(axis=1)
+            fail = active & bad
+            if prev is not None:
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    ratio = nrm / prev
+                out_env = ~((ratio <= self.envelope) & (ratio >= 1.0 / self.envelope)).all(axis=1)
+                fail |= active & ~bad & out_env
+            for i in np.flatnonzero(fail):
+                reason[i] = "non-finite" if bad[i] else "energy/enstrophy envelope"
+            if check:
+                e_loc = F.fno_sample_errors(x, 3, ref, 3, 2, npix, I)
+                loc = active & ~fail & ~(e_loc <= self.tol)
+                for i in np.flatnonzero(loc):
+                    reason[i] = f"local check {e_loc[i]:.3g} > {self.tol}"
+                fail |= loc
+            if fail.any():
+                ids = [int(i) for i in np.flatnonzero(fail)]
+                fb_step[ids] = s
+                active[ids] = False
+                sol = new_solver([self.inst[i] for i in ids], self.params, seed_fields=False)
+                for q, i in enumerate(ids):
+                    sol.set_field_coarse(q, c.Nc, x_prev[i], 3)
+                solvers.append((sol, ids))
+                if log:
+                    log(f"step {s}: instances {ids} -> solver ({reason[ids[0]]})")
+            for sol, ids in solvers:
+                sol.step(c.every)
+                for q, i in enumerate(ids):
+                    sol.field_coarse(q, c.Nc, x[i], 3)
+            prev = nrm if prev is None else np.where(active[:, None], nrm, prev)
+            if judge is not None:
+                tgt = judge(s + 1)
+                if tgt is not None:
+                    err[s] = F.fno_sample_errors(x, 3, tgt, tgt.shape[-1], 2, npix, I)
+            if log and (s + 1) % 50 == 0:
+                log(f"rollout step {s + 1}/{steps}: mean err {np.nanmean(err[s]):.3e}, "
+                    f"{int(active.sum())} on the network")
+        torch.cuda.synchronize()
+        secs = time.time() - t0
+        for sol, _ in solvers:
+            sol.close()
+        return RolloutResult(err, fb_step, reason, secs, t_sur)

@@ -55,6 +55,9 @@ def lib() -> ctypes.CDLL:
             "ttsh_mask_from_binary": [vp, i32, dp, i32],
             "ttsh_set_field": [vp, i32, dp, i32],
             "ttsh_get_field": [vp, i32, dp, dp, i32],
+            "ttsh_get_field_coarse": [vp, i32, i32, dp, i64],
+            "ttsh_set_field_coarse": [vp, i32, i32, dp, i64],
+            "ttsh_project_coarse": [vp, i32, dp, i64, i32, dp],
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
             "ttsh_step": [vp, i64],
@@ -160,6 +163,35 @@ def ttsh_get_field(ctx, inst, v_out, omega_out=None):
         raise ValueError("v and omega must both be host or both be device buffers")
     _check(lib().ttsh_get_field(ctx, inst, p, q, w))
     return v_out, omega_out
+
+
+def ttsh_get_field_coarse(ctx, inst, Nc, out, pix_stride=2):
+    """out: float32 GPU tensor holding at least Nc*Nc*pix_stride values;
+    component c of node (i, j) lands at flat index (i*Nc + j)*pix_stride + c."""
+    if not out.is_cuda or out.dtype.itemsize != 4:
+        raise ValueError("out must be a float32 GPU tensor")
+    if out.numel() < (Nc * Nc - 1) * pix_stride + 2:
+        raise ValueError("out too small")
+    return _check(lib().ttsh_get_field_coarse(ctx, int(inst), int(Nc), ctypes.c_void_p(out.data_ptr()),
+                                              int(pix_stride)))
+
+
+def _dev_addr(x):
+    return ctypes.c_void_p(x if isinstance(x, int) else x.data_ptr())
+
+
+def ttsh_set_field_coarse(ctx, inst, Nc, v, pix_stride=2):
+    """v: float32 GPU tensor (or device address) laid out as for
+    ttsh_get_field_coarse."""
+    return _check(lib().ttsh_set_field_coarse(ctx, int(inst), int(Nc), _dev_addr(v), int(pix_stride)))
+
+
+def ttsh_project_coarse(ctx, N, v, pix_stride, batch, norms=False):
+    """Project `batch` float32 fields in place; returns [batch][2] norms if asked."""
+    out = np.empty((batch, 2), dtype=np.float64) if norms else None
+    _check(lib().ttsh_project_coarse(ctx, int(N), _dev_addr(v), int(pix_stride), int(batch),
+                                     out.ctypes.data_as(ctypes.c_void_p) if norms else None))
+    return out
 
 
 def ttsh_set_state(ctx, inst, vhat):
@@ -278,6 +310,15 @@ class Solver:
         w = np.empty((n, n)) if omega else None
         ttsh_get_field(self.ctx, inst, v, w)
         return (v, w) if omega else v
+
+    def field_coarse(self, inst, Nc, out, pix_stride=2):
+        ttsh_get_field_coarse(self.ctx, inst, Nc, out, pix_stride)
+
+    def set_field_coarse(self, inst, Nc, v, pix_stride=2):
+        ttsh_set_field_coarse(self.ctx, inst, Nc, v, pix_stride)
+
+    def project_coarse(self, N, v, pix_stride, batch, norms=False):
+        return ttsh_project_coarse(self.ctx, N, v, pix_stride, batch, norms)
 
     def state(self, inst):
         M = self.N[inst] // 4

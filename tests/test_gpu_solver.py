@@ -275,3 +275,88 @@ def test_block_sizes_agree_and_tuner_restores_state(gpu):
     for bs in (64, 128):
         for a, b in zip(out[bs], out[256]):
             assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+
+
+def test_reseed_matches_oracle(gpu):
+    """Continuation: all destinations take resample(source) + P DFT(noise),
+    sources read before any destination is written (a swap included)."""
+    say("reseed")
+    p = O.workload_params()
+    Ns, Ls = [128, 256, 128, 64], [64.0, 128.0, 64.0, 32.0]
+    s = gpu.Solver(Ns, Ls, p, 64)
+    for i, (N, L) in enumerate(zip(Ns, Ls)):
+        s.mask_tanh(i, [(0.0, 0.0)], [L / 4], 0.5)
+        s.set_field(i, W.uniform_field(50 + i, N, 0.3))
+    s.step(5)
+    s.sync()
+    before = [O.from_compact(s.state(i), N) for i, N in enumerate(Ns)]
+    dst, src = [0, 1, 2, 3], [1, 0, 3, 2]
+    noise = [W.uniform_field(60 + q, Ns[d], 1e-3) for q, d in enumerate(dst)]
+    s.reseed(dst, src, np.concatenate([n.ravel() for n in noise]))
+    for q, (d, sr) in enumerate(zip(dst, src)):
+        want = O.resample(before[sr], Ns[d]) + O.project_field(noise[q], Ls[d])
+        got = O.from_compact(s.state(d), Ns[d])
+        assert np.abs(got - want).max() < 1e-12 * np.abs(want).max(), (d, sr)
+
+
+# ---- coarse fields (surrogate data path) ------------------------------------------
+@pytest.mark.parametrize("N,Nc", [(256, 128), (128, 128), (512, 64)])
+def test_coarse_field_matches_oracle_resample(gpu, N, Nc):
+    """get_field_coarse = field(resample(state, Nc)); set_field_coarse puts
+    back resample(P DFT(coarse field), N); FP64 state, float32 fields."""
+    import torch
+    say("coarse field", N, Nc)
+    p = O.workload_params()
+    L = 64.0
+    s = gpu.Solver([N], [L], p, 64)
+    s.mask_tanh(0, [(0.0, 0.0)], [L / 4], 0.5)
+    s.set_field(0, W.uniform_field(70, N, 0.3))
+    s.step(3)
+    s.sync()
+    vh = O.from_compact(s.state(0), N)
+    want = O.field(O.resample(vh, Nc))
+    buf = torch.zeros(Nc * Nc * 3, dtype=torch.float32, device="cuda")
+    s.field_coarse(0, Nc, buf, 3)
+    got = buf.cpu().numpy().astype(np.float64).reshape(Nc, Nc, 3)
+    assert np.all(got[..., 2] == 0.0)  # the third channel is not touched
+    got = np.moveaxis(got[..., :2], -1, 0)
+    assert np.abs(got - want).max() <= 2e-6 * np.abs(want).max()
+    # back onto the native grid
+    s.set_field_coarse(0, Nc, buf, 3)
+    s.sync()
+    back = O.from_compact(s.state(0), N)
+    c32 = got.astype(np.float32).astype(np.float64)
+    ref = O.resample(O.project_field(c32, L), N)
+    assert np.abs(back - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the field is already in the coarse state space: a round trip returns it
+    s.field_coarse(0, Nc, buf, 3)
+    again = np.moveaxis(buf.cpu().numpy().astype(np.float64).reshape(Nc, Nc, 3)[..., :2], -1, 0)
+    assert np.abs(again - c32).max() <= 2e-6 * np.abs(c32).max()
+
+
+def test_project_coarse_matches_oracle(gpu):
+    """Batched in-place projection of channels-last float32 fields equals
+    the oracle's cut + Leray projection; the norms equal the sums of |v|^2 and
+    of the integer-mode vorticity squared."""
+    import torch
+    say("project coarse", 128, "batch 3")
+    N, B, ch = 128, 3, 3
+    p = O.workload_params()
+    s = gpu.Solver([N], [64.0], p, 32)
+    rng = np.random.default_rng(80)
+    x = rng.standard_normal((B, N, N, ch)).astype(np.float32)
+    dev = torch.from_numpy(x.copy()).cuda()
+    nrm = s.project_coarse(N, dev, ch, B, norms=True)
+    got = dev.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[..., 2], x[..., 2].astype(np.float64))
+    for b in range(B):
+        v = np.moveaxis(x[b, ..., :2].astype(np.float64), -1, 0)
+        # L = 2 pi makes the oracle's wavenumbers the integer modes
+        vh = O.project_field(v, 2 * np.pi)
+        want = O.field(vh)
+        g = np.moveaxis(got[b, ..., :2], -1, 0)
+        assert np.abs(g - want).max() <= 2e-6 * np.abs(want).max()
+        kx, ky, _, _ = O.grid(N, 2 * np.pi)
+        w = O.field(O.vorticity_hat(vh, kx, ky)[None])[0]
+        assert abs(nrm[b, 0] - np.sum(want ** 2)) <= 1e-9 * np.sum(want ** 2)
+        assert abs(nrm[b, 1] - np.sum(w ** 2)) <= 1e-9 * np.sum(w ** 2)

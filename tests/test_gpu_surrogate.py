@@ -1,0 +1,110 @@
+"""The surrogate end to end on the GPU: data from solver trajectories, a
+short training run of the network by the library's own forward/backward/Adam
+kernels, what the trained network gains over the method without it, and the
+rollout's acceptance checks and solver fallback.
+
+Instances: the six smallest radii of the radius sweep (R = 8 .. 19.6, both
+ramps, native grid 128^2, box L = 3.2 R), recorded from the seeded start
+every 20 solver steps, so the data hold the growth of the unstable band and
+the formation of the confined flow.  Radius j = 3 (both ramps) is held out."""
+import numpy as np
+import pytest
+
+from oracle import ttsh as O
+from paper_2304_03306_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N_RADII = 6
+N_SNAP = 100
+EVERY = 20
+HELD_OUT = [6, 7]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def data(gpu):
+    from paper_2304_03306_amd import surrogate as S
+    say("surrogate data", N_RADII, "radii x 2 ramps,", N_SNAP, "snapshots every", EVERY)
+    inst = W.radius_sweep().instances[:2 * N_RADII]
+    assert all(i.N == 128 for i in inst)
+    p = O.workload_params()
+    masks = S.coarse_masks(inst, 128, p)
+    solver = S.new_solver(inst, p)
+    D = S.collect(solver, masks, N_SNAP, EVERY, 128)
+    return dict(inst=inst, p=p, masks=masks, solver=solver, D=D)
+
+
+def test_collected_snapshots_are_the_solver_trajectory(data, gpu):
+    """Snapshot t of instance i is the solver's field after t*EVERY steps
+    (a fresh run of the same instance reproduces it bit for bit), and channel
+    2 is the coarse mask."""
+    import torch
+    from paper_2304_03306_amd import surrogate as S
+    say("surrogate snapshots vs fresh run")
+    D = data["D"]
+    assert torch.equal(D[5, :, :, :, 2].cpu(), torch.from_numpy(data["masks"]))
+    s = S.new_solver(data["inst"][2:3], data["p"])
+    s.step(5 * EVERY)
+    buf = torch.zeros((128, 128, 3), dtype=torch.float32, device="cuda")
+    s.field_coarse(0, 128, buf, 3)
+    assert torch.equal(buf[..., :2], D[5, 2, :, :, :2])
+
+
+@pytest.fixture(scope="module")
+def trained(data, gpu):
+    from paper_2304_03306_amd import surrogate as S
+    say("surrogate training (time-limited)")
+    cfg = S.SurrogateConfig(batch=64, lr=2e-3)
+    tr = S.Trainer(cfg, seed=0)
+    train_ids = [i for i in range(2 * N_RADII) if i not in HELD_OUT]
+    hist = tr.train(data["D"], train_ids, epochs=40, seed=1, log=lambda m: print(m, flush=True),
+                    time_limit=90.0)
+    return tr, hist
+
+
+def test_trained_network_beats_persistence(data, trained):
+    """What the trained network gains: on held-out radii its one-step
+    prediction (projected) is at least twice as close to the solver as the
+    field left unchanged (persistence), and training lowered the loss."""
+    from paper_2304_03306_amd import surrogate as S
+    tr, hist = trained
+    assert hist[-1][1] < 0.5 * hist[0][1], hist
+    ev = tr.eval_one_step(data["D"], HELD_OUT, project=data["solver"])
+    print("held-out one-step errors", ev, flush=True)
+    assert np.isfinite(ev["network_projected"])
+    assert ev["network_projected"] <= ev["network"] * (1 + 1e-3)
+    assert ev["network_projected"] < 0.5 * ev["persistence"], ev
+
+
+def test_rollout_is_judged_and_falls_back(data, trained):
+    """A rollout over all instances: per-step errors against the recorded
+    solver trajectory are finite; with corrupted weights every instance fails
+    acceptance at the first step and continues on the solver, so its error
+    stays that of the coarse restart (small)."""
+    import torch
+    from paper_2304_03306_amd import surrogate as S
+    say("surrogate rollout + fallback")
+    tr, _ = trained
+    D = data["D"]
+    t0, steps = 40, 20
+    judge = lambda s: D[t0 + s] if t0 + s < D.shape[0] else None
+    ro = S.Rollout(tr.net, tr.cfg, data["inst"], data["p"], data["solver"], check_every=10, tol=0.2)
+    res = ro.run(D[t0], steps, judge=judge, log=lambda m: print(m, flush=True))
+    print("rollout mean err per step", np.nanmean(res.err, axis=1), "fallbacks", res.fallback_step, flush=True)
+    assert np.isfinite(res.err).all()
+    # corrupted weights -> non-finite output -> all instances on the solver
+    good = tr.net.params()
+    bad = good.copy()
+    bad[: bad.size // 2] = np.nan
+    tr.net.set_params(bad)
+    try:
+        res2 = ro.run(D[t0], 5, judge=judge)
+    finally:
+        tr.net.set_params(good)
+    assert (res2.fallback_step == 0).all(), res2.fallback_step
+    assert all(r == "non-finite" for r in res2.reason)
+    assert np.isfinite(res2.err).all() and res2.err.max() < 0.05, res2.err
