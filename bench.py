@@ -164,11 +164,10 @@ def main():
         sys.exit(2)
 
     import torch
-    from oracle import ttsh as O
     from paper_2304_03306_amd import ttsh as T, workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    params = O.workload_params()
+    params = W.workload_coefficients()
     wl = W.radius_sweep() if args.workload == "sweep" else W.dumbbells()
     log(f"[bench] workload {wl.name}: {len(wl.instances)} instances, {wl.points} points/step")
     state_bytes = 8 if args.precision == 32 else 16

@@ -11,6 +11,7 @@
 // exact GELU, GELU' and the saving of pre-activations into its epilogue.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <random>
 #include <string>
@@ -49,6 +50,7 @@ __device__ inline float gelu_grad(float x) {
 struct Op {
   const bf16* p;
   long long s1, s2, r, c;  // batch strides (b1, b2), row stride, column stride
+  int kvec;                // set by the launcher: runs of 4 along k are contiguous and 8-byte aligned
 };
 
 struct GemmArgs {
@@ -66,13 +68,15 @@ struct GemmArgs {
   bf16* pre_out;           // act 1: store the pre-activation (same strides as C)
   const float* skip;       // float C only: C[i][j] += skip[i * skip_r + j] (after everything else)
   long long skip_r;
+  int vecC;                // set by the launcher: rows of C hold aligned runs of 4 contiguous columns
 };
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline short4_t load_frag(const bf16* base, long long r, long long c, int row, int k0,
-                                     int nrow, int K) {
+                                     int nrow, int K, int kvec) {
+  if (kvec && row < nrow && k0 + 3 < K) return *(const short4_t*)(base + (long long)row * r + k0);
   short4_t v;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -83,8 +87,12 @@ __device__ inline short4_t load_frag(const bf16* base, long long r, long long c,
 }
 
 // One wavefront computes one 32 x 32 tile of C as 2 x 2 MFMA 16 x 16 blocks.
-// MFMA 16x16x16 operand layout (lane l): A row l%16, k = 4(l/16)..+3; B column
-// l%16, same k; result column l%16, rows 4(l/16)..+3.
+// MFMA 16x16x16 operand layout (lane l): first operand row l%16, k =
+// 4(l/16)..+3; second operand column l%16, same k; result column l%16, rows
+// 4(l/16)..+3.  The product is formed transposed (C^T = B^T A^T: the B
+// fragment goes first), so that lane l ends up with row l%16 of the block and
+// four consecutive columns 4(l/16)..+3: one vector store per block when C's
+// columns are contiguous.
 __device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, int b1, int b2,
                                  int i0, int j0, int lane, float4_t (&acc)[2][2]) {
   const bf16* pa = A.p + b1 * A.s1 + b2 * A.s2;
@@ -94,15 +102,15 @@ __device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, 
     short4_t a[2], b[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      a[s] = load_frag(pa, A.r, A.c, i0 + 16 * s + rl, k0 + kq, M, K);
+      a[s] = load_frag(pa, A.r, A.c, i0 + 16 * s + rl, k0 + kq, M, K, A.kvec);
       // B[k][j]: treat as rows j with stride B.c, columns k with stride B.r
-      b[s] = load_frag(pb, B.c, B.r, j0 + 16 * s + rl, k0 + kq, N, K);
+      b[s] = load_frag(pb, B.c, B.r, j0 + 16 * s + rl, k0 + kq, N, K, B.kvec);
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int t = 0; t < 2; ++t)
-        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], b[t], acc[s][t], 0, 0, 0);
+        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[t], a[s], acc[s][t], 0, 0, 0);
   }
 }
 
@@ -130,28 +138,51 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int 
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t) {
+      const int i = i0 + 16 * s + (lane & 15);
+      const int jb = j0 + 16 * t + (lane >> 4) * 4;
+      if (i >= g.M || jb >= g.N) continue;
+      const long long ob = cbase + (long long)i * g.rC + (long long)jb * g.cC;
+      float v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = i0 + 16 * s + (lane >> 4) * 4 + q;
-        const int j = j0 + 16 * t + (lane & 15);
-        if (i >= g.M || j >= g.N) continue;
-        const long long off = cbase + (long long)i * g.rC + (long long)j * g.cC;
-        float v = g.alpha * acc[s][t][q] + (g.K2 > 0 ? g.alpha2 * acc2[s][t][q] : 0.f);
-        if (g.accumulate) v += ((float*)g.C)[off];
-        if (g.bias) v += g.bias[j];
+      for (int e = 0; e < 4; ++e) {
+        const int j = jb + e;
+        v[e] = 0.f;
+        if (j >= g.N) continue;
+        const long long off = ob + (long long)e * g.cC;
+        float x = g.alpha * acc[s][t][e] + (g.K2 > 0 ? g.alpha2 * acc2[s][t][e] : 0.f);
+        if (g.accumulate) x += ((float*)g.C)[off];
+        if (g.bias) x += g.bias[j];
         if (g.act == 1) {
-          if (g.pre_out) g.pre_out[off] = f2bf(v);
-          v = gelu(v);
+          if (g.pre_out) g.pre_out[off] = f2bf(x);
+          x = gelu(x);
         } else if (g.act == 2) {
-          v *= gelu_grad(bf2f(g.pre_in[off]));
+          x *= gelu_grad(bf2f(g.pre_in[off]));
         }
-        if (g.skip) v += g.skip[(long long)i * g.skip_r + j];
-        if (g.c_bf16)
-          ((bf16*)g.C)[off] = f2bf(v);
-        else
-          ((float*)g.C)[off] = v;
+        if (g.skip) x += g.skip[(long long)i * g.skip_r + j];
+        v[e] = x;
       }
+      if (g.vecC && jb + 3 < g.N) {
+        if (g.c_bf16) {
+          uint2 o;
+          o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+          o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+          *(uint2*)((bf16*)g.C + ob) = o;
+        } else {
+          *(float4*)((float*)g.C + ob) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (jb + e >= g.N) continue;
+          const long long off = ob + (long long)e * g.cC;
+          if (g.c_bf16)
+            ((bf16*)g.C)[off] = f2bf(v[e]);
+          else
+            ((float*)g.C)[off] = v[e];
+        }
+      }
+    }
 }
 
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
@@ -163,7 +194,14 @@ hipError_t gemm(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-Op op(const bf16* p, long long r, long long c, long long s1 = 0, long long s2 = 0) { return Op{p, s1, s2, r, c}; }
+Op op(const bf16* p, long long r, long long c, long long s1 = 0, long long s2 = 0) { return Op{p, s1, s2, r, c, 0}; }
+
+// k runs of 4 are one aligned 8-byte load when the k stride is 1 and every
+// other stride and the base keep 4-element alignment
+int kvec_ok(const Op& o, bool a_side) {
+  const long long ks = a_side ? o.c : o.r, rs = a_side ? o.r : o.c;
+  return ks == 1 && rs % 4 == 0 && o.s1 % 4 == 0 && o.s2 % 4 == 0 && ((uintptr_t)o.p & 7) == 0;
+}
 
 
 
@@ -183,6 +221,89 @@ __global__ void k_lift(const bf16* __restrict__ x, const bf16* __restrict__ Pw,
   float v = Pb[c];
   for (int k = 0; k < cin; ++k) v += bf2f(x[p * cin + k]) * bf2f(Pw[k * C + c]);
   h[i] = f2bf(v);
+}
+
+// the same with one thread per point and 8 channels (C % 8 == 0): 16-byte stores
+__global__ void k_lift8(const bf16* __restrict__ x, const bf16* __restrict__ Pw, const float* __restrict__ Pb,
+                        bf16* __restrict__ h, long long npts, int cin, int C) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int groups = C / 8;
+  if (i >= npts * groups) return;
+  const long long p = i / groups;
+  const int c0 = (int)(i % groups) * 8;
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = Pb[c0 + e];
+  for (int k = 0; k < cin; ++k) {
+    const float xk = bf2f(x[p * cin + k]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] += xk * bf2f(Pw[k * C + c0 + e]);
+  }
+  uint4 o;
+  o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+  o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+  o.z = (unsigned)f2bf(v[4]) | ((unsigned)f2bf(v[5]) << 16);
+  o.w = (unsigned)f2bf(v[6]) | ((unsigned)f2bf(v[7]) << 16);
+  *(uint4*)(h + p * C + c0) = o;
+}
+
+// Inference projection fused in one pass, so that the hidden layer stays in
+// registers: y[p][o] = sum_k GELU(u[p][k]) Q2[k][o] + Q2_b[o] (+ skip[p][o]),
+// u = h Q1 + Q1_b.  Computed transposed on the matrix cores (u^T = Q1^T h^T,
+// then y^T = Q2^T a^T) because the result layout of the first product (lane =
+// point column, 4 consecutive hidden rows) is exactly the operand layout the
+// second one needs.  A wavefront handles 16 points per iteration.
+template <int C, int HID>
+__global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, const bf16* __restrict__ Q1,
+                                                    const float* __restrict__ b1, const bf16* __restrict__ Q2,
+                                                    const float* __restrict__ b2, int cout, float* __restrict__ y,
+                                                    long long ys, const float* __restrict__ skip, long long skip_r,
+                                                    long long npts) {
+  constexpr int HB = HID / 16, KB = C / 16;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6), nwave = (long long)gridDim.x * 4;
+  short4_t qa[HB][KB], qb[HB];
+  float bias1[HB][4];
+#pragma unroll
+  for (int hb = 0; hb < HB; ++hb) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) qa[hb][kb][e] = (short)Q1[(16 * kb + q4 + e) * HID + 16 * hb + l16];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      bias1[hb][e] = b1[16 * hb + q4 + e];
+      qb[hb][e] = l16 < cout ? (short)Q2[(16 * hb + q4 + e) * cout + l16] : (short)0;
+    }
+  }
+  for (long long t = wave; t * 16 < npts; t += nwave) {
+    const long long p = t * 16 + l16;
+    const bool ok = p < npts;
+    short4_t hv[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      hv[kb] = ok ? *(const short4_t*)(h + p * C + 16 * kb + q4) : short4_t{0, 0, 0, 0};
+    float4_t acc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int hb = 0; hb < HB; ++hb) {
+      float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa[hb][kb], hv[kb], acc, 0, 0, 0);
+      short4_t av;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) av[e] = (short)f2bf(gelu(acc[e] + bias1[hb][e]));
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qb[hb], av, acc2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int o = q4 + e;
+      if (ok && o < cout) {
+        float v = acc2[e] + b2[o];
+        if (skip) v += skip[p * skip_r + o];
+        y[p * ys + o] = v;
+      }
+    }
+  }
 }
 
 // dz = dh * GELU'(z)
@@ -489,7 +610,16 @@ int cgemm(fno_ctx* c, const GemmArgs& g, const std::pair<const char*, size_t>* e
   if (g.skip && (g.c_bf16 || g.skip_r < 0 ||
                  !inside(c, g.skip, (long long)(g.M - 1) * g.skip_r + g.N - 1, 4, extra, nextra)))
     return ffail(TTSH_EINVAL, "GEMM residual input out of bounds (internal layout error)");
-  const hipError_t e = gemm(g, c->s);
+  GemmArgs gv = g;
+  gv.A.kvec = kvec_ok(g.A, true);
+  gv.B.kvec = kvec_ok(g.B, false);
+  gv.A2.kvec = g.K2 > 0 && kvec_ok(g.A2, true);
+  gv.B2.kvec = g.K2 > 0 && kvec_ok(g.B2, false);
+  {
+    const size_t al = g.c_bf16 ? 8 : 16;
+    gv.vecC = g.cC == 1 && g.rC % 4 == 0 && g.sC1 % 4 == 0 && g.sC2 % 4 == 0 && ((uintptr_t)g.C % al) == 0;
+  }
+  const hipError_t e = gemm(gv, c->s);
   if (e != hipSuccess) return ffail(TTSH_EHIP, std::string("GEMM launch: ") + hipGetErrorString(e));
   return TTSH_OK;
 }
@@ -768,8 +898,12 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
       return ffail(TTSH_EINVAL, "output overlaps the input other than as its first channels");
   }
   hipLaunchKernelGGL(k_to_bf16, dim3(nb(P * c->cin)), dim3(256), 0, c->s, x, c->xb, P * c->cin);
-  hipLaunchKernelGGL(k_lift, dim3(nb(P * C)), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb, c->h[0], P,
-                     c->cin, C);
+  if (C % 8 == 0)
+    hipLaunchKernelGGL(k_lift8, dim3(nb(P * (C / 8))), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb,
+                       c->h[0], P, c->cin, C);
+  else
+    hipLaunchKernelGGL(k_lift, dim3(nb(P * C)), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb, c->h[0], P,
+                       c->cin, C);
   FCHK(hipGetLastError());
   int rc;
   for (int l = 0; l < c->L; ++l) {
@@ -793,6 +927,16 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
       g.pre_out = c->z[l];
     }
     if ((rc = cgemm(c, g))) return rc;
+  }
+  if (!train && C == 32 && c->hid == 128 && c->cout <= 16) {
+    // h_L is [P][C] (inside h[L]), y and skip were range-checked above
+    const long long tiles = (P + 15) / 16;
+    const long long blocks = std::min<long long>((tiles + 3) / 4, 8192);
+    hipLaunchKernelGGL((k_proj_fused<32, 128>), dim3((unsigned)blocks), dim3(256), 0, c->s, c->h[c->L], c->Q1,
+                       c->theta + c->oQ1b, c->Q2, c->theta + c->oQ2b, c->cout, y, (long long)ys,
+                       residual ? x : nullptr, (long long)c->cin, P);
+    FCHK(hipGetLastError());
+    return TTSH_OK;
   }
   // projection: a = GELU(h_L Q1 + Q1_b) (pre-activation u kept), y = a Q2 + Q2_b
   GemmArgs g = ga();

@@ -170,7 +170,7 @@ class Trainer:
                 acc += self.batch_step(D, perm[b * c.batch:(b + 1) * c.batch], lr)
                 k += 1
             hist.append((ep, acc / nb, time.time() - t0))
-            if log:
+            if log and (ep % 10 == 0 or ep == epochs - 1):
                 log(f"epoch {ep} loss {acc / nb:.4e} ({time.time() - t0:.1f} s)")
             if time_limit is not None and time.time() - t0 > time_limit:
                 break
@@ -311,3 +311,128 @@ class Rollout:
         for sol, _ in solvers:
             sol.close()
         return RolloutResult(err, fb_step, reason, secs, t_sur)
+
+
+def solver_step_seconds(solver: T.Solver, every: int, reps: int = 20) -> float:
+    """Wall seconds for `every` solver steps of the whole context (graph
+    replays, device-synchronised)."""
+    torch = _torch()
+    solver.step(every)
+    solver.sync()
+    t0 = time.time()
+    for _ in range(reps):
+        solver.step(every)
+    solver.sync()
+    torch.cuda.synchronize()
+    return (time.time() - t0) / reps
+
+
+def surrogate_step_seconds(net: F.FNO, checker: T.Solver, x, Nc: int, reps: int = 20) -> float:
+    """Wall seconds of one surrogate step for the batch x (inference forward
+    with residual output in place, projection with the acceptance norms)."""
+    torch = _torch()
+    y = x.clone()
+    B = x.shape[0]
+    net.forward_ex(y, y, 3, True, B)
+    checker.project_coarse(Nc, y, 3, B, norms=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(reps):
+        net.forward_ex(y, y, 3, True, B)
+        checker.project_coarse(Nc, y, 3, B, norms=True)
+    torch.cuda.synchronize()
+    return (time.time() - t0) / reps
+
+
+def first_exceeding(curve: np.ndarray, thr: float) -> int:
+    """Index of the first entry above thr (len(curve) if none)."""
+    above = np.flatnonzero(~(curve <= thr))
+    return int(above[0]) if above.size else len(curve)
+
+
+def main(argv=None):
+    """Radius-sweep surrogate: collect, train, roll out, judge; one JSON report."""
+    import argparse
+    import json
+    from . import workloads as Wl
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--transient", type=int, default=2000, help="solver steps before the first snapshot")
+    ap.add_argument("--snapshots", type=int, default=1001)
+    ap.add_argument("--train-until", type=int, default=500, help="pairs with t < this are training data")
+    ap.add_argument("--rollout", type=int, default=500, help="surrogate steps of the rollout")
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--train-seconds", type=float, default=300.0)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--threshold", type=float, default=0.1)
+    ap.add_argument("--check-every", type=int, default=25)
+    ap.add_argument("--report", default="surrogate_report.json")
+    a = ap.parse_args(argv)
+    torch = _torch()
+    log = lambda m: print(f"[surrogate] {m}", flush=True)
+    wl = Wl.radius_sweep()
+    inst = wl.instances
+    params = Wl.workload_coefficients()
+    cfg = SurrogateConfig(batch=a.batch, lr=a.lr)
+    I, Nc = len(inst), cfg.Nc
+    masks = coarse_masks(inst, Nc, params)
+    solver = new_solver(inst, params)
+    log(f"{I} instances, transient {a.transient} steps, {a.snapshots} snapshots every {cfg.every}")
+    D = collect(solver, masks, a.snapshots, cfg.every, Nc, transient=a.transient, log=log)
+    train_ids, test_ids = split_by_radius(I // 2)
+    # training pairs: snapshots 0 .. train_until (the rollout starts after them)
+    tr = Trainer(cfg, seed=0)
+    Dtrain = D[:a.train_until + 1]
+    hist = tr.train(Dtrain, train_ids, a.epochs, seed=1, log=log, time_limit=a.train_seconds)
+    log(f"trained {len(hist)} epochs in {hist[-1][2]:.0f} s, loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
+    t0 = a.train_until
+    Deval = D[t0:]
+    one = {"test": tr.eval_one_step(Deval, test_ids, project=solver),
+           "train_radii_later_times": tr.eval_one_step(Deval, train_ids, project=solver)}
+    log(f"one-step errors after the training window: {one}")
+    steps = min(a.rollout, D.shape[0] - 1 - t0)
+    judge = lambda s: D[t0 + s] if t0 + s < D.shape[0] else None
+    # pure network (no checks), then with acceptance checks and fallback
+    ro_free = Rollout(tr.net, cfg, inst, params, solver, envelope=float("inf"), check_every=0)
+    free = ro_free.run(D[t0], steps, judge=judge, log=log)
+    ro = Rollout(tr.net, cfg, inst, params, solver, check_every=a.check_every, tol=a.threshold)
+    guarded = ro.run(D[t0], steps, judge=judge, log=log)
+    # persistence for reference
+    npix = Nc * Nc
+    pers = np.stack([F.fno_sample_errors(D[t0], 3, D[t0 + s + 1], 3, 2, npix, I) for s in range(steps)])
+    t_sur = surrogate_step_seconds(tr.net, solver, D[t0], Nc)
+    t_sol = solver_step_seconds(solver, cfg.every)
+    test = np.array(test_ids)
+    curve = np.nanmean(free.err[:, test], axis=1)
+    s_star = first_exceeding(curve, a.threshold)
+    rep = {
+        "instances": I, "coarse_grid": Nc, "solver_steps_per_surrogate_step": cfg.every,
+        "network": dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, hidden=cfg.hidden,
+                        params=int(tr.net.n), dtype="bf16 storage, fp32 accumulation"),
+        "data": dict(transient=a.transient, snapshots=a.snapshots, train_pairs=len(tr.pairs(Dtrain, train_ids)),
+                     train_instances=train_ids, test_instances=test_ids),
+        "training": dict(epochs=len(hist), seconds=hist[-1][2], loss_first=hist[0][1], loss_last=hist[-1][1],
+                         batch=cfg.batch, lr=cfg.lr, schedule="cosine"),
+        "one_step": one,
+        "rollout_test_mean_err": curve.tolist(),
+        "rollout_train_mean_err": np.nanmean(free.err[:, train_ids], axis=1).tolist(),
+        "persistence_test_mean_err": pers[:, test].mean(axis=1).tolist(),
+        "threshold": a.threshold,
+        "steps_within_threshold": s_star,
+        "solver_steps_within_threshold": s_star * cfg.every,
+        "guarded": dict(fallback_step=guarded.fallback_step.tolist(), reason=guarded.reason,
+                        test_mean_err=np.nanmean(guarded.err[:, test], axis=1).tolist(),
+                        seconds=guarded.seconds, seconds_network=guarded.seconds_surrogate),
+        "seconds_per_surrogate_step": t_sur,
+        "seconds_per_solver_20_steps": t_sol,
+        "speedup_per_step": t_sol / t_sur,
+    }
+    with open(a.report, "w") as f:
+        json.dump(rep, f, indent=1)
+    log(f"speedup {t_sol / t_sur:.2f}x per surrogate step ({t_sur * 1e3:.2f} ms vs {t_sol * 1e3:.2f} ms); "
+        f"test error stays <= {a.threshold} for {s_star} surrogate steps ({s_star * cfg.every} solver steps)")
+    return rep
+
+
+if __name__ == "__main__":
+    main()

@@ -44,6 +44,38 @@ def binary_outside(N: int, L: float, centers, radii) -> np.ndarray:
     return out.astype(np.uint8)
 
 
+@dataclasses.dataclass(frozen=True)
+class Coefficients:
+    """Coefficients of the general form L(k) = -alpha - Gamma0 k^2 - Gamma2 k^4
+    with cubic (beta), advection (lambda0, lambda1) and mask (gamma_v,
+    gamma_w) terms, the time step and the stepper.  Defaults: the workloads'
+    set (alpha = -1, beta = 1, Gamma0 = -1, Gamma2 = 1, lambda0 = 3,
+    lambda1 = 0, one penalisation 100 on the velocity, none on the
+    vorticity, dt = 0.01, integrating-factor Euler)."""
+    alpha: float = -1.0
+    beta: float = 1.0
+    gamma0: float = -1.0
+    gamma2: float = 1.0
+    lambda0: float = 3.0
+    lambda1: float = 0.0
+    gamma_v: float = 100.0
+    gamma_w: float = 0.0
+    dt: float = 0.01
+    scheme: str = "ifeuler"
+
+
+def workload_coefficients(dt: float = 0.01) -> Coefficients:
+    return Coefficients(dt=dt)
+
+
+def paper_coefficients(dt: float = 0.01) -> Coefficients:
+    """The paper's preset (a, b, lambda, gamma_v, gamma_w) = (0.5, 1.6, 9, 40, 4)
+    in the general form: alpha = 1 - a, Gamma0 = -2, Gamma2 = 1 (model
+    subsection; Table I)."""
+    return Coefficients(alpha=0.5, beta=1.6, gamma0=-2.0, gamma2=1.0, lambda0=9.0, lambda1=0.0,
+                        gamma_v=40.0, gamma_w=4.0, dt=dt)
+
+
 @dataclasses.dataclass
 class Instance:
     N: int

@@ -204,3 +204,31 @@ def test_residual_forward_in_place_and_gather(gpu):
     src = torch.from_numpy(x.copy()).cuda()
     net.gather(dst, 2, src, SMALL.cin, 2, SMALL.H * SMALL.W, [2, 0])
     assert np.array_equal(dst.cpu().numpy(), x[[2, 0], ..., :2])
+
+
+def test_fused_inference_projection_matches_training_path(gpu):
+    """With width 32 and hidden 128 an inference forward runs the projection
+    fused (the hidden layer never leaves registers); it must give what the
+    unfused training-mode forward gives, in plain and residual in-place form,
+    and stay within the BF16 tolerance of the FP64 oracle."""
+    import torch
+    say("fno fused projection")
+    cfg = F.Config(H=32, W=48, cin=3, cout=2, width=32, modes=4, layers=1, hidden=128)
+    B = 3
+    net, p = make_net(gpu, cfg, B, seed=13)
+    rng = np.random.default_rng(14)
+    x = rng.standard_normal((B, cfg.H, cfg.W, cfg.cin)).astype(np.float32)
+    xd = torch.from_numpy(x.copy()).cuda()
+    y1 = torch.empty((B, cfg.H, cfg.W, cfg.cout), dtype=torch.float32, device="cuda")
+    y2 = torch.empty_like(y1)
+    net.forward(xd, y1, train=False)
+    net.forward(xd, y2, train=True)
+    a, b = y1.cpu().numpy().astype(np.float64), y2.cpu().numpy().astype(np.float64)
+    assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
+    ref = F.forward(p, x.astype(np.float64), cfg)
+    assert rel(a, ref) < 3e-2
+    net.forward_ex(xd, xd, cfg.cin, True, B)
+    got = xd.cpu().numpy().astype(np.float64)
+    want = x[..., :2].astype(np.float64) + a
+    assert np.abs(got[..., :2] - want).max() <= 1e-5 * np.abs(want).max()
+    assert np.array_equal(got[..., 2], x[..., 2].astype(np.float64))
