@@ -62,6 +62,14 @@ int fno_forward(fno_ctx* ctx, const float* x, float* y, int batch, int train);
  * dl/dy for fno_backward.                                                  */
 int fno_loss(fno_ctx* ctx, const float* y, const float* t, int batch, double* loss);
 
+/* fno_loss with another normaliser: loss = mean over samples of
+ * ||y - t|| / ||t - ref|| (the relative error of the change from ref when y
+ * and t are fields one step apart and ref is the earlier field), ref holding
+ * the cout channels of sample s, pixel p at ref[(s*H*W + p)*ref_stride + c]
+ * (e.g. the network's input, ref_stride = cin).  ref = NULL is fno_loss.   */
+int fno_loss_ex(fno_ctx* ctx, const float* y, const float* t, const float* ref, int64_t ref_stride, int batch,
+                double* loss);
+
 /* Gradients of the loss with respect to every parameter (overwritten). */
 int fno_backward(fno_ctx* ctx, int batch);
 

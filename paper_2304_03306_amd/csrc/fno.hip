@@ -324,14 +324,19 @@ __global__ void k_gather(float* __restrict__ dst, long long dch, const float* __
 }
 
 // per-sample sums of (y - t)^2 and t^2 (FP64), one block per sample
+// With ref non-null the second sum is of (t - ref)^2, ref holding the same
+// channels at pixel stride ref_s (the denominator of an increment loss).
 __global__ void __launch_bounds__(256) k_loss_sums(const float* __restrict__ y, const float* __restrict__ t,
-                                                   long long per, double* __restrict__ out) {
+                                                   long long per, const float* __restrict__ ref, long long ref_s,
+                                                   int nch, double* __restrict__ out) {
   const long long base = (long long)blockIdx.x * per;
   double a = 0.0, b = 0.0;
   for (long long i = threadIdx.x; i < per; i += blockDim.x) {
     const double d = (double)y[base + i] - (double)t[base + i];
     a += d * d;
-    b += (double)t[base + i] * (double)t[base + i];
+    double tv = (double)t[base + i];
+    if (ref) tv -= (double)ref[((base + i) / nch) * ref_s + (base + i) % nch];
+    b += tv * tv;
   }
   __shared__ double red[4][2];
   a = ttsh::wave_sum_from(a, 1);
@@ -965,10 +970,17 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
 }
 
 int fno_loss(fno_ctx* c, const float* y, const float* t, int B, double* loss) {
+  return fno_loss_ex(c, y, t, nullptr, 0, B, loss);
+}
+
+int fno_loss_ex(fno_ctx* c, const float* y, const float* t, const float* ref, int64_t ref_stride, int B,
+                double* loss) {
   if (!c || !y || !t || !loss) return ffail(TTSH_EINVAL, "null argument");
   if (B < 1 || B > c->maxB) return ffail(TTSH_EINVAL, "batch out of range");
+  if (ref && ref_stride < c->cout) return ffail(TTSH_EINVAL, "reference pixel stride smaller than cout");
   const long long per = (long long)c->H * c->W * c->cout;
-  hipLaunchKernelGGL(k_loss_sums, dim3(B), dim3(256), 0, c->s, y, t, per, c->lsum);
+  hipLaunchKernelGGL(k_loss_sums, dim3(B), dim3(256), 0, c->s, y, t, per, ref, (long long)ref_stride, c->cout,
+                     c->lsum);
   hipLaunchKernelGGL(k_loss_grad, dim3(nb(per * B)), dim3(256), 0, c->s, y, t, c->lsum, per, B, c->dy);
   FCHK(hipGetLastError());
   std::vector<double> h(2 * B);

@@ -28,6 +28,7 @@ def lib():
             "fno_gather": ([vp, vp, i64, vp, i64, i32, i64, vp, i32], ctypes.c_int),
             "fno_sample_errors": ([vp, i64, vp, i64, i32, i64, i32, vp], ctypes.c_int),
             "fno_loss": ([vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+            "fno_loss_ex": ([vp, vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "fno_backward": ([vp, i32], ctypes.c_int),
             "fno_adam_step": ([vp, f32, f32, f32, f32], ctypes.c_int),
             "fno_gemm_bf16": ([i32, i32, i32, i32, f32, vp, i64, i64, i64, vp, i64, i64, i64, vp, i64, i64, i64],
@@ -123,6 +124,12 @@ class FNO:
     def loss(self, y, t):
         out = ctypes.c_double()
         _check(lib().fno_loss(self.ctx, _ptr(y), _ptr(t), int(y.shape[0]), ctypes.byref(out)))
+        return out.value
+
+    def loss_ex(self, y, t, ref, ref_stride, batch):
+        out = ctypes.c_double()
+        _check(lib().fno_loss_ex(self.ctx, _ptr(y), _ptr(t), _ptr(ref), int(ref_stride), int(batch),
+                                 ctypes.byref(out)))
         return out.value
 
     def backward(self, batch):

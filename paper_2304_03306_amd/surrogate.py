@@ -44,6 +44,7 @@ class SurrogateConfig:
     lr: float = 1e-3
     cin: int = 3           # v_x, v_y, K
     cout: int = 2
+    increment_loss: bool = False  # normalise the loss by the change over the step (fno_loss_ex)
 
 
 def _torch():
@@ -67,10 +68,13 @@ def coarse_masks(instances: Sequence[Instance], Nc: int, params) -> np.ndarray:
         s.close()
 
 
-def new_solver(instances: Sequence[Instance], params, precision=T.TTSH_FP32, seed_fields=True) -> T.Solver:
+def new_solver(instances: Sequence[Instance], params, precision=T.TTSH_FP32, seed_fields=True,
+               graph_steps: int = 20) -> T.Solver:
     """A solver context over the instances, masks set, started from each
-    instance's seeded initial field."""
+    instance's seeded initial field; steps are replayed from graphs of
+    graph_steps steps (one surrogate step's worth)."""
     s = T.Solver([i.N for i in instances], [i.L for i in instances], params, precision)
+    s.option(T.TTSH_OPT_GRAPH_STEPS, graph_steps)
     for q, inst in enumerate(instances):
         s.mask_tanh(q, inst.centers, inst.radii, inst.xi)
         if seed_fields:
@@ -145,7 +149,10 @@ class Trainer:
         self.net.gather(self.xb, c.cin, D, 3, c.cin, npix, idx)
         self.net.gather(self.tb, c.cout, D, 3, c.cout, npix, idx + I)
         self.net.forward_ex(self.xb, self.yb, c.cout, True, B, train=True)
-        loss = self.net.loss(self.yb[:B], self.tb[:B])
+        if c.increment_loss:
+            loss = self.net.loss_ex(self.yb, self.tb, self.xb, c.cin, B)
+        else:
+            loss = self.net.loss(self.yb[:B], self.tb[:B])
         self.net.backward(B)
         self.net.adam_step(lr)
         self.step_count += 1

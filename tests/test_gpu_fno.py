@@ -232,3 +232,38 @@ def test_fused_inference_projection_matches_training_path(gpu):
     want = x[..., :2].astype(np.float64) + a
     assert np.abs(got[..., :2] - want).max() <= 1e-5 * np.abs(want).max()
     assert np.array_equal(got[..., 2], x[..., 2].astype(np.float64))
+
+
+def test_increment_loss_and_its_gradient(gpu):
+    """fno_loss_ex normalises each sample's error by ||t - ref|| (ref: the
+    input's first channels, pixel stride cin); its value is that mean, and
+    the gradients are the oracle backward of dl/dy = (y - t) / (||y - t||
+    ||t - ref|| B).  With ref = NULL it is fno_loss."""
+    import torch
+    from paper_2304_03306_amd import fno
+    say("fno increment loss")
+    B = 3
+    net, p = make_net(gpu, SMALL, B, seed=15)
+    rng = np.random.default_rng(16)
+    x = rng.standard_normal((B, SMALL.H, SMALL.W, SMALL.cin)).astype(np.float32)
+    t = rng.standard_normal((B, SMALL.H, SMALL.W, SMALL.cout)).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = torch.empty((B, SMALL.H, SMALL.W, SMALL.cout), dtype=torch.float32, device="cuda")
+    net.forward(xd, y, train=True)
+    yh = y.cpu().numpy().astype(np.float64)
+    t64, ref = t.astype(np.float64), x[..., :SMALL.cout].astype(np.float64)
+    num = np.sqrt(((yh - t64) ** 2).sum(axis=(1, 2, 3)))
+    den = np.sqrt(((t64 - ref) ** 2).sum(axis=(1, 2, 3)))
+    got = net.loss_ex(y, td, xd, SMALL.cin, B)
+    assert abs(got - np.mean(num / den)) <= 1e-9 * got
+    plain = net.loss(y, td)
+    assert abs(plain - np.mean(num / np.sqrt((t64 ** 2).sum(axis=(1, 2, 3))))) <= 1e-9 * plain
+    net.loss_ex(y, td, xd, SMALL.cin, B)
+    net.backward(B)
+    g = fno.unflatten(net.grads(), p, SMALL.layers)
+    _, cache = F.forward(p, x.astype(np.float64), SMALL, keep=True)
+    gy = (yh - t64) / (num * den * B)[:, None, None, None]
+    go = F.backward(p, cache, gy, SMALL)
+    for k in go:
+        e = rel(g[k], go[k])
+        assert e < 6e-2, (k, e)

@@ -360,3 +360,31 @@ def test_project_coarse_matches_oracle(gpu):
         w = O.field(O.vorticity_hat(vh, kx, ky)[None])[0]
         assert abs(nrm[b, 0] - np.sum(want ** 2)) <= 1e-9 * np.sum(want ** 2)
         assert abs(nrm[b, 1] - np.sum(w ** 2)) <= 1e-9 * np.sum(w ** 2)
+
+
+def test_failure_injection_nonfinite_input_and_unstable_mask(gpu):
+    """Conditions forced from the host, every kernel exits normally: a NaN in
+    an input field is refused with TTSH_ENONFINITE; with K = 1 and
+    gamma_v dt = 3 the explicit mask term multiplies the field by -2 each
+    step, the values overflow, and the guard in ttsh_sync reports the
+    instance."""
+    import dataclasses
+    say("failure injection")
+    N, L = 64, 32.0
+    p = O.workload_params()
+    s = make(gpu, N, L, p, 32)
+    v = W.uniform_field(3, N, 0.1, 32)
+    v[1, 5, 7] = np.nan
+    with pytest.raises(gpu.TTSHError) as e:
+        s.set_field(0, v)
+    assert e.value.code == gpu.TTSH_ENONFINITE
+    bad = dataclasses.replace(p, gamma_v=300.0)
+    u = gpu.Solver([N, N], [L, L], bad, 32)
+    u.set_mask(0, np.zeros((N, N)))
+    u.set_mask(1, np.ones((N, N)))
+    u.set_field(0, W.uniform_field(4, N, 0.1, 32))
+    u.set_field(1, W.uniform_field(5, N, 0.1, 32))
+    u.step(300)
+    with pytest.raises(gpu.TTSHError) as e:
+        u.sync()
+    assert e.value.code == gpu.TTSH_ENONFINITE and "instance 1" in str(e.value)

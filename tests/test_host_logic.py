@@ -77,3 +77,21 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ttsh, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         ttsh.lib()
+
+
+def test_surrogate_split_and_pair_indexing():
+    """Held-out radii take both ramps; pair indices address D[t][i] with the
+    successor D[t+1][i] at index + I; the threshold search finds the first
+    step above it (NaN counts as above)."""
+    import numpy as np
+    from paper_2304_03306_amd import surrogate as S
+    train, test = S.split_by_radius(32)
+    assert test == [2 * j + r for j in (3, 7, 11, 15, 19, 23, 27, 31) for r in (0, 1)]
+    assert sorted(train + test) == list(range(64)) and not set(train) & set(test)
+    D = np.zeros((5, 4, 2, 2, 3))  # [n_snap][I][Nc][Nc][3]
+    idx = S.Trainer.pairs(None, D, [1, 3])
+    assert idx.tolist() == [1, 3, 5, 7, 9, 11, 13, 15]
+    assert (idx // 4).max() == 3  # every pair's successor (t + 1) exists
+    assert S.first_exceeding(np.array([0.01, 0.05, 0.2, 0.01]), 0.1) == 2
+    assert S.first_exceeding(np.array([0.01, np.nan]), 0.1) == 1
+    assert S.first_exceeding(np.array([0.01, 0.02]), 0.1) == 2
