@@ -33,6 +33,72 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_radius_sweep.json")
+STEP_SOURCES = ("common.hpp", "fft.hpp", "step.hpp", "step_multi.hpp", "step_multi.hip")
+
+
+def step_source_hash() -> str:
+    """SHA-256 over the sources that define the two step kernels; a traffic
+    measurement is only reported while these are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2304_03306_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _pmc_means(path: str, counter: str) -> dict:
+    """Mean counter value per kernel name over the dispatches of a rocprofv3
+    counter_collection.csv."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            a = acc.setdefault(r["Kernel_Name"], [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+    return {k: v[0] / v[1] for k, v in acc.items()}
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib) -> dict:
+    """HBM bytes per dispatch of the step kernels from FETCH_SIZE / WRITE_SIZE
+    runs (KiB per dispatch), scaled by what the same counters read for a
+    device copy of copy_mib MiB (bytes moved per counted byte)."""
+    copy_bytes = copy_mib * (1 << 20)
+    cf = [v for k, v in _pmc_means(copy_fetch_csv, "FETCH_SIZE").items() if "copyBuffer" in k]
+    cw = [v for k, v in _pmc_means(copy_write_csv, "WRITE_SIZE").items() if "copyBuffer" in k]
+    fscale = copy_bytes / (cf[0] * 1024.0)
+    wscale = copy_bytes / (cw[0] * 1024.0)
+    fetch, write = _pmc_means(fetch_csv, "FETCH_SIZE"), _pmc_means(write_csv, "WRITE_SIZE")
+    kernels = {}
+    for name in fetch:
+        if ("row_multi" in name or "col_multi" in name) and name in write:
+            kernels[name] = {"fetch_kib": fetch[name], "write_kib": write[name],
+                             "bytes": fetch[name] * 1024.0 * fscale + write[name] * 1024.0 * wscale}
+    return {"source_sha256": step_source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+            "copy_mib": copy_mib, "kernels": kernels}
+
+
+def measured_traffic(kernel: str, block: int):
+    """Bytes per launch of the given step kernel from the committed counter
+    summary, or None if it is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != step_source_hash():
+        return None
+    for name, v in t.get("kernels", {}).items():
+        if (name.startswith(f"void ttsh::{kernel}<float") and name.endswith(f", {block}>(ttsh::MultiArgs)")
+                and ", false, " in name and (kernel == "row_multi" or ", 0, " in name)):
+            return v["bytes"]
+    return None
+
+
 def kept_modes(N: int) -> int:
     """Stored modes per component that the 1/2 rule keeps: m_x = 0..M,
     m_y = -M..M with m_x^2 + m_y^2 <= M^2 (M = N/4)."""
@@ -146,16 +212,31 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = autotuned)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (scale for the HBM byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                         "COPY_WRITE_CSV", "COPY_MIB"),
+                    help="write the HBM traffic summary of the step kernels from rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        a = args.summarize_pmc
+        summary = summarize_pmc(a[0], a[1], a[2], a[3], int(a[4]))
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(summary, f, indent=1)
+        print(json.dumps(summary, indent=1))
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(10):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        log(f"[bench] copied {args.copy_calibration} MiB 10 times")
+        gbs = 2 * n * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"[bench] copied {args.copy_calibration} MiB 11 times: {gbs:.0f} GB/s read + write")
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -208,8 +289,9 @@ def main():
         counts[i.N] = counts.get(i.N, 0) + 1
     row_b = sum(pass_bytes(N, state_bytes)[0] * n for N, n in counts.items())
     col_b = sum(pass_bytes(N, state_bytes)[1] * n for N, n in counts.items())
-    kern = [("row_multi", row_us, row_b), ("col_multi", col_us, col_b)]
+    kern = [("row_multi", row_us, row_b, block[0]), ("col_multi", col_us, col_b, block[1])]
     dom = max(kern, key=lambda k: k[1])
+    traffic = measured_traffic(dom[0], dom[3]) if args.precision == 32 else None
     achieved = dom[2] / (dom[1] * 1e-6) / 1e9
     step_bytes = row_b + col_b
     step_us = row_us + col_us
@@ -264,8 +346,8 @@ def main():
                                  "FP32 transforms, FP64 state") + ", FP64 k-space update",
                    "parallelism": "single GPU, instances batched per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": dom[0], "avg_us": dom[1], "bytes_per_launch": dom[2]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom[0], "block": dom[3], "avg_us": dom[1], "bytes_per_launch": dom[2]},
         "step_hbm": {"algorithmic_bytes": step_bytes, "kernel_us": step_us,
                      "GBps": step_bytes / (step_us * 1e-6) / 1e9,
                      "frac": step_bytes / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,

@@ -95,3 +95,37 @@ def test_surrogate_split_and_pair_indexing():
     assert S.first_exceeding(np.array([0.01, 0.05, 0.2, 0.01]), 0.1) == 2
     assert S.first_exceeding(np.array([0.01, np.nan]), 0.1) == 1
     assert S.first_exceeding(np.array([0.01, 0.02]), 0.1) == 2
+
+
+def test_pmc_summary_scaling_and_source_check(tmp_path, monkeypatch):
+    """The traffic summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+    by the bytes a known device copy moves per counted byte, averages over
+    dispatches, and bench reports it only while the kernel sources hash the
+    same."""
+    import json
+    import bench
+
+    def csv(path, rows):
+        with open(path, "w") as f:
+            f.write('"Kernel_Name","Counter_Name","Counter_Value"\n')
+            for k, c, v in rows:
+                f.write(f'"{k}","{c}",{v}\n')
+    row = "void ttsh::row_multi<float, false, 64>(ttsh::MultiArgs)"
+    col = "void ttsh::col_multi<float, float, false, 0, 128>(ttsh::MultiArgs)"
+    csv(tmp_path / "f.csv", [(row, "FETCH_SIZE", 100.0), (row, "FETCH_SIZE", 300.0), (col, "FETCH_SIZE", 50.0)])
+    csv(tmp_path / "w.csv", [(row, "WRITE_SIZE", 40.0), (col, "WRITE_SIZE", 80.0)])
+    csv(tmp_path / "cf.csv", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0)])  # 1 MiB read, counted half
+    csv(tmp_path / "cw.csv", [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0)])
+    s = bench.summarize_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"),
+                            str(tmp_path / "cw.csv"), 1)
+    assert s["fetch_scale"] == 2.0 and s["write_scale"] == 1.0
+    assert s["kernels"][row]["bytes"] == 200.0 * 1024 * 2 + 40.0 * 1024
+    out = tmp_path / "t.json"
+    out.write_text(json.dumps(s))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    assert bench.measured_traffic("row_multi", 64) == s["kernels"][row]["bytes"]
+    assert bench.measured_traffic("col_multi", 128) == s["kernels"][col]["bytes"]
+    assert bench.measured_traffic("row_multi", 128) is None
+    s["source_sha256"] = "0" * 64
+    out.write_text(json.dumps(s))
+    assert bench.measured_traffic("row_multi", 64) is None
