@@ -256,10 +256,12 @@ def main():
     s.option(T.TTSH_OPT_GUARD, 0)
     if args.block:
         s.option(T.TTSH_OPT_BLOCK, args.block)
-        block = (args.block, args.block)
+        block, split = (args.block, args.block), (0, 0)
     else:
-        block, tuned_us = s.tune(20)
-        log(f"[bench] autotuned workgroup sizes (row, column) {block} ({tuned_us:.1f} us/step)")
+        cfg, tuned_us = s.tune(20)
+        block, split = cfg[:2], cfg[2:]
+        log(f"[bench] autotuned (row, column) workgroup sizes {block}, one launch per grid size {split} "
+            f"({tuned_us:.1f} us/step)")
 
     parity = {}
     if not args.no_parity and args.workload == "sweep":
@@ -303,7 +305,8 @@ def main():
         pw = W.circle_fp32_512()
         ps = setup(T, W, pw, params, args.precision)
         ps.option(T.TTSH_OPT_GUARD, 0)
-        pblock, _ = ps.tune(20)
+        pcfg, _ = ps.tune(20)
+        pblock = pcfg[:2]
         perr = None
         if not args.no_parity:
             ps.step(1000)
@@ -342,6 +345,7 @@ def main():
         "config": {"workload": wl.name, "instances": len(wl.instances),
                    "grids": " + ".join(f"{counts[N]}x{N}^2" for N in sizes),
                    "points_per_step": wl.points, "dt": params.dt, "block": block,
+                   "launch_per_grid_size": split,
                    "precision": ("FP32 transforms and state" if args.precision == 32 else
                                  "FP32 transforms, FP64 state") + ", FP64 k-space update",
                    "parallelism": "single GPU, instances batched per grid size"},

@@ -94,6 +94,12 @@ int fno_forward_ex(fno_ctx* ctx, const float* x, float* y, int64_t y_pix_stride,
 int fno_gather(fno_ctx* ctx, float* dst, int64_t dst_ch, const float* src, int64_t src_ch, int nch,
                int64_t npix, const int64_t* idx, int n);
 
+/* Add uniform noise amp * U[-1, 1) to channels 0..nch-1 of npix pixels of
+ * x (device float32, pixel stride pix_stride); the noise is a counter-based
+ * SplitMix64 stream of (seed, element index), reproducible for any launch
+ * shape.  For training-time input perturbation.  Asynchronous.            */
+int fno_perturb(fno_ctx* ctx, float* x, int64_t pix_stride, int nch, int64_t npix, float amp, uint64_t seed);
+
 /* Relative L2 error per sample between device float32 fields laid out with
  * pixel strides: sample s, pixel p, channel c at y[(s*npix + p)*ys + c] and
  * t[(s*npix + p)*ts + c], c < nch;  out[s] = ||y_s - t_s|| / ||t_s|| (host,
@@ -101,7 +107,8 @@ int fno_gather(fno_ctx* ctx, float* dst, int64_t dst_ch, const float* src, int64
 int fno_sample_errors(const float* y, int64_t ys, const float* t, int64_t ts, int nch, int64_t npix,
                       int batch, double* out);
 
-/* Batched strided GEMM on the matrix cores, exposed for testing:
+/* Batched strided GEMM on the matrix cores, exposed for testing (it takes
+ * the LDS-staged path whenever the strides allow, as the network does):
  * C[b][i][j] = alpha sum_k A[b][i][k] B[b][k][j] with A, B bfloat16 (raw
  * uint16 storage) and C float32, all device pointers; element (i, k) of
  * batch b of A sits at A + b*sA + i*rA + k*cA (likewise B, C).  Synchronous. */

@@ -88,7 +88,10 @@ enum {
   TTSH_OPT_GRAPH_STEPS = 1, /* steps captured per HIP graph (0 = no graph); default 50 */
   TTSH_OPT_BLOCK = 2,       /* workgroup size of the step kernels: 64, 128 or 256
                                (8 x size >= largest N), 0 = chosen from the batch */
-  TTSH_OPT_GUARD = 4        /* 1: ttsh_sync checks the state for NaN/Inf; default 1 */
+  TTSH_OPT_GUARD = 4,       /* 1: ttsh_sync checks the state for NaN/Inf; default 1 */
+  TTSH_OPT_SPLIT = 8        /* bit 0: row pass, bit 1: column pass launched once per grid
+                               size (kernels compiled for that size) instead of once for
+                               all sizes; default 0 */
 };
 
 /* Create a context holding n_inst independent instances advanced together.
@@ -198,13 +201,15 @@ int ttsh_sync(ttsh_ctx* ctx);
  * out[1] = column pass.  Synchronous.                                      */
 int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
 
-/* Autotuner: time nsteps steps with every usable workgroup size (HIP events,
- * after two warm-up steps), keep the fastest size for each of the two passes
- * independently, and restore the state the context had before the call.
- * Writes 1000 x (row-pass size) + (column-pass size) and the microseconds per
- * step of that choice (either pointer may be NULL).  A later
- * TTSH_OPT_BLOCK sets both passes again.  Synchronous.                     */
-int ttsh_tune(ttsh_ctx* ctx, int64_t nsteps, int* bs_out, double* us_out);
+/* Autotuner: time nsteps steps with every usable workgroup size, each as one
+ * launch for all grid sizes and as one launch per grid size (HIP events,
+ * after two warm-up steps), keep the fastest configuration for each of the
+ * two passes independently, and restore the state the context had before the
+ * call.  cfg_out (4 ints, may be NULL): row-pass size, column-pass size,
+ * row-pass split (0/1), column-pass split (0/1); us_out: microseconds per step
+ * of that choice (may be NULL).  A later TTSH_OPT_BLOCK / TTSH_OPT_SPLIT
+ * overrides it.  Synchronous.                                               */
+int ttsh_tune(ttsh_ctx* ctx, int64_t nsteps, int* cfg_out, double* us_out);
 
 /* Number of distinct grid sizes (size classes) in the context; their sizes in
  * increasing order go to N_out (may be NULL).                               */

@@ -69,6 +69,7 @@ struct GemmArgs {
   const float* skip;       // float C only: C[i][j] += skip[i * skip_r + j] (after everything else)
   long long skip_r;
   int vecC;                // set by the launcher: rows of C hold aligned runs of 4 contiguous columns
+  int staged;              // set by the launcher: operands staged through LDS (gemm_part_lds)
 };
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
@@ -114,14 +115,66 @@ __device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, 
   }
 }
 
+// The same product with both operands staged through the wavefront's own LDS
+// in chunks of 32 along k: rows of A (k contiguous) and rows of B (n
+// contiguous) are read with coalesced 16-byte loads, B is transposed on its
+// way into LDS, and the fragments are 8-byte LDS reads.  Requires unit
+// column strides, row and batch strides and K, N multiples of 8, and 16-byte
+// aligned operands (the launcher checks).
+constexpr int kKC = 32, kLDK = 40;  // k chunk, LDS row stride (bf16) with padding
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline void gemm_part_lds(const Op& A, const Op& B, int K, int M, int N, int b1, int b2, int i0, int j0,
+                                     int lane, float4_t (&acc)[2][2], bf16* __restrict__ As,
+                                     bf16* __restrict__ Bt) {
+  const bf16* pa = A.p + b1 * A.s1 + b2 * A.s2;
+  const bf16* pb = B.p + b1 * B.s1 + b2 * B.s2;
+  const int rl = lane & 15, kq = (lane >> 4) * 4;
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int r = pass * 16 + (lane >> 2), seg = (lane & 3) * 8;
+      uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+      if (i0 + r < M && k0 + seg < K) va = *(const uint4*)(pa + (long long)(i0 + r) * A.r + k0 + seg);
+      if (k0 + r < K && j0 + seg < N) vb = *(const uint4*)(pb + (long long)(k0 + r) * B.r + j0 + seg);
+      *(uint4*)(As + r * kLDK + seg) = va;
+      const bf16* e = (const bf16*)&vb;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Bt[(seg + q) * kLDK + r] = e[q];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int kk = 0; kk < kKC; kk += 16) {
+      short4_t a[2], b[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        a[s] = *(const short4_t*)(As + (16 * s + rl) * kLDK + kk + kq);
+        b[s] = *(const short4_t*)(Bt + (16 * s + rl) * kLDK + kk + kq);
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[t], a[s], acc[s][t], 0, 0, 0);
+    }
+    wave_lds_sync();  // the next chunk overwrites the staging buffers
+  }
+}
+
+// Work items (batch, tile) are numbered batch-major and dealt four to a
+// workgroup, one per wavefront, so that GEMMs with a single tile per batch
+// still fill every wavefront.
+template <bool STAGED>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int tiles) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long nbatch = (long long)g.nb1 * g.nb2;
-  const int groups = (tiles + 3) / 4;
-  const long long blk = blockIdx.x;
-  const long long batch = blk / groups;
-  const int tile = (int)(blk % groups) * 4 + wave;
-  if (batch >= nbatch || tile >= tiles) return;  // whole wavefront exits together
+  const long long item = (long long)blockIdx.x * 4 + wave;
+  if (item >= nbatch * tiles) return;  // whole wavefront exits together
+  const long long batch = item / tiles;
+  const int tile = (int)(item % tiles);
   const int b1 = (int)(batch / g.nb2), b2 = (int)(batch % g.nb2);
   const int i0 = (tile / tiles_n) * 32, j0 = (tile % tiles_n) * 32;
   float4_t acc[2][2], acc2[2][2];
@@ -132,8 +185,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int 
       acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
       acc2[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
     }
-  gemm_part(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc);
-  if (g.K2 > 0) gemm_part(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2);
+  if constexpr (STAGED) {
+    __shared__ __align__(16) bf16 stage[4][2][32 * kLDK];
+    gemm_part_lds(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc, stage[wave][0], stage[wave][1]);
+    if (g.K2 > 0)
+      gemm_part_lds(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2, stage[wave][0], stage[wave][1]);
+  } else {
+    gemm_part(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc);
+    if (g.K2 > 0) gemm_part(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2);
+  }
   const long long cbase = b1 * g.sC1 + b2 * g.sC2;
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -188,10 +248,19 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int 
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
   const int tiles_n = (g.N + 31) / 32, tiles = ((g.M + 31) / 32) * tiles_n;
-  const long long blocks = (long long)g.nb1 * g.nb2 * ((tiles + 3) / 4);
+  const long long blocks = ((long long)g.nb1 * g.nb2 * tiles + 3) / 4;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
+  if (g.staged)
+    hipLaunchKernelGGL(gemm_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
+  else
+    hipLaunchKernelGGL(gemm_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
   return hipGetLastError();
+}
+
+// operands a staged launch can take: unit column stride, 8-element row and
+// batch strides, 16-byte aligned base
+bool stage_ok(const Op& o) {
+  return o.c == 1 && o.r % 8 == 0 && o.s1 % 8 == 0 && o.s2 % 8 == 0 && ((uintptr_t)o.p & 15) == 0;
 }
 
 Op op(const bf16* p, long long r, long long c, long long s1 = 0, long long s2 = 0) { return Op{p, s1, s2, r, c, 0}; }
@@ -352,6 +421,24 @@ __global__ void __launch_bounds__(256) k_loss_sums(const float* __restrict__ y, 
   }
 }
 
+// x[p][c] += amp * u, u uniform in [-1, 1) from SplitMix64 (Steele, Lea and
+// Flood 2014) of seed + element index: a counter-based stream, the same for
+// any launch shape.
+__device__ inline unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_perturb(float* __restrict__ x, long long stride, int nch, long long tot, float amp,
+                          unsigned long long seed) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const unsigned long long r = splitmix64(seed * 0x100000001B3ull + (unsigned long long)i);
+  const float u = (float)(r >> 40) * (1.0f / 8388608.0f) - 1.0f;  // 24 bits -> [-1, 1)
+  x[(i / nch) * stride + i % nch] += amp * u;
+}
+
 // per-sample sums of (y - t)^2 and t^2 over strided channels-last fields
 __global__ void __launch_bounds__(256) k_err_sums(const float* __restrict__ y, long long ys,
                                                   const float* __restrict__ t, long long ts, int nch,
@@ -481,6 +568,7 @@ struct fno_ctx {
   size_t part_n = 0;
   double* lsum = nullptr;
   long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
+  int staged_gemm = 1;        // GEMMs whose operands allow it stage them through LDS
   std::vector<void*> allocs;
   std::vector<std::pair<const char*, size_t>> extents;  // (start, bytes) of every buffer
 };
@@ -624,6 +712,8 @@ int cgemm(fno_ctx* c, const GemmArgs& g, const std::pair<const char*, size_t>* e
     const size_t al = g.c_bf16 ? 8 : 16;
     gv.vecC = g.cC == 1 && g.rC % 4 == 0 && g.sC1 % 4 == 0 && g.sC2 % 4 == 0 && ((uintptr_t)g.C % al) == 0;
   }
+  gv.staged = c->staged_gemm && g.K % 8 == 0 && g.N % 8 == 0 && stage_ok(g.A) && stage_ok(g.B) &&
+              (g.K2 <= 0 || (g.K2 % 8 == 0 && stage_ok(g.A2) && stage_ok(g.B2)));
   const hipError_t e = gemm(gv, c->s);
   if (e != hipSuccess) return ffail(TTSH_EHIP, std::string("GEMM launch: ") + hipGetErrorString(e));
   return TTSH_OK;
@@ -929,7 +1019,7 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     g.bias = c->theta + c->ob[l];
     if (!last) {
       g.act = 1;
-      g.pre_out = c->z[l];
+      if (train) g.pre_out = c->z[l];  // pre-activations are kept for the backward pass only
     }
     if ((rc = cgemm(c, g))) return rc;
   }
@@ -965,7 +1055,6 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
       {(const char*)y, (size_t)((P - 1) * ys + c->cout) * sizeof(float)},
       {(const char*)x, (size_t)(P * c->cin) * sizeof(float)}};
   if ((rc = cgemm(c, q, ext, 2))) return rc;
-  (void)train;
   return TTSH_OK;
 }
 
@@ -1101,6 +1190,17 @@ int fno_gather(fno_ctx* c, float* dst, int64_t dch, const float* src, int64_t sc
   return TTSH_OK;
 }
 
+int fno_perturb(fno_ctx* c, float* x, int64_t pix_stride, int nch, int64_t npix, float amp, uint64_t seed) {
+  if (!c || !x) return ffail(TTSH_EINVAL, "null argument");
+  if (nch < 1 || npix < 1 || pix_stride < nch) return ffail(TTSH_EINVAL, "invalid sizes");
+  if (!(amp >= 0.f)) return ffail(TTSH_EINVAL, "amplitude must be >= 0");
+  const long long tot = (long long)npix * nch;
+  hipLaunchKernelGGL(k_perturb, dim3(nb(tot)), dim3(256), 0, c->s, x, (long long)pix_stride, nch, tot, amp,
+                     (unsigned long long)seed);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
 int fno_sample_errors(const float* y, int64_t ys, const float* t, int64_t ts, int nch, int64_t npix, int B,
                       double* out) {
   if (!y || !t || !out) return ffail(TTSH_EINVAL, "null argument");
@@ -1132,6 +1232,8 @@ int fno_gemm_bf16(int batch, int M, int N, int K, float alpha, const uint16_t* A
   g.A = op(A, rA, cA, sA, 0);
   g.B = op(B, rB, cB, sB, 0);
   g.C = C; g.c_bf16 = 0; g.sC1 = sC; g.rC = rC; g.cC = cC;
+  // the path the network's GEMMs take for these strides
+  g.staged = K % 8 == 0 && N % 8 == 0 && stage_ok(g.A) && stage_ok(g.B);
   FCHK(gemm(g, 0));
   FCHK(hipDeviceSynchronize());
   return TTSH_OK;

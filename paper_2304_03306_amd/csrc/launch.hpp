@@ -22,6 +22,9 @@ struct SizeOps {
 struct MultiOps {
   hipError_t (*row)(const MultiArgs&, int gw, hipStream_t);
   hipError_t (*col)(const MultiArgs&, int gw, int mode, hipStream_t);
+  // the same passes as one launch per size class
+  hipError_t (*row_split)(const MultiArgs&, int gw, hipStream_t);
+  hipError_t (*col_split)(const MultiArgs&, int gw, int mode, hipStream_t);
 };
 
 const SizeOps* size_ops(int N);

@@ -61,15 +61,93 @@ hipError_t col(const MultiArgs& a, int gw, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
+// the arguments of class q alone
+MultiArgs only(const MultiArgs& a, int q) {
+  MultiArgs o = a;
+  o.ncls = 1;
+  o.c[0] = a.c[q];
+  o.start[0] = 0;
+  o.start[1] = a.start[q + 1] - a.start[q];
+  return o;
+}
+
+template <int N>
+hipError_t row_one_n(const MultiArgs& o, int gw, hipStream_t s) {
+  if constexpr (TileOf<N, BS>::ok) {
+    const size_t lds = (row_smem_n<T, BS, N>());
+    if (gw)
+      hipLaunchKernelGGL((row_one<N, T, true, BS>), dim3(o.start[1]), dim3(BS), lds, s, o);
+    else
+      hipLaunchKernelGGL((row_one<N, T, false, BS>), dim3(o.start[1]), dim3(BS), lds, s, o);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+hipError_t col_one_n(const MultiArgs& o, int gw, int mode, hipStream_t s) {
+  if constexpr (TileOf<N, BS>::ok) {
+    if (mode == 1)
+      hipLaunchKernelGGL((col_one<N, T, S, false, 1, BS>), dim3(o.start[1]), dim3(BS),
+                         (col_smem_n<T, BS, false, N>()), s, o);
+    else if (gw)
+      hipLaunchKernelGGL((col_one<N, T, S, true, 0, BS>), dim3(o.start[1]), dim3(BS),
+                         (col_smem_n<T, BS, true, N>()), s, o);
+    else
+      hipLaunchKernelGGL((col_one<N, T, S, false, 0, BS>), dim3(o.start[1]), dim3(BS),
+                         (col_smem_n<T, BS, false, N>()), s, o);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+#if TTSH_PREC != 96
+hipError_t row_split(const MultiArgs& a, int gw, hipStream_t s) {
+  for (int q = 0; q < a.ncls; ++q) {
+    const MultiArgs o = only(a, q);
+    hipError_t e = hipErrorInvalidValue;
+    switch (o.c[0].N) {
+      case 64: e = row_one_n<64>(o, gw, s); break;
+      case 128: e = row_one_n<128>(o, gw, s); break;
+      case 256: e = row_one_n<256>(o, gw, s); break;
+      case 512: e = row_one_n<512>(o, gw, s); break;
+      case 1024: e = row_one_n<1024>(o, gw, s); break;
+      default: break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+#endif
+
+hipError_t col_split(const MultiArgs& a, int gw, int mode, hipStream_t s) {
+  for (int q = 0; q < a.ncls; ++q) {
+    const MultiArgs o = only(a, q);
+    hipError_t e = hipErrorInvalidValue;
+    switch (o.c[0].N) {
+      case 64: e = col_one_n<64>(o, gw, mode, s); break;
+      case 128: e = col_one_n<128>(o, gw, mode, s); break;
+      case 256: e = col_one_n<256>(o, gw, mode, s); break;
+      case 512: e = col_one_n<512>(o, gw, mode, s); break;
+      case 1024: e = col_one_n<1024>(o, gw, mode, s); break;
+      default: break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 #define TTSH_CAT4(a, b, c, d) a##b##c##d
 #define TTSH_NAME(p, b) TTSH_CAT4(multi_ops_, p, _, b)
 const MultiOps* TTSH_NAME(TTSH_PREC, TTSH_BS)() {
 #if TTSH_PREC != 96
-  static const MultiOps ops = {row, col};
+  static const MultiOps ops = {row, col, row_split, col_split};
 #else
-  static const MultiOps ops = {nullptr, col};
+  static const MultiOps ops = {nullptr, col, nullptr, col_split};
 #endif
   return &ops;
 }

@@ -145,4 +145,28 @@ __global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
   }
 }
 
+// One size class per launch (args.c[0] only): the same tile bodies compiled
+// for a single N, so that the register budget is that of this N alone and the
+// tile decode is constant; the autotuner picks this or the multi-size launch.
+template <int N, class T, bool GW, int BS>
+__global__ void __launch_bounds__(BS) row_one(MultiArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const ClassArgs& d = a.c[0];
+  const int inst = b / d.tiles;
+  const int tile = b - inst * d.tiles;
+  const RowCoef<T> c{(T)a.beta, (T)a.gamma_v, (T)a.lambda0, (T)a.gamma_w};
+  row_go<N, T, GW, BS>(d, c, inst, tile, smem);
+}
+
+template <int N, class T, class S, bool GW, int MODE, int BS>
+__global__ void __launch_bounds__(BS) col_one(MultiArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const ClassArgs& d = a.c[0];
+  const int inst = b / d.tiles;
+  const int tile = b - inst * d.tiles;
+  col_go<N, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem);
+}
+
 }  // namespace ttsh

@@ -134,6 +134,7 @@ struct ttsh_ctx {
   int bs = 0;       // workgroup size of the column pass in use
   int bs_row = 0;   // workgroup size of the row pass in use
   int opt_bs = 0;   // requested by TTSH_OPT_BLOCK (0 = chosen)
+  int split_row = 0, split_col = 0;  // one launch per size class (TTSH_OPT_SPLIT)
   int guard = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -243,10 +244,12 @@ MultiArgs multi_args(ttsh_ctx* c, int row, int inst) {
 }
 
 hipError_t launch_row(ttsh_ctx* c, const MultiArgs& m, hipStream_t s) {
-  return multi_ops(c->prec == 64 ? 64 : 32, c->bs_row)->row(m, c->gw, s);
+  const MultiOps* o = multi_ops(c->prec == 64 ? 64 : 32, c->bs_row);
+  return c->split_row ? o->row_split(m, c->gw, s) : o->row(m, c->gw, s);
 }
 hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) {
-  return multi_ops(c->prec, c->bs)->col(m, c->gw, mode, s);
+  const MultiOps* o = multi_ops(c->prec, c->bs);
+  return c->split_col ? o->col_split(m, c->gw, mode, s) : o->col(m, c->gw, mode, s);
 }
 
 int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
@@ -496,6 +499,12 @@ int ttsh_set_option(ttsh_ctx* c, int key, int64_t value) {
       if (rc) return rc;
       break;
     }
+    case TTSH_OPT_SPLIT:
+      if (value < 0 || value > 3) return fail(TTSH_EINVAL, "split must be 0..3");
+      c->split_row = (int)(value & 1);
+      c->split_col = (int)((value >> 1) & 1);
+      drop_graph(c);
+      break;
     case TTSH_OPT_GUARD:
       c->guard = value != 0;
       break;
@@ -952,7 +961,7 @@ int ttsh_pass_times(ttsh_ctx* c, int64_t nsteps, double* out) {
   return TTSH_OK;
 }
 
-int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* bs_out, double* us_out) {
+int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
   if (!c) return fail(TTSH_EINVAL, "null context");
   if (nsteps < 1 || nsteps > 100000) return fail(TTSH_EINVAL, "nsteps must be in 1..1e5");
   // save the state and the mixed-domain v, omega of every class
@@ -979,17 +988,20 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* bs_out, double* us_out) {
   };
   int rc = TTSH_OK;
   if (copy_all(true) != hipSuccess) rc = fail(TTSH_EHIP, "tuner save failed");
-  const int keep_bs = c->bs, keep_row = c->bs_row;
-  int best_row = 0, best_col = 0;
+  const int keep_bs = c->bs, keep_row = c->bs_row, keep_sr = c->split_row, keep_sc = c->split_col;
+  int best_row = 0, best_col = 0, best_sr = 0, best_sc = 0;
   double row_us = 0.0, col_us = 0.0;
-  for (int bs : {64, 128, 256}) {
-    if (rc != TTSH_OK || !bs_valid(c, bs)) continue;
-    c->bs = c->bs_row = bs;
-    double t[2];
-    if (enqueue_steps(c, 2, c->stream) != TTSH_OK) { rc = TTSH_EHIP; break; }  // warm-up
-    if ((rc = ttsh_pass_times(c, nsteps, t)) != TTSH_OK) break;
-    if (!best_row || t[0] < row_us) { best_row = bs; row_us = t[0]; }
-    if (!best_col || t[1] < col_us) { best_col = bs; col_us = t[1]; }
+  for (int split = 0; split < 2 && rc == TTSH_OK; ++split) {
+    for (int bs : {64, 128, 256}) {
+      if (rc != TTSH_OK || !bs_valid(c, bs)) continue;
+      c->bs = c->bs_row = bs;
+      c->split_row = c->split_col = split;
+      double t[2];
+      if (enqueue_steps(c, 2, c->stream) != TTSH_OK) { rc = TTSH_EHIP; break; }  // warm-up
+      if ((rc = ttsh_pass_times(c, nsteps, t)) != TTSH_OK) break;
+      if (!best_row || t[0] < row_us) { best_row = bs; best_sr = split; row_us = t[0]; }
+      if (!best_col || t[1] < col_us) { best_col = bs; best_sc = split; col_us = t[1]; }
+    }
   }
   if (copy_all(false) != hipSuccess && rc == TTSH_OK) rc = fail(TTSH_EHIP, "tuner restore failed");
   hipStreamSynchronize(c->stream);
@@ -997,17 +1009,26 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* bs_out, double* us_out) {
   if (rc != TTSH_OK || !best_row) {
     c->bs = keep_bs;
     c->bs_row = keep_row;
+    c->split_row = keep_sr;
+    c->split_col = keep_sc;
     return rc ? rc : fail(TTSH_EUNSUPPORTED, "no workgroup size to tune");
   }
   // the two passes are tuned independently (the data layout does not depend
   // on the workgroup size)
   c->bs_row = best_row;
   c->bs = best_col;
+  c->split_row = best_sr;
+  c->split_col = best_sc;
   c->opt_bs = 0;
   drop_graph(c);
   const int best = best_col;
   const double best_us = row_us + col_us;
-  if (bs_out) *bs_out = best_row * 1000 + best;
+  if (cfg_out) {
+    cfg_out[0] = best_row;
+    cfg_out[1] = best;
+    cfg_out[2] = best_sr;
+    cfg_out[3] = best_sc;
+  }
   if (us_out) *us_out = best_us;
   return TTSH_OK;
 }

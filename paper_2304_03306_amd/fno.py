@@ -26,6 +26,7 @@ def lib():
             "fno_forward": ([vp, vp, vp, i32, i32], ctypes.c_int),
             "fno_forward_ex": ([vp, vp, vp, i64, i32, i32, i32], ctypes.c_int),
             "fno_gather": ([vp, vp, i64, vp, i64, i32, i64, vp, i32], ctypes.c_int),
+            "fno_perturb": ([vp, vp, i64, i32, i64, f32, u64], ctypes.c_int),
             "fno_sample_errors": ([vp, i64, vp, i64, i32, i64, i32, vp], ctypes.c_int),
             "fno_loss": ([vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "fno_loss_ex": ([vp, vp, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -112,6 +113,9 @@ class FNO:
         yp = ctypes.c_void_p(y) if isinstance(y, int) else _ptr(y)
         _check(lib().fno_forward_ex(self.ctx, _ptr(x), yp, int(y_pix_stride), int(bool(residual)), int(batch),
                                     int(bool(train))))
+
+    def perturb(self, x, pix_stride, nch, npix, amp, seed):
+        _check(lib().fno_perturb(self.ctx, _ptr(x), int(pix_stride), int(nch), int(npix), float(amp), int(seed)))
 
     def gather(self, dst, dst_ch, src, src_ch, nch, npix, idx):
         """Copy samples idx (host int64 indices) of src into dst."""

@@ -45,6 +45,7 @@ class SurrogateConfig:
     cin: int = 3           # v_x, v_y, K
     cout: int = 2
     increment_loss: bool = False  # normalise the loss by the change over the step (fno_loss_ex)
+    input_noise: float = 0.0      # uniform perturbation of the input velocity in training
 
 
 def _torch():
@@ -69,7 +70,7 @@ def coarse_masks(instances: Sequence[Instance], Nc: int, params) -> np.ndarray:
 
 
 def new_solver(instances: Sequence[Instance], params, precision=T.TTSH_FP32, seed_fields=True,
-               graph_steps: int = 20) -> T.Solver:
+               graph_steps: int = 20, tune: bool = True) -> T.Solver:
     """A solver context over the instances, masks set, started from each
     instance's seeded initial field; steps are replayed from graphs of
     graph_steps steps (one surrogate step's worth)."""
@@ -79,6 +80,8 @@ def new_solver(instances: Sequence[Instance], params, precision=T.TTSH_FP32, see
         s.mask_tanh(q, inst.centers, inst.radii, inst.xi)
         if seed_fields:
             s.set_field(q, uniform_field(inst.seed, inst.N, 0.01, precision))
+    if tune:
+        s.tune(graph_steps)  # workgroup sizes per pass; the state is restored
     return s
 
 
@@ -148,6 +151,8 @@ class Trainer:
         B = len(idx)
         self.net.gather(self.xb, c.cin, D, 3, c.cin, npix, idx)
         self.net.gather(self.tb, c.cout, D, 3, c.cout, npix, idx + I)
+        if c.input_noise > 0:
+            self.net.perturb(self.xb, c.cin, c.cout, B * npix, c.input_noise, self.step_count + 1)
         self.net.forward_ex(self.xb, self.yb, c.cout, True, B, train=True)
         if c.increment_loss:
             loss = self.net.loss_ex(self.yb, self.tb, self.xb, c.cin, B)
@@ -371,19 +376,32 @@ def main(argv=None):
     ap.add_argument("--train-seconds", type=float, default=300.0)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--modes", type=int, default=16)
+    ap.add_argument("--input-noise", type=float, default=0.0)
     ap.add_argument("--threshold", type=float, default=0.1)
     ap.add_argument("--check-every", type=int, default=25)
     ap.add_argument("--report", default="surrogate_report.json")
+    ap.add_argument("--speed-only", action="store_true",
+                    help="only time one surrogate step against the solver's 20 steps (untrained weights)")
     a = ap.parse_args(argv)
     torch = _torch()
     log = lambda m: print(f"[surrogate] {m}", flush=True)
     wl = Wl.radius_sweep()
     inst = wl.instances
     params = Wl.workload_coefficients()
-    cfg = SurrogateConfig(batch=a.batch, lr=a.lr)
+    cfg = SurrogateConfig(batch=a.batch, lr=a.lr, modes=a.modes, input_noise=a.input_noise)
     I, Nc = len(inst), cfg.Nc
     masks = coarse_masks(inst, Nc, params)
     solver = new_solver(inst, params)
+    if a.speed_only:
+        D = collect(solver, masks, 1, cfg.every, Nc, transient=a.transient)
+        net = F.FNO(width=cfg.width, modes=cfg.modes, layers=cfg.layers, cin=cfg.cin, cout=cfg.cout,
+                    hidden=cfg.hidden, H=Nc, W=Nc, max_batch=I, seed=0)
+        t_sur = surrogate_step_seconds(net, solver, D[0], Nc)
+        t_sol = solver_step_seconds(solver, cfg.every)
+        log(f"surrogate step {t_sur * 1e3:.3f} ms, {cfg.every} solver steps {t_sol * 1e3:.3f} ms: "
+            f"{t_sol / t_sur:.2f}x")
+        return {"seconds_per_surrogate_step": t_sur, "seconds_per_solver_steps": t_sol}
     log(f"{I} instances, transient {a.transient} steps, {a.snapshots} snapshots every {cfg.every}")
     D = collect(solver, masks, a.snapshots, cfg.every, Nc, transient=a.transient, log=log)
     train_ids, test_ids = split_by_radius(I // 2)
@@ -415,7 +433,8 @@ def main(argv=None):
     rep = {
         "instances": I, "coarse_grid": Nc, "solver_steps_per_surrogate_step": cfg.every,
         "network": dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, hidden=cfg.hidden,
-                        params=int(tr.net.n), dtype="bf16 storage, fp32 accumulation"),
+                        params=int(tr.net.n), dtype="bf16 storage, fp32 accumulation",
+                        input_noise=cfg.input_noise),
         "data": dict(transient=a.transient, snapshots=a.snapshots, train_pairs=len(tr.pairs(Dtrain, train_ids)),
                      train_instances=train_ids, test_instances=test_ids),
         "training": dict(epochs=len(hist), seconds=hist[-1][2], loss_first=hist[0][1], loss_last=hist[-1][1],

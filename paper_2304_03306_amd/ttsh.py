@@ -19,7 +19,7 @@ TTSH_OK, TTSH_EINVAL, TTSH_EUNSUPPORTED, TTSH_EHIP, TTSH_ENONFINITE, TTSH_ENOMEM
 TTSH_HOST, TTSH_DEVICE = 0, 1
 TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX = 0, 1, 2
 TTSH_FP32, TTSH_FP64, TTSH_FP32_STATE64 = 32, 64, 96
-TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD = 1, 2, 4
+TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD, TTSH_OPT_SPLIT = 1, 2, 4, 8
 SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX}
 
 
@@ -256,12 +256,13 @@ def ttsh_pass_times(ctx, nsteps):
 
 
 def ttsh_tune(ctx, nsteps):
-    """Pick the fastest workgroup sizes; returns ((row_size, col_size), us_per_step)."""
-    bs = ctypes.c_int()
+    """Pick the fastest launch configuration of each pass; returns
+    ((row_size, col_size, row_split, col_split), us_per_step)."""
+    cfg = (ctypes.c_int * 4)()
     us = ctypes.c_double()
-    _check(lib().ttsh_tune(ctx, int(nsteps), ctypes.cast(ctypes.byref(bs), ctypes.c_void_p),
+    _check(lib().ttsh_tune(ctx, int(nsteps), ctypes.cast(cfg, ctypes.c_void_p),
                            ctypes.cast(ctypes.byref(us), ctypes.c_void_p)))
-    return (bs.value // 1000, bs.value % 1000), us.value
+    return tuple(cfg), us.value
 
 
 def ttsh_last_error() -> str:

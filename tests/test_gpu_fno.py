@@ -34,8 +34,11 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("case", ["plain", "transposed", "batched_odd"])
+@pytest.mark.parametrize("case", ["plain", "transposed", "batched_odd", "staged_tails"])
 def test_gemm_layout_matches_numpy(gpu, case):
+    """plain and staged_tails take the LDS-staged path (unit column strides,
+    K and N multiples of 8; staged_tails has ragged M and a K that is not a
+    multiple of the 32-wide k chunk), the others the direct-load path."""
     import torch
     from paper_2304_03306_amd import fno
     say("gemm", case)
@@ -44,6 +47,8 @@ def test_gemm_layout_matches_numpy(gpu, case):
         bt, M, N, K = 1, 64, 96, 48
     elif case == "transposed":
         bt, M, N, K = 1, 37, 29, 70
+    elif case == "staged_tails":
+        bt, M, N, K = 3, 37, 24, 40
     else:
         bt, M, N, K = 5, 33, 17, 19
     A = rng.standard_normal((bt, M, K))
@@ -267,3 +272,23 @@ def test_increment_loss_and_its_gradient(gpu):
     for k in go:
         e = rel(g[k], go[k])
         assert e < 6e-2, (k, e)
+
+
+def test_perturb_is_bounded_reproducible_and_channel_limited(gpu):
+    """fno_perturb adds amp * U[-1, 1) to the first nch channels only, the
+    same for the same seed, different for another seed, mean near zero."""
+    import torch
+    say("fno perturb")
+    net, _ = make_net(gpu, SMALL, 2, seed=17)
+    x0 = torch.zeros((2, SMALL.H, SMALL.W, 3), dtype=torch.float32, device="cuda")
+    a, b, c = x0.clone(), x0.clone(), x0.clone()
+    npix = 2 * SMALL.H * SMALL.W
+    net.perturb(a, 3, 2, npix, 0.01, 5)
+    net.perturb(b, 3, 2, npix, 0.01, 5)
+    net.perturb(c, 3, 2, npix, 0.01, 6)
+    a, b, c = a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert np.all(a[..., 2] == 0)
+    d = a[..., :2]
+    assert np.abs(d).max() <= 0.01 and np.abs(d).max() > 0.0099
+    assert abs(d.mean()) < 3 * 0.01 / np.sqrt(3 * d.size)

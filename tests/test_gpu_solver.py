@@ -251,30 +251,36 @@ def test_norms(gpu):
 
 def test_block_sizes_agree_and_tuner_restores_state(gpu):
     """The workgroup size only changes how rows and columns are grouped (and
-    the order of the k = 0 row-sum reduction); the tuner leaves the state as
-    it found it."""
+    the order of the k = 0 row-sum reduction); launching each grid size on its
+    own runs the same tile code, bit for bit; the tuner leaves the state as it
+    found it."""
     say("block sizes / tuner")
     p = O.workload_params()
     Ns, Ls = [256, 128, 512], [100.0, 64.0, 256.0]
     out = {}
-    for bs in (64, 128, 256):
+    for bs, split in ((64, 0), (128, 0), (256, 0), (64, 3), (128, 1), (256, 2)):
         s = gpu.Solver(Ns, Ls, p, 32)
         s.option(gpu.TTSH_OPT_BLOCK, bs)
+        s.option(gpu.TTSH_OPT_SPLIT, split)
         for i, (N, L) in enumerate(zip(Ns, Ls)):
             s.mask_tanh(i, [(0.0, 0.0)], [L / 4], 0.5)
             s.set_field(i, W.uniform_field(40 + i, N, 0.2, 32))
-        if bs == 128:
+        if bs == 128 and split == 0:
             before = [s.state(i) for i in range(3)]
-            (brow, bcol), us = s.tune(3)
+            (brow, bcol, srow, scol), us = s.tune(3)
             assert brow in (64, 128, 256) and bcol in (64, 128, 256) and us > 0
+            assert srow in (0, 1) and scol in (0, 1)
             for i in range(3):
                 assert np.array_equal(s.state(i), before[i])
         s.step(20)
         s.sync()
-        out[bs] = [s.state(i) for i in range(3)]
-    for bs in (64, 128):
-        for a, b in zip(out[bs], out[256]):
-            assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+        out[(bs, split)] = [s.state(i) for i in range(3)]
+    for key, st in out.items():
+        for a, b in zip(st, out[(256, 0)]):
+            assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max(), key
+    # a per-size launch runs the same tile code as the multi-size launch
+    for a, b in zip(out[(64, 3)], out[(64, 0)]):
+        assert np.array_equal(a, b)
 
 
 def test_reseed_matches_oracle(gpu):
