@@ -41,9 +41,22 @@ __host__ __device__ inline float bf2f(bf16 h) {
   return f;
 }
 
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz and Stegun, Handbook of Mathematical Functions, 7.1.26:
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2}, t = 1/(1 + p x),
+// |error| <= 1.5e-7 for x >= 0 (odd extension).  The activations it feeds are
+// stored in BF16 (relative resolution 2^-8), so the error is far below what is
+// kept, and it costs a third of the library erf.
+__device__ inline float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+}
+// exact (erf) GELU and its derivative
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ inline float gelu_grad(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
 
 // ---- GEMM -------------------------------------------------------------------------------

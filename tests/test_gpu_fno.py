@@ -292,3 +292,31 @@ def test_perturb_is_bounded_reproducible_and_channel_limited(gpu):
     d = a[..., :2]
     assert np.abs(d).max() <= 0.01 and np.abs(d).max() > 0.0099
     assert abs(d.mean()) < 3 * 0.01 / np.sqrt(3 * d.size)
+
+
+def test_gelu_matches_exact_erf_form(gpu):
+    """The library's GELU (erf by Abramowitz-Stegun 7.1.26, |error| <= 1.5e-7)
+    against the FP64 oracle's exact erf GELU: a network whose only non-zero
+    parameters make channel c of every point GELU(GELU(z_c)) for 16 values
+    z_c in [-6, 6] and output their mean; equal to BF16 rounding."""
+    import torch
+    from paper_2304_03306_amd import fno
+    say("fno gelu")
+    cfg = F.Config(H=16, W=16, cin=1, cout=1, width=16, modes=2, layers=2, hidden=16)
+    p = F.init_params(cfg, 0)
+    for k in p:
+        p[k] = np.zeros_like(p[k])
+    z = np.linspace(-6.0, 6.0, 16)
+    p["b0"] = z  # layer 0 output channel c = GELU(z[c])
+    p["W1"] = np.eye(16)  # layer 1 (no activation): passes it through
+    p["Q1_w"] = np.eye(16)
+    p["Q2_w"] = np.full((16, 1), 1.0 / 16)
+    net = fno.FNO(width=16, modes=2, layers=2, cin=1, cout=1, hidden=16, H=16, W=16, max_batch=1, seed=0)
+    net.set_params(fno.flatten_params(p, cfg.layers))
+    x = torch.zeros((1, 16, 16, 1), dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    net.forward(x, y, train=True)
+    pq = fno.unflatten(net.params(), p, cfg.layers)
+    ref = F.forward(pq, np.zeros((1, 16, 16, 1)), cfg)
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 2e-2 * max(1.0, np.abs(ref).max())
