@@ -143,6 +143,17 @@ int ttsh_get_field(ttsh_ctx* ctx, int inst, double* v, double* omega, int where)
  * Asynchronous on the context's stream.                                    */
 int ttsh_get_field_coarse(ttsh_ctx* ctx, int inst, int Nc, float* out, int64_t pix_stride);
 
+/* Order parameters of instance inst from its real-space fields (FP64, fixed
+ * summation order; node (i, j) at x = (j - N/2) L/N, y = (i - N/2) L/N):
+ *   out[0] = Psi, the vortex order parameter about (cx, cy) (circle
+ *            section): ([sum |e_theta . v| / sum |v|] - 2/pi) / (1 - 2/pi);
+ *   out[1] = Psi_2 (two-chamber section): with w_l, w_r the vorticity at the
+ *            nodes of largest |omega| left of x = cx and at or right of it
+ *            (ties to the first node in row-major order),
+ *            |w_l + w_r| / (|w_l| + |w_r|).
+ * Synchronous.                                                              */
+int ttsh_order(ttsh_ctx* ctx, int inst, double cx, double cy, double* out);
+
 /* Inverse of ttsh_get_field_coarse: set instance inst from a coarse real
  * velocity on an Nc x Nc grid of the same box (device float32, layout as in
  * ttsh_get_field_coarse).  The field is transformed, cut to the coarse 1/2

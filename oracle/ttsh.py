@@ -441,6 +441,22 @@ def vortex_order(v: np.ndarray, L: float, center=(0.0, 0.0)) -> float:
     return float((num / den - 2.0 / math.pi) / (1.0 - 2.0 / math.pi))
 
 
+def vortex_order2(w: np.ndarray, L: float, split_x: float = 0.0) -> float:
+    """Order parameter Psi_2 of the two-chamber (dumbbell) section: with
+    x_left / x_right the nodes of largest |omega| left of x = split_x and at or
+    right of it, |w(x_left) + w(x_right)| / (|w(x_left)| + |w(x_right)|); 1 for
+    co-rotating (ferromagnetic), 0 for counter-rotating vortices.  Ties go to
+    the first node in row-major order."""
+    N = w.shape[-1]
+    x, _ = node_coords(N, L)
+    left = x < split_x
+    aw = np.abs(w)
+    iL = int(np.argmax(np.where(left, aw, -1.0)))
+    iR = int(np.argmax(np.where(left, -1.0, aw)))
+    wl, wr = w.flat[iL], w.flat[iR]
+    return float(abs(wl + wr) / (abs(wl) + abs(wr)))
+
+
 def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
     """||a - b||_2 / ||b||_2 over all entries, FP64 sums."""
     a = np.asarray(a, dtype=np.float64)

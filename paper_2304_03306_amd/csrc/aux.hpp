@@ -273,6 +273,81 @@ __global__ void k_resample(const C2<S>* __restrict__ src, int Ns, C2<double>* __
   dst[i] = v;
 }
 
+// ---- order parameters on the real-space fields ------------------------------
+// Vortex order parameter about (cx, cy) of the velocity in Z (real part v_x,
+// imaginary part v_y, node (i, j) at x = (j - N/2) dx, y = (i - N/2) dx):
+// sums of |e_theta . v| and |v| in FP64 in a fixed order (one workgroup).
+__global__ void __launch_bounds__(1024) k_order_psi(const C2<double>* __restrict__ Z, int N, double dx, double cx,
+                                                    double cy, double* __restrict__ out) {
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+    const double x = ((i % N) - N / 2) * dx - cx, y = ((i / N) - N / 2) * dx - cy;
+    const double r = sqrt(x * x + y * y);
+    const C2<double> v = Z[i];
+    if (r > 0.0) num += fabs((-y * v.x + x * v.y) / r);
+    den += sqrt(v.x * v.x + v.y * v.y);
+  }
+  num = wave_sum_from(num, 1);
+  den = wave_sum_from(den, 1);
+  __shared__ double red[16][2];
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = num;
+    red[threadIdx.x >> 6][1] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += red[w][0];
+      b += red[w][1];
+    }
+    const double two_pi = 2.0 / M_PI;
+    out[0] = (a / b - two_pi) / (1.0 - two_pi);
+  }
+}
+
+// Two-chamber order parameter from the vorticity in the real part of Z: the
+// nodes of largest |omega| left of x = cx and at or right of it (ties to the
+// lower index), |w_l + w_r| / (|w_l| + |w_r|).
+__global__ void __launch_bounds__(1024) k_order_psi2(const C2<double>* __restrict__ Z, int N, double dx, double cx,
+                                                     double* __restrict__ out) {
+  double best[2] = {-1.0, -1.0};
+  int at[2] = {0, 0};
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+    const double x = ((i % N) - N / 2) * dx;
+    const int side = x < cx ? 0 : 1;
+    const double a = fabs(Z[i].x);
+    if (a > best[side]) {  // i grows per thread: the first of equal values is kept
+      best[side] = a;
+      at[side] = i;
+    }
+  }
+  __shared__ double bv[2][1024];
+  __shared__ int bi[2][1024];
+  for (int q = 0; q < 2; ++q) {
+    bv[q][threadIdx.x] = best[q];
+    bi[q][threadIdx.x] = at[q];
+  }
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int q = 0; q < 2; ++q) {
+        const double v2 = bv[q][threadIdx.x + o];
+        const int i2 = bi[q][threadIdx.x + o];
+        if (v2 > bv[q][threadIdx.x] || (v2 == bv[q][threadIdx.x] && i2 < bi[q][threadIdx.x])) {
+          bv[q][threadIdx.x] = v2;
+          bi[q][threadIdx.x] = i2;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double wl = Z[bi[0][0]].x, wr = Z[bi[1][0]].x;
+    out[1] = fabs(wl + wr) / (fabs(wl) + fabs(wr));
+  }
+}
+
 // ---- FP64 norms on the compact state -----------------------------------------
 // out[0] = sum_x |v|^2 (Parseval, unitary), out[1..2] = <v_x>, <v_y>,
 // out[3] = max |k . v_hat|, out[4] = 1 if any entry is non-finite.

@@ -778,6 +778,36 @@ int ttsh_project_coarse(ttsh_ctx* c, int N, float* v, int64_t pix_stride, int ba
   return TTSH_OK;
 }
 
+int ttsh_order(ttsh_ctx* c, int inst, double cx, double cy, double* out) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!out) return fail(TTSH_EINVAL, "null output");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, n = N * N;
+  const double L = c->L[inst], dk = 2.0 * M_PI / L, dx = L / N;
+  for (int what = 0; what < 2; ++what) {
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_state_to_full<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                         at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), (C2<double>*)c->scr0, N, dk, what);
+    else
+      hipLaunchKernelGGL(k_state_to_full<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                         at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), (C2<double>*)c->scr0, N, dk, what);
+    HIPCHK(hipGetLastError());
+    HIPCHK(size_ops(N)->fft2(c->scr0, 1, +1, 1, c->tw64[N], c->stream));
+    if (what == 0)
+      hipLaunchKernelGGL(k_order_psi, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx, cy,
+                         c->dnorm);
+    else
+      hipLaunchKernelGGL(k_order_psi2, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx,
+                         c->dnorm);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipMemcpyAsync(out, c->dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
 int ttsh_set_state(ttsh_ctx* c, int inst, const double* vhat, int where) {
   int rc = check_inst(c, inst);
   if (rc) return rc;

@@ -174,3 +174,52 @@ def unflatten(vec: np.ndarray, like: dict, layers: int) -> dict:
     for k in ("Q1_w", "Q1_b", "Q2_w", "Q2_b"):
         out[k] = take(like[k].shape)
     return out
+
+
+def main(argv=None):
+    """Time the network on random inputs: inference (residual, in place) and
+    one training step (forward, loss, backward, Adam), HIP-synchronised."""
+    import argparse
+    import time
+
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--width", type=int, default=32)
+    ap.add_argument("--modes", type=int, default=16)
+    ap.add_argument("--layers", type=int, default=4)
+    ap.add_argument("--hidden", type=int, default=128)
+    ap.add_argument("--iters", type=int, default=5)
+    ap.add_argument("--no-train", action="store_true")
+    a = ap.parse_args(argv)
+    B, n = a.batch, a.size
+    net = FNO(width=a.width, modes=a.modes, layers=a.layers, cin=3, cout=2, hidden=a.hidden, H=n, W=n,
+              max_batch=B, seed=0)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(B, n, n, 3, device="cuda", generator=gen)
+    t = torch.randn(B, n, n, 2, device="cuda", generator=gen)
+    y = torch.empty(B, n, n, 2, device="cuda")
+    net.forward_ex(x, y, 2, True, B)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(a.iters):
+        net.forward_ex(x, y, 2, True, B)
+    torch.cuda.synchronize()
+    inf = (time.time() - t0) / a.iters
+    out = {"batch": B, "size": n, "inference_ms": inf * 1e3}
+    if not a.no_train:
+        t0 = time.time()
+        for _ in range(a.iters):
+            net.forward_ex(x, y, 2, True, B, train=True)
+            net.loss(y, t)
+            net.backward(B)
+            net.adam_step(1e-4)
+        torch.cuda.synchronize()
+        out["train_step_ms"] = (time.time() - t0) / a.iters * 1e3
+    print(out, flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -58,6 +58,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_get_field_coarse": [vp, i32, i32, dp, i64],
             "ttsh_set_field_coarse": [vp, i32, i32, dp, i64],
             "ttsh_project_coarse": [vp, i32, dp, i64, i32, dp],
+            "ttsh_order": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
             "ttsh_step": [vp, i64],
@@ -174,6 +175,13 @@ def ttsh_get_field_coarse(ctx, inst, Nc, out, pix_stride=2):
         raise ValueError("out too small")
     return _check(lib().ttsh_get_field_coarse(ctx, int(inst), int(Nc), ctypes.c_void_p(out.data_ptr()),
                                               int(pix_stride)))
+
+
+def ttsh_order(ctx, inst, center=(0.0, 0.0)):
+    """(Psi about center, Psi_2 split at x = center[0])."""
+    out = (ctypes.c_double * 2)()
+    _check(lib().ttsh_order(ctx, int(inst), float(center[0]), float(center[1]), ctypes.cast(out, ctypes.c_void_p)))
+    return out[0], out[1]
 
 
 def _dev_addr(x):
@@ -311,6 +319,9 @@ class Solver:
         w = np.empty((n, n)) if omega else None
         ttsh_get_field(self.ctx, inst, v, w)
         return (v, w) if omega else v
+
+    def order(self, inst, center=(0.0, 0.0)):
+        return ttsh_order(self.ctx, inst, center)
 
     def field_coarse(self, inst, Nc, out, pix_stride=2):
         ttsh_get_field_coarse(self.ctx, inst, Nc, out, pix_stride)

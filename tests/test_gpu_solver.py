@@ -394,3 +394,27 @@ def test_failure_injection_nonfinite_input_and_unstable_mask(gpu):
     with pytest.raises(gpu.TTSHError) as e:
         u.sync()
     assert e.value.code == gpu.TTSH_ENONFINITE and "instance 1" in str(e.value)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_order_parameters_match_oracle(gpu, prec):
+    """Psi and Psi_2 from the library equal the oracle's on the same state:
+    a 256^2 dumbbell instance after 300 steps and a circle after 200."""
+    say("order parameters", prec)
+    p = O.workload_params()
+    N, L = 256, 128.0
+    s = gpu.Solver([N, N], [L, L], p, prec)
+    s.mask_tanh(0, [(-20.0, 0.0), (20.0, 0.0)], [20.0, 20.0], 0.5)
+    s.mask_tanh(1, [(0.0, 0.0)], [30.0], 0.5)
+    s.set_field(0, W.uniform_field(90, N, 0.1, prec))
+    s.set_field(1, W.uniform_field(91, N, 0.1, prec))
+    s.step(300)
+    s.sync()
+    for i, cen in ((0, (0.0, 0.0)), (1, (0.0, 0.0)), (1, (3.0, -2.0))):
+        vh = O.from_compact(s.state(i), N)
+        v = O.field(vh)
+        kx, ky, _, _ = O.grid(N, L)
+        w = O.field(O.vorticity_hat(vh, kx, ky)[None])[0]
+        psi, psi2 = s.order(i, cen)
+        assert abs(psi - O.vortex_order(v, L, cen)) < 1e-12
+        assert abs(psi2 - O.vortex_order2(w, L, cen[0])) < 1e-12

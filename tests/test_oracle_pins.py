@@ -397,3 +397,21 @@ def test_resample_preserves_band_limited_field():
     down = O.resample(vh64, Ns)
     keep = O.dealias_keep(Ns)
     assert np.abs(down[:, ~keep]).max() == 0
+
+
+def test_vortex_order2_limits():
+    """Psi_2 (two-chamber section): two co-rotating Gaussian vortices give 1,
+    counter-rotating ones 0, whatever their (unequal) strengths and the
+    background noise below their peaks."""
+    N, L = 64, 64.0
+    x, y = O.node_coords(N, L)
+    bump = lambda cx, a: a * np.exp(-((x - cx) ** 2 + y ** 2) / 20.0)
+    rng = np.random.default_rng(0)
+    noise = 1e-3 * rng.standard_normal((N, N))
+    w_same = bump(-16.0, 1.0) + bump(16.0, 0.7) + noise
+    w_opp = bump(-16.0, 1.0) + bump(16.0, -0.7) + noise
+    assert abs(O.vortex_order2(w_same, L) - 1.0) < 1e-12
+    assert O.vortex_order2(w_opp, L) < 0.2 and abs(O.vortex_order2(w_opp, L) - 0.3 / 1.7) < 5e-3
+    # the split decides which peaks compete: past the right vortex the right
+    # side holds only noise, so Psi_2 is ~1 whatever the vortices' signs
+    assert O.vortex_order2(w_opp, L, split_x=30.0) > 0.99
