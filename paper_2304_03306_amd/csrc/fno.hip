@@ -82,7 +82,7 @@ struct GemmArgs {
   const float* skip;       // float C only: C[i][j] += skip[i * skip_r + j] (after everything else)
   long long skip_r;
   int vecC;                // set by the launcher: rows of C hold aligned runs of 4 contiguous columns
-  int staged;              // set by the launcher: operands staged through LDS (gemm_part_lds)
+  int staged;              // set by the launcher: -1 direct loads, else 2 FA + FB of gemm_part_lds
 };
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
@@ -129,17 +129,41 @@ __device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, 
 }
 
 // The same product with both operands staged through the wavefront's own LDS
-// in chunks of 32 along k: rows of A (k contiguous) and rows of B (n
-// contiguous) are read with coalesced 16-byte loads, B is transposed on its
-// way into LDS, and the fragments are 8-byte LDS reads.  Requires unit
-// column strides, row and batch strides and K, N multiples of 8, and 16-byte
-// aligned operands (the launcher checks).
+// in chunks of 32 along k, read from HBM with coalesced 16-byte loads along
+// whichever dimension is contiguous: FA = 0 when A's rows run along k, 1 when
+// its columns do (A given transposed); FB = 0 when B's rows run along n, 1
+// when along k.  LDS holds A as [m][k] and B as [n][k] (k contiguous, what the
+// MFMA fragments read 4 at a time), so the operands whose memory runs along
+// the other dimension are transposed on their way in.  The launcher checks
+// unit strides, multiples of 8 and 16-byte alignment.
 constexpr int kKC = 32, kLDK = 40;  // k chunk, LDS row stride (bf16) with padding
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// stage a 32 x 32 block: rows `lo` (m or n, limit `nlo`) and k from k0 (limit
+// K) of an operand whose element (row, k) sits at base + row * rs + k * ks;
+// KRUN: the 16-byte runs go along k (ks == 1), else along rows (rs == 1)
+template <bool KRUN>
+__device__ inline void stage_block(const bf16* __restrict__ base, long long rs, long long ks, int lo, int nlo, int k0,
+                                   int K, int lane, bf16* __restrict__ dst) {
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int a = pass * 16 + (lane >> 2), seg = (lane & 3) * 8;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if constexpr (KRUN) {  // a = row, seg = k offset
+      if (lo + a < nlo && k0 + seg < K) v = *(const uint4*)(base + (long long)(lo + a) * rs + k0 + seg);
+      *(uint4*)(dst + a * kLDK + seg) = v;
+    } else {  // a = k offset, seg = row offset
+      if (k0 + a < K && lo + seg < nlo) v = *(const uint4*)(base + (long long)(k0 + a) * ks + lo + seg);
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dst[(seg + q) * kLDK + a] = e[q];
+    }
+  }
+}
+template <int FA, int FB>
 __device__ inline void gemm_part_lds(const Op& A, const Op& B, int K, int M, int N, int b1, int b2, int i0, int j0,
                                      int lane, float4_t (&acc)[2][2], bf16* __restrict__ As,
                                      bf16* __restrict__ Bt) {
@@ -147,17 +171,9 @@ __device__ inline void gemm_part_lds(const Op& A, const Op& B, int K, int M, int
   const bf16* pb = B.p + b1 * B.s1 + b2 * B.s2;
   const int rl = lane & 15, kq = (lane >> 4) * 4;
   for (int k0 = 0; k0 < K; k0 += kKC) {
-#pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-      const int r = pass * 16 + (lane >> 2), seg = (lane & 3) * 8;
-      uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
-      if (i0 + r < M && k0 + seg < K) va = *(const uint4*)(pa + (long long)(i0 + r) * A.r + k0 + seg);
-      if (k0 + r < K && j0 + seg < N) vb = *(const uint4*)(pb + (long long)(k0 + r) * B.r + j0 + seg);
-      *(uint4*)(As + r * kLDK + seg) = va;
-      const bf16* e = (const bf16*)&vb;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Bt[(seg + q) * kLDK + r] = e[q];
-    }
+    // A(i, k) at pa + i * A.r + k * A.c;  B(k, j) at pb + k * B.r + j * B.c
+    stage_block<FA == 0>(pa, A.r, A.c, i0, M, k0, K, lane, As);
+    stage_block<FB == 1>(pb, B.c, B.r, j0, N, k0, K, lane, Bt);
     wave_lds_sync();
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 16) {
@@ -180,7 +196,8 @@ __device__ inline void gemm_part_lds(const Op& A, const Op& B, int K, int M, int
 // Work items (batch, tile) are numbered batch-major and dealt four to a
 // workgroup, one per wavefront, so that GEMMs with a single tile per batch
 // still fill every wavefront.
-template <bool STAGED>
+// STAGED: -1 direct loads; else 2 * FA + FB of the LDS-staged form
+template <int STAGED>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int tiles) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long nbatch = (long long)g.nb1 * g.nb2;
@@ -198,11 +215,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int 
       acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
       acc2[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
     }
-  if constexpr (STAGED) {
+  if constexpr (STAGED >= 0) {
+    constexpr int FA = STAGED >> 1, FB = STAGED & 1;
     __shared__ __align__(16) bf16 stage[4][2][32 * kLDK];
-    gemm_part_lds(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc, stage[wave][0], stage[wave][1]);
+    gemm_part_lds<FA, FB>(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc, stage[wave][0], stage[wave][1]);
     if (g.K2 > 0)
-      gemm_part_lds(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2, stage[wave][0], stage[wave][1]);
+      gemm_part_lds<FA, FB>(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2, stage[wave][0],
+                            stage[wave][1]);
   } else {
     gemm_part(g.A, g.B, g.K, g.M, g.N, b1, b2, i0, j0, lane, acc);
     if (g.K2 > 0) gemm_part(g.A2, g.B2, g.K2, g.M, g.N, b1, b2, i0, j0, lane, acc2);
@@ -263,17 +282,35 @@ hipError_t gemm(const GemmArgs& g, hipStream_t s) {
   const int tiles_n = (g.N + 31) / 32, tiles = ((g.M + 31) / 32) * tiles_n;
   const long long blocks = ((long long)g.nb1 * g.nb2 * tiles + 3) / 4;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (g.staged)
-    hipLaunchKernelGGL(gemm_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
-  else
-    hipLaunchKernelGGL(gemm_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
+  switch (g.staged) {
+    case 0: hipLaunchKernelGGL(gemm_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles); break;
+    case 1: hipLaunchKernelGGL(gemm_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles); break;
+    case 2: hipLaunchKernelGGL(gemm_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles); break;
+    case 3: hipLaunchKernelGGL(gemm_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles); break;
+    default: hipLaunchKernelGGL(gemm_kernel<-1>, dim3((unsigned)blocks), dim3(256), 0, s, g, tiles_n, tiles);
+  }
   return hipGetLastError();
 }
 
-// operands a staged launch can take: unit column stride, 8-element row and
-// batch strides, 16-byte aligned base
-bool stage_ok(const Op& o) {
-  return o.c == 1 && o.r % 8 == 0 && o.s1 % 8 == 0 && o.s2 % 8 == 0 && ((uintptr_t)o.p & 15) == 0;
+// Form (0 or 1) in which an operand can be staged through LDS, -1 if none:
+// its 16-byte runs go along `first` (the row dimension m of A / k of B: form
+// 0 for A means runs along k) -- see gemm_part_lds.  `run` is the stride of
+// the contiguous dimension (1), `other` the other stride; the contiguous
+// dimension's extent must be a multiple of 8.
+int stage_form(const Op& o, bool is_a, int M_or_N, int K) {
+  if (((uintptr_t)o.p & 15) || o.s1 % 8 || o.s2 % 8) return -1;
+  // A(i, k) = p[i r + k c]; B(k, j) = p[k r + j c]
+  const long long kstride = is_a ? o.c : o.r, xstride = is_a ? o.r : o.c;
+  if (kstride == 1 && xstride % 8 == 0 && K % 8 == 0) return is_a ? 0 : 1;  // runs along k
+  if (xstride == 1 && kstride % 8 == 0 && M_or_N % 8 == 0) return is_a ? 1 : 0;  // runs along m / n
+  return -1;
+}
+// staged form of a whole GEMM (both products share it), -1 if not stageable
+int staged_form(const GemmArgs& g) {
+  const int fa = stage_form(g.A, true, g.M, g.K), fb = stage_form(g.B, false, g.N, g.K);
+  if (fa < 0 || fb < 0) return -1;
+  if (g.K2 > 0 && (stage_form(g.A2, true, g.M, g.K2) != fa || stage_form(g.B2, false, g.N, g.K2) != fb)) return -1;
+  return 2 * fa + fb;
 }
 
 Op op(const bf16* p, long long r, long long c, long long s1 = 0, long long s2 = 0) { return Op{p, s1, s2, r, c, 0}; }
@@ -388,11 +425,18 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
   }
 }
 
-// dz = dh * GELU'(z)
+// dz = dh * GELU'(z), eight elements per thread with 16-byte accesses (n % 8 == 0)
 __global__ void k_gelu_back(const bf16* __restrict__ dh, const bf16* __restrict__ z, bf16* __restrict__ dz,
                             long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dz[i] = f2bf(bf2f(dh[i]) * gelu_grad(bf2f(z[i])));
+  const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  if (i >= n) return;
+  const uint4 a = *(const uint4*)(dh + i), b = *(const uint4*)(z + i);
+  const bf16* pa = (const bf16*)&a;
+  const bf16* pb = (const bf16*)&b;
+  bf16 o[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) o[q] = f2bf(bf2f(pa[q]) * gelu_grad(bf2f(pb[q])));
+  *(uint4*)(dz + i) = *(const uint4*)o;
 }
 
 __global__ void k_gather(float* __restrict__ dst, long long dch, const float* __restrict__ src, long long sch,
@@ -725,8 +769,7 @@ int cgemm(fno_ctx* c, const GemmArgs& g, const std::pair<const char*, size_t>* e
     const size_t al = g.c_bf16 ? 8 : 16;
     gv.vecC = g.cC == 1 && g.rC % 4 == 0 && g.sC1 % 4 == 0 && g.sC2 % 4 == 0 && ((uintptr_t)g.C % al) == 0;
   }
-  gv.staged = c->staged_gemm && g.K % 8 == 0 && g.N % 8 == 0 && stage_ok(g.A) && stage_ok(g.B) &&
-              (g.K2 <= 0 || (g.K2 % 8 == 0 && stage_ok(g.A2) && stage_ok(g.B2)));
+  gv.staged = c->staged_gemm ? staged_form(g) : -1;
   const hipError_t e = gemm(gv, c->s);
   if (e != hipSuccess) return ffail(TTSH_EHIP, std::string("GEMM launch: ") + hipGetErrorString(e));
   return TTSH_OK;
@@ -734,6 +777,7 @@ int cgemm(fno_ctx* c, const GemmArgs& g, const std::pair<const char*, size_t>* e
 
 GemmArgs ga() {
   GemmArgs g{};
+  g.staged = -1;
   g.nb1 = g.nb2 = 1;
   g.alpha = 1.f;
   g.alpha2 = 1.f;
@@ -1123,7 +1167,8 @@ int fno_backward(fno_ctx* c, int B) {
   for (int l = c->L - 1; l >= 0; --l) {
     const bf16* dz = dh;
     if (l < c->L - 1) {
-      hipLaunchKernelGGL(k_gelu_back, dim3(nb(P * C)), dim3(256), 0, c->s, dh, c->z[l], c->dz, P * C);
+      // P * C is a multiple of 8: P = batch H W with H, W multiples of 16
+      hipLaunchKernelGGL(k_gelu_back, dim3(nb((P * C + 7) / 8)), dim3(256), 0, c->s, dh, c->z[l], c->dz, P * C);
       FCHK(hipGetLastError());
       dz = c->dz;
     }
@@ -1246,7 +1291,7 @@ int fno_gemm_bf16(int batch, int M, int N, int K, float alpha, const uint16_t* A
   g.B = op(B, rB, cB, sB, 0);
   g.C = C; g.c_bf16 = 0; g.sC1 = sC; g.rC = rC; g.cC = cC;
   // the path the network's GEMMs take for these strides
-  g.staged = K % 8 == 0 && N % 8 == 0 && stage_ok(g.A) && stage_ok(g.B);
+  g.staged = staged_form(g);
   FCHK(gemm(g, 0));
   FCHK(hipDeviceSynchronize());
   return TTSH_OK;

@@ -34,11 +34,12 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("case", ["plain", "transposed", "batched_odd", "staged_tails"])
+@pytest.mark.parametrize("case", ["plain", "transposed", "batched_odd", "staged_tails", "tA", "tB", "tAB"])
 def test_gemm_layout_matches_numpy(gpu, case):
-    """plain and staged_tails take the LDS-staged path (unit column strides,
-    K and N multiples of 8; staged_tails has ragged M and a K that is not a
-    multiple of the 32-wide k chunk), the others the direct-load path."""
+    """plain and staged_tails take the LDS-staged path with A's rows along k
+    and B's along n (staged_tails: ragged M, K not a multiple of the 32-wide
+    k chunk); tA, tB, tAB stage A and/or B given transposed; transposed (odd
+    sizes) and batched_odd take the direct-load path."""
     import torch
     from paper_2304_03306_amd import fno
     say("gemm", case)
@@ -49,16 +50,19 @@ def test_gemm_layout_matches_numpy(gpu, case):
         bt, M, N, K = 1, 37, 29, 70
     elif case == "staged_tails":
         bt, M, N, K = 3, 37, 24, 40
+    elif case in ("tA", "tB", "tAB"):
+        bt, M, N, K = 2, 40, 24, 72
     else:
         bt, M, N, K = 5, 33, 17, 19
     A = rng.standard_normal((bt, M, K))
     B = rng.standard_normal((bt, K, N))
     Ab, Bb = bf16_round(A), bf16_round(B)
-    if case == "transposed":  # pass A^T / B^T storage with swapped strides
-        At = np.ascontiguousarray(Ab.transpose(0, 2, 1))
-        Bt = np.ascontiguousarray(Bb.transpose(0, 2, 1))
+    if case in ("transposed", "tA", "tB", "tAB"):  # A^T and/or B^T storage with swapped strides
+        ta, tb = case in ("transposed", "tA", "tAB"), case in ("transposed", "tB", "tAB")
+        At = np.ascontiguousarray(Ab.transpose(0, 2, 1)) if ta else Ab
+        Bt = np.ascontiguousarray(Bb.transpose(0, 2, 1)) if tb else Bb
         dA, dB = torch.from_numpy(At.view(np.int16)).cuda(), torch.from_numpy(Bt.view(np.int16)).cuda()
-        strides = (M * K, 1, M, K * N, 1, K)
+        strides = ((M * K, 1, M) if ta else (M * K, K, 1)) + ((K * N, 1, K) if tb else (K * N, N, 1))
     else:
         dA, dB = torch.from_numpy(Ab.view(np.int16)).cuda(), torch.from_numpy(Bb.view(np.int16)).cuda()
         strides = (M * K, K, 1, K * N, N, 1)
