@@ -48,6 +48,19 @@ def step_source_hash() -> str:
     return h.hexdigest()
 
 
+def source_revision():
+    """Git commit of the tree (with a mark if it has local changes), or None."""
+    import subprocess
+    try:
+        rev = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"], capture_output=True, text=True,
+                             timeout=10).stdout.strip()
+        dirty = subprocess.run(["git", "-C", ROOT, "status", "--porcelain", "--untracked-files=no"],
+                               capture_output=True, text=True, timeout=10).stdout.strip()
+        return (rev + ("+local-changes" if dirty else "")) or None
+    except (OSError, subprocess.SubprocessError):
+        return None
+
+
 def _pmc_means(path: str, counter: str) -> dict:
     """Mean counter value per kernel name over the dispatches of a rocprofv3
     counter_collection.csv."""
@@ -359,6 +372,7 @@ def main():
         "parity": {"rel_l2_step1000_vs_fp64_oracle": parity, "all_finite": finite},
         "plain": plain,
         "cpu_baseline": cpu,
+        "source": source_revision(),
     }
     print(json.dumps(out), flush=True)
 

@@ -418,3 +418,46 @@ def test_order_parameters_match_oracle(gpu, prec):
         psi, psi2 = s.order(i, cen)
         assert abs(psi - O.vortex_order(v, L, cen)) < 1e-12
         assert abs(psi2 - O.vortex_order2(w, L, cen[0])) < 1e-12
+
+
+@pytest.mark.parametrize("g", ["rot", "refl", "transpose"])
+def test_d4_equivariance_on_device(gpu, g):
+    """With a centred circular mask, the square grid's symmetries commute with
+    the time step: the step of a rotated (reflected, transposed) field is the
+    rotated step.  Paper preset (the gamma_w path runs too), FP64, two
+    instances of one context."""
+    say("D4 equivariance", g)
+    N, L = 128, 64.0
+    p = O.paper_params()
+    act = {"rot": O.rotate90, "refl": O.reflect_x, "transpose": O.transpose_xy}[g]
+    s = gpu.Solver([N, N], [L, L], p, 64)
+    for i in range(2):
+        s.mask_tanh(i, [(0.0, 0.0)], [20.0], 0.5)
+    v0 = O.field(O.project_field(W.uniform_field(12, N, 0.5), L))
+    s.set_field(0, v0)
+    s.set_field(1, act(v0))
+    s.step(20)
+    s.sync()
+    a, b = s.field(0), s.field(1)
+    assert np.abs(act(a) - b).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_runs_are_bitwise_deterministic(gpu):
+    """Two contexts fed the same inputs produce bit-identical states (no
+    atomics or order-dependent reductions in the step), mixed grid sizes,
+    FP32."""
+    say("determinism")
+    p = O.workload_params()
+    Ns, Ls = [128, 256, 512], [64.0, 100.0, 256.0]
+    out = []
+    for rep in range(2):
+        s = gpu.Solver(Ns, Ls, p, 32)
+        for i, (N, L) in enumerate(zip(Ns, Ls)):
+            s.mask_tanh(i, [(0.0, 0.0)], [L / 4], 0.5)
+            s.set_field(i, W.uniform_field(20 + i, N, 0.3, 32))
+        s.step(100)
+        s.sync()
+        out.append([s.state(i) for i in range(3)])
+        s.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
