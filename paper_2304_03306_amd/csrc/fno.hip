@@ -395,33 +395,49 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
       qb[hb][e] = l16 < cout ? (short)Q2[(16 * hb + q4 + e) * cout + l16] : (short)0;
     }
   }
-  for (long long t = wave; t * 16 < npts; t += nwave) {
-    const long long p = t * 16 + l16;
-    const bool ok = p < npts;
-    short4_t hv[KB];
+  // two independent groups of 16 points per iteration, for instruction-level
+  // parallelism between their MFMA and GELU chains
+  constexpr int G = 2;
+  for (long long t = wave * G; t * 16 < npts; t += nwave * G) {
+    long long p[G];
+    bool ok[G];
+    short4_t hv[G][KB];
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
-      hv[kb] = ok ? *(const short4_t*)(h + p * C + 16 * kb + q4) : short4_t{0, 0, 0, 0};
-    float4_t acc2 = {0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < G; ++g) {
+      p[g] = (t + g) * 16 + l16;
+      ok[g] = p[g] < npts;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        hv[g][kb] = ok[g] ? *(const short4_t*)(h + p[g] * C + 16 * kb + q4) : short4_t{0, 0, 0, 0};
+    }
+    float4_t acc2[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc2[g] = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int hb = 0; hb < HB; ++hb) {
-      float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa[hb][kb], hv[kb], acc, 0, 0, 0);
-      short4_t av;
+      for (int g = 0; g < G; ++g) {
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) av[e] = (short)f2bf(gelu(acc[e] + bias1[hb][e]));
-      acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qb[hb], av, acc2, 0, 0, 0);
-    }
+        for (int kb = 0; kb < KB; ++kb)
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa[hb][kb], hv[g][kb], acc, 0, 0, 0);
+        short4_t av;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int o = q4 + e;
-      if (ok && o < cout) {
-        float v = acc2[e] + b2[o];
-        if (skip) v += skip[p * skip_r + o];
-        y[p * ys + o] = v;
+        for (int e = 0; e < 4; ++e) av[e] = (short)f2bf(gelu(acc[e] + bias1[hb][e]));
+        acc2[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qb[hb], av, acc2[g], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = q4 + e;
+        if (ok[g] && o < cout) {
+          float v = acc2[g][e] + b2[o];
+          if (skip) v += skip[p[g] * skip_r + o];
+          y[p[g] * ys + o] = v;
+        }
+      }
   }
 }
 
@@ -1083,7 +1099,7 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
   if (!train && C == 32 && c->hid == 128 && c->cout <= 16) {
     // h_L is [P][C] (inside h[L]), y and skip were range-checked above
     const long long tiles = (P + 15) / 16;
-    const long long blocks = std::min<long long>((tiles + 3) / 4, 8192);
+    const long long blocks = std::min<long long>((tiles + 7) / 8, 8192);  // 4 waves x 2 groups
     hipLaunchKernelGGL((k_proj_fused<32, 128>), dim3((unsigned)blocks), dim3(256), 0, c->s, c->h[c->L], c->Q1,
                        c->theta + c->oQ1b, c->Q2, c->theta + c->oQ2b, c->cout, y, (long long)ys,
                        residual ? x : nullptr, (long long)c->cin, P);
