@@ -89,3 +89,15 @@ def test_hysteresis_scan_runs_all_stages(gpu):
     assert np.isfinite(up).all() and np.isfinite(down).all()
     assert (np.abs(up) <= 1.0 + 1e-12).all() and (np.abs(down) <= 1.0 + 1e-12).all()
     assert rep["radii"][0] == 8.0 and abs(rep["radii"][-1] - 80.0) < 1e-12
+
+
+def test_circle_driver_short_run(gpu):
+    """The paper-preset circle driver on two small radii for a few thousand
+    steps: finite order parameters and energies, one record per radius."""
+    from paper_2304_03306_amd import circle
+    print("[case] circle driver 256^2 x 2 radii", flush=True)
+    rep = circle.run([5.2, 5.6], N=256, L=40.96, steps=3000, transient=1000, every=200)
+    assert [r["R"] for r in rep["radii"]] == [5.2, 5.6]
+    for r in rep["radii"]:
+        assert np.isfinite(r["psi_mean"]) and np.isfinite(r["energy_mean"]) and r["energy_mean"] >= 0
+    assert np.array(rep["psi_series"]).shape == (10, 2)
