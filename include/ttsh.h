@@ -95,7 +95,9 @@ enum {
 };
 
 /* Create a context holding n_inst independent instances advanced together.
- *   N[i]   grid points per side of instance i: 64, 128, 256, 512 or 1024
+ *   N[i]   grid points per side of instance i: 64, 128, 256, 512, 1024 or 2048
+ *          (2048 with TTSH_FP32 or TTSH_FP32_STATE64 only; its passes run with
+ *          256-thread workgroups)
  *   L[i]   box side of instance i (> 0)
  *   p      coefficients shared by all instances
  *   precision  TTSH_FP32, TTSH_FP64 or TTSH_FP32_STATE64
@@ -135,7 +137,7 @@ int ttsh_set_field(ttsh_ctx* ctx, int inst, const double* v, int where);
 int ttsh_get_field(ttsh_ctx* ctx, int inst, double* v, double* omega, int where);
 
 /* Coarse real velocity of instance inst on an Nc x Nc grid of the same box
- * (Nc one of 64..1024, at most the context's largest N): the modes inside
+ * (Nc one of 64..2048, at most the context's largest N): the modes inside
  * both grids' 1/2-rule disks are copied by integer mode index, scaled by Nc/N
  * for the unitary DFT, and transformed back.  Output: device float32,
  * channels-last with a stride: component c of node (i, j) goes to

@@ -16,7 +16,7 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 OUT = HERE / "_build"
 LIB = HERE / "libttsh.so"
-SIZES = (64, 128, 256, 512, 1024)
+SIZES = (64, 128, 256, 512, 1024, 2048)
 PRECS = (32, 64, 96)
 BLOCKS = (64, 128, 256)
 ARCH = os.environ.get("TTSH_ARCH", "gfx950")

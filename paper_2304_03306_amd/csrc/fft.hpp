@@ -1,6 +1,6 @@
 // Workgroup-level Stockham FFT staged through LDS, for gfx950.
 //
-// One transform of length N (64..1024, a power of two) is carried by TT = N/8
+// One transform of length N (64..2048, a power of two) is carried by TT = N/8
 // threads of a workgroup; thread t holds the 8 elements t + e*TT (e = 0..7)
 // in registers.  Each stage of radix R (8, or a final 4 or 2) reads its
 // butterfly inputs x[i + r*N/R] from exactly those registers, multiplies by

@@ -1,5 +1,5 @@
 // Full-array transforms for one grid size, TTSH_N (defined on the compiler
-// command line: 64, 128, 256, 512 or 1024), used by the set-up and read-out
+// command line: 64, 128, 256, 512, 1024 or 2048), used by the set-up and read-out
 // paths.
 #include "fft_full.hpp"
 #include "launch.hpp"

@@ -73,7 +73,7 @@ MultiArgs only(const MultiArgs& a, int q) {
 
 template <int N>
 hipError_t row_one_n(const MultiArgs& o, int gw, hipStream_t s) {
-  if constexpr (TileOf<N, BS>::ok) {
+  if constexpr (row_smem_n<T, BS, N>() > 0) {
     const size_t lds = (row_smem_n<T, BS, N>());
     if (gw)
       hipLaunchKernelGGL((row_one<N, T, true, BS>), dim3(o.start[1]), dim3(BS), lds, s, o);
@@ -87,7 +87,7 @@ hipError_t row_one_n(const MultiArgs& o, int gw, hipStream_t s) {
 
 template <int N>
 hipError_t col_one_n(const MultiArgs& o, int gw, int mode, hipStream_t s) {
-  if constexpr (TileOf<N, BS>::ok) {
+  if constexpr (col_smem_n<T, BS, true, N>() > 0) {
     if (mode == 1)
       hipLaunchKernelGGL((col_one<N, T, S, false, 1, BS>), dim3(o.start[1]), dim3(BS),
                          (col_smem_n<T, BS, false, N>()), s, o);
@@ -114,6 +114,7 @@ hipError_t row_split(const MultiArgs& a, int gw, hipStream_t s) {
       case 256: e = row_one_n<256>(o, gw, s); break;
       case 512: e = row_one_n<512>(o, gw, s); break;
       case 1024: e = row_one_n<1024>(o, gw, s); break;
+      case 2048: e = row_one_n<2048>(o, gw, s); break;
       default: break;
     }
     if (e != hipSuccess) return e;
@@ -132,6 +133,7 @@ hipError_t col_split(const MultiArgs& a, int gw, int mode, hipStream_t s) {
       case 256: e = col_one_n<256>(o, gw, mode, s); break;
       case 512: e = col_one_n<512>(o, gw, mode, s); break;
       case 1024: e = col_one_n<1024>(o, gw, mode, s); break;
+      case 2048: e = col_one_n<2048>(o, gw, mode, s); break;
       default: break;
     }
     if (e != hipSuccess) return e;

@@ -12,7 +12,7 @@
 
 namespace ttsh {
 
-constexpr int kMaxClasses = 5;
+constexpr int kMaxClasses = 6;
 
 struct ClassArgs {
   int N;       // grid points per side
@@ -46,27 +46,38 @@ struct TileOf {
 // LDS bytes of one tile of size N; the launch allocates the largest over the
 // size classes present (dynamic LDS), so that a context without the small
 // grids, whose padded tiles need the most LDS, keeps a higher occupancy.
+// A tile needs at most 64 KB of LDS (FP64 transforms of 2048 points do not fit:
+// 0 here, and contexts ask for them are refused).
+constexpr size_t kMaxTileLds = 65536;
 template <class T, int BS, int N>
 constexpr size_t row_smem_n() {
-  if constexpr (TileOf<N, BS>::ok) return RowSmem<N, TileOf<N, BS>::R, T>::bytes;
-  else return 0;
+  if constexpr (TileOf<N, BS>::ok) {
+    constexpr size_t b = RowSmem<N, TileOf<N, BS>::R, T>::bytes;
+    return b <= kMaxTileLds ? b : 0;
+  } else {
+    return 0;
+  }
 }
 template <class T, int BS, bool GW, int N>
 constexpr size_t col_smem_n() {
-  if constexpr (TileOf<N, BS>::ok) return ColSmem<N, TileOf<N, BS>::R, T, GW>::bytes;
-  else return 0;
+  if constexpr (TileOf<N, BS>::ok) {
+    constexpr size_t b = ColSmem<N, TileOf<N, BS>::R, T, GW>::bytes;
+    return b <= kMaxTileLds ? b : 0;
+  } else {
+    return 0;
+  }
 }
 template <class T, int BS>
 constexpr size_t row_smem_of(int N) {
   return N == 64 ? row_smem_n<T, BS, 64>() : N == 128 ? row_smem_n<T, BS, 128>()
        : N == 256 ? row_smem_n<T, BS, 256>() : N == 512 ? row_smem_n<T, BS, 512>()
-       : N == 1024 ? row_smem_n<T, BS, 1024>() : 0;
+       : N == 1024 ? row_smem_n<T, BS, 1024>() : N == 2048 ? row_smem_n<T, BS, 2048>() : 0;
 }
 template <class T, int BS, bool GW>
 constexpr size_t col_smem_of(int N) {
   return N == 64 ? col_smem_n<T, BS, GW, 64>() : N == 128 ? col_smem_n<T, BS, GW, 128>()
        : N == 256 ? col_smem_n<T, BS, GW, 256>() : N == 512 ? col_smem_n<T, BS, GW, 512>()
-       : N == 1024 ? col_smem_n<T, BS, GW, 1024>() : 0;
+       : N == 1024 ? col_smem_n<T, BS, GW, 1024>() : N == 2048 ? col_smem_n<T, BS, GW, 2048>() : 0;
 }
 
 // Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
@@ -89,7 +100,7 @@ __device__ __forceinline__ int class_of(const MultiArgs& a, int b) {
 template <int N, class T, bool GW, int BS>
 __device__ __forceinline__ void row_go(const ClassArgs& d, const RowCoef<T>& c, int inst, int tile,
                                        unsigned char* smem) {
-  if constexpr (TileOf<N, BS>::ok)
+  if constexpr (row_smem_n<T, BS, N>() > 0)
     row_body<N, TileOf<N, BS>::R, T, GW>((const C2<T>*)d.X_in, (C2<T>*)d.Y, (const T*)d.K,
                                          (T*)d.rowsum, (const C2<T>*)d.tw, c, inst, tile, smem);
 }
@@ -117,7 +128,7 @@ __global__ void __launch_bounds__(BS) row_multi(MultiArgs a) {
 template <int N, class T, class S, bool GW, int MODE, int BS>
 __device__ __forceinline__ void col_go(const ClassArgs& d, const LinCoef& lc, int inst, int tile,
                                        unsigned char* smem) {
-  if constexpr (TileOf<N, BS>::ok) {
+  if constexpr (col_smem_n<T, BS, GW, N>() > 0) {
     LinCoef l = lc;
     l.dt_over_N = lc.dt / N;  // the unnormalised forward FFT carries N x the unitary DFT
     col_body<N, TileOf<N, BS>::R, T, S, GW, MODE>((const C2<T>*)d.Y, (C2<T>*)d.X_out, (C2<S>*)d.st,
@@ -148,6 +159,8 @@ __global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
 // One size class per launch (args.c[0] only): the same tile bodies compiled
 // for a single N, so that the register budget is that of this N alone and the
 // tile decode is constant; the autotuner picks this or the multi-size launch.
+// Grids of 2048 points are served only here (their tiles would raise the
+// register budget of the multi-size kernels for every other size).
 template <int N, class T, bool GW, int BS>
 __global__ void __launch_bounds__(BS) row_one(MultiArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];

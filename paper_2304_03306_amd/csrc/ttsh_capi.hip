@@ -25,6 +25,7 @@ const SizeOps* ops_128();
 const SizeOps* ops_256();
 const SizeOps* ops_512();
 const SizeOps* ops_1024();
+const SizeOps* ops_2048();
 const SizeOps* size_ops(int N) {
   switch (N) {
     case 64: return ops_64();
@@ -32,6 +33,7 @@ const SizeOps* size_ops(int N) {
     case 256: return ops_256();
     case 512: return ops_512();
     case 1024: return ops_1024();
+    case 2048: return ops_2048();
     default: return nullptr;
   }
 }
@@ -243,13 +245,17 @@ MultiArgs multi_args(ttsh_ctx* c, int row, int inst) {
   return m;
 }
 
+// contexts with 2048-point grids always launch per size class (the multi-size
+// kernels are not compiled for that size)
+bool must_split(const ttsh_ctx* c) { return max_N(c) > 1024; }
+
 hipError_t launch_row(ttsh_ctx* c, const MultiArgs& m, hipStream_t s) {
   const MultiOps* o = multi_ops(c->prec == 64 ? 64 : 32, c->bs_row);
-  return c->split_row ? o->row_split(m, c->gw, s) : o->row(m, c->gw, s);
+  return c->split_row || must_split(c) ? o->row_split(m, c->gw, s) : o->row(m, c->gw, s);
 }
 hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) {
   const MultiOps* o = multi_ops(c->prec, c->bs);
-  return c->split_col ? o->col_split(m, c->gw, mode, s) : o->col(m, c->gw, mode, s);
+  return c->split_col || must_split(c) ? o->col_split(m, c->gw, mode, s) : o->col(m, c->gw, mode, s);
 }
 
 int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
@@ -403,8 +409,11 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
     if (!std::isfinite(v)) return fail(TTSH_EINVAL, "non-finite coefficient");
   if (!(p->dt > 0)) return fail(TTSH_EINVAL, "dt must be > 0");
   for (int i = 0; i < n_inst; ++i) {
-    if (!size_ops(N[i])) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024");
+    if (!size_ops(N[i])) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
     if (!(L[i] > 0) || !std::isfinite(L[i])) return fail(TTSH_EINVAL, "L must be > 0");
+    // FP64 transforms of 2048 points need more LDS than one workgroup has
+    if (N[i] == 2048 && precision == TTSH_FP64)
+      return fail(TTSH_EUNSUPPORTED, "N = 2048 needs FP32 transforms (TTSH_FP32 or TTSH_FP32_STATE64)");
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(TTSH_EHIP, "no HIP device available");
@@ -663,7 +672,7 @@ int ttsh_get_field_coarse(ttsh_ctx* c, int inst, int Nc, float* out, int64_t pix
   if (rc) return rc;
   if (!out) return fail(TTSH_EINVAL, "null output");
   if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
-  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024");
+  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024, 2048");
   if (Nc > max_N(c)) return fail(TTSH_EINVAL, "Nc larger than the context's largest grid");
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
@@ -695,7 +704,7 @@ int ttsh_set_field_coarse(ttsh_ctx* c, int inst, int Nc, const float* v, int64_t
   if (rc) return rc;
   if (!v) return fail(TTSH_EINVAL, "null input");
   if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
-  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024");
+  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024, 2048");
   if (Nc > max_N(c)) return fail(TTSH_EINVAL, "Nc larger than the context's largest grid");
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
@@ -729,7 +738,7 @@ int ttsh_project_coarse(ttsh_ctx* c, int N, float* v, int64_t pix_stride, int ba
   if (!v) return fail(TTSH_EINVAL, "null field");
   if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
   if (batch < 1) return fail(TTSH_EINVAL, "batch must be >= 1");
-  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024");
+  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
   const size_t n = (size_t)batch * N * N;
   if (n > (size_t)INT32_MAX) return fail(TTSH_EINVAL, "batch too large");
   const size_t bytes = n * sizeof(C2<double>);
@@ -1021,7 +1030,7 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
   const int keep_bs = c->bs, keep_row = c->bs_row, keep_sr = c->split_row, keep_sc = c->split_col;
   int best_row = 0, best_col = 0, best_sr = 0, best_sc = 0;
   double row_us = 0.0, col_us = 0.0;
-  for (int split = 0; split < 2 && rc == TTSH_OK; ++split) {
+  for (int split = must_split(c) ? 1 : 0; split < 2 && rc == TTSH_OK; ++split) {
     for (int bs : {64, 128, 256}) {
       if (rc != TTSH_OK || !bs_valid(c, bs)) continue;
       c->bs = c->bs_row = bs;
@@ -1066,7 +1075,7 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
 int ttsh_fft2(const double* in, double* out, int N, int batch, int inverse, int precision) {
   if (!in || !out) return fail(TTSH_EINVAL, "null pointer");
   const SizeOps* ops = size_ops(N);
-  if (!ops) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024");
+  if (!ops) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
   if (batch < 1) return fail(TTSH_EINVAL, "batch must be >= 1");
   if (precision != 32 && precision != 64) return fail(TTSH_EINVAL, "precision must be 32 or 64");
   int ndev = 0;

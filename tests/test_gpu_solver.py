@@ -22,7 +22,7 @@ def make(gpu, N, L, p, prec, n=1):
 
 
 # ---- transforms -----------------------------------------------------------------
-@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024, 2048])
 @pytest.mark.parametrize("prec,tol", [(64, 2e-14), (32, 2e-6)])
 def test_fft2_matches_numpy(gpu, N, prec, tol):
     import torch
@@ -155,14 +155,19 @@ def test_circle64_fp64_2000_steps(gpu):
         assert err < tol, (upto, err)
 
 
-@pytest.mark.parametrize("N,steps", [(128, 200), (256, 100)])
-def test_fp32_steps(gpu, N, steps):
-    say("fp32 steps", N, steps)
+@pytest.mark.parametrize("N,steps,prec,preset", [(128, 200, 32, "workload"), (256, 100, 32, "workload"),
+                                                  (2048, 4, 32, "workload"), (2048, 4, 96, "paper")])
+def test_fp32_steps(gpu, N, steps, prec, preset):
+    """FP32 transforms against the FP64 oracle; 2048^2 runs on per-size
+    launches with 256-thread workgroups (also with the FP64 state and the
+    paper's coefficients, whose gamma_w term takes the third forcing
+    transform)."""
+    say("fp32 steps", N, steps, prec, preset)
     L = N * 0.5
-    p = O.workload_params()
+    p = O.workload_params() if preset == "workload" else O.paper_params()
     K = O.mask_tanh(N, L, [(0.0, 0.0)], [L / 4], 0.5)
-    v0 = W.uniform_field(9, N, 0.01, 32)
-    s, vh = run_pair(gpu, N, L, p, 32, K, v0, steps)
+    v0 = W.uniform_field(9, N, 0.01 if N < 2048 else 0.3, 32)
+    s, vh = run_pair(gpu, N, L, p, prec, K, v0, steps)
     err = O.rel_l2(s.field(0), O.field(vh))
     print("rel_l2", err)
     assert err < 1e-5
