@@ -14,7 +14,11 @@
 // costs (#stages - 1) LDS round trips and needs no bit reversal.
 //
 // NF independent transforms that share the same threads are processed
-// together, so that one barrier serves all of them.
+// together.  At most TTSH_FFT_SLOTS of them occupy LDS at a time: with as many
+// slots as transforms one barrier pair per stage serves all of them; with
+// fewer, the transforms take turns in the slots (one more barrier per extra
+// transform and stage), which shrinks the LDS footprint of a transform group
+// and lets more waves stay resident on a CU.
 //
 // All threads of the workgroup must call these functions (they contain
 // __syncthreads); threads that carry no useful data just transform zeros.
@@ -37,6 +41,13 @@ template <int N>
 struct Padded {
   static constexpr int value = N + (N >> TTSH_PAD_SHIFT);
 };
+
+#ifndef TTSH_FFT_SLOTS
+#define TTSH_FFT_SLOTS 2
+#endif
+static_assert(TTSH_FFT_SLOTS >= 2, "the slot rotation needs at least two slots");
+// LDS regions of Padded<N> entries that NF transforms use during an exchange
+__host__ __device__ constexpr int fft_slots(int nf) { return nf < TTSH_FFT_SLOTS ? nf : TTSH_FFT_SLOTS; }
 
 // ---- radix-R DFTs, DIR = -1 forward (e^{-2 pi i nk/R}), +1 inverse ---------
 template <int DIR, class T>
@@ -92,7 +103,7 @@ struct Dft<8, DIR, T> {
 
 // ---- one Stockham stage, recursing into the next ---------------------------
 // v[f][e] holds element t + e*TT of transform f.  `lds` points at this group's
-// NF regions of Padded<N> entries each.  `tw[j]` = e^{-2 pi i j / N}.
+// fft_slots(NF) regions of Padded<N> entries each.  `tw[j]` = e^{-2 pi i j / N}.
 template <int N, int DIR, int NF, int P, class T>
 struct FftStage {
   static constexpr int E = kFftE;
@@ -103,42 +114,65 @@ struct FftStage {
   static constexpr bool LAST = (P * R == N);
   static constexpr int NP = Padded<N>::value;
 
-  __device__ static __forceinline__ void run(C2<T> (&v)[NF][E], C2<T>* lds, int t,
-                                             const C2<T>* __restrict__ tw) {
+  // twiddle multiplication and radix-R DFT of the NB butterflies of transform
+  // f; the outputs go back to registers (last stage) or to LDS region `slot`
+  __device__ static __forceinline__ void butterflies(C2<T> (&v)[NF][E], int f, C2<T>* slot, int t,
+                                                     const C2<T>* __restrict__ tw) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    for (int b = 0; b < NB; ++b) {
+      const int i = t + b * TT;
+      const int k = i & (P - 1);
+      C2<T> u[R];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int i = t + b * TT;
-        const int k = i & (P - 1);
-        C2<T> u[R];
+      for (int r = 0; r < R; ++r) u[r] = v[f][b + r * NB];
+      if constexpr (P > 1) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) u[r] = v[f][b + r * NB];
-        if constexpr (P > 1) {
-#pragma unroll
-          for (int r = 1; r < R; ++r) {
-            C2<T> w = tw[r * k * (N / (P * R))];
-            if constexpr (DIR > 0) w.y = -w.y;
-            u[r] = cmul(u[r], w);
-          }
-        }
-        Dft<R, DIR, T>::run(u);
-        if constexpr (LAST) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) v[f][b + r * NB] = u[r];
-        } else {
-          const int j0 = (i - k) * R + k;
-#pragma unroll
-          for (int r = 0; r < R; ++r) lds[f * NP + lds_pad(j0 + r * P)] = u[r];
+        for (int r = 1; r < R; ++r) {
+          C2<T> w = tw[r * k * (N / (P * R))];
+          if constexpr (DIR > 0) w.y = -w.y;
+          u[r] = cmul(u[r], w);
         }
       }
+      Dft<R, DIR, T>::run(u);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[f][b + r * NB] = u[r];
+      } else {
+        const int j0 = (i - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) slot[lds_pad(j0 + r * P)] = u[r];
+      }
     }
-    if constexpr (!LAST) {
+  }
+
+  __device__ static __forceinline__ void gather(C2<T> (&v)[NF][E], int f, const C2<T>* slot, int t) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[f][e] = slot[lds_pad(t + e * TT)];
+  }
+
+  __device__ static __forceinline__ void run(C2<T> (&v)[NF][E], C2<T>* lds, int t,
+                                             const C2<T>* __restrict__ tw) {
+    constexpr int NS = fft_slots(NF);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) butterflies(v, f, lds, t, tw);
+    } else if constexpr (NS == NF) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) butterflies(v, f, lds + f * NP, t, tw);
       __syncthreads();
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
+      for (int f = 0; f < NF; ++f) gather(v, f, lds + f * NP, t);
+      __syncthreads();
+      FftStage<N, DIR, NF, P * R, T>::run(v, lds, t, tw);
+    } else {
+      // transform f uses slot f % NS; the barrier after writing f also orders
+      // every read of f - NS (issued before it) ahead of the reuse of its slot
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[f][e] = lds[f * NP + lds_pad(t + e * TT)];
+      for (int f = 0; f < NF; ++f) {
+        butterflies(v, f, lds + (f % NS) * NP, t, tw);
+        __syncthreads();
+        gather(v, f, lds + (f % NS) * NP, t);
+      }
       __syncthreads();
       FftStage<N, DIR, NF, P * R, T>::run(v, lds, t, tw);
     }

@@ -90,7 +90,7 @@ struct Geo {
   // LDS stride between transform groups that share a wavefront: TTSH_LDS_OFF
   // complex entries off a multiple of 32 (chosen by measuring LDS bank
   // conflicts on gfx950).
-  static constexpr int LS = (3 * NP + 31) / 32 * 32 + TTSH_LDS_OFF;
+  static constexpr int LS = (fft_slots(3) * NP + 31) / 32 * 32 + TTSH_LDS_OFF;
 };
 
 // index of mixed-domain entry (field f, column m, row y)
@@ -142,15 +142,6 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
   const T* Kp = K + inst * N * N;
   C2<T>* L = lds + lane * G::LS;
 
-  // mask rows first, so their latency hides behind the gather and transforms
-  T kr[2][E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int x = t + e * TT;
-    kr[0][e] = Kp[(size_t)y0 * N + x];
-    kr[1][e] = Kp[(size_t)(y0 + 1) * N + x];
-  }
-
   // gather Z(m) over the full row spectrum from the stored m_x = 0..M half
   C2<T> z[3][E];
 #pragma unroll
@@ -182,6 +173,17 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     z[2][e] = pack_pq(w.a, w.b);  // omega(y0) + i omega(y0+1)
   }
   fft<N, +1, 3>(z, L, t, tw);
+
+  // mask rows, loaded after the inverse transforms: issued before them they
+  // would hold 16 registers through the transforms (the row pass ran ~5 %
+  // slower that way on gfx950)
+  T kr[2][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int x = t + e * TT;
+    kr[0][e] = Kp[(size_t)y0 * N + x];
+    kr[1][e] = Kp[(size_t)(y0 + 1) * N + x];
+  }
 
   // real-space forcing at x = t + e*TT
   C2<T> wv[NFY][E];
@@ -274,9 +276,28 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
 template <int N, int TC, class T, bool GW>
 struct ColSmem {
   static constexpr size_t fft = (size_t)TC * Geo<N>::LS * sizeof(C2<T>);
-  static constexpr size_t herm = (size_t)2 * N * sizeof(C2<double>);
+  static constexpr size_t herm = (size_t)N * sizeof(C2<double>);
   static constexpr size_t bytes = fft > herm ? fft : herm;
 };
+
+// u(m_y) <- (u(m_y) + u(-m_y)^*)/2 over one column held as u[e] = entry
+// t + e*TT by the threads with `active`; H holds N entries of LDS, and every
+// thread of the workgroup must call this
+template <int N>
+__device__ __forceinline__ void hermitian_fix(C2<double> (&u)[kFftE], C2<double>* H, int t, bool active) {
+  constexpr int E = kFftE, TT = N / E;
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) H[t + e * TT] = u[e];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = cscale(u[e] + conj(H[(N - (t + e * TT)) & (N - 1)]), 0.5);
+  }
+  __syncthreads();
+}
 
 template <int N, int TC, class T, class S, bool GW, int MODE>
 __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X,
@@ -402,26 +423,10 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
   }
 
   if constexpr (MODE == 0) {
-    if (tile == 0) {  // Hermitian correction on the m_x = 0 column
+    if (tile == 0) {  // Hermitian correction on the m_x = 0 column, x then y
       C2<double>* H = reinterpret_cast<C2<double>*>(smem);
-      __syncthreads();
-      if (col == 0) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          H[t + e * TT] = nx[e];
-          H[N + t + e * TT] = ny[e];
-        }
-      }
-      __syncthreads();
-      if (col == 0) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int mir = (N - (t + e * TT)) & (N - 1);
-          nx[e] = cscale(nx[e] + conj(H[mir]), 0.5);
-          ny[e] = cscale(ny[e] + conj(H[N + mir]), 0.5);
-        }
-      }
-      __syncthreads();
+      hermitian_fix<N>(nx, H, t, col == 0);
+      hermitian_fix<N>(ny, H, t, col == 0);
     }
     // round to the stored precision; the transforms below start from the
     // stored values, so the stored spectrum is the whole state of the run
