@@ -44,6 +44,18 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
                int H, int W, int max_batch, uint64_t seed, void* stream);
 void fno_destroy(fno_ctx* ctx);
 
+/* Implementation switches (value 1 = on, the default; 0 = off), for
+ * comparing the kernel paths against each other.  Both leave the network's
+ * function unchanged; results may differ by BF16 rounding.
+ * FNO_OPT_STAGED_GEMM: GEMM operands staged through LDS where the layout allows.
+ * FNO_OPT_FUSED_TAIL: each Fourier layer's 1x1 convolution, inverse k_x
+ *   transform, bias and GELU fused with the next layer's k_x transform in one
+ *   kernel (width 32, 16 modes, W = 128 only).
+ * Returns TTSH_EINVAL for an unknown option. */
+#define FNO_OPT_STAGED_GEMM 1
+#define FNO_OPT_FUSED_TAIL 2
+int fno_set_option(fno_ctx* ctx, int option, int value);
+
 /* Number of float32 parameters (the length of the vectors below). */
 int64_t fno_num_params(fno_ctx* ctx);
 

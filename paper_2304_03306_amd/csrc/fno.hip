@@ -441,6 +441,137 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
   }
 }
 
+// Tail of one Fourier layer for C = 32 channels, 2m = 32 kept k_x rows and
+// W = 128 points per image row, fused so that the new activation row is used
+// while it is on chip.  A workgroup takes one image row (b, y) per iteration,
+// its four wavefronts 32 points x each:
+//   out[x][c] = act(sum_j Ax[x][j] T2[b][y][j][c] + sum_k h[b][y][x][k] Wl[k][c] + bias[c])
+// stored to hn[b][y][x][c] (the pre-activation to z[b][y][x][c] when z is
+// given), and with NEXT the next layer's truncated k_x transform of that row,
+//   T1[b][j][y][c] = sum_x Dx[j][x] out_bf16[x][c],
+// from the rounded values that were stored (the same operand the separate
+// analysis GEMM reads back).  The four wavefronts' partial sums over their 32
+// points are added in a fixed order.  The product is formed untransposed, so
+// that lane l holds column c = l%16 and four consecutive points: exactly the
+// operand layout of the Dx product; the stores go through LDS to 32-byte rows.
+template <bool ACT, bool NEXT>
+__global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, const bf16* __restrict__ T2,
+                                                    const bf16* __restrict__ Ax, const bf16* __restrict__ Wl,
+                                                    const float* __restrict__ bias, const bf16* __restrict__ Dx,
+                                                    bf16* __restrict__ hn, bf16* __restrict__ z,
+                                                    bf16* __restrict__ T1, int H, long long rows) {
+  constexpr int C = 32, J = 32, W = 128;
+  __shared__ __align__(16) bf16 Ts[C * kLDK];      // T2 block transposed: [c][j]
+  __shared__ __align__(16) bf16 Os[4][32 * kLDK];  // per wavefront output tile [x][c]
+  __shared__ float Rs[NEXT ? 4 : 1][J][C + 1];     // partial k_x transforms [wave][j][c]
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int tid = threadIdx.x;
+  // row-independent operands, held in registers
+  short4_t a1[2][2], b2[2][2], a3[2][2];
+  float bc[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      a1[s][kk] = *(const short4_t*)(Ax + (32 * w + 16 * s + l16) * J + 16 * kk + q4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b2[s][kk][e] = (short)Wl[(16 * kk + q4 + e) * C + 16 * s + l16];
+      if constexpr (NEXT) a3[s][kk] = *(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + 16 * kk + q4);
+    }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) bc[t] = bias[16 * t + l16];
+
+  for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+    const bf16* hp = h + row * (W * C);
+    short4_t a2[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+        a2[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+    {  // T2[b][y] (J x C) into LDS as [c][j]
+      const int j = tid >> 3, c0 = (tid & 7) * 4;
+      const uint2 v = *(const uint2*)(T2 + row * (J * C) + j * C + c0);
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Ts[(c0 + q) * kLDK + j] = e[q];
+    }
+    __syncthreads();
+    float4_t acc[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          const short4_t b1 = *(const short4_t*)(Ts + (16 * t + l16) * kLDK + 16 * kk + q4);
+          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[s][kk], b1, acc[s][t], 0, 0, 0);
+          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[s][kk], b2[t][kk], acc[s][t], 0, 0, 0);
+        }
+      }
+    // acc[s][t][e] = out[x = 32 w + 16 s + q4 + e][c = 16 t + l16]
+    bf16* Ow = Os[w];
+    bf16* hrow = hn + row * (W * C) + 32 * w * C;
+    const int sr = lane >> 1, sh = (lane & 1) * 16;  // store: tile row, first channel
+    if (z) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Ow[(16 * s + q4 + e) * kLDK + 16 * t + l16] = f2bf(acc[s][t][e] + bc[t]);
+      wave_lds_sync();
+      bf16* zrow = z + row * (W * C) + 32 * w * C;
+      *(uint4*)(zrow + sr * C + sh) = *(const uint4*)(Ow + sr * kLDK + sh);
+      *(uint4*)(zrow + sr * C + sh + 8) = *(const uint4*)(Ow + sr * kLDK + sh + 8);
+      wave_lds_sync();
+    }
+    short4_t b3[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float v = acc[s][t][e] + bc[t];
+          if constexpr (ACT) v = gelu(v);
+          const bf16 o = f2bf(v);
+          b3[s][t][e] = (short)o;
+          Ow[(16 * s + q4 + e) * kLDK + 16 * t + l16] = o;
+        }
+    wave_lds_sync();
+    *(uint4*)(hrow + sr * C + sh) = *(const uint4*)(Ow + sr * kLDK + sh);
+    *(uint4*)(hrow + sr * C + sh + 8) = *(const uint4*)(Ow + sr * kLDK + sh + 8);
+    if constexpr (NEXT) {
+      // partial transform over this wavefront's 32 points: p[r][t][e] = P[16 r + q4 + e][16 t + l16]
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          float4_t p = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < 2; ++s) p = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[r][s], b3[s][t], p, 0, 0, 0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Rs[w][16 * r + q4 + e][16 * t + l16] = p[e];
+        }
+      __syncthreads();
+      const int j = tid >> 3, c0 = (tid & 7) * 4;
+      const long long b = row / H, y = row % H;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = ((Rs[0][j][c0 + q] + Rs[1][j][c0 + q]) + Rs[2][j][c0 + q]) + Rs[3][j][c0 + q];
+      uint2 o;
+      o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+      o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+      *(uint2*)(T1 + ((b * J + j) * H + y) * C + c0) = o;
+    } else {
+      __syncthreads();  // Ts is overwritten by the next row
+    }
+    wave_lds_sync();  // Os is overwritten by the next row
+  }
+}
+
 // dz = dh * GELU'(z), eight elements per thread with 16-byte accesses (n % 8 == 0)
 __global__ void k_gelu_back(const bf16* __restrict__ dh, const bf16* __restrict__ z, bf16* __restrict__ dz,
                             long long n) {
@@ -642,6 +773,7 @@ struct fno_ctx {
   double* lsum = nullptr;
   long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
   int staged_gemm = 1;        // GEMMs whose operands allow it stage them through LDS
+  int fused_tail = 1;         // the layer tail kernel where the shape allows it (C = 32, 2m = 32, W = 128)
   std::vector<void*> allocs;
   std::vector<std::pair<const char*, size_t>> extents;  // (start, bytes) of every buffer
 };
@@ -804,11 +936,10 @@ GemmArgs ga() {
 // Forward truncated rfft2 of src [B][H][W][C] into the mode layout
 // dst [m][4m][B][C] (rows 0..2m-1 real parts, 2m..4m-1 imaginary parts);
 // Dxm is the k_x matrix (Dx, or DxG for the backward weights).
-int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, int B) {
-  int rc;
+// (the k_x step alone: T1 [B][2m][H][C] = Dxm (2m x W) . src[b][y] (W x C))
+int spectral_analysis_x(fno_ctx* c, const bf16* src, const bf16* Dxm, int B) {
   const int C = c->C, m = c->m, H = c->H, W = c->W;
   const long long HWC = (long long)H * W * C, HC = (long long)H * C;
-  // T1 [B][2m][H][C] = Dxm (2m x W) . src[b][y] (W x C)
   GemmArgs g = ga();
   g.M = 2 * m; g.N = C; g.K = W;
   g.nb1 = B; g.nb2 = H;
@@ -816,7 +947,12 @@ int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, i
   g.B = op(src, C, 1, HWC, (long long)W * C);
   g.C = c->T1; g.c_bf16 = 1;
   g.sC1 = 2LL * m * HC; g.sC2 = C; g.rC = HC; g.cC = 1;
-  if ((rc = cgemm(c, g))) return rc;
+  return cgemm(c, g);
+}
+// (the k_y step alone, from T1)
+int spectral_analysis_y(fno_ctx* c, bf16* dst, int B) {
+  const int C = c->C, m = c->m, H = c->H;
+  const long long HC = (long long)H * C;
   // dst[kx] (4m x C per b) = DyRe . T1_re + DyIm . T1_im
   GemmArgs h = ga();
   h.M = 4 * m; h.N = C; h.K = H; h.K2 = H;
@@ -827,7 +963,38 @@ int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, i
   h.B2 = op(c->T1 + (long long)m * HC, C, 1, 2LL * m * HC, HC);
   h.C = dst; h.c_bf16 = 1;
   h.sC1 = C; h.sC2 = 4LL * m * B * C; h.rC = (long long)B * C; h.cC = 1;
-  if ((rc = cgemm(c, h))) return rc;
+  return cgemm(c, h);
+}
+int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, int B) {
+  int rc;
+  if ((rc = spectral_analysis_x(c, src, Dxm, B))) return rc;
+  return spectral_analysis_y(c, dst, B);
+}
+
+bool tail_fusable(const fno_ctx* c) { return c->fused_tail && c->C == 32 && c->m == 16 && c->W == 128; }
+
+// One launch of k_layer_tail for layer l (act and next: not the last layer).
+// Every operand is a context buffer sized for the maximum batch.
+int layer_tail(fno_ctx* c, int l, int B, bool train) {
+  const bool last = l == c->L - 1;
+  const long long rows = (long long)B * c->H, P = rows * c->W;
+  const std::pair<const char*, size_t>* none = nullptr;
+  const bf16* zp = (train && !last) ? c->z[l] : nullptr;
+  if (!inside(c, c->h[l], P * 32 - 1, 2, none, 0) || !inside(c, c->h[l + 1], P * 32 - 1, 2, none, 0) ||
+      !inside(c, c->T2, rows * 32 * 32 - 1, 2, none, 0) || !inside(c, c->T1, rows * 32 * 32 - 1, 2, none, 0) ||
+      !inside(c, zp, P * 32 - 1, 2, none, 0) || !inside(c, c->Ax, 128 * 32 - 1, 2, none, 0) ||
+      !inside(c, c->Dx, 32 * 128 - 1, 2, none, 0) || !inside(c, c->Wl[l], 32 * 32 - 1, 2, none, 0))
+    return ffail(TTSH_EINVAL, "layer tail operand out of bounds (internal layout error)");
+  const unsigned blocks = (unsigned)std::min<long long>(rows, 1280);
+  const float* bias = c->theta + c->ob[l];
+  bf16* z = train && !last ? c->z[l] : nullptr;
+  if (last)
+    hipLaunchKernelGGL((k_layer_tail<false, false>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax,
+                       c->Wl[l], bias, c->Dx, c->h[l + 1], z, c->T1, c->H, rows);
+  else
+    hipLaunchKernelGGL((k_layer_tail<true, true>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax,
+                       c->Wl[l], bias, c->Dx, c->h[l + 1], z, c->T1, c->H, rows);
+  FCHK(hipGetLastError());
   return TTSH_OK;
 }
 
@@ -1047,6 +1214,14 @@ int fno_get_grads(fno_ctx* c, float* p) {
   return TTSH_OK;
 }
 
+int fno_set_option(fno_ctx* c, int option, int value) {
+  if (!c) return ffail(TTSH_EINVAL, "null context");
+  if (option == FNO_OPT_STAGED_GEMM) c->staged_gemm = value != 0;
+  else if (option == FNO_OPT_FUSED_TAIL) c->fused_tail = value != 0;
+  else return ffail(TTSH_EINVAL, "unknown option");
+  return TTSH_OK;
+}
+
 int fno_forward(fno_ctx* c, const float* x, float* y, int B, int train) {
   return c ? fno_forward_ex(c, x, y, c->cout, 0, B, train) : ffail(TTSH_EINVAL, "null context");
 }
@@ -1074,11 +1249,19 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
                        c->cin, C);
   FCHK(hipGetLastError());
   int rc;
+  const bool fuse = tail_fusable(c);
   for (int l = 0; l < c->L; ++l) {
     const bool last = l == c->L - 1;
-    if ((rc = spectral_analysis(c, c->h[l], c->Dx, c->G[l], B))) return rc;
+    // with the fused tail, the previous layer already left T1 (the k_x step of h_l)
+    if (l == 0 || !fuse)
+      if ((rc = spectral_analysis_x(c, c->h[l], c->Dx, B))) return rc;
+    if ((rc = spectral_analysis_y(c, c->G[l], B))) return rc;
     if ((rc = spectral_mix(c, c->G[l], c->Wb[l], false, c->O, B))) return rc;
     if ((rc = spectral_synth_y(c, c->O, B))) return rc;
+    if (fuse) {
+      if ((rc = layer_tail(c, l, B, train != 0))) return rc;
+      continue;
+    }
     // h_{l+1} = act(Ax . T2[b][y] + h_l[b][y] . W_l + b_l)
     GemmArgs g = ga();
     g.M = W; g.N = C; g.K = 2 * m; g.K2 = C;

@@ -11,6 +11,9 @@ from .ttsh import TTSH_OK, TTSHError, lib as _ttsh_lib
 
 _sig_done = False
 
+FNO_OPT_STAGED_GEMM = 1
+FNO_OPT_FUSED_TAIL = 2
+
 
 def lib():
     global _sig_done
@@ -23,6 +26,7 @@ def lib():
             "fno_set_params": ([vp, vp], ctypes.c_int),
             "fno_get_params": ([vp, vp], ctypes.c_int),
             "fno_get_grads": ([vp, vp], ctypes.c_int),
+            "fno_set_option": ([vp, i32, i32], ctypes.c_int),
             "fno_forward": ([vp, vp, vp, i32, i32], ctypes.c_int),
             "fno_forward_ex": ([vp, vp, vp, i64, i32, i32, i32], ctypes.c_int),
             "fno_gather": ([vp, vp, i64, vp, i64, i32, i64, vp, i32], ctypes.c_int),
@@ -104,6 +108,9 @@ class FNO:
         a = np.empty(self.n, dtype=np.float32)
         _check(lib().fno_get_grads(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
         return a
+
+    def set_option(self, option: int, value: int):
+        _check(lib().fno_set_option(self.ctx, int(option), int(value)))
 
     def forward(self, x, y, train=False):
         _check(lib().fno_forward(self.ctx, _ptr(x), _ptr(y), int(x.shape[0]), int(bool(train))))

@@ -243,6 +243,50 @@ def test_fused_inference_projection_matches_training_path(gpu):
     assert np.array_equal(got[..., 2], x[..., 2].astype(np.float64))
 
 
+def test_fused_layer_tail_matches_oracle_and_unfused_path(gpu):
+    """Width 32, 16 modes and W = 128 take the fused layer tail (1x1
+    convolution, inverse k_x transform, bias, GELU and the next layer's k_x
+    transform in one kernel, the transform's k axis split over four
+    wavefronts).  Inference and training outputs and the gradients must stay
+    within the BF16 tolerance of the FP64 oracle, and the fused path must agree
+    with the separate GEMMs (FNO_OPT_FUSED_TAIL = 0) to BF16 rounding; the
+    batch (5 samples x 32 rows) is not a multiple of the persistent grid."""
+    import torch
+    from paper_2304_03306_amd import fno
+    say("fno fused layer tail")
+    cfg = F.Config(H=32, W=128, cin=3, cout=2, width=32, modes=16, layers=3, hidden=16)
+    B = 5
+    net, p = make_net(gpu, cfg, B, seed=21)
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((B, cfg.H, cfg.W, cfg.cin)).astype(np.float32)
+    t = rng.standard_normal((B, cfg.H, cfg.W, cfg.cout)).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    out = {}
+    for fused in (1, 0):
+        net.set_option(fno.FNO_OPT_FUSED_TAIL, fused)
+        y = torch.empty((B, cfg.H, cfg.W, cfg.cout), dtype=torch.float32, device="cuda")
+        net.forward(xd, y, train=False)
+        yt = torch.empty_like(y)
+        net.forward(xd, yt, train=True)
+        loss = net.loss(yt, td)
+        net.backward(B)
+        out[fused] = (y.cpu().numpy().astype(np.float64), yt.cpu().numpy().astype(np.float64), loss,
+                      fno.unflatten(net.grads(), p, cfg.layers))
+    yo, cache = F.forward(p, x.astype(np.float64), cfg, keep=True)
+    lo, gy = F.rel_l2_loss(yo, t.astype(np.float64))
+    go = F.backward(p, cache, gy, cfg)
+    y1, yt1, l1, g1 = out[1]
+    y0, yt0, l0, g0 = out[0]
+    print("fused/oracle", rel(y1, yo), "fused/unfused", rel(y1, y0), flush=True)
+    assert rel(y1, yo) < 3e-2 and rel(yt1, yo) < 3e-2
+    assert rel(y1, y0) < 1e-2 and rel(yt1, yt0) < 1e-2
+    assert abs(l1 - lo) < 2e-2 * lo
+    for k in go:
+        e, d = rel(g1[k], go[k]), rel(g1[k], g0[k])
+        print(k, "grad rel", e, "vs unfused", d, flush=True)
+        assert e < 6e-2 and d < 3e-2, (k, e, d)
+
+
 def test_increment_loss_and_its_gradient(gpu):
     """fno_loss_ex normalises each sample's error by ||t - ref|| (ref: the
     input's first channels, pixel stride cin); its value is that mean, and
