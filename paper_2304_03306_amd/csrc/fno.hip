@@ -28,11 +28,22 @@ using bf16 = uint16_t;
 
 // ---- BF16 <-> FP32 (round to nearest even) ---------------------------------------
 __host__ __device__ inline bf16 f2bf(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(bf16, (__bf16)f);  // v_cvt_pk_bf16_f32, round to nearest even
+#else
   uint32_t u;
   memcpy(&u, &f, 4);
   if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
   u += 0x7fffu + ((u >> 16) & 1u);
   return (bf16)(u >> 16);
+#endif
+}
+typedef float float2v_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned uint2v_t __attribute__((ext_vector_type(2)));
+// two values in one v_cvt_pk_bf16_f32 (round to nearest even), a in the low half
+__device__ inline unsigned pack2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(float2v_t{a, b}, bf16x2_t));
 }
 __host__ __device__ inline float bf2f(bf16 h) {
   const uint32_t u = (uint32_t)h << 16;
@@ -41,22 +52,29 @@ __host__ __device__ inline float bf2f(bf16 h) {
   return f;
 }
 
-// erf by Abramowitz and Stegun, Handbook of Mathematical Functions, 7.1.26:
-// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2}, t = 1/(1 + p x),
-// |error| <= 1.5e-7 for x >= 0 (odd extension).  The activations it feeds are
-// stored in BF16 (relative resolution 2^-8), so the error is far below what is
-// kept, and it costs a third of the library erf.
-__device__ inline float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
-  const float poly =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+// erfc of a / sqrt(2) for a >= 0 by Abramowitz and Stegun, Handbook of
+// Mathematical Functions, 7.1.28: erf(u) = 1 - (1 + a1 u + ... + a6 u^6)^-16,
+// |error| <= 3e-7 (the coefficients below are a_i 2^{-i/2}, so that the
+// polynomial takes a directly).  One reciprocal and no exponential; the
+// activations it feeds are stored in BF16 (relative resolution 2^-8).
+__device__ inline float erfc_half(float a) {
+  constexpr double r = 0.70710678118654752440;
+  constexpr float b1 = (float)(0.0705230784 * r), b2 = (float)(0.0422820123 * r * r),
+                  b3 = (float)(0.0092705272 * r * r * r), b4 = (float)(0.0001520143 * r * r * r * r),
+                  b5 = (float)(0.0002765672 * r * r * r * r * r), b6 = (float)(0.0000430638 * r * r * r * r * r * r);
+  const float p = fmaf(a, fmaf(a, fmaf(a, fmaf(a, fmaf(a, fmaf(a, b6, b5), b4), b3), b2), b1), 1.0f);
+  const float q = __builtin_amdgcn_rcpf(p), q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
+  return q8 * q8;
 }
-// exact (erf) GELU and its derivative
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+// Phi(x) = (1 + erf(x / sqrt 2)) / 2, the standard normal distribution
+__device__ inline float norm_cdf(float x) {
+  const float h = 0.5f * erfc_half(fabsf(x));
+  return x >= 0.f ? 1.0f - h : h;
+}
+// exact (erf) GELU x Phi(x) and its derivative Phi(x) + x phi(x)
+__device__ inline float gelu(float x) { return x * norm_cdf(x); }
 __device__ inline float gelu_grad(float x) {
-  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+  return norm_cdf(x) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
 
 // ---- GEMM -------------------------------------------------------------------------------
@@ -87,6 +105,9 @@ struct GemmArgs {
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+__device__ inline short4_t pack4(float a, float b, float c, float d) {
+  return __builtin_bit_cast(short4_t, uint2v_t{pack2(a, b), pack2(c, d)});
+}
 
 __device__ inline short4_t load_frag(const bf16* base, long long r, long long c, int row, int k0,
                                      int nrow, int K, int kvec) {
@@ -257,8 +278,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int tiles_n, int 
       if (g.vecC && jb + 3 < g.N) {
         if (g.c_bf16) {
           uint2 o;
-          o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-          o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+          o.x = pack2(v[0], v[1]);
+          o.y = pack2(v[2], v[3]);
           *(uint2*)((bf16*)g.C + ob) = o;
         } else {
           *(float4*)((float*)g.C + ob) = make_float4(v[0], v[1], v[2], v[3]);
@@ -359,10 +380,10 @@ __global__ void k_lift8(const bf16* __restrict__ x, const bf16* __restrict__ Pw,
     for (int e = 0; e < 8; ++e) v[e] += xk * bf2f(Pw[k * C + c0 + e]);
   }
   uint4 o;
-  o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-  o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-  o.z = (unsigned)f2bf(v[4]) | ((unsigned)f2bf(v[5]) << 16);
-  o.w = (unsigned)f2bf(v[6]) | ((unsigned)f2bf(v[7]) << 16);
+  o.x = pack2(v[0], v[1]);
+  o.y = pack2(v[2], v[3]);
+  o.z = pack2(v[4], v[5]);
+  o.w = pack2(v[6], v[7]);
   *(uint4*)(h + p * C + c0) = o;
 }
 
@@ -421,9 +442,8 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb)
           acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa[hb][kb], hv[g][kb], acc, 0, 0, 0);
-        short4_t av;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) av[e] = (short)f2bf(gelu(acc[e] + bias1[hb][e]));
+        const short4_t av = pack4(gelu(acc[0] + bias1[hb][0]), gelu(acc[1] + bias1[hb][1]),
+                                  gelu(acc[2] + bias1[hb][2]), gelu(acc[3] + bias1[hb][3]));
         acc2[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qb[hb], av, acc2[g], 0, 0, 0);
       }
     }
@@ -562,8 +582,8 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] = ((Rs[0][j][c0 + q] + Rs[1][j][c0 + q]) + Rs[2][j][c0 + q]) + Rs[3][j][c0 + q];
       uint2 o;
-      o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-      o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+      o.x = pack2(v[0], v[1]);
+      o.y = pack2(v[2], v[3]);
       *(uint2*)(T1 + ((b * J + j) * H + y) * C + c0) = o;
     } else {
       __syncthreads();  // Ts is overwritten by the next row
