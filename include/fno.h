@@ -48,12 +48,14 @@ void fno_destroy(fno_ctx* ctx);
  * comparing the kernel paths against each other.  Both leave the network's
  * function unchanged; results may differ by BF16 rounding.
  * FNO_OPT_STAGED_GEMM: GEMM operands staged through LDS where the layout allows.
- * FNO_OPT_FUSED_TAIL: each Fourier layer's 1x1 convolution, inverse k_x
- *   transform, bias and GELU fused with the next layer's k_x transform in one
- *   kernel (width 32, 16 modes, W = 128 only).
+ * FNO_OPT_SPECIALIZED: kernels written for width 32 and 16 modes: each
+ *   Fourier layer's 1x1 convolution, inverse k_x transform, bias and GELU
+ *   fused with the next layer's k_x transform (W = 128), and the k_y
+ *   transform and synthesis as one kernel each (H = 128); other shapes take
+ *   the general GEMMs.
  * Returns TTSH_EINVAL for an unknown option. */
 #define FNO_OPT_STAGED_GEMM 1
-#define FNO_OPT_FUSED_TAIL 2
+#define FNO_OPT_SPECIALIZED 2
 int fno_set_option(fno_ctx* ctx, int option, int value);
 
 /* Number of float32 parameters (the length of the vectors below). */

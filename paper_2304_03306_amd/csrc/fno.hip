@@ -592,6 +592,119 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
   }
 }
 
+// The k_y step of the truncated transform for C = 32, 2m = 32 and H = 128,
+// one (sample b, k_x) pair per workgroup iteration.  With the real and
+// imaginary k_x rows R = T1[b][kx], I = T1[b][m + kx] (H x C each),
+//   G[kx][q][b][c] = sum_y DyRe[q][y] R[y][c] + DyIm[q][y] I[y][c],  q < 4m,
+// wavefront w computing rows q = 16w .. 16w + 15 over all of y from the two
+// blocks staged in LDS as [c][y]; the product is formed transposed so that a
+// lane stores four consecutive channels.
+__global__ void __launch_bounds__(256) k_yanalysis(const bf16* __restrict__ T1, const bf16* __restrict__ DyRe,
+                                                   const bf16* __restrict__ DyIm, bf16* __restrict__ G, int B,
+                                                   long long items) {
+  constexpr int C = 32, H = 128, m = 16, Q = 4 * m, LD = H + 8;
+  __shared__ __align__(16) bf16 Rs[2][C * LD];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int tid = threadIdx.x;
+  short4_t aR[H / 16], aI[H / 16];
+#pragma unroll
+  for (int kk = 0; kk < H / 16; ++kk) {
+    aR[kk] = *(const short4_t*)(DyRe + (16 * w + l16) * H + 16 * kk + q4);
+    aI[kk] = *(const short4_t*)(DyIm + (16 * w + l16) * H + 16 * kk + q4);
+  }
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int kx = (int)(it % m);
+    const long long b = it / m;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // 2 blocks x 128 rows x 4 runs of 8 channels
+      const int seg = tid + 256 * i, part = seg >> 9, y = (seg & 511) >> 2, c0 = (seg & 3) * 8;
+      const uint4 v = *(const uint4*)(T1 + ((b * 2 * m + part * m + kx) * H + y) * C + c0);
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Rs[part][(c0 + q) * LD + y] = e[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < H / 16; ++kk) {
+        const short4_t bR = *(const short4_t*)(Rs[0] + (16 * t + l16) * LD + 16 * kk + q4);
+        const short4_t bI = *(const short4_t*)(Rs[1] + (16 * t + l16) * LD + 16 * kk + q4);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bR, aR[kk], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bI, aI[kk], acc, 0, 0, 0);
+      }
+      // lane: row q = 16 w + l16, channels 16 t + q4 .. + 3
+      *(short4_t*)(G + (((long long)kx * Q + 16 * w + l16) * B + b) * C + 16 * t + q4) =
+          pack4(acc[0], acc[1], acc[2], acc[3]);
+    }
+    __syncthreads();  // Rs is overwritten by the next pair
+  }
+}
+
+// The k_y synthesis for C = 32, 2m = 32 and H = 128, one (sample b, k_x) pair
+// per workgroup iteration: from the mixed modes O[kx][ky][b] = (O_r, O_i),
+//   T2[b][y][kx][c]     = sum_ky Ec[y][ky] O_r[ky][c] - Es[y][ky] O_i[ky][c]
+//   T2[b][y][m + kx][c] = sum_ky Es[y][ky] O_r[ky][c] + Ec[y][ky] O_i[ky][c]
+// wavefront w computing y = 32w .. 32w + 31, both parts, from O_r and O_i
+// staged in LDS as [c][ky].
+__global__ void __launch_bounds__(256) k_ysynth(const bf16* __restrict__ O, const bf16* __restrict__ Ec,
+                                                const bf16* __restrict__ Es, const bf16* __restrict__ Esn,
+                                                bf16* __restrict__ T2, int B, long long items) {
+  constexpr int C = 32, H = 128, m = 16, K = 2 * m;
+  __shared__ __align__(16) bf16 Os[2][C * kLDK];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int tid = threadIdx.x;
+  short4_t ac[2][2], as[2][2], an[2][2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int off = (32 * w + 16 * s + l16) * K + 16 * kk + q4;
+      ac[s][kk] = *(const short4_t*)(Ec + off);
+      as[s][kk] = *(const short4_t*)(Es + off);
+      an[s][kk] = *(const short4_t*)(Esn + off);
+    }
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int kx = (int)(it % m);
+    const long long b = it / m;
+    {  // 2 parts x 32 ky x 4 runs of 8 channels
+      const int part = tid >> 7, ky = (tid >> 2) & 31, c0 = (tid & 3) * 8;
+      const uint4 v = *(const uint4*)(O + (((long long)kx * K + ky) * B + b) * 2 * C + part * C + c0);
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Os[part][(c0 + q) * kLDK + ky] = e[q];
+    }
+    __syncthreads();
+    short4_t br[2][2], bi[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        br[t][kk] = *(const short4_t*)(Os[0] + (16 * t + l16) * kLDK + 16 * kk + q4);
+        bi[t][kk] = *(const short4_t*)(Os[1] + (16 * t + l16) * kLDK + 16 * kk + q4);
+      }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        float4_t fr = {0.f, 0.f, 0.f, 0.f}, fi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          fr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[t][kk], ac[s][kk], fr, 0, 0, 0);
+          fr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[t][kk], an[s][kk], fr, 0, 0, 0);
+          fi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[t][kk], as[s][kk], fi, 0, 0, 0);
+          fi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[t][kk], ac[s][kk], fi, 0, 0, 0);
+        }
+        // lane: y = 32 w + 16 s + l16, channels 16 t + q4 .. + 3
+        bf16* row = T2 + ((b * H + 32 * w + 16 * s + l16) * K) * C + 16 * t + q4;
+        *(short4_t*)(row + kx * C) = pack4(fr[0], fr[1], fr[2], fr[3]);
+        *(short4_t*)(row + (m + kx) * C) = pack4(fi[0], fi[1], fi[2], fi[3]);
+      }
+    __syncthreads();  // Os is overwritten by the next pair
+  }
+}
+
 // dz = dh * GELU'(z), eight elements per thread with 16-byte accesses (n % 8 == 0)
 __global__ void k_gelu_back(const bf16* __restrict__ dh, const bf16* __restrict__ z, bf16* __restrict__ dz,
                             long long n) {
@@ -793,7 +906,7 @@ struct fno_ctx {
   double* lsum = nullptr;
   long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
   int staged_gemm = 1;        // GEMMs whose operands allow it stage them through LDS
-  int fused_tail = 1;         // the layer tail kernel where the shape allows it (C = 32, 2m = 32, W = 128)
+  int specialized = 1;        // kernels for C = 32, 2m = 32 and W = 128 (layer tail) / H = 128 (k_y steps)
   std::vector<void*> allocs;
   std::vector<std::pair<const char*, size_t>> extents;  // (start, bytes) of every buffer
 };
@@ -969,10 +1082,23 @@ int spectral_analysis_x(fno_ctx* c, const bf16* src, const bf16* Dxm, int B) {
   g.sC1 = 2LL * m * HC; g.sC2 = C; g.rC = HC; g.cC = 1;
   return cgemm(c, g);
 }
+bool y_specialized(const fno_ctx* c) { return c->specialized && c->C == 32 && c->m == 16 && c->H == 128; }
+
 // (the k_y step alone, from T1)
 int spectral_analysis_y(fno_ctx* c, bf16* dst, int B) {
   const int C = c->C, m = c->m, H = c->H;
   const long long HC = (long long)H * C;
+  if (y_specialized(c)) {
+    const std::pair<const char*, size_t>* none = nullptr;
+    const long long items = (long long)B * m;
+    if (!inside(c, c->T1, items * 2 * H * C - 1, 2, none, 0) || !inside(c, dst, items * 4 * m * C - 1, 2, none, 0) ||
+        !inside(c, c->DyRe, 4LL * m * H - 1, 2, none, 0) || !inside(c, c->DyIm, 4LL * m * H - 1, 2, none, 0))
+      return ffail(TTSH_EINVAL, "k_y analysis operand out of bounds (internal layout error)");
+    hipLaunchKernelGGL(k_yanalysis, dim3((unsigned)std::min<long long>(items, 1024)), dim3(256), 0, c->s, c->T1,
+                       c->DyRe, c->DyIm, dst, B, items);
+    FCHK(hipGetLastError());
+    return TTSH_OK;
+  }
   // dst[kx] (4m x C per b) = DyRe . T1_re + DyIm . T1_im
   GemmArgs h = ga();
   h.M = 4 * m; h.N = C; h.K = H; h.K2 = H;
@@ -991,7 +1117,7 @@ int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, i
   return spectral_analysis_y(c, dst, B);
 }
 
-bool tail_fusable(const fno_ctx* c) { return c->fused_tail && c->C == 32 && c->m == 16 && c->W == 128; }
+bool tail_fusable(const fno_ctx* c) { return c->specialized && c->C == 32 && c->m == 16 && c->W == 128; }
 
 // One launch of k_layer_tail for layer l (act and next: not the last layer).
 // Every operand is a context buffer sized for the maximum batch.
@@ -1024,6 +1150,18 @@ int spectral_synth_y(fno_ctx* c, const bf16* src, int B) {
   int rc;
   const int C = c->C, m = c->m, H = c->H;
   const long long modeS = (long long)B * 2 * C;  // stride between k_y rows
+  if (y_specialized(c)) {
+    const std::pair<const char*, size_t>* none = nullptr;
+    const long long items = (long long)B * m;
+    if (!inside(c, src, 2LL * m * m * modeS - 1, 2, none, 0) || !inside(c, c->T2, (long long)B * H * 2 * m * C - 1, 2, none, 0) ||
+        !inside(c, c->Ec, (long long)H * 2 * m - 1, 2, none, 0) || !inside(c, c->Es, (long long)H * 2 * m - 1, 2, none, 0) ||
+        !inside(c, c->Esn, (long long)H * 2 * m - 1, 2, none, 0))
+      return ffail(TTSH_EINVAL, "k_y synthesis operand out of bounds (internal layout error)");
+    hipLaunchKernelGGL(k_ysynth, dim3((unsigned)std::min<long long>(items, 1024)), dim3(256), 0, c->s, src, c->Ec,
+                       c->Es, c->Esn, c->T2, B, items);
+    FCHK(hipGetLastError());
+    return TTSH_OK;
+  }
   for (int part = 0; part < 2; ++part) {
     // part 0: Fr = Ec . O_r + (-Es) . O_i ;  part 1: Fi = Es . O_r + Ec . O_i
     GemmArgs g = ga();
@@ -1237,7 +1375,7 @@ int fno_get_grads(fno_ctx* c, float* p) {
 int fno_set_option(fno_ctx* c, int option, int value) {
   if (!c) return ffail(TTSH_EINVAL, "null context");
   if (option == FNO_OPT_STAGED_GEMM) c->staged_gemm = value != 0;
-  else if (option == FNO_OPT_FUSED_TAIL) c->fused_tail = value != 0;
+  else if (option == FNO_OPT_SPECIALIZED) c->specialized = value != 0;
   else return ffail(TTSH_EINVAL, "unknown option");
   return TTSH_OK;
 }

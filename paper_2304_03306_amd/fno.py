@@ -12,7 +12,7 @@ from .ttsh import TTSH_OK, TTSHError, lib as _ttsh_lib
 _sig_done = False
 
 FNO_OPT_STAGED_GEMM = 1
-FNO_OPT_FUSED_TAIL = 2
+FNO_OPT_SPECIALIZED = 2
 
 
 def lib():

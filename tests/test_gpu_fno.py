@@ -243,19 +243,20 @@ def test_fused_inference_projection_matches_training_path(gpu):
     assert np.array_equal(got[..., 2], x[..., 2].astype(np.float64))
 
 
-def test_fused_layer_tail_matches_oracle_and_unfused_path(gpu):
-    """Width 32, 16 modes and W = 128 take the fused layer tail (1x1
-    convolution, inverse k_x transform, bias, GELU and the next layer's k_x
-    transform in one kernel, the transform's k axis split over four
-    wavefronts).  Inference and training outputs and the gradients must stay
-    within the BF16 tolerance of the FP64 oracle, and the fused path must agree
-    with the separate GEMMs (FNO_OPT_FUSED_TAIL = 0) to BF16 rounding; the
-    batch (5 samples x 32 rows) is not a multiple of the persistent grid."""
+def test_specialized_kernels_match_oracle_and_general_path(gpu):
+    """Width 32, 16 modes and 128 x 128 take the specialized kernels: the
+    fused layer tail (1x1 convolution, inverse k_x transform, bias, GELU and
+    the next layer's k_x transform in one kernel, the transform's k axis split
+    over four wavefronts) and the k_y transform and synthesis kernels.
+    Inference and training outputs and the gradients must stay within the BF16
+    tolerance of the FP64 oracle, and agree with the general GEMMs
+    (FNO_OPT_SPECIALIZED = 0) to BF16 rounding; the batch (3 samples) leaves
+    the persistent grids partly idle."""
     import torch
     from paper_2304_03306_amd import fno
-    say("fno fused layer tail")
-    cfg = F.Config(H=32, W=128, cin=3, cout=2, width=32, modes=16, layers=3, hidden=16)
-    B = 5
+    say("fno specialized kernels")
+    cfg = F.Config(H=128, W=128, cin=3, cout=2, width=32, modes=16, layers=3, hidden=16)
+    B = 3
     net, p = make_net(gpu, cfg, B, seed=21)
     rng = np.random.default_rng(22)
     x = rng.standard_normal((B, cfg.H, cfg.W, cfg.cin)).astype(np.float32)
@@ -263,7 +264,7 @@ def test_fused_layer_tail_matches_oracle_and_unfused_path(gpu):
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
     out = {}
     for fused in (1, 0):
-        net.set_option(fno.FNO_OPT_FUSED_TAIL, fused)
+        net.set_option(fno.FNO_OPT_SPECIALIZED, fused)
         y = torch.empty((B, cfg.H, cfg.W, cfg.cout), dtype=torch.float32, device="cuda")
         net.forward(xd, y, train=False)
         yt = torch.empty_like(y)
