@@ -474,12 +474,16 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
 // points are added in a fixed order.  The product is formed untransposed, so
 // that lane l holds column c = l%16 and four consecutive points: exactly the
 // operand layout of the Dx product; the stores go through LDS to 32-byte rows.
-template <bool ACT, bool NEXT>
+// With LIFT the row is instead the lifting layer's output: h is the input
+// x[b][y][x][k] (cin <= 16 channels), Wl the lifting weights Pw[k][c] and bias
+// Pb, out = Pb + sum_k x[k] Pw[k][c], one MFMA k step with k padded to 16.
+constexpr int kMaxLiftCin = 16;
+template <bool ACT, bool NEXT, bool LIFT>
 __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, const bf16* __restrict__ T2,
                                                     const bf16* __restrict__ Ax, const bf16* __restrict__ Wl,
                                                     const float* __restrict__ bias, const bf16* __restrict__ Dx,
                                                     bf16* __restrict__ hn, bf16* __restrict__ z,
-                                                    bf16* __restrict__ T1, int H, long long rows) {
+                                                    bf16* __restrict__ T1, int H, long long rows, int cin) {
   constexpr int C = 32, J = 32, W = 128;
   __shared__ __align__(16) bf16 Ts[C * kLDK];      // T2 block transposed: [c][j]
   __shared__ __align__(16) bf16 Os[4][32 * kLDK];  // per wavefront output tile [x][c]
@@ -487,49 +491,71 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
   const int tid = threadIdx.x;
   // row-independent operands, held in registers
-  short4_t a1[2][2], b2[2][2], a3[2][2];
-  float bc[2];
+  short4_t a1[2][2], b2[2][2], a3[2][2], pw[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      a1[s][kk] = *(const short4_t*)(Ax + (32 * w + 16 * s + l16) * J + 16 * kk + q4);
+      if constexpr (!LIFT) {
+        a1[s][kk] = *(const short4_t*)(Ax + (32 * w + 16 * s + l16) * J + 16 * kk + q4);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) b2[s][kk][e] = (short)Wl[(16 * kk + q4 + e) * C + 16 * s + l16];
+        for (int e = 0; e < 4; ++e) b2[s][kk][e] = (short)Wl[(16 * kk + q4 + e) * C + 16 * s + l16];
+      }
       if constexpr (NEXT) a3[s][kk] = *(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + 16 * kk + q4);
     }
+  float bc[2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) bc[t] = bias[16 * t + l16];
+  for (int t = 0; t < 2; ++t) {
+    bc[t] = bias[16 * t + l16];
+    if constexpr (LIFT) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pw[t][e] = q4 + e < cin ? (short)Wl[(q4 + e) * C + 16 * t + l16] : (short)0;
+    }
+  }
 
   for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
-    const bf16* hp = h + row * (W * C);
-    short4_t a2[2][2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-        a2[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
-    {  // T2[b][y] (J x C) into LDS as [c][j]
-      const int j = tid >> 3, c0 = (tid & 7) * 4;
-      const uint2 v = *(const uint2*)(T2 + row * (J * C) + j * C + c0);
-      const bf16* e = (const bf16*)&v;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Ts[(c0 + q) * kLDK + j] = e[q];
-    }
-    __syncthreads();
     float4_t acc[2][2];
+    if constexpr (LIFT) {
+      __syncthreads();  // the previous row's reads of Rs are done before it is rewritten
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+      for (int s = 0; s < 2; ++s) {
+        const bf16* xr = h + (row * W + 32 * w + 16 * s + l16) * cin;
+        short4_t xa;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
+        for (int e = 0; e < 4; ++e) xa[e] = q4 + e < cin ? (short)xr[q4 + e] : (short)0;
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          const short4_t b1 = *(const short4_t*)(Ts + (16 * t + l16) * kLDK + 16 * kk + q4);
-          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[s][kk], b1, acc[s][t], 0, 0, 0);
-          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[s][kk], b2[t][kk], acc[s][t], 0, 0, 0);
-        }
+        for (int t = 0; t < 2; ++t)
+          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, pw[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       }
+    } else {
+      const bf16* hp = h + row * (W * C);
+      short4_t a2[2][2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+          a2[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+      {  // T2[b][y] (J x C) into LDS as [c][j]
+        const int j = tid >> 3, c0 = (tid & 7) * 4;
+        const uint2 v = *(const uint2*)(T2 + row * (J * C) + j * C + c0);
+        const bf16* e = (const bf16*)&v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ts[(c0 + q) * kLDK + j] = e[q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kk = 0; kk < 2; ++kk) {
+            const short4_t b1 = *(const short4_t*)(Ts + (16 * t + l16) * kLDK + 16 * kk + q4);
+            acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[s][kk], b1, acc[s][t], 0, 0, 0);
+            acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[s][kk], b2[t][kk], acc[s][t], 0, 0, 0);
+          }
+        }
+    }
     // acc[s][t][e] = out[x = 32 w + 16 s + q4 + e][c = 16 t + l16]
     bf16* Ow = Os[w];
     bf16* hrow = hn + row * (W * C) + 32 * w * C;
@@ -1119,6 +1145,22 @@ int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, i
 
 bool tail_fusable(const fno_ctx* c) { return c->specialized && c->C == 32 && c->m == 16 && c->W == 128; }
 
+// The lifting layer fused with the first layer's k_x transform: h[0] and T1
+// from the BF16 input xb.
+int lift_tail(fno_ctx* c, int B) {
+  const long long rows = (long long)B * c->H, P = rows * c->W;
+  const std::pair<const char*, size_t>* none = nullptr;
+  if (!inside(c, c->xb, P * c->cin - 1, 2, none, 0) || !inside(c, c->h[0], P * 32 - 1, 2, none, 0) ||
+      !inside(c, c->T1, rows * 32 * 32 - 1, 2, none, 0) || !inside(c, c->Pw, (long long)c->cin * 32 - 1, 2, none, 0) ||
+      !inside(c, c->Dx, 32 * 128 - 1, 2, none, 0))
+    return ffail(TTSH_EINVAL, "lift operand out of bounds (internal layout error)");
+  const unsigned blocks = (unsigned)std::min<long long>(rows, 1280);
+  hipLaunchKernelGGL((k_layer_tail<false, true, true>), dim3(blocks), dim3(256), 0, c->s, c->xb, nullptr, nullptr,
+                     c->Pw, c->theta + c->oPb, c->Dx, c->h[0], nullptr, c->T1, c->H, rows, c->cin);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
 // One launch of k_layer_tail for layer l (act and next: not the last layer).
 // Every operand is a context buffer sized for the maximum batch.
 int layer_tail(fno_ctx* c, int l, int B, bool train) {
@@ -1135,11 +1177,11 @@ int layer_tail(fno_ctx* c, int l, int B, bool train) {
   const float* bias = c->theta + c->ob[l];
   bf16* z = train && !last ? c->z[l] : nullptr;
   if (last)
-    hipLaunchKernelGGL((k_layer_tail<false, false>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax,
-                       c->Wl[l], bias, c->Dx, c->h[l + 1], z, c->T1, c->H, rows);
+    hipLaunchKernelGGL((k_layer_tail<false, false, false>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax,
+                       c->Wl[l], bias, c->Dx, c->h[l + 1], z, c->T1, c->H, rows, 0);
   else
-    hipLaunchKernelGGL((k_layer_tail<true, true>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax,
-                       c->Wl[l], bias, c->Dx, c->h[l + 1], z, c->T1, c->H, rows);
+    hipLaunchKernelGGL((k_layer_tail<true, true, false>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax,
+                       c->Wl[l], bias, c->Dx, c->h[l + 1], z, c->T1, c->H, rows, 0);
   FCHK(hipGetLastError());
   return TTSH_OK;
 }
@@ -1399,19 +1441,22 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
       return ffail(TTSH_EINVAL, "output overlaps the input other than as its first channels");
   }
   hipLaunchKernelGGL(k_to_bf16, dim3(nb(P * c->cin)), dim3(256), 0, c->s, x, c->xb, P * c->cin);
-  if (C % 8 == 0)
+  const bool fuse = tail_fusable(c);
+  const bool fuse_lift = fuse && c->cin <= kMaxLiftCin;
+  int rc;
+  if (fuse_lift) {
+    if ((rc = lift_tail(c, B))) return rc;
+  } else if (C % 8 == 0)
     hipLaunchKernelGGL(k_lift8, dim3(nb(P * (C / 8))), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb,
                        c->h[0], P, c->cin, C);
   else
     hipLaunchKernelGGL(k_lift, dim3(nb(P * C)), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb, c->h[0], P,
                        c->cin, C);
   FCHK(hipGetLastError());
-  int rc;
-  const bool fuse = tail_fusable(c);
   for (int l = 0; l < c->L; ++l) {
     const bool last = l == c->L - 1;
-    // with the fused tail, the previous layer already left T1 (the k_x step of h_l)
-    if (l == 0 || !fuse)
+    // with the fused tail (and lift), the previous step already left T1 (the k_x step of h_l)
+    if (l == 0 ? !fuse_lift : !fuse)
       if ((rc = spectral_analysis_x(c, c->h[l], c->Dx, B))) return rc;
     if ((rc = spectral_analysis_y(c, c->G[l], B))) return rc;
     if ((rc = spectral_mix(c, c->G[l], c->Wb[l], false, c->O, B))) return rc;
