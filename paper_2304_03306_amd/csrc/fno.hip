@@ -731,6 +731,54 @@ __global__ void __launch_bounds__(256) k_ysynth(const bf16* __restrict__ O, cons
   }
 }
 
+// Per-mode channel mixing for C = 32 (2C = 64): for mode (kx, q) the rows b
+// of [G_r, G_i] (B x 64, G[kx][q][b][c] and G[kx][2m + q][b][c]) times the
+// 64 x 64 block V, out[kx][q][b][n] = sum_k [G_r, G_i][b][k] V[k][n], with V
+// given transposed (Vt[n][k], rows along k): WbT for the forward product,
+// Wb itself for the adjoint (V = Wb^T).  One workgroup per mode, its
+// wavefronts taking the 32 x 32 output tiles in turn; every fragment is read
+// straight from memory with 8-byte loads, and the product is formed
+// transposed so that a lane stores four consecutive outputs.
+__global__ void __launch_bounds__(256) k_mix(const bf16* __restrict__ G, const bf16* __restrict__ Vt,
+                                             bf16* __restrict__ out, int B, int m) {
+  constexpr int C = 32, C2 = 64;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const long long mode = blockIdx.x;  // kx * 2m + q
+  const int kx = (int)(mode / (2 * m)), q = (int)(mode % (2 * m));
+  const bf16* Gr = G + ((long long)kx * 4 * m + q) * B * C;
+  const bf16* Gi = Gr + 2LL * m * B * C;
+  const bf16* V = Vt + mode * C2 * C2;
+  bf16* o = out + mode * B * C2;
+  const int tiles = (B + 31) / 32 * 2;
+  for (int tile = w; tile < tiles; tile += 4) {
+    const int i0 = (tile >> 1) * 32, j0 = (tile & 1) * 32;
+    short4_t a[2][4], v[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = i0 + 16 * s + l16;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        a[s][kk] = row < B ? *(const short4_t*)((kk < 2 ? Gr : Gi) + (long long)row * C + 16 * (kk & 1) + q4)
+                           : short4_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) v[t][kk] = *(const short4_t*)(V + (j0 + 16 * t + l16) * C2 + 16 * kk + q4);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int row = i0 + 16 * s + l16;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(v[t][kk], a[s][kk], acc, 0, 0, 0);
+        if (row < B) *(short4_t*)(o + (long long)row * C2 + j0 + 16 * t + q4) = pack4(acc[0], acc[1], acc[2], acc[3]);
+      }
+    }
+  }
+}
+
 // dz = dh * GELU'(z), eight elements per thread with 16-byte accesses (n % 8 == 0)
 __global__ void k_gelu_back(const bf16* __restrict__ dh, const bf16* __restrict__ z, bf16* __restrict__ dz,
                             long long n) {
@@ -882,8 +930,9 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
 }
 
 // Wb[kx][q] = [[R_r, R_i], [-R_i, R_r]] (2C x 2C, bf16) from the master R
+// (and its per-mode transpose WbT[kx][q][j][i] = Wb[kx][q][i][j])
 __global__ void k_build_wb(const float* __restrict__ Rr, const float* __restrict__ Ri, bf16* __restrict__ Wb,
-                           int m, int C) {
+                           bf16* __restrict__ WbT, int m, int C) {
   const long long n = (long long)2 * m * m * 4 * C * C;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
@@ -896,6 +945,7 @@ __global__ void k_build_wb(const float* __restrict__ Rr, const float* __restrict
   if (i < C) v = (j < C) ? Rr[src] : Ri[src];
   else v = (j < C) ? -Ri[src] : Rr[src];
   Wb[idx] = f2bf(v);
+  WbT[(mode * C2 + j) * C2 + i] = f2bf(v);
 }
 
 unsigned nb(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -919,7 +969,7 @@ struct fno_ctx {
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   int adam_t = 0;
   // bf16 compute copies
-  bf16 *Pw = nullptr, *Wl[16] = {}, *Wb[16] = {}, *Q1 = nullptr, *Q2 = nullptr;
+  bf16 *Pw = nullptr, *Wl[16] = {}, *Wb[16] = {}, *WbT[16] = {}, *Q1 = nullptr, *Q2 = nullptr;
   // DFT matrices (bf16)
   bf16 *Dx, *DxG, *DyRe, *DyIm, *Ec, *Es, *Esn, *Ax, *Ax1;
   // activations
@@ -1038,7 +1088,7 @@ int refresh_weights(fno_ctx* c) {
     const long long nwb = (long long)2 * m * m * 4 * C * C;
     const long long nR = (long long)2 * m * m * C * C;
     hipLaunchKernelGGL(k_build_wb, dim3(nb(nwb)), dim3(256), 0, c->s, c->theta + c->oR[l], c->theta + c->oR[l] + nR,
-                       c->Wb[l], m, C);
+                       c->Wb[l], c->WbT[l], m, C);
   }
   hipLaunchKernelGGL(k_to_bf16, dim3(nb((long long)C * c->hid)), dim3(256), 0, c->s, c->theta + c->oQ1, c->Q1,
                      (long long)C * c->hid);
@@ -1221,10 +1271,21 @@ int spectral_synth_y(fno_ctx* c, const bf16* src, int B) {
 }
 
 // Mode mixing: out[kx][q][b][0:2C] = [G_r, G_i][b] . Wb (forward) or Wb^T (adjoint)
-int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, bool transpose, bf16* out, int B) {
+int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, const bf16* WbT, bool transpose, bf16* out, int B) {
   int rc;
   const int C = c->C, m = c->m;
   const long long C2 = 2LL * C;
+  if (c->specialized && C == 32) {
+    const std::pair<const char*, size_t>* none = nullptr;
+    const bf16* Vt = transpose ? Wb : WbT;
+    const long long modes = 2LL * m * m;
+    if (!inside(c, G, modes * 2 * B * C - 1, 2, none, 0) || !inside(c, Vt, modes * C2 * C2 - 1, 2, none, 0) ||
+        !inside(c, out, modes * B * C2 - 1, 2, none, 0))
+      return ffail(TTSH_EINVAL, "mode mixing operand out of bounds (internal layout error)");
+    hipLaunchKernelGGL(k_mix, dim3((unsigned)modes), dim3(256), 0, c->s, G, Vt, out, B, m);
+    FCHK(hipGetLastError());
+    return TTSH_OK;
+  }
   GemmArgs g = ga();
   g.M = B; g.N = 2 * C; g.K = C; g.K2 = C;
   g.nb1 = m; g.nb2 = 2 * m;
@@ -1351,7 +1412,8 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
   for (int l = 0; l < layers; ++l)
     if ((rc = alloc(c, &c->z[l], (size_t)(P * C))) || (rc = alloc(c, &c->G[l], (size_t)modesz)) ||
         (rc = alloc(c, &c->Wl[l], (size_t)(C * C))) ||
-        (rc = alloc(c, &c->Wb[l], (size_t)(2 * m * m * 4 * C * C))))
+        (rc = alloc(c, &c->Wb[l], (size_t)(2 * m * m * 4 * C * C))) ||
+        (rc = alloc(c, &c->WbT[l], (size_t)(2 * m * m * 4 * C * C))))
       return bail(rc);
   // partial sums of the split-K reductions: (points/4096) x the largest gradient block
   const long long maxblk = std::max<long long>({C * C, C * hidden, (long long)hidden * cout, cin * C});
@@ -1459,7 +1521,7 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     if (l == 0 ? !fuse_lift : !fuse)
       if ((rc = spectral_analysis_x(c, c->h[l], c->Dx, B))) return rc;
     if ((rc = spectral_analysis_y(c, c->G[l], B))) return rc;
-    if ((rc = spectral_mix(c, c->G[l], c->Wb[l], false, c->O, B))) return rc;
+    if ((rc = spectral_mix(c, c->G[l], c->Wb[l], c->WbT[l], false, c->O, B))) return rc;
     if ((rc = spectral_synth_y(c, c->O, B))) return rc;
     if (fuse) {
       if ((rc = layer_tail(c, l, B, train != 0))) return rc;
@@ -1600,7 +1662,7 @@ int fno_backward(fno_ctx* c, int B) {
       if ((rc = cgemm(c, r))) return rc;
     }
     // g_F = g_G Wb^T  (into gF, mode layout [m][2m][B][2C])
-    if ((rc = spectral_mix(c, c->gG, c->Wb[l], true, c->gF, B))) return rc;
+    if ((rc = spectral_mix(c, c->gG, c->Wb[l], c->WbT[l], true, c->gF, B))) return rc;
     if ((rc = spectral_synth_y(c, c->gF, B))) return rc;
     // dh_l = Ax1 . T2 + dz W_l^T
     GemmArgs e = ga();
