@@ -907,13 +907,50 @@ __global__ void k_colsum_part(const bf16* __restrict__ a, long long rows, int nc
   }
 }
 
-// out[j] = sum_c part[c][j] (fixed order)
-__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, long long n, float* __restrict__ out) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// the same for ncol = 8 * 2^k <= 256: a thread adds 8 adjacent columns with
+// 16-byte loads; rows are dealt round robin to the 256 / (ncol / 8) row lanes,
+// whose sums are then added in lane order
+__global__ void __launch_bounds__(256) k_colsum_part8(const bf16* __restrict__ a, long long rows, int ncol,
+                                                      long long chunk, float* __restrict__ part) {
+  const int tpr = ncol / 8, rpi = 256 / tpr;
+  const int g = threadIdx.x % tpr, r = threadIdx.x / tpr;
+  const long long r0 = (long long)blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
+  float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (long long row = r0 + r; row < r1; row += rpi) {
+    const uint4 u = *(const uint4*)(a + row * ncol + 8 * g);
+    const bf16* e = (const bf16*)&u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] += bf2f(e[q]);
+  }
+  __shared__ float red[256 * 8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[r * ncol + 8 * g + q] = v[q];
+  __syncthreads();
+  if (threadIdx.x < ncol) {
+    float s = 0.f;
+    for (int q = 0; q < rpi; ++q) s += red[q * ncol + threadIdx.x];
+    part[(long long)blockIdx.x * ncol + threadIdx.x] = s;
+  }
+}
+
+// out[j] = sum_c part[c][j] in a fixed order: 16 interleaved partial sums per
+// column (c = g, g + 16, ...), then added for g = 0..15; 16 columns per block
+__global__ void __launch_bounds__(256) k_reduce_parts(const float* __restrict__ part, int nparts, long long n,
+                                                      float* __restrict__ out) {
+  const int jj = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const long long j = (long long)blockIdx.x * 16 + jj;
   float s = 0.f;
-  for (int c = 0; c < nparts; ++c) s += part[(long long)c * n + j];
-  out[j] = s;
+  if (j < n)
+    for (int c = g; c < nparts; c += 16) s += part[(long long)c * n + j];
+  __shared__ float red[16][16];
+  red[g][jj] = s;
+  __syncthreads();
+  if (g == 0 && j < n) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][jj];
+    out[j] = t;
+  }
 }
 
 __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
@@ -1307,12 +1344,16 @@ int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, const bf16* WbT, boo
 
 long long pts(const fno_ctx* c, int B) { return (long long)B * c->H * c->W; }
 
+// points per partial product of a weight gradient: short enough that the
+// partial products (one wavefront per 32 x 32 tile each) fill the chip
+constexpr long long kWgradChunk = 1024;
+
 // split-K weight gradient: out (M x N, float, += into grad) = A^T-like product
 // over the point axis.  A[i][p] at A + i*rA + p*cA, B[p][j] at B + p*rB + j*cB.
 int wgrad(fno_ctx* c, int M, int N, long long P, const bf16* A, long long rA, long long cA, const bf16* Bm,
           long long rB, long long cB, float* out) {
   int rc;
-  const long long chunk = 4096;
+  const long long chunk = kWgradChunk;
   const long long nchunk = (P + chunk - 1) / chunk;
   if ((size_t)(nchunk * M * N) > c->part_n) return ffail(TTSH_ENOMEM, "fno partials buffer too small");
   GemmArgs g = ga();
@@ -1336,20 +1377,26 @@ int wgrad(fno_ctx* c, int M, int N, long long P, const bf16* A, long long rA, lo
     t.C = c->part + (nchunk - 1) * M * N;
     if ((rc = cgemm(c, t))) return rc;
   }
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nb((long long)M * N)), dim3(256), 0, c->s, c->part, (int)nchunk,
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nb((long long)M * N, 16)), dim3(256), 0, c->s, c->part, (int)nchunk,
                      (long long)M * N, out);
   FCHK(hipGetLastError());
   return TTSH_OK;
 }
 
 int colsum(fno_ctx* c, const bf16* a, long long rows, int ncol, float* out) {
-  const long long chunk = 8192;
+  const bool vec = ncol % 8 == 0 && ncol <= 256 && ((ncol / 8) & (ncol / 8 - 1)) == 0 && ((uintptr_t)a & 15) == 0;
+  const long long chunk = vec ? 2048 : 8192;
   const long long nchunk = (rows + chunk - 1) / chunk;
   if ((size_t)(nchunk * ncol) > c->part_n) return ffail(TTSH_ENOMEM, "fno partials buffer too small");
-  const int lanes = std::max(1, std::min(1024 / ncol, 64));
-  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)nchunk), dim3(lanes * ncol), 0, c->s, a, rows, ncol, chunk,
-                     c->part);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nb(ncol)), dim3(256), 0, c->s, c->part, (int)nchunk, (long long)ncol, out);
+  if (vec) {
+    hipLaunchKernelGGL(k_colsum_part8, dim3((unsigned)nchunk), dim3(256), 0, c->s, a, rows, ncol, chunk, c->part);
+  } else {
+    const int lanes = std::max(1, std::min(1024 / ncol, 64));
+    hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)nchunk), dim3(lanes * ncol), 0, c->s, a, rows, ncol, chunk,
+                       c->part);
+  }
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nb(ncol, 16)), dim3(256), 0, c->s, c->part, (int)nchunk, (long long)ncol,
+                     out);
   FCHK(hipGetLastError());
   return TTSH_OK;
 }
@@ -1415,9 +1462,9 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
         (rc = alloc(c, &c->Wb[l], (size_t)(2 * m * m * 4 * C * C))) ||
         (rc = alloc(c, &c->WbT[l], (size_t)(2 * m * m * 4 * C * C))))
       return bail(rc);
-  // partial sums of the split-K reductions: (points/4096) x the largest gradient block
+  // partial sums of the split-K reductions: (points / kWgradChunk) x the largest gradient block
   const long long maxblk = std::max<long long>({C * C, C * hidden, (long long)hidden * cout, cin * C});
-  c->part_n = (size_t)((P + 4095) / 4096 + 1) * (size_t)std::max<long long>(maxblk, 1024);
+  c->part_n = (size_t)((P + kWgradChunk - 1) / kWgradChunk + 1) * (size_t)std::max<long long>(maxblk, 1024);
   if ((rc = alloc(c, &c->part, c->part_n))) return bail(rc);
   if ((rc = make_dft(c))) return bail(rc);
   // seeded initial parameters (same distributions as the oracle's)
