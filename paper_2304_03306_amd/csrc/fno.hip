@@ -779,6 +779,163 @@ __global__ void __launch_bounds__(256) k_mix(const bf16* __restrict__ G, const b
   }
 }
 
+// Backward of the projection y = GELU(u) Q2 + b2, u = h Q1 + b1, for C = 32
+// and HID = 128, fused so that the hidden layer never reaches memory.  Per
+// group of 16 points a wavefront recomputes u^T = Q1^T h^T on the matrix cores
+// (the forward's operand layout: lane = point, four consecutive hidden rows),
+// forms a = GELU(u) and du = (dy Q2^T) GELU'(u) in registers, writes
+// dh = du Q1^T (du is already the second operand of that product), and adds
+// the group to its running weight gradients dQ1^T = du^T h and dQ2 = a^T dy
+// (operands transposed through the wavefront's LDS) and the bias gradients.
+// Each wavefront finally writes its sums to slot `wave` of part, laid out as
+// the gradient vector [dQ1 (C x HID) | db1 (HID) | dQ2 (HID x cout) | db2 (cout)],
+// and the slots are reduced afterwards in a fixed order.
+constexpr int kProjBackMaxCout = 4;
+template <int C, int HID>
+__global__ void __launch_bounds__(256, 2) k_proj_back(const bf16* __restrict__ h, const bf16* __restrict__ Q1,
+                                                      const float* __restrict__ b1, const bf16* __restrict__ Q2,
+                                                      const bf16* __restrict__ dy, int cout, bf16* __restrict__ dh,
+                                                      float* __restrict__ part, long long npts) {
+  constexpr int HB = HID / 16, KB = C / 16, LDJ = HID + 8, LDC = C + 8, MO = kProjBackMaxCout;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const long long wave = (long long)blockIdx.x * 4 + w, nwave = (long long)gridDim.x * 4;
+  __shared__ float Q2s[HID][MO], B1s[HID];
+  __shared__ __align__(16) bf16 Q1s[C * LDJ], Q1t[HID * LDC];  // Q1 [c][j] and Q1^T [j][c]
+  __shared__ __align__(16) bf16 DU[4][16 * LDJ], AA[4][16 * LDJ], HS[4][16 * LDC], DY[4][16 * 16];
+  for (int i = threadIdx.x; i < HID * MO; i += 256) {
+    const int j = i / MO, o = i % MO;
+    Q2s[j][o] = o < cout ? bf2f(Q2[j * cout + o]) : 0.f;
+  }
+  for (int i = threadIdx.x; i < HID; i += 256) B1s[i] = b1[i];
+  for (int i = threadIdx.x; i < C * HID / 8; i += 256) {
+    const int c = i / (HID / 8), j0 = (i % (HID / 8)) * 8;
+    *(uint4*)(Q1s + c * LDJ + j0) = *(const uint4*)(Q1 + c * HID + j0);
+  }
+  for (int i = threadIdx.x; i < C * HID; i += 256) {
+    const int c = i / HID, j = i % HID;
+    Q1t[j * LDC + c] = Q1[i];
+  }
+  __syncthreads();
+  float4_t g1[HB][KB], g2[HB];  // g1[jb][cb][e] = dQ1^T[16 jb + q4 + e][16 cb + l16]; g2[jb][e] = dQ2[16 jb + q4 + e][l16]
+  float gb1[HB][4], gb2 = 0.f;  // gb1: this lane's point; gb2: output l16, points q4 .. q4 + 3
+#pragma unroll
+  for (int hb = 0; hb < HB; ++hb) {
+    g2[hb] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) g1[hb][kb] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) gb1[hb][e] = 0.f;
+  }
+  bf16 *du_s = DU[w], *a_s = AA[w], *h_s = HS[w], *dy_s = DY[w];
+  for (long long t = wave; t * 16 < npts; t += nwave) {
+    const long long p = t * 16 + l16;
+    const bool ok = p < npts;
+    short4_t hv[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) hv[kb] = ok ? *(const short4_t*)(h + p * C + 16 * kb + q4) : short4_t{0, 0, 0, 0};
+    float dyv[MO];  // this lane's point
+#pragma unroll
+    for (int o = 0; o < MO; ++o) dyv[o] = (ok && o < cout) ? bf2f(dy[p * cout + o]) : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dy_s[l16 * 16 + q4 + e] = (ok && q4 + e < cout) ? dy[p * cout + q4 + e] : (bf16)0;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) *(short4_t*)(h_s + l16 * LDC + 16 * kb + q4) = hv[kb];
+#pragma unroll
+    for (int hb = 0; hb < HB; ++hb) {
+      float4_t u = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        u = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(*(const short4_t*)(Q1t + (16 * hb + l16) * LDC + 16 * kb + q4),
+                                                       hv[kb], u, 0, 0, 0);
+      float a4[4], d4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 16 * hb + q4 + e;
+        const float uv = u[e] + B1s[j];
+        const float ph = norm_cdf(uv);
+        float da = 0.f;
+#pragma unroll
+        for (int o = 0; o < MO; ++o) da += dyv[o] * Q2s[j][o];
+        a4[e] = ok ? uv * ph : 0.f;
+        d4[e] = ok ? da * (ph + uv * 0.39894228040143268f * __expf(-0.5f * uv * uv)) : 0.f;
+      }
+      const short4_t duf = pack4(d4[0], d4[1], d4[2], d4[3]);
+      // rows = points, for dh below and the weight gradients
+      *(short4_t*)(du_s + l16 * LDJ + 16 * hb + q4) = duf;
+      *(short4_t*)(a_s + l16 * LDJ + 16 * hb + q4) = pack4(a4[0], a4[1], a4[2], a4[3]);
+      // the bias gradient adds the stored (rounded) du, as the unfused path does
+#pragma unroll
+      for (int e = 0; e < 4; ++e) gb1[hb][e] += bf2f((bf16)duf[e]);
+    }
+    wave_lds_sync();
+    // dh^T = Q1 du^T: lane = point, channels 16 cb + q4 .. + 3
+#pragma unroll
+    for (int cb = 0; cb < KB; ++cb) {
+      float4_t d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int hb = 0; hb < HB; ++hb)
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(*(const short4_t*)(Q1s + (16 * cb + l16) * LDJ + 16 * hb + q4),
+                                                       *(const short4_t*)(du_s + l16 * LDJ + 16 * hb + q4), d, 0, 0, 0);
+      if (ok) *(short4_t*)(dh + p * C + 16 * cb + q4) = pack4(d[0], d[1], d[2], d[3]);
+    }
+    // weight gradients: contraction over the group's 16 points
+    short4_t hT[KB], dyb;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) hT[kb][e] = (short)h_s[(q4 + e) * LDC + 16 * kb + l16];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dyb[e] = (short)dy_s[(q4 + e) * 16 + l16];
+#pragma unroll
+    for (int jb = 0; jb < HB; ++jb) {
+      short4_t duT, aT;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        duT[e] = (short)du_s[(q4 + e) * LDJ + 16 * jb + l16];
+        aT[e] = (short)a_s[(q4 + e) * LDJ + 16 * jb + l16];
+      }
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) g1[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(duT, hT[kb], g1[jb][kb], 0, 0, 0);
+      g2[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aT, dyb, g2[jb], 0, 0, 0);
+    }
+    // db2: this lane adds points q4 .. q4 + 3 of output l16 (the four lane groups are added at the end)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) gb2 += bf2f((bf16)dyb[e]);
+    wave_lds_sync();
+  }
+  // bias gradient db1: lanes with the same q4 hold different points
+#pragma unroll
+  for (int hb = 0; hb < HB; ++hb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float v = gb1[hb][e];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      gb1[hb][e] = v;
+    }
+  gb2 += __shfl_xor(gb2, 16);
+  gb2 += __shfl_xor(gb2, 32);
+  float* slot = part + wave * (long long)(C * HID + HID + HID * cout + cout);
+#pragma unroll
+  for (int jb = 0; jb < HB; ++jb) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) slot[(16 * kb + l16) * HID + 16 * jb + q4 + e] = g1[jb][kb][e];
+    if (l16 == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) slot[C * HID + 16 * jb + q4 + e] = gb1[jb][e];
+    }
+    if (l16 < cout) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) slot[C * HID + HID + (16 * jb + q4 + e) * cout + l16] = g2[jb][e];
+    }
+  }
+  if (q4 == 0 && l16 < cout) slot[C * HID + HID + HID * cout + l16] = gb2;
+}
+
 // dz = dh * GELU'(z), eight elements per thread with 16-byte accesses (n % 8 == 0)
 __global__ void k_gelu_back(const bf16* __restrict__ dh, const bf16* __restrict__ z, bf16* __restrict__ dz,
                             long long n) {
@@ -1020,6 +1177,7 @@ struct fno_ctx {
   long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
   int staged_gemm = 1;        // GEMMs whose operands allow it stage them through LDS
   int specialized = 1;        // kernels for C = 32, 2m = 32 and W = 128 (layer tail) / H = 128 (k_y steps)
+  bool proj_train_fused = false;  // the last training forward left no hidden layer (fused backward)
   std::vector<void*> allocs;
   std::vector<std::pair<const char*, size_t>> extents;  // (start, bytes) of every buffer
 };
@@ -1465,6 +1623,8 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
   // partial sums of the split-K reductions: (points / kWgradChunk) x the largest gradient block
   const long long maxblk = std::max<long long>({C * C, C * hidden, (long long)hidden * cout, cin * C});
   c->part_n = (size_t)((P + kWgradChunk - 1) / kWgradChunk + 1) * (size_t)std::max<long long>(maxblk, 1024);
+  // (and 2048 wavefront slots of the fused projection backward: two workgroups per CU)
+  c->part_n = std::max<size_t>(c->part_n, (size_t)2048 * (size_t)(C * hidden + hidden + (long long)hidden * cout + cout));
   if ((rc = alloc(c, &c->part, c->part_n))) return bail(rc);
   if ((rc = make_dft(c))) return bail(rc);
   // seeded initial parameters (same distributions as the oracle's)
@@ -1591,7 +1751,12 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     }
     if ((rc = cgemm(c, g))) return rc;
   }
-  if (!train && C == 32 && c->hid == 128 && c->cout <= 16) {
+  // the fused projection: always for inference; in training too with the
+  // specialized kernels, whose fused backward recomputes the hidden layer
+  const bool proj_fused = C == 32 && c->hid == 128 && c->cout <= 16 &&
+                          (!train || (c->specialized && c->cout <= kProjBackMaxCout));
+  c->proj_train_fused = train && proj_fused;
+  if (proj_fused) {
     // h_L is [P][C] (inside h[L]), y and skip were range-checked above
     const long long tiles = (P + 15) / 16;
     const long long blocks = std::min<long long>((tiles + 7) / 8, 8192);  // 4 waves x 2 groups
@@ -1656,6 +1821,21 @@ int fno_backward(fno_ctx* c, int B) {
   const long long P = pts(c, B);
   int rc;
   // projection
+  if (c->proj_train_fused) {
+    // one slot of partial gradients per wavefront, [dQ1 | db1 | dQ2 | db2] as in the parameter vector
+    const long long S = (long long)C * hid + hid + (long long)hid * co + co;
+    const long long groups = (P + 15) / 16;
+    const long long blocks = std::max<long long>(1, std::min<long long>({(groups + 3) / 4, 512, (long long)c->part_n / (4 * S)}));
+    const std::pair<const char*, size_t>* none = nullptr;
+    if ((long long)c->part_n < 4 * S || !inside(c, c->h[c->L], P * C - 1, 2, none, 0) ||
+        !inside(c, c->dy, P * co - 1, 2, none, 0) || !inside(c, c->dh0, P * C - 1, 2, none, 0))
+      return ffail(TTSH_EINVAL, "projection backward operand out of bounds (internal layout error)");
+    hipLaunchKernelGGL((k_proj_back<32, 128>), dim3((unsigned)blocks), dim3(256), 0, c->s, c->h[c->L], c->Q1,
+                       c->theta + c->oQ1b, c->Q2, c->dy, co, c->dh0, c->part, P);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nb(S, 16)), dim3(256), 0, c->s, c->part, (int)(blocks * 4), S,
+                       c->grad + c->oQ1);
+    FCHK(hipGetLastError());
+  } else {
   if ((rc = wgrad(c, hid, co, P, c->a, 1, hid, c->dy, co, 1, c->grad + c->oQ2))) return rc;
   if ((rc = colsum(c, c->dy, P, co, c->grad + c->oQ2b))) return rc;
   GemmArgs g = ga();  // du = (dy Q2^T) * GELU'(u)
@@ -1673,6 +1853,7 @@ int fno_backward(fno_ctx* c, int B) {
   d.B = op(c->Q1, 1, hid);
   d.C = c->dh0; d.c_bf16 = 1; d.rC = C; d.cC = 1;
   if ((rc = cgemm(c, d))) return rc;
+  }
   bf16* dh = c->dh0;
   bf16* dh_next = c->dh1;
   for (int l = c->L - 1; l >= 0; --l) {

@@ -218,9 +218,11 @@ def test_residual_forward_in_place_and_gather(gpu):
 def test_fused_inference_projection_matches_training_path(gpu):
     """With width 32 and hidden 128 an inference forward runs the projection
     fused (the hidden layer never leaves registers); it must give what the
-    unfused training-mode forward gives, in plain and residual in-place form,
-    and stay within the BF16 tolerance of the FP64 oracle."""
+    unfused training-mode forward of the general kernels gives, in plain and
+    residual in-place form, and stay within the BF16 tolerance of the FP64
+    oracle."""
     import torch
+    from paper_2304_03306_amd import fno
     say("fno fused projection")
     cfg = F.Config(H=32, W=48, cin=3, cout=2, width=32, modes=4, layers=1, hidden=128)
     B = 3
@@ -231,7 +233,9 @@ def test_fused_inference_projection_matches_training_path(gpu):
     y1 = torch.empty((B, cfg.H, cfg.W, cfg.cout), dtype=torch.float32, device="cuda")
     y2 = torch.empty_like(y1)
     net.forward(xd, y1, train=False)
+    net.set_option(fno.FNO_OPT_SPECIALIZED, 0)
     net.forward(xd, y2, train=True)
+    net.set_option(fno.FNO_OPT_SPECIALIZED, 1)
     a, b = y1.cpu().numpy().astype(np.float64), y2.cpu().numpy().astype(np.float64)
     assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
     ref = F.forward(p, x.astype(np.float64), cfg)
@@ -244,10 +248,13 @@ def test_fused_inference_projection_matches_training_path(gpu):
 
 
 def test_specialized_kernels_match_oracle_and_general_path(gpu):
-    """Width 32, 16 modes and 128 x 128 take the specialized kernels: the
-    fused layer tail (1x1 convolution, inverse k_x transform, bias, GELU and
-    the next layer's k_x transform in one kernel, the transform's k axis split
-    over four wavefronts) and the k_y transform and synthesis kernels.
+    """Width 32, 16 modes, hidden 128 and 128 x 128 take the specialized
+    kernels: the lift fused with the first k_x transform, the fused layer tail
+    (1x1 convolution, inverse k_x transform, bias, GELU and the next layer's
+    k_x transform in one kernel, the transform's k axis split over four
+    wavefronts), the k_y transform, mixing and synthesis kernels, and the
+    fused projection forward and backward (hidden layer recomputed, never
+    stored; weight gradients summed per wavefront, then reduced).
     Inference and training outputs and the gradients must stay within the BF16
     tolerance of the FP64 oracle, and agree with the general GEMMs
     (FNO_OPT_SPECIALIZED = 0) to BF16 rounding; the batch (3 samples) leaves
@@ -255,7 +262,7 @@ def test_specialized_kernels_match_oracle_and_general_path(gpu):
     import torch
     from paper_2304_03306_amd import fno
     say("fno specialized kernels")
-    cfg = F.Config(H=128, W=128, cin=3, cout=2, width=32, modes=16, layers=3, hidden=16)
+    cfg = F.Config(H=128, W=128, cin=3, cout=2, width=32, modes=16, layers=3, hidden=128)
     B = 3
     net, p = make_net(gpu, cfg, B, seed=21)
     rng = np.random.default_rng(22)
