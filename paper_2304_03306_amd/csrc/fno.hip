@@ -346,6 +346,11 @@ int kvec_ok(const Op& o, bool a_side) {
 
 
 // ---- element-wise kernels ------------------------------------------------------------------
+// y[j][i] = x[i][j] for an n x n matrix
+__global__ void k_transpose_bf16(const float* __restrict__ x, bf16* __restrict__ y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * n) y[(i % n) * n + i / n] = f2bf(x[i]);
+}
 __global__ void k_to_bf16(const float* __restrict__ x, bf16* __restrict__ y, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = f2bf(x[i]);
@@ -477,13 +482,19 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
 // With LIFT the row is instead the lifting layer's output: h is the input
 // x[b][y][x][k] (cin <= 16 channels), Wl the lifting weights Pw[k][c] and bias
 // Pb, out = Pb + sum_k x[k] Pw[k][c], one MFMA k step with k padded to 16.
+// With DGRAD it is the backward of a layer: out = Ax1 T2 + dz Wl^T (Wl given
+// transposed, no bias) is the gradient with respect to the previous layer's
+// output, rounded to BF16 and multiplied by GELU'(zin) of that layer's stored
+// pre-activation: the next gradient dz, stored to hn, whose k_x transform
+// with DxG (passed as Dx) is formed as above.
 constexpr int kMaxLiftCin = 16;
-template <bool ACT, bool NEXT, bool LIFT>
+template <bool ACT, bool NEXT, bool LIFT, bool DGRAD = false>
 __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, const bf16* __restrict__ T2,
                                                     const bf16* __restrict__ Ax, const bf16* __restrict__ Wl,
                                                     const float* __restrict__ bias, const bf16* __restrict__ Dx,
                                                     bf16* __restrict__ hn, bf16* __restrict__ z,
-                                                    bf16* __restrict__ T1, int H, long long rows, int cin) {
+                                                    bf16* __restrict__ T1, int H, long long rows, int cin,
+                                                    const bf16* __restrict__ zin = nullptr) {
   constexpr int C = 32, J = 32, W = 128;
   __shared__ __align__(16) bf16 Ts[C * kLDK];      // T2 block transposed: [c][j]
   __shared__ __align__(16) bf16 Os[4][32 * kLDK];  // per wavefront output tile [x][c]
@@ -506,7 +517,7 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
   float bc[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    bc[t] = bias[16 * t + l16];
+    bc[t] = (DGRAD || !bias) ? 0.f : bias[16 * t + l16];
     if constexpr (LIFT) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) pw[t][e] = q4 + e < cin ? (short)Wl[(q4 + e) * C + 16 * t + l16] : (short)0;
@@ -573,6 +584,12 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
       *(uint4*)(zrow + sr * C + sh + 8) = *(const uint4*)(Ow + sr * kLDK + sh + 8);
       wave_lds_sync();
     }
+    if constexpr (DGRAD) {  // the wavefront's 32 x 32 tile of zin into Ow, 16-byte runs
+      const bf16* zr = zin + row * (W * C) + 32 * w * C;
+      *(uint4*)(Ow + sr * kLDK + sh) = *(const uint4*)(zr + sr * C + sh);
+      *(uint4*)(Ow + sr * kLDK + sh + 8) = *(const uint4*)(zr + sr * C + sh + 8);
+      wave_lds_sync();
+    }
     short4_t b3[2][2];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -582,10 +599,17 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
         for (int e = 0; e < 4; ++e) {
           float v = acc[s][t][e] + bc[t];
           if constexpr (ACT) v = gelu(v);
-          const bf16 o = f2bf(v);
-          b3[s][t][e] = (short)o;
-          Ow[(16 * s + q4 + e) * kLDK + 16 * t + l16] = o;
+          if constexpr (DGRAD)
+            v = bf2f(f2bf(v)) * gelu_grad(bf2f(Ow[(16 * s + q4 + e) * kLDK + 16 * t + l16]));
+          b3[s][t][e] = (short)f2bf(v);
         }
+    if constexpr (DGRAD) wave_lds_sync();  // zin read before the tile is overwritten
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ow[(16 * s + q4 + e) * kLDK + 16 * t + l16] = (bf16)b3[s][t][e];
     wave_lds_sync();
     *(uint4*)(hrow + sr * C + sh) = *(const uint4*)(Ow + sr * kLDK + sh);
     *(uint4*)(hrow + sr * C + sh + 8) = *(const uint4*)(Ow + sr * kLDK + sh + 8);
@@ -1163,7 +1187,7 @@ struct fno_ctx {
   float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   int adam_t = 0;
   // bf16 compute copies
-  bf16 *Pw = nullptr, *Wl[16] = {}, *Wb[16] = {}, *WbT[16] = {}, *Q1 = nullptr, *Q2 = nullptr;
+  bf16 *Pw = nullptr, *Wl[16] = {}, *WlT[16] = {}, *Wb[16] = {}, *WbT[16] = {}, *Q1 = nullptr, *Q2 = nullptr;
   // DFT matrices (bf16)
   bf16 *Dx, *DxG, *DyRe, *DyIm, *Ec, *Es, *Esn, *Ax, *Ax1;
   // activations
@@ -1280,6 +1304,8 @@ int refresh_weights(fno_ctx* c) {
   for (int l = 0; l < c->L; ++l) {
     hipLaunchKernelGGL(k_to_bf16, dim3(nb((long long)C * C)), dim3(256), 0, c->s, c->theta + c->oW[l], c->Wl[l],
                        (long long)C * C);
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(nb((long long)C * C)), dim3(256), 0, c->s, c->theta + c->oW[l],
+                       c->WlT[l], C);
     const long long nwb = (long long)2 * m * m * 4 * C * C;
     const long long nR = (long long)2 * m * m * C * C;
     hipLaunchKernelGGL(k_build_wb, dim3(nb(nwb)), dim3(256), 0, c->s, c->theta + c->oR[l], c->theta + c->oR[l] + nR,
@@ -1389,6 +1415,29 @@ int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, i
 }
 
 bool tail_fusable(const fno_ctx* c) { return c->specialized && c->C == 32 && c->m == 16 && c->W == 128; }
+
+// Backward tail of layer l: dh_l = Ax1 T2 + dz W_l^T into `out`; for l > 0
+// multiplied by GELU'(z[l-1]) (the next gradient dz) with its k_x transform
+// (DxG) into T1.
+int layer_tail_back(fno_ctx* c, int l, int B, const bf16* dz, bf16* out) {
+  const long long rows = (long long)B * c->H, P = rows * c->W;
+  const std::pair<const char*, size_t>* none = nullptr;
+  const bf16* zin = l > 0 ? c->z[l - 1] : nullptr;
+  if (!inside(c, dz, P * 32 - 1, 2, none, 0) || !inside(c, out, P * 32 - 1, 2, none, 0) ||
+      !inside(c, c->T2, rows * 32 * 32 - 1, 2, none, 0) || !inside(c, c->T1, rows * 32 * 32 - 1, 2, none, 0) ||
+      !inside(c, zin, P * 32 - 1, 2, none, 0) || !inside(c, c->Ax1, 128 * 32 - 1, 2, none, 0) ||
+      !inside(c, c->DxG, 32 * 128 - 1, 2, none, 0) || !inside(c, c->WlT[l], 32 * 32 - 1, 2, none, 0))
+    return ffail(TTSH_EINVAL, "layer tail (backward) operand out of bounds (internal layout error)");
+  const unsigned blocks = (unsigned)std::min<long long>(rows, 1280);
+  if (l > 0)
+    hipLaunchKernelGGL((k_layer_tail<false, true, false, true>), dim3(blocks), dim3(256), 0, c->s, dz, c->T2,
+                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, zin);
+  else
+    hipLaunchKernelGGL((k_layer_tail<false, false, false, false>), dim3(blocks), dim3(256), 0, c->s, dz, c->T2,
+                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, nullptr);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
 
 // The lifting layer fused with the first layer's k_x transform: h[0] and T1
 // from the BF16 input xb.
@@ -1616,7 +1665,7 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
     if ((rc = alloc(c, &c->h[l], (size_t)(P * C)))) return bail(rc);
   for (int l = 0; l < layers; ++l)
     if ((rc = alloc(c, &c->z[l], (size_t)(P * C))) || (rc = alloc(c, &c->G[l], (size_t)modesz)) ||
-        (rc = alloc(c, &c->Wl[l], (size_t)(C * C))) ||
+        (rc = alloc(c, &c->Wl[l], (size_t)(C * C))) || (rc = alloc(c, &c->WlT[l], (size_t)(C * C))) ||
         (rc = alloc(c, &c->Wb[l], (size_t)(2 * m * m * 4 * C * C))) ||
         (rc = alloc(c, &c->WbT[l], (size_t)(2 * m * m * 4 * C * C))))
       return bail(rc);
@@ -1854,11 +1903,14 @@ int fno_backward(fno_ctx* c, int B) {
   d.C = c->dh0; d.c_bf16 = 1; d.rC = C; d.cC = 1;
   if ((rc = cgemm(c, d))) return rc;
   }
+  // with the specialized kernels each layer's backward tail leaves the next
+  // gradient already multiplied by GELU' (in dh) and its k_x transform (in T1)
+  const bool fuse_b = tail_fusable(c);
   bf16* dh = c->dh0;
   bf16* dh_next = c->dh1;
   for (int l = c->L - 1; l >= 0; --l) {
     const bf16* dz = dh;
-    if (l < c->L - 1) {
+    if (l < c->L - 1 && !fuse_b) {
       // P * C is a multiple of 8: P = batch H W with H, W multiples of 16
       hipLaunchKernelGGL(k_gelu_back, dim3(nb((P * C + 7) / 8)), dim3(256), 0, c->s, dh, c->z[l], c->dz, P * C);
       FCHK(hipGetLastError());
@@ -1867,7 +1919,9 @@ int fno_backward(fno_ctx* c, int B) {
     if ((rc = wgrad(c, C, C, P, c->h[l], 1, C, dz, C, 1, c->grad + c->oW[l]))) return rc;
     if ((rc = colsum(c, dz, P, C, c->grad + c->ob[l]))) return rc;
     // g_G = (w/(HW)) trunc rfft2(dz)
-    if ((rc = spectral_analysis(c, dz, c->DxG, c->gG, B))) return rc;
+    if (!fuse_b || l == c->L - 1)
+      if ((rc = spectral_analysis_x(c, dz, c->DxG, B))) return rc;
+    if ((rc = spectral_analysis_y(c, c->gG, B))) return rc;
     // dR per mode (kx, q): dR_r = F_r^T gG_r + F_i^T gG_i ; dR_i = F_r^T gG_i - F_i^T gG_r
     const long long nR = 2LL * m * m * C * C;
     for (int part = 0; part < 2; ++part) {
@@ -1892,6 +1946,11 @@ int fno_backward(fno_ctx* c, int B) {
     // g_F = g_G Wb^T  (into gF, mode layout [m][2m][B][2C])
     if ((rc = spectral_mix(c, c->gG, c->Wb[l], c->WbT[l], true, c->gF, B))) return rc;
     if ((rc = spectral_synth_y(c, c->gF, B))) return rc;
+    if (fuse_b) {
+      if ((rc = layer_tail_back(c, l, B, dz, dh_next))) return rc;
+      std::swap(dh, dh_next);
+      continue;
+    }
     // dh_l = Ax1 . T2 + dz W_l^T
     GemmArgs e = ga();
     e.M = W; e.N = C; e.K = 2 * m; e.K2 = C;
