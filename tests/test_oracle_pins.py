@@ -415,3 +415,79 @@ def test_vortex_order2_limits():
     # the split decides which peaks compete: past the right vortex the right
     # side holds only noise, so Psi_2 is ~1 whatever the vortices' signs
     assert O.vortex_order2(w_opp, L, split_x=30.0) > 0.99
+
+
+# ---- second-order exponential Runge-Kutta (ETD2RK, Cox and Matthews 2002) -----------------
+def test_phi_functions_match_high_precision():
+    """phi_1(z) = (e^z - 1)/z and phi_2(z) = (e^z - 1 - z)/z^2 against 40-digit
+    evaluations, across the series / closed-form switch and the stiff range."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    z = np.array([0.0, 1e-12, -3e-6, 4e-3, -9.9e-3, 1.0e-2, -1.5e-2, 0.3, -2.0, 1.25, -80.0, -5e3])
+    p1, p2 = O.phi_functions(z)
+    for zi, a, b in zip(z, p1, p2):
+        if zi == 0.0:
+            w1, w2 = 1.0, 0.5
+        else:
+            q = mpmath.mpf(float(zi))
+            w1, w2 = float(mpmath.expm1(q) / q), float((mpmath.expm1(q) - q) / q ** 2)
+        assert abs(a - w1) <= 1e-15 * abs(w1) and abs(b - w2) <= 1e-13 * abs(w2), (zi, a, w1, b, w2)
+
+
+@pytest.mark.parametrize("k2,rate", [(0.5, 1.25), (PHI, 0.0), (2.0, 1.0 + 2.0 - 4.0)])
+def test_etdrk2_linear_modes_are_exact(k2, rate):
+    """With the forcing switched off both stages reduce to e^{L dt}: the
+    measured rate of a single mode is L(k) to round-off (P3/P4)."""
+    N, n = 16, 200
+    p = dataclasses.replace(zero_nl(O.workload_params()), scheme="etdrk2")
+    L = 2 * math.pi * math.sqrt(2.0 / k2)
+    v0 = O.project_field(mode_field(N, L, 1, 1), L)
+    vh = O.run_velocity(v0, np.zeros((N, N)), p, L, n)
+    got = math.log(abs(vh[1, 1, 1]) / abs(v0[1, 1, 1])) / (n * p.dt)
+    assert abs(got - rate) < 1e-11, (got, rate)
+
+
+@pytest.mark.parametrize("preset", ["workload", "paper"])
+def test_etdrk2_second_order_convergence(preset):
+    """Errors against the finest run scale as dt^2: for dt = 8h, 4h, 2h against
+    h the differences are c (64 - 1, 16 - 1, 4 - 1) h^2, ratios 21 and 5 (a
+    dropped or mis-weighted second stage falls back to first order: 7 and 3).
+    The paper preset exercises the gamma_w (vorticity) source as well."""
+    N, L = 16, 16.0
+    K = O.mask_tanh(N, L, [(0, 0)], [5.0], 0.5)
+    v0 = O.project_field(W.uniform_field(11, N, 0.8), L)
+    if preset == "workload":
+        base, T_end, dts = dataclasses.replace(O.workload_params(), gamma_v=10.0), 0.4, (0.01, 0.005, 0.0025, 0.00125)
+    else:
+        base, T_end, dts = dataclasses.replace(O.paper_params(), gamma_v=10.0, gamma_w=2.0), 0.2, (0.004, 0.002, 0.001, 0.0005)
+    out = {dt: O.run_velocity(v0, K, dataclasses.replace(base, dt=dt, scheme="etdrk2"), L, int(round(T_end / dt)))
+           for dt in dts}
+    e = [np.abs(out[dt] - out[dts[-1]]).max() for dt in dts[:3]]
+    assert abs(e[0] / e[2] - 21.0) < 1.5 and abs(e[1] / e[2] - 5.0) < 0.2, e
+
+
+def test_etdrk2_solves_the_same_equation_as_algorithm_1():
+    """ETD2RK and the paper's first-order scheme converge to the same
+    solution: ETD2RK at dt agrees with the Richardson extrapolation
+    2 u_ifeuler(dt/2) - u_ifeuler(dt) (second-order accurate) to within 2 % of
+    the difference between the two schemes at dt."""
+    N, L, T_end, dt = 16, 16.0, 0.4, 0.0025
+    K = O.mask_tanh(N, L, [(0, 0)], [5.0], 0.5)
+    v0 = O.project_field(W.uniform_field(11, N, 0.8), L)
+    base = dataclasses.replace(O.workload_params(), gamma_v=10.0)
+    etd = O.run_velocity(v0, K, dataclasses.replace(base, dt=dt, scheme="etdrk2"), L, int(round(T_end / dt)))
+    if1 = O.run_velocity(v0, K, dataclasses.replace(base, dt=dt), L, int(round(T_end / dt)))
+    if2 = O.run_velocity(v0, K, dataclasses.replace(base, dt=dt / 2), L, int(round(2 * T_end / dt)))
+    assert np.abs(etd - (2 * if2 - if1)).max() < 0.02 * np.abs(etd - if1).max()
+
+
+def test_etdrk2_stays_divergence_free_and_hermitian():
+    N, L = 32, 32.0
+    K = O.mask_tanh(N, L, [(0, 0)], [10.0], 0.5)
+    p = dataclasses.replace(O.workload_params(), scheme="etdrk2")
+    vh = O.project_field(W.uniform_field(13, N, 0.01), L)
+    kx, ky, _, _ = O.grid(N, L)
+    for _ in range(1500):
+        vh = O.run_velocity(vh, K, p, L, 1)
+    assert np.abs(kx * vh[0] + ky * vh[1]).max() < 1e-13 * np.abs(vh).max()
+    assert np.array_equal(vh, np.conj(O.reflect(vh)))
