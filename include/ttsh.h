@@ -62,11 +62,17 @@ enum {
 enum { TTSH_HOST = 0, TTSH_DEVICE = 1 };
 
 /* One-step map of the stiff linear part, u' = A u + B dt f with
- * L = -alpha - Gamma0 k^2 - Gamma2 k^4:
- *   TTSH_IFEULER  A = B = exp(L dt)           (Algorithm 1, the default)
- *   TTSH_ETD1     A = exp(L dt), B = (exp(L dt) - 1)/(L dt)
- *   TTSH_IMEX     A = B = 1/(1 - L dt)                                     */
-enum { TTSH_IFEULER = 0, TTSH_ETD1 = 1, TTSH_IMEX = 2 };
+ * L = -alpha - Gamma0 k^2 - Gamma2 k^4, z = L dt:
+ *   TTSH_IFEULER  A = B = exp(z)              (Algorithm 1, the default)
+ *   TTSH_ETD1     A = exp(z), B = (exp(z) - 1)/z
+ *   TTSH_IMEX     A = B = 1/(1 - z)
+ *   TTSH_ETDRK2   second-order exponential Runge-Kutta (Cox and Matthews,
+ *                 J. Comput. Phys. 176 (2002), ETD2RK): a = exp(z) u +
+ *                 dt phi1(z) f(u), then u' = a + dt phi2(z) (f(a) - f(u)),
+ *                 phi2(z) = (exp(z) - 1 - z)/z^2; two forcing evaluations
+ *                 (twice the kernels) per step and, per instance, a second
+ *                 state and the stage-1 forcing spectra on the device.     */
+enum { TTSH_IFEULER = 0, TTSH_ETD1 = 1, TTSH_IMEX = 2, TTSH_ETDRK2 = 3 };
 
 /* Arithmetic of the step (precision argument of ttsh_create):
  *   TTSH_FP64         everything in FP64;
@@ -80,7 +86,7 @@ typedef struct {
   double gamma_v; /* velocity damping in the wall, -gamma_v K v  (eq. (4)) */
   double gamma_w; /* vorticity damping in the wall, -gamma_w K omega (eq. (4)) */
   double dt;
-  int scheme;     /* TTSH_IFEULER, TTSH_ETD1 or TTSH_IMEX */
+  int scheme;     /* TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX or TTSH_ETDRK2 */
 } ttsh_params;
 
 /* Options for ttsh_set_option. */

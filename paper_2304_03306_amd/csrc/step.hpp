@@ -49,16 +49,41 @@ namespace ttsh {
 // Coefficients of the linear one-step map u' = A u + B dt f, evaluated per
 // mode in FP64 from the integer m^2: L = -alpha - Gamma0 k^2 - Gamma2 k^4,
 // k^2 = dk^2 m^2, z = L dt;  scheme 0: A = B = e^z (integrating-factor Euler),
-// 1: A = e^z, B = (e^z - 1)/z, 2: A = B = 1/(1 - z).
+// 1: A = e^z, B = (e^z - 1)/z, 2: A = B = 1/(1 - z).  Scheme 3, the
+// second-order exponential Runge-Kutta method (Cox and Matthews 2002,
+// ETD2RK), takes two column passes per step: stage 1 (column MODE 2) is the
+// scheme-1 map into a second state a, stage 2 (MODE 3) is
+// u' = a + phi_2(z) dt (f(a) - f(u)) with phi_2(z) = (e^z - 1 - z)/z^2.
 struct LinCoef {
   double alpha, gamma0, gamma2, dt, dt_over_N;
   int scheme;
 };
 
+// phi_2(z) = (e^z - 1 - z)/z^2; its Taylor series sum_j z^j/(j+2)! below
+// |z| = 1e-2, where the closed form loses digits to cancellation
+__device__ __forceinline__ double phi2(double z) {
+  if (fabs(z) < 1e-2) {
+    double s = 1.0 / 40320.0;  // 1/8!
+    s = fma(s, z, 1.0 / 5040.0);
+    s = fma(s, z, 1.0 / 720.0);
+    s = fma(s, z, 1.0 / 120.0);
+    s = fma(s, z, 1.0 / 24.0);
+    s = fma(s, z, 1.0 / 6.0);
+    return fma(s, z, 0.5);
+  }
+  return (expm1(z) - z) / (z * z);
+}
+
+// (A, B) of column MODE 0 (one-stage schemes) or of an ETD2RK stage
+// (MODE 2: A = e^z, B = phi_1(z); MODE 3: A = 1, B = phi_2(z))
+template <int MODE>
 __device__ __forceinline__ void linear_ab(const LinCoef& c, double dk, int m2, double& A, double& B) {
   const double k2 = dk * dk * (double)m2;
   const double z = (-c.alpha - c.gamma0 * k2 - c.gamma2 * k2 * k2) * c.dt;
-  if (c.scheme == 1) {
+  if constexpr (MODE == 3) {
+    A = 1.0;
+    B = phi2(z);
+  } else if (MODE == 2 || c.scheme == 1) {
     A = exp(z);
     B = (z == 0.0) ? 1.0 : expm1(z) / z;
   } else if (c.scheme == 2) {
@@ -299,12 +324,18 @@ __device__ __forceinline__ void hermitian_fix(C2<double> (&u)[kFftE], C2<double>
   __syncthreads();
 }
 
+// MODE 2 / 3: the two stages of ETD2RK.  Stage 1 reads st and writes the
+// stage state st2, and keeps its forcing spectra (compact, as the state:
+// [NFY][M+1][2M+2]) in fst and its k = 0 forcing sums in s1st; stage 2 reads
+// st2 and the kept values and writes st.
 template <int N, int TC, class T, class S, bool GW, int MODE>
 __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X,
                                          C2<S>* __restrict__ st, const T* __restrict__ rowsum,
                                          const double* __restrict__ dkv,
                                          const C2<T>* __restrict__ tw, const LinCoef& lc,
-                                         size_t inst, int tile, unsigned char* smem) {
+                                         size_t inst, int tile, unsigned char* smem,
+                                         C2<S>* __restrict__ st2 = nullptr, C2<T>* __restrict__ fst = nullptr,
+                                         double* __restrict__ s1st = nullptr) {
   using G = Geo<N>;
   constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, SP = G::SP, NP = G::NP;
   constexpr int NFY = GW ? 3 : 2;
@@ -324,11 +355,13 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
   const bool valid = mx <= M;
   const double dk = dkv[inst];
   C2<T>* L = reinterpret_cast<C2<T>*>(smem) + col * G::LS;
-  C2<S>* stp = st + inst * 2 * MP * SP;
+  C2<S>* stp = (MODE == 3 ? st2 : st) + inst * 2 * MP * SP;         // state read
+  C2<S>* stq = (MODE == 2 ? st2 : st) + inst * 2 * MP * SP;         // state written
+  C2<T>* fsp = (MODE >= 2) ? fst + inst * NFY * MP * SP : nullptr;  // stage-1 forcing
 
   C2<T> f[NFY][E];
   double s1x = 0.0, s1y = 0.0;
-  if constexpr (MODE == 0) {
+  if constexpr (MODE != 1) {
     if (tile == 0) {  // sum of the row sums: DFT of the k = 0 forcing
       const T* rs = rowsum + inst * 2 * N;
       double a = 0.0, b = 0.0;
@@ -349,6 +382,15 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
         s1y += R[2 * w + 1];
       }
       __syncthreads();
+      if constexpr (MODE == 2) {
+        if (tid == 0) {
+          s1st[2 * inst] = s1x;
+          s1st[2 * inst + 1] = s1y;
+        }
+      } else if constexpr (MODE == 3) {
+        s1x -= s1st[2 * inst];
+        s1y -= s1st[2 * inst + 1];
+      }
     }
     const C2<T>* Yp = Y + inst * NFY * G::MP4 * N;
     const T h = (T)0.5;
@@ -364,6 +406,25 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       if constexpr (GW) f[2][e] = valid ? Yp[mix_idx<N>(2, mx, t + e * TT)] : mk<T>(0, 0);
     }
     fft<N, -1, NFY>(f, L, t, tw);
+    if constexpr (MODE >= 2) {  // keep (stage 1) or subtract (stage 2) the stage-1 forcing
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = t + e * TT;
+        const bool lo = idx <= M, hi = idx >= N - M;
+        const int pos = lo ? idx : idx - (N - 2 * M - 1);
+        const int my = lo ? idx : idx - N;
+        if (valid && (lo || hi) && mx * mx + my * my <= M * M) {
+#pragma unroll
+          for (int q = 0; q < NFY; ++q) {
+            C2<T>& slot = fsp[(q * MP + mx) * SP + pos];
+            if constexpr (MODE == 2)
+              slot = f[q][e];
+            else
+              f[q][e] = f[q][e] - slot;
+          }
+        }
+      }
+    }
   }
 
   // k-space update in FP64
@@ -379,10 +440,10 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
     if (valid && (lo || hi) && m2 <= M * M) {
       const C2<double> ux = cvt<double>(stp[(0 * MP + mx) * SP + pos]);
       const C2<double> uy = cvt<double>(stp[(1 * MP + mx) * SP + pos]);
-      if constexpr (MODE == 0) {
+      if constexpr (MODE != 1) {
         const double dt_over_N = lc.dt_over_N;
         double A, B;
-        linear_ab(lc, dk, m2, A, B);
+        linear_ab<MODE>(lc, dk, m2, A, B);
         // 1/m^2: FP32 reciprocal refined by two Newton steps in FP64
         // (m^2 <= 2^16, so the result is the correctly rounded FP64 value to
         // within an ulp)
@@ -422,7 +483,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
     }
   }
 
-  if constexpr (MODE == 0) {
+  if constexpr (MODE != 1) {
     if (tile == 0) {  // Hermitian correction on the m_x = 0 column, x then y
       C2<double>* H = reinterpret_cast<C2<double>*>(smem);
       hermitian_fix<N>(nx, H, t, col == 0);
@@ -444,8 +505,8 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
         const int pos = lo ? idx : idx - (N - 2 * M - 1);
         const int my = lo ? idx : idx - N;
         if ((lo || hi) && mx * mx + my * my <= M * M) {
-          stp[(0 * MP + mx) * SP + pos] = cvt<S>(nx[e]);
-          stp[(1 * MP + mx) * SP + pos] = cvt<S>(ny[e]);
+          stq[(0 * MP + mx) * SP + pos] = cvt<S>(nx[e]);
+          stq[(1 * MP + mx) * SP + pos] = cvt<S>(ny[e]);
         }
       }
     }

@@ -48,16 +48,25 @@ hipError_t row(const MultiArgs& a, int gw, hipStream_t s) {
 }
 #endif
 
+template <bool GW, int MODE>
+void col_multi_launch(const MultiArgs& a, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((col_multi<T, S, GW, MODE, BS>), dim3(a.start[a.ncls]), dim3(BS), lds, s, a);
+}
+
+// mode: 0 one-stage step, 1 state -> X only, 2 / 3 the ETD2RK stages
 hipError_t col(const MultiArgs& a, int gw, int mode, hipStream_t s) {
-  const int grid = a.start[a.ncls];
   const size_t lds = gw && mode != 1 ? lds_bytes(a, col_smem_of<T, BS, true>) : lds_bytes(a, col_smem_of<T, BS, false>);
   if (lds == 0) return hipErrorInvalidValue;
-  if (mode == 1)
-    hipLaunchKernelGGL((col_multi<T, S, false, 1, BS>), dim3(grid), dim3(BS), lds, s, a);
-  else if (gw)
-    hipLaunchKernelGGL((col_multi<T, S, true, 0, BS>), dim3(grid), dim3(BS), lds, s, a);
-  else
-    hipLaunchKernelGGL((col_multi<T, S, false, 0, BS>), dim3(grid), dim3(BS), lds, s, a);
+  switch (mode * 2 + (gw ? 1 : 0)) {
+    case 0: col_multi_launch<false, 0>(a, lds, s); break;
+    case 1: col_multi_launch<true, 0>(a, lds, s); break;
+    case 2: case 3: col_multi_launch<false, 1>(a, lds, s); break;
+    case 4: col_multi_launch<false, 2>(a, lds, s); break;
+    case 5: col_multi_launch<true, 2>(a, lds, s); break;
+    case 6: col_multi_launch<false, 3>(a, lds, s); break;
+    case 7: col_multi_launch<true, 3>(a, lds, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -85,18 +94,25 @@ hipError_t row_one_n(const MultiArgs& o, int gw, hipStream_t s) {
   }
 }
 
+template <int N, bool GW, int MODE>
+void col_one_launch(const MultiArgs& o, hipStream_t s) {
+  hipLaunchKernelGGL((col_one<N, T, S, GW, MODE, BS>), dim3(o.start[1]), dim3(BS), (col_smem_n<T, BS, GW, N>()), s,
+                     o);
+}
+
 template <int N>
 hipError_t col_one_n(const MultiArgs& o, int gw, int mode, hipStream_t s) {
   if constexpr (col_smem_n<T, BS, true, N>() > 0) {
-    if (mode == 1)
-      hipLaunchKernelGGL((col_one<N, T, S, false, 1, BS>), dim3(o.start[1]), dim3(BS),
-                         (col_smem_n<T, BS, false, N>()), s, o);
-    else if (gw)
-      hipLaunchKernelGGL((col_one<N, T, S, true, 0, BS>), dim3(o.start[1]), dim3(BS),
-                         (col_smem_n<T, BS, true, N>()), s, o);
-    else
-      hipLaunchKernelGGL((col_one<N, T, S, false, 0, BS>), dim3(o.start[1]), dim3(BS),
-                         (col_smem_n<T, BS, false, N>()), s, o);
+    switch (mode * 2 + (gw ? 1 : 0)) {
+      case 0: col_one_launch<N, false, 0>(o, s); break;
+      case 1: col_one_launch<N, true, 0>(o, s); break;
+      case 2: case 3: col_one_launch<N, false, 1>(o, s); break;
+      case 4: col_one_launch<N, false, 2>(o, s); break;
+      case 5: col_one_launch<N, true, 2>(o, s); break;
+      case 6: col_one_launch<N, false, 3>(o, s); break;
+      case 7: col_one_launch<N, true, 3>(o, s); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;

@@ -26,6 +26,9 @@ struct ClassArgs {
   void* rowsum;
   const double* dk;
   const void* tw;
+  void* st2;      // ETD2RK stage state (same layout as st), else null
+  void* fst;      // ETD2RK stage-1 forcing spectra, else null
+  double* s1st;   // ETD2RK stage-1 k = 0 forcing sums [n][2], else null
 };
 
 struct MultiArgs {
@@ -133,7 +136,7 @@ __device__ __forceinline__ void col_go(const ClassArgs& d, const LinCoef& lc, in
     l.dt_over_N = lc.dt / N;  // the unnormalised forward FFT carries N x the unitary DFT
     col_body<N, TileOf<N, BS>::R, T, S, GW, MODE>((const C2<T>*)d.Y, (C2<T>*)d.X_out, (C2<S>*)d.st,
                                                   (const T*)d.rowsum, d.dk, (const C2<T>*)d.tw, l,
-                                                  inst, tile, smem);
+                                                  inst, tile, smem, (C2<S>*)d.st2, (C2<T>*)d.fst, d.s1st);
   }
 }
 

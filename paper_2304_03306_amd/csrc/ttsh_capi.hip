@@ -100,12 +100,17 @@ struct SizeClass {
   void* rowsum = nullptr;
   double* dk = nullptr;
   void* tw = nullptr;    // run precision
+  void* st2 = nullptr;   // ETD2RK: stage state (as st), stage-1 forcing spectra, k = 0 sums
+  void* fst = nullptr;
+  double* s1st = nullptr;
   // per-instance strides in elements
   // mixed-domain arrays hold M+1 columns padded to a multiple of 4
   size_t mp4() const { return (size_t)((N / 4 + 1 + 3) / 4 * 4); }
   size_t sX() const { return (size_t)3 * mp4() * N; }
   size_t sY(int gw) const { return (size_t)(gw ? 3 : 2) * mp4() * N; }
   size_t sSt() const { return (size_t)2 * (N / 4 + 1) * (N / 2 + 2); }
+  // compact forcing spectra of an ETD2RK stage, complex elements
+  size_t sF(int gw) const { return (size_t)(gw ? 3 : 2) * (N / 4 + 1) * (N / 2 + 2); }
   size_t sK() const { return (size_t)N * N; }
 };
 
@@ -217,6 +222,11 @@ ClassArgs class_args(ttsh_ctx* c, SizeClass& k, int first, int count, int row) {
   a.rowsum = (char*)k.rowsum + first * (size_t)2 * k.N * er;
   a.dk = k.dk + first;
   a.tw = k.tw;
+  if (k.st2) {
+    a.st2 = (char*)k.st2 + first * k.sSt() * es;
+    a.fst = (char*)k.fst + first * k.sF(c->gw) * 2 * er;
+    a.s1st = k.s1st + 2 * first;
+  }
   return a;
 }
 
@@ -261,9 +271,14 @@ hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) 
 int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
   if (n <= 0) return TTSH_OK;
   const MultiArgs r = multi_args(c, 1, -1), q = multi_args(c, 0, -1);
+  const bool two_stage = c->p.scheme == TTSH_ETDRK2;
   for (int64_t i = 0; i < n; ++i) {
     HIPCHK(launch_row(c, r, s));
-    HIPCHK(launch_col(c, q, 0, s));
+    HIPCHK(launch_col(c, q, two_stage ? 2 : 0, s));
+    if (two_stage) {  // the forcing of the stage state, then the second stage
+      HIPCHK(launch_row(c, r, s));
+      HIPCHK(launch_col(c, q, 3, s));
+    }
   }
   return TTSH_OK;
 }
@@ -376,7 +391,7 @@ void free_ctx(ttsh_ctx* c) {
   if (!c) return;
   drop_graph(c);
   for (auto& k : c->cls) {
-    for (void* p : {k.X, k.Y, k.st, k.K, k.rowsum, (void*)k.dk, k.tw})
+    for (void* p : {k.X, k.Y, k.st, k.K, k.rowsum, (void*)k.dk, k.tw, k.st2, k.fst, (void*)k.s1st})
       if (p) hipFree(p);
   }
   for (auto& kv : c->tw64) hipFree(kv.second);
@@ -403,7 +418,7 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
   if (n_inst < 1 || n_inst > 4096) return fail(TTSH_EINVAL, "n_inst must be in 1..4096");
   if (precision != TTSH_FP32 && precision != TTSH_FP64 && precision != TTSH_FP32_STATE64)
     return fail(TTSH_EINVAL, "precision must be TTSH_FP32, TTSH_FP64 or TTSH_FP32_STATE64");
-  if (p->scheme < TTSH_IFEULER || p->scheme > TTSH_IMEX) return fail(TTSH_EINVAL, "unknown scheme");
+  if (p->scheme < TTSH_IFEULER || p->scheme > TTSH_ETDRK2) return fail(TTSH_EINVAL, "unknown scheme");
   const double coef[] = {p->alpha, p->beta, p->gamma0, p->gamma2, p->lambda0, p->lambda1, p->gamma_v, p->gamma_w, p->dt};
   for (double v : coef)
     if (!std::isfinite(v)) return fail(TTSH_EINVAL, "non-finite coefficient");
@@ -445,12 +460,18 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
         k.ids.push_back(i);
       }
     const size_t n = k.ids.size();
-    struct {
+    struct Alloc {
       void** p;
       size_t bytes;
-    } al[] = {{&k.X, n * k.sX() * 2 * er},       {&k.Y, n * k.sY(c->gw) * 2 * er},
-              {&k.st, n * k.sSt() * es},         {&k.K, n * k.sK() * er},
-              {&k.rowsum, n * 2 * (size_t)Nc * er}, {(void**)&k.dk, n * sizeof(double)}};
+    };
+    std::vector<Alloc> al = {{&k.X, n * k.sX() * 2 * er},       {&k.Y, n * k.sY(c->gw) * 2 * er},
+                             {&k.st, n * k.sSt() * es},         {&k.K, n * k.sK() * er},
+                             {&k.rowsum, n * 2 * (size_t)Nc * er}, {(void**)&k.dk, n * sizeof(double)}};
+    if (p->scheme == TTSH_ETDRK2) {
+      al.push_back({&k.st2, n * k.sSt() * es});
+      al.push_back({&k.fst, n * k.sF(c->gw) * 2 * er});
+      al.push_back({(void**)&k.s1st, n * 2 * sizeof(double)});
+    }
     for (auto& a : al) {
       if (hipMalloc(a.p, a.bytes) != hipSuccess) {
         c->cls.push_back(k);
