@@ -181,10 +181,27 @@ int max_N(const ttsh_ctx* c) {
   return m;
 }
 
+// the tiles of a size-N class fit the per-tile LDS limit at workgroup size BS
+// (transform precision T; the column pass with and without the vorticity source)
+template <class T, int BS>
+bool tiles_fit(int N, int gw) {
+  return row_smem_of<T, BS>(N) > 0 && col_smem_of<T, BS, false>(N) > 0 && (!gw || col_smem_of<T, BS, true>(N) > 0);
+}
+
 // A workgroup of bs threads carries one transform of length N with N/8
-// threads, so bs is usable when 8 bs >= N for every size class.
+// threads, so bs is usable when 8 bs >= N for every size class and every
+// class's tiles fit the LDS limit (FP64 tiles of many small columns do not).
 bool bs_valid(const ttsh_ctx* c, int bs) {
-  return (bs == 64 || bs == 128 || bs == 256) && 8 * bs >= max_N(c);
+  if (!(bs == 64 || bs == 128 || bs == 256) || 8 * bs < max_N(c)) return false;
+  const bool f64 = c->prec == 64;
+  for (auto& k : c->cls) {
+    bool ok = false;
+    if (bs == 64) ok = f64 ? tiles_fit<double, 64>(k.N, c->gw) : tiles_fit<float, 64>(k.N, c->gw);
+    if (bs == 128) ok = f64 ? tiles_fit<double, 128>(k.N, c->gw) : tiles_fit<float, 128>(k.N, c->gw);
+    if (bs == 256) ok = f64 ? tiles_fit<double, 256>(k.N, c->gw) : tiles_fit<float, 256>(k.N, c->gw);
+    if (!ok) return false;
+  }
+  return true;
 }
 
 // Default workgroup size: the largest one that still gives >= 2048 row-pass

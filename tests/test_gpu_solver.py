@@ -514,3 +514,25 @@ def test_etdrk2_mixed_sizes(gpu, split):
     for q in range(len(Ns)):
         err = O.rel_l2(s.field(q), O.field(refs[q]))
         assert err < 1e-12, (q, err)
+
+
+def test_fp64_radius_sweep_context_runs(gpu):
+    """The 64-instance radius sweep in FP64: the default workgroup size must
+    be one whose tiles fit the LDS limit for every grid size present (FP64
+    tiles of 16 columns of 128 points at 256 threads do not), so setting a
+    field and stepping work; one step matches the oracle."""
+    say("fp64 radius sweep context")
+    wl = W.radius_sweep()
+    inst = wl.instances
+    p = O.workload_params()
+    s = gpu.Solver([i.N for i in inst], [i.L for i in inst], p, 64)
+    q = 0
+    i = inst[q]
+    K = O.mask_tanh(i.N, i.L, i.centers, i.radii, i.xi)
+    v0 = W.uniform_field(i.seed, i.N, 0.3)
+    s.mask_tanh(q, i.centers, i.radii, i.xi)
+    s.set_field(q, v0)
+    s.step(1)
+    s.sync()
+    ref = O.run_velocity(O.project_field(v0, i.L), K, p, i.L, 1)
+    assert O.rel_l2(s.field(q), O.field(ref)) < 1e-12
