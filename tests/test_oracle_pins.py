@@ -491,3 +491,30 @@ def test_etdrk2_stays_divergence_free_and_hermitian():
         vh = O.run_velocity(vh, K, p, L, 1)
     assert np.abs(kx * vh[0] + ky * vh[1]).max() < 1e-13 * np.abs(vh).max()
     assert np.array_equal(vh, np.conj(O.reflect(vh)))
+
+
+# ---- vortex counting (topological charge of the velocity direction field) --------------------
+def test_vortex_count_closed_forms():
+    """Index of the direction field of v: +1 at vortex centres of either sense,
+    -1 at saddles.  psi = sin x sin y on the periodic box has four centres and
+    four saddles (Poincare-Hopf: the indices sum to zero on the torus); a
+    localised vortex and a saddle inside a disk count (1, 0) and (0, 1);
+    a uniform flow has none; reversing v changes nothing."""
+    N, L = 64, 2 * math.pi
+    x, y = O.node_coords(N, L)
+    x, y = x + 0.013, y + 0.021  # critical points off the nodes
+    cell = np.stack([np.sin(x) * np.cos(y), -np.cos(x) * np.sin(y)])
+    zero = np.zeros((N, N))
+    assert O.vortex_count(cell, zero, 0.5, 0.0) == (4, 4)
+    assert O.vortex_count(-cell, zero, 0.5, 0.0) == (4, 4)
+    r2 = (x - 0.3) ** 2 + (y + 0.2) ** 2
+    disk = (r2 > 2.0).astype(float)
+    g = np.exp(-r2 / 0.5)
+    vort = np.stack([-(y + 0.2) * g, (x - 0.3) * g])
+    assert O.vortex_count(vort, disk, 0.5, 1e-12) == (1, 0)
+    assert O.vortex_count(-vort, disk, 0.5, 1e-12) == (1, 0)
+    assert O.vortex_count(np.stack([x - 0.3, -(y + 0.2)]), disk, 0.5, 1e-12) == (0, 1)
+    assert O.vortex_count(np.stack([np.ones((N, N)), 0.3 * np.ones((N, N))]), zero, 0.5, 0.0) == (0, 0)
+    # cells touching the excluded region (mask or slow nodes) do not count
+    assert O.vortex_count(vort, np.ones((N, N)), 0.5, 1e-12) == (0, 0)
+    assert O.vortex_count(vort, disk, 0.5, 10.0) == (0, 0)
