@@ -162,6 +162,16 @@ int ttsh_get_field_coarse(ttsh_ctx* ctx, int inst, int Nc, float* out, int64_t p
  * Synchronous.                                                              */
 int ttsh_order(ttsh_ctx* ctx, int inst, double cx, double cy, double* out);
 
+/* Vortex count of instance inst (the topological defects of the direction of
+ * v, used to tell single vortices, pairs and disordered states apart): over
+ * the grid cells whose four corner nodes all have K < kmax and |v| > vmin, the
+ * winding number n of v around the cell (+1 at vortex centres of either sense
+ * of rotation, -1 at saddles), from the real-space field in FP64.
+ * out[0] = sum of n over cells with n > 0, out[1] = sum of -n over cells with
+ * n < 0 (host ints).  vmin >= 0 excludes nodes where the direction of v is not
+ * defined (stagnant wall region); vmin < 0 is EINVAL.  Synchronous.         */
+int ttsh_vortices(ttsh_ctx* ctx, int inst, double kmax, double vmin, int* out);
+
 /* Inverse of ttsh_get_field_coarse: set instance inst from a coarse real
  * velocity on an Nc x Nc grid of the same box (device float32, layout as in
  * ttsh_get_field_coarse).  The field is transformed, cut to the coarse 1/2

@@ -4,9 +4,11 @@ The circle section's set-up: the paper's preset (a, b, lambda, gamma_v,
 gamma_w) = (0.5, 1.6, 9, 40, 4), the mask built by Algorithm 2 from the binary
 "outside the circle" field, a box of side 40.96, random small initial fields.
 Each radius is one instance of one context; after a transient the vortex
-order parameter Psi and the kinetic energy are sampled at fixed intervals,
-and the run reports, per radius, their mean and spread and the dominant
-frequency of Psi(t) (oscillating states show one).  The grid is coarser than
+order parameter Psi, the kinetic energy and the vortex count (centres and
+saddles of the velocity direction inside the circle, ttsh_vortices) are
+sampled at fixed intervals, and the run reports, per radius, their mean and
+spread, the most frequent vortex count and the dominant frequency of Psi(t)
+(oscillating states show one).  The grid is coarser than
 the paper's (its 8192^2 resolves the wall much more sharply), so the radii
 at which the states change can shift.
 
@@ -40,11 +42,16 @@ def run(radii, N=1024, L=40.96, steps=200_000, transient=50_000, every=200, seed
         nsamp = (steps - transient) // every
         psi = np.zeros((nsamp, n))
         energy = np.zeros((nsamp, n))
+        centres = np.zeros((nsamp, n), dtype=np.int64)
+        saddles = np.zeros((nsamp, n), dtype=np.int64)
         for k in range(nsamp):
             s.step(every)
             for q in range(n):
                 psi[k, q] = s.order(q)[0]
-                energy[k, q] = s.norms(q)[0] * (L / N) ** 2  # integral of |v|^2 over the box
+                sq = s.norms(q)[0]
+                energy[k, q] = sq * (L / N) ** 2  # integral of |v|^2 over the box
+                # nodes slower than 1e-3 of the rms speed have no defined direction
+                centres[k, q], saddles[k, q] = s.vortices(q, 0.5, 1e-3 * np.sqrt(sq / (N * N)))
             if log and (k + 1) % max(1, nsamp // 10) == 0:
                 log(f"sample {k + 1}/{nsamp}: Psi {np.round(psi[k], 3).tolist()}")
         s.sync()
@@ -56,9 +63,14 @@ def run(radii, N=1024, L=40.96, steps=200_000, transient=50_000, every=200, seed
             spec = np.abs(np.fft.rfft(series - series.mean())) ** 2
             freq = np.fft.rfftfreq(len(series), dt)
             f_peak = float(freq[1 + int(np.argmax(spec[1:]))]) if len(series) > 2 else 0.0
+            pairs, counts = np.unique(np.stack([centres[:, q], saddles[:, q]], axis=1), axis=0, return_counts=True)
+            top = pairs[int(np.argmax(counts))]
             out.append({"R": R, "psi_mean": float(series.mean()), "psi_std": float(series.std()),
                         "energy_mean": float(energy[:, q].mean()), "energy_std": float(energy[:, q].std()),
-                        "psi_peak_frequency": f_peak})
+                        "psi_peak_frequency": f_peak,
+                        "vortex_count_mode": [int(top[0]), int(top[1])],
+                        "vortex_count_mode_fraction": float(counts.max() / nsamp),
+                        "centres_mean": float(centres[:, q].mean()), "saddles_mean": float(saddles[:, q].mean())})
         return {"N": N, "L": L, "steps": steps, "transient": transient, "sample_every": every,
                 "coefficients": "paper preset (a, b, lambda, gamma_v, gamma_w) = (0.5, 1.6, 9, 40, 4)",
                 "mask": "Algorithm 2 from the binary outside-the-circle field",
@@ -85,8 +97,10 @@ def main(argv=None):
         json.dump(rep, f)
     for r in rep["radii"]:
         print(f"[circle] R={r['R']:.2f}: Psi {r['psi_mean']:.3f} +- {r['psi_std']:.3f}, energy "
-              f"{r['energy_mean']:.3g} +- {r['energy_std']:.2g}, Psi peak frequency {r['psi_peak_frequency']:.4g}",
-              flush=True)
+              f"{r['energy_mean']:.3g} +- {r['energy_std']:.2g}, Psi peak frequency {r['psi_peak_frequency']:.4g}, "
+              f"vortex count (centres, saddles) {tuple(r['vortex_count_mode'])} in "
+              f"{100 * r['vortex_count_mode_fraction']:.0f} % of samples (mean {r['centres_mean']:.2f}, "
+              f"{r['saddles_mean']:.2f})", flush=True)
     return rep
 
 

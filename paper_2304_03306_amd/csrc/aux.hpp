@@ -306,6 +306,72 @@ __global__ void __launch_bounds__(1024) k_order_psi(const C2<double>* __restrict
   }
 }
 
+// Topological defects of the direction field of v = (Re Z, Im Z): per grid
+// cell (corners (i, j), (i, j+1), (i+1, j+1), (i+1, j), periodic,
+// counter-clockwise) with every corner at K < kmax and |v| > vmin, the
+// winding number of v around the cell, counted in quarter turns: each corner
+// vector's quadrant is found by exact sign tests, a step to the next or
+// previous quadrant is +-1, to the opposite one +-2 with the sign of the cross
+// product of the two vectors; the sum over the four edges is 4n.  out[0] =
+// sum of n > 0 (vortex centres), out[1] = sum of |n| over n < 0 (saddles).
+// One workgroup; integer sums, so the result does not depend on the order.
+__device__ __forceinline__ int quadrant(double x, double y) {
+  if (x > 0.0 && y >= 0.0) return 0;
+  if (x <= 0.0 && y > 0.0) return 1;
+  if (x < 0.0 && y <= 0.0) return 2;
+  return 3;
+}
+template <class T>
+__global__ void __launch_bounds__(1024) k_vortex_count(const C2<double>* __restrict__ Z, const T* __restrict__ K,
+                                                       int N, double kmax, double vmin, int* __restrict__ out) {
+  int pos = 0, neg = 0;
+  const double v2 = vmin * vmin;
+  for (int c = threadIdx.x; c < N * N; c += blockDim.x) {
+    const int i = c / N, j = c % N, i1 = (i + 1) & (N - 1), j1 = (j + 1) & (N - 1);
+    const int idx[4] = {i * N + j, i * N + j1, i1 * N + j1, i1 * N + j};
+    bool ok = true;
+    C2<double> w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      w[q] = Z[idx[q]];
+      ok = ok && (double)K[idx[q]] < kmax && w[q].x * w[q].x + w[q].y * w[q].y > v2 &&
+           (w[q].x != 0.0 || w[q].y != 0.0);
+    }
+    if (!ok) continue;
+    int turns = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const C2<double> a = w[q], b = w[(q + 1) & 3];
+      const int d = (quadrant(b.x, b.y) - quadrant(a.x, a.y) + 4) & 3;
+      if (d == 1) turns += 1;
+      else if (d == 3) turns -= 1;
+      else if (d == 2) turns += (a.x * b.y - a.y * b.x) >= 0.0 ? 2 : -2;
+    }
+    const int n = turns / 4;
+    if (n > 0) pos += n;
+    if (n < 0) neg -= n;
+  }
+  __shared__ int red[16][2];
+  for (int o = 32; o > 0; o >>= 1) {
+    pos += __shfl_xor(pos, o);
+    neg += __shfl_xor(neg, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = pos;
+    red[threadIdx.x >> 6][1] = neg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0, b = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += red[w][0];
+      b += red[w][1];
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
 // Two-chamber order parameter from the vorticity in the real part of Z: the
 // nodes of largest |omega| left of x = cx and at or right of it (ties to the
 // lower index), |w_l + w_r| / (|w_l| + |w_r|).

@@ -855,6 +855,36 @@ int ttsh_order(ttsh_ctx* c, int inst, double cx, double cy, double* out) {
   return TTSH_OK;
 }
 
+int ttsh_vortices(ttsh_ctx* c, int inst, double kmax, double vmin, int* out) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!out) return fail(TTSH_EINVAL, "null output");
+  if (!(vmin >= 0.0)) return fail(TTSH_EINVAL, "vmin must be >= 0");
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, n = N * N;
+  const double dk = 2.0 * M_PI / c->L[inst];
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_state_to_full<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), (C2<double>*)c->scr0, N, dk, 0);
+  else
+    hipLaunchKernelGGL(k_state_to_full<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), (C2<double>*)c->scr0, N, dk, 0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(size_ops(N)->fft2(c->scr0, 1, +1, 1, c->tw64[N], c->stream));
+  int* dcount = reinterpret_cast<int*>(c->dnorm);  // [2], inside the norms scratch
+  if (c->prec == 64)
+    hipLaunchKernelGGL(k_vortex_count<double>, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0,
+                       at<const double>(k.K, k.sK(), sizeof(double), j), N, kmax, vmin, dcount);
+  else
+    hipLaunchKernelGGL(k_vortex_count<float>, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0,
+                       at<const float>(k.K, k.sK(), sizeof(float), j), N, kmax, vmin, dcount);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, dcount, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTSH_OK;
+}
+
 int ttsh_set_state(ttsh_ctx* c, int inst, const double* vhat, int where) {
   int rc = check_inst(c, inst);
   if (rc) return rc;

@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_set_field_coarse": [vp, i32, i32, dp, i64],
             "ttsh_project_coarse": [vp, i32, dp, i64, i32, dp],
             "ttsh_order": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
+            "ttsh_vortices": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
             "ttsh_step": [vp, i64],
@@ -182,6 +183,12 @@ def ttsh_order(ctx, inst, center=(0.0, 0.0)):
     out = (ctypes.c_double * 2)()
     _check(lib().ttsh_order(ctx, int(inst), float(center[0]), float(center[1]), ctypes.cast(out, ctypes.c_void_p)))
     return out[0], out[1]
+
+def ttsh_vortices(ctx, inst, kmax=0.5, vmin=0.0):
+    """(vortex centres, saddles) of instance inst, see include/ttsh.h."""
+    out = (ctypes.c_int * 2)()
+    _check(lib().ttsh_vortices(ctx, int(inst), float(kmax), float(vmin), ctypes.cast(out, ctypes.c_void_p)))
+    return int(out[0]), int(out[1])
 
 
 def _dev_addr(x):
@@ -322,6 +329,9 @@ class Solver:
 
     def order(self, inst, center=(0.0, 0.0)):
         return ttsh_order(self.ctx, inst, center)
+
+    def vortices(self, inst, kmax=0.5, vmin=0.0):
+        return ttsh_vortices(self.ctx, inst, kmax, vmin)
 
     def field_coarse(self, inst, Nc, out, pix_stride=2):
         ttsh_get_field_coarse(self.ctx, inst, Nc, out, pix_stride)
