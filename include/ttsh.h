@@ -166,7 +166,10 @@ int ttsh_order(ttsh_ctx* ctx, int inst, double cx, double cy, double* out);
  * v, used to tell single vortices, pairs and disordered states apart): over
  * the grid cells whose four corner nodes all have K < kmax and |v| > vmin, the
  * winding number n of v around the cell (+1 at vortex centres of either sense
- * of rotation, -1 at saddles), from the real-space field in FP64.
+ * of rotation, -1 at saddles), and over the nodes with K < kmax but
+ * |v| <= vmin whose eight neighbours qualify (a defect sitting on a node, as
+ * at the centre of a symmetric vortex), the winding number around that ring;
+ * from the real-space field in FP64.
  * out[0] = sum of n over cells with n > 0, out[1] = sum of -n over cells with
  * n < 0 (host ints).  vmin >= 0 excludes nodes where the direction of v is not
  * defined (stagnant wall region); vmin < 0 is EINVAL.  Synchronous.         */

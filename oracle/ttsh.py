@@ -507,25 +507,37 @@ def vortex_order2(w: np.ndarray, L: float, split_x: float = 0.0) -> float:
 
 
 def vortex_count(v: np.ndarray, K: np.ndarray, kmax: float, vmin: float):
-    """Topological defects of the velocity direction field: for every grid
-    cell (nodes (i, j), (i, j+1), (i+1, j+1), (i+1, j), periodic, taken
-    counter-clockwise) whose four corners all have K < kmax and |v| > vmin,
-    the winding number n = (1/2 pi) sum of the edge-to-edge changes of the
-    angle of v, each wrapped into (-pi, pi].  Vortex centres (of either sense
-    of rotation) carry n = +1, saddles (hyperbolic stagnation points) n = -1.
-    Returns (sum of n over cells with n > 0, sum of |n| over cells with n < 0)."""
+    """Topological defects of the velocity direction field.  A node is inside
+    when K < kmax and has a direction when |v| > vmin.  For every grid cell
+    (nodes (i, j), (i, j+1), (i+1, j+1), (i+1, j), periodic, taken
+    counter-clockwise) whose four corners are inside with a direction, the
+    winding number n = (1/2 pi) sum of the corner-to-corner changes of the
+    angle of v, each wrapped into (-pi, pi]; for every inside node without a
+    direction (a defect sitting exactly on a node, as at the centre of a
+    symmetric vortex) whose eight neighbours are inside with a direction, the
+    same sum around that ring.  Vortex centres (of either sense of rotation)
+    carry n = +1, saddles (hyperbolic stagnation points) n = -1.  Returns
+    (sum of n where n > 0, sum of |n| where n < 0)."""
     th = np.arctan2(v[1], v[0])
     sp = np.hypot(v[0], v[1])
-    corners = [(0, 0), (0, 1), (1, 1), (1, 0)]
-    ths = [np.roll(th, (-a, -b), (0, 1)) for a, b in corners]
-    ok = np.ones(th.shape, dtype=bool)
-    for a, b in corners:
-        ok &= (np.roll(K, (-a, -b), (0, 1)) < kmax) & (np.roll(sp, (-a, -b), (0, 1)) > vmin)
-    w = np.zeros(th.shape)
-    for q in range(4):
-        d = ths[(q + 1) % 4] - ths[q]
-        w += d - 2 * np.pi * np.ceil((d - np.pi) / (2 * np.pi))  # into (-pi, pi]
-    n = np.rint(w / (2 * np.pi)).astype(np.int64) * ok
+    inside = K < kmax
+    good = inside & (sp > vmin)
+
+    def winding(path):
+        w = np.zeros(th.shape)
+        for q in range(len(path)):
+            a, b = path[q], path[(q + 1) % len(path)]
+            d = np.roll(th, (-b[0], -b[1]), (0, 1)) - np.roll(th, (-a[0], -a[1]), (0, 1))
+            w += d - 2 * np.pi * np.ceil((d - np.pi) / (2 * np.pi))  # into (-pi, pi]
+        ok = np.ones(th.shape, dtype=bool)
+        for a in path:
+            ok &= np.roll(good, (-a[0], -a[1]), (0, 1))
+        return np.rint(w / (2 * np.pi)).astype(np.int64) * ok
+
+    cells = winding([(0, 0), (0, 1), (1, 1), (1, 0)])
+    ring = winding([(-1, -1), (-1, 0), (-1, 1), (0, 1), (1, 1), (1, 0), (1, -1), (0, -1)])
+    ring = ring * (inside & ~(sp > vmin))
+    n = np.concatenate([cells.ravel(), ring.ravel()])
     return int(n[n > 0].sum()), int(-n[n < 0].sum())
 
 

@@ -306,50 +306,77 @@ __global__ void __launch_bounds__(1024) k_order_psi(const C2<double>* __restrict
   }
 }
 
-// Topological defects of the direction field of v = (Re Z, Im Z): per grid
-// cell (corners (i, j), (i, j+1), (i+1, j+1), (i+1, j), periodic,
-// counter-clockwise) with every corner at K < kmax and |v| > vmin, the
-// winding number of v around the cell, counted in quarter turns: each corner
-// vector's quadrant is found by exact sign tests, a step to the next or
-// previous quadrant is +-1, to the opposite one +-2 with the sign of the cross
-// product of the two vectors; the sum over the four edges is 4n.  out[0] =
-// sum of n > 0 (vortex centres), out[1] = sum of |n| over n < 0 (saddles).
-// One workgroup; integer sums, so the result does not depend on the order.
+// Topological defects of the direction field of v = (Re Z, Im Z).  A node is
+// inside when K < kmax and has a direction when |v|^2 > vmin^2.  Per grid cell
+// (corners (i, j), (i, j+1), (i+1, j+1), (i+1, j), periodic, counter-
+// clockwise) with all four corners inside with a direction, and per inside
+// node without a direction whose eight neighbours are inside with one (a
+// defect sitting on the node), the winding number of v around the cell or the
+// ring, counted in quarter turns: each vector's quadrant comes from exact sign
+// tests, a step to the next or previous quadrant is +-1, to the opposite one
+// +-2 with the sign of the cross product of the two vectors; the sum around
+// the loop is 4n.  out[0] = sum of n > 0 (vortex centres), out[1] = sum of |n|
+// over n < 0 (saddles).  One workgroup; integer sums, independent of order.
 __device__ __forceinline__ int quadrant(double x, double y) {
   if (x > 0.0 && y >= 0.0) return 0;
   if (x <= 0.0 && y > 0.0) return 1;
   if (x < 0.0 && y <= 0.0) return 2;
   return 3;
 }
+template <int P>
+__device__ __forceinline__ int winding_quarters(const C2<double> (&w)[P]) {
+  int turns = 0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const C2<double> a = w[q], b = w[(q + 1) % P];
+    const int d = (quadrant(b.x, b.y) - quadrant(a.x, a.y) + 4) & 3;
+    if (d == 1) turns += 1;
+    else if (d == 3) turns -= 1;
+    else if (d == 2) turns += (a.x * b.y - a.y * b.x) >= 0.0 ? 2 : -2;
+  }
+  return turns;
+}
 template <class T>
 __global__ void __launch_bounds__(1024) k_vortex_count(const C2<double>* __restrict__ Z, const T* __restrict__ K,
                                                        int N, double kmax, double vmin, int* __restrict__ out) {
   int pos = 0, neg = 0;
   const double v2 = vmin * vmin;
+  auto inside = [&](int id) { return (double)K[id] < kmax; };
+  auto fast = [&](const C2<double>& z) { return z.x * z.x + z.y * z.y > v2 && (z.x != 0.0 || z.y != 0.0); };
+  const int m = N - 1;  // N is a power of two: (i + d) & m wraps
   for (int c = threadIdx.x; c < N * N; c += blockDim.x) {
-    const int i = c / N, j = c % N, i1 = (i + 1) & (N - 1), j1 = (j + 1) & (N - 1);
-    const int idx[4] = {i * N + j, i * N + j1, i1 * N + j1, i1 * N + j};
-    bool ok = true;
-    C2<double> w[4];
+    const int i = c / N, j = c % N;
+    {  // the cell with lower-left corner (i, j)
+      const int id[4] = {i * N + j, i * N + ((j + 1) & m), ((i + 1) & m) * N + ((j + 1) & m), ((i + 1) & m) * N + j};
+      C2<double> w[4];
+      bool ok = true;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      w[q] = Z[idx[q]];
-      ok = ok && (double)K[idx[q]] < kmax && w[q].x * w[q].x + w[q].y * w[q].y > v2 &&
-           (w[q].x != 0.0 || w[q].y != 0.0);
+      for (int q = 0; q < 4; ++q) {
+        w[q] = Z[id[q]];
+        ok = ok && inside(id[q]) && fast(w[q]);
+      }
+      if (ok) {
+        const int n = winding_quarters(w) / 4;
+        if (n > 0) pos += n;
+        if (n < 0) neg -= n;
+      }
     }
-    if (!ok) continue;
-    int turns = 0;
+    if (inside(c) && !fast(Z[c])) {  // a defect on node (i, j): the ring of its neighbours
+      const int di[8] = {-1, -1, -1, 0, 1, 1, 1, 0}, dj[8] = {-1, 0, 1, 1, 1, 0, -1, -1};
+      C2<double> w[8];
+      bool ok = true;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const C2<double> a = w[q], b = w[(q + 1) & 3];
-      const int d = (quadrant(b.x, b.y) - quadrant(a.x, a.y) + 4) & 3;
-      if (d == 1) turns += 1;
-      else if (d == 3) turns -= 1;
-      else if (d == 2) turns += (a.x * b.y - a.y * b.x) >= 0.0 ? 2 : -2;
+      for (int q = 0; q < 8; ++q) {
+        const int id = ((i + di[q]) & m) * N + ((j + dj[q]) & m);
+        w[q] = Z[id];
+        ok = ok && inside(id) && fast(w[q]);
+      }
+      if (ok) {
+        const int n = winding_quarters(w) / 4;
+        if (n > 0) pos += n;
+        if (n < 0) neg -= n;
+      }
     }
-    const int n = turns / 4;
-    if (n > 0) pos += n;
-    if (n < 0) neg -= n;
   }
   __shared__ int red[16][2];
   for (int o = 32; o > 0; o >>= 1) {

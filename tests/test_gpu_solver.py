@@ -542,8 +542,9 @@ def test_fp64_radius_sweep_context_runs(gpu):
 def test_vortex_count_matches_oracle(gpu, prec):
     """ttsh_vortices against the oracle's winding-number count on the same
     real-space field (read back from the device), for a cellular flow on the
-    open periodic box (four centres, four saddles) and for a seeded field
-    after 300 steps inside a circle (wall region and slow nodes excluded)."""
+    open periodic box (four centres, four saddles), a vortex centred on a node
+    (counted from the ring of its neighbours) and a seeded field after 300
+    steps inside a circle (wall region and slow nodes excluded)."""
     say("vortex count", prec)
     N, L = 128, 2 * math.pi * 4
     p = O.workload_params()
@@ -555,6 +556,13 @@ def test_vortex_count_matches_oracle(gpu, prec):
     s.set_field(0, cell)
     got = s.vortices(0, 0.5, 0.0)
     assert got == O.vortex_count(s.field(0), np.zeros((N, N)), 0.5, 0.0) == (4, 4), got
+    g = np.exp(-(x * x + y * y) / 20.0)
+    s.set_field(0, np.stack([-y * g, x * g]))
+    disk = O.mask_tanh(N, L, [(0.0, 0.0)], [8.0], 0.5)
+    s.set_mask(0, disk)
+    v = s.field(0)
+    got = s.vortices(0, 0.5, 1e-9)
+    assert got == O.vortex_count(v, s.mask(0), 0.5, 1e-9) == (1, 0), got
     K = O.mask_tanh(N, L, [(0.0, 0.0)], [L / 3], 0.5)
     s.set_mask(1, K)
     s.set_field(1, W.uniform_field(5, N, 0.01, prec))

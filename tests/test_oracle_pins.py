@@ -518,3 +518,18 @@ def test_vortex_count_closed_forms():
     # cells touching the excluded region (mask or slow nodes) do not count
     assert O.vortex_count(vort, np.ones((N, N)), 0.5, 1e-12) == (0, 0)
     assert O.vortex_count(vort, disk, 0.5, 10.0) == (0, 0)
+
+
+def test_vortex_count_defect_on_a_node():
+    """A vortex centred exactly on a node (v = 0 there, as for a symmetric
+    vortex in a circle centred on a node) is counted once, from the ring of
+    the node's eight neighbours; so is a saddle on a node."""
+    N, L = 64, 32.0
+    x, y = O.node_coords(N, L)
+    r2 = x * x + y * y
+    disk = (r2 > 100.0).astype(float)
+    g = np.exp(-r2 / 20.0)
+    vort = np.stack([-y * g, x * g])
+    assert vort[:, N // 2, N // 2].tolist() == [0.0, 0.0]
+    assert O.vortex_count(vort, disk, 0.5, 1e-12) == (1, 0)
+    assert O.vortex_count(np.stack([x, -y]), disk, 0.5, 1e-12) == (0, 1)
