@@ -8,8 +8,9 @@ ramp from the next smaller radius, the downward ramp from the next larger one
 (ttsh_reseed: mode-index transfer between the grids, plus projected uniform
 noise) -- so that after S stages instance j of a ramp has been continued
 through the S radii before it, as the sequential protocol would, but with all
-instances busy.  The vortex order parameter Psi of every instance is taken at
-the end of each stage (ttsh_order).
+instances busy.  The vortex order parameter Psi of every instance and its
+vortex count (centres and saddles of the velocity direction inside the
+circle, ttsh_vortices) are taken at the end of each stage.
 
 Every step of the computation runs in the library; this module orders the
 calls and keeps the record.
@@ -39,6 +40,8 @@ def run(stages: int, steps: int, log=None, tune: bool = True) -> dict:
             s.tune(20)
         src = W.sweep_chain(n // 2)
         psi = np.zeros((stages, n))
+        centres = np.zeros((stages, n), dtype=np.int64)
+        saddles = np.zeros((stages, n), dtype=np.int64)
         seconds = []
         for st in range(stages):
             t0 = time.time()
@@ -47,6 +50,9 @@ def run(stages: int, steps: int, log=None, tune: bool = True) -> dict:
             seconds.append(time.time() - t0)
             for q in range(n):
                 psi[st, q] = s.order(q, inst[q].centers[0])[0]
+                # nodes slower than 1e-3 of the rms speed have no defined direction
+                vmin = 1e-3 * np.sqrt(s.norms(q)[0] / inst[q].N ** 2)
+                centres[st, q], saddles[st, q] = s.vortices(q, 0.5, vmin)
             if log:
                 log(f"stage {st}: {steps} steps in {seconds[-1]:.2f} s; "
                     f"Psi up {np.round(psi[st, 0::2], 2).tolist()}")
@@ -57,6 +63,8 @@ def run(stages: int, steps: int, log=None, tune: bool = True) -> dict:
         radii = [inst[2 * j].radii[0] for j in range(n // 2)]
         return {"radii": radii, "stages": stages, "steps_per_stage": steps,
                 "psi_up": psi[:, 0::2].tolist(), "psi_down": psi[:, 1::2].tolist(),
+                "centres_up": centres[:, 0::2].tolist(), "centres_down": centres[:, 1::2].tolist(),
+                "saddles_up": saddles[:, 0::2].tolist(), "saddles_down": saddles[:, 1::2].tolist(),
                 "seconds_per_stage": seconds,
                 "points_per_step": wl.points,
                 "throughput": wl.points * steps / float(np.mean(seconds))}
