@@ -11,8 +11,11 @@ orders the calls, moves buffers and keeps host-side bookkeeping (sample
 indices, learning-rate schedule, acceptance decisions).
 
 Data layout on the device: snapshots D[t][i] of instance i at surrogate step
-t, each a channels-last float32 Nc x Nc x 3 field (v_x, v_y, K), where K is
-the instance's mask sampled on the coarse grid.  One surrogate step advances
+t, each a channels-last float32 Nc x Nc x cin field (v_x, v_y, K[, dx]), where
+K is the instance's mask sampled on the coarse grid and the optional fourth
+channel holds the coarse grid spacing L/Nc of the instance's box as a
+constant (the radius sets the box, so this tells the network the physical
+scale the coarse fields are on).  One surrogate step advances
 `every` solver steps.  The network predicts the change of (v_x, v_y) over one
 surrogate step (residual output), and the rollout projects each prediction
 onto the coarse solver's state space (1/2-rule cutoff, divergence-free) as a
@@ -42,7 +45,7 @@ class SurrogateConfig:
     hidden: int = 128
     batch: int = 256
     lr: float = 1e-3
-    cin: int = 3           # v_x, v_y, K
+    cin: int = 3           # v_x, v_y, K (4: and the grid spacing, see scale_channel)
     cout: int = 2
     increment_loss: bool = False  # normalise the loss by the change over the step (fno_loss_ex)
     input_noise: float = 0.0      # uniform perturbation of the input velocity in training
@@ -94,18 +97,25 @@ def snapshot(solver: T.Solver, n_inst: int, Nc: int, out) -> None:
 
 
 def collect(solver: T.Solver, masks: np.ndarray, n_snap: int, every: int, Nc: int, transient: int = 0,
-            log=None):
+            log=None, spacing: Optional[Sequence[float]] = None):
     """Run the solver and record n_snap snapshots, `every` steps apart, after
-    `transient` steps.  Returns a device tensor D [n_snap][I][Nc][Nc][3]."""
+    `transient` steps.  Returns a device tensor D [n_snap][I][Nc][Nc][cin]
+    with cin = 3, or 4 when the coarse grid spacings of the instances are
+    given (a constant fourth channel)."""
     torch = _torch()
     I = masks.shape[0]
-    D = torch.empty((n_snap, I, Nc, Nc, 3), dtype=torch.float32, device="cuda")
+    cin = 3 if spacing is None else 4
+    D = torch.empty((n_snap, I, Nc, Nc, cin), dtype=torch.float32, device="cuda")
     Kd = torch.from_numpy(masks).cuda()
+    if spacing is not None:
+        hd = torch.tensor(np.asarray(spacing, dtype=np.float32), device="cuda")[:, None, None].expand(I, Nc, Nc)
     if transient:
         solver.step(transient)
     t0 = time.time()
     for t in range(n_snap):
         D[t, :, :, :, 2] = Kd
+        if spacing is not None:
+            D[t, :, :, :, 3] = hd
         snapshot(solver, I, Nc, D[t])
         if t + 1 < n_snap:
             solver.step(every)
@@ -149,8 +159,9 @@ class Trainer:
         I = D.shape[1]
         npix = c.Nc * c.Nc
         B = len(idx)
-        self.net.gather(self.xb, c.cin, D, 3, c.cin, npix, idx)
-        self.net.gather(self.tb, c.cout, D, 3, c.cout, npix, idx + I)
+        dch = D.shape[-1]
+        self.net.gather(self.xb, c.cin, D, dch, c.cin, npix, idx)
+        self.net.gather(self.tb, c.cout, D, dch, c.cout, npix, idx + I)
         if c.input_noise > 0:
             self.net.perturb(self.xb, c.cin, c.cout, B * npix, c.input_noise, self.step_count + 1)
         self.net.forward_ex(self.xb, self.yb, c.cout, True, B, train=True)
@@ -202,8 +213,8 @@ class Trainer:
         for b0 in range(0, len(pairs), c.batch):
             idx = pairs[b0:b0 + c.batch]
             B = len(idx)
-            self.net.gather(xb, c.cin, D, 3, c.cin, npix, idx)
-            self.net.gather(self.tb, c.cout, D, 3, c.cout, npix, idx + I)
+            self.net.gather(xb, c.cin, D, D.shape[-1], c.cin, npix, idx)
+            self.net.gather(self.tb, c.cout, D, D.shape[-1], c.cout, npix, idx + I)
             pers.append(F.fno_sample_errors(xb, c.cin, self.tb, c.cout, c.cout, npix, B))
             self.net.forward_ex(xb, self.yb, c.cout, True, B)
             errs.append(F.fno_sample_errors(self.yb, c.cout, self.tb, c.cout, c.cout, npix, B))
@@ -249,11 +260,12 @@ class Rollout:
         self.envelope, self.check_every, self.tol = envelope, check_every, tol
 
     def run(self, x0, steps: int, judge=None, log=None) -> RolloutResult:
-        """x0: device [I][Nc][Nc][3] (v_x, v_y, K) at surrogate step 0.
+        """x0: device [I][Nc][Nc][cin] (v_x, v_y, K[, dx]) at surrogate step 0.
         judge(s) -> device [I][Nc][Nc][>=2] solver fields at step s, or None."""
         torch = _torch()
         c = self.cfg
         I = x0.shape[0]
+        ch = x0.shape[-1]  # pixel stride of the coarse fields
         npix = c.Nc * c.Nc
         x = x0.clone()
         x_prev = torch.empty_like(x)
@@ -273,13 +285,13 @@ class Rollout:
             if check:
                 ids = np.flatnonzero(active)
                 for i in ids:
-                    self.checker.set_field_coarse(int(i), c.Nc, x[i], 3)
+                    self.checker.set_field_coarse(int(i), c.Nc, x[i], ch)
                 self.checker.step(c.every)
                 for i in ids:
-                    self.checker.field_coarse(int(i), c.Nc, ref[i], 3)
+                    self.checker.field_coarse(int(i), c.Nc, ref[i], ch)
             ts = time.time()
-            self.net.forward_ex(x, x, 3, True, I)
-            nrm = self.checker.project_coarse(c.Nc, x, 3, I, norms=True)
+            self.net.forward_ex(x, x, ch, True, I)
+            nrm = self.checker.project_coarse(c.Nc, x, ch, I, norms=True)
             t_sur += time.time() - ts
             bad = ~np.isfinite(nrm).all(axis=1)
             fail = active & bad
@@ -291,7 +303,7 @@ class Rollout:
             for i in np.flatnonzero(fail):
                 reason[i] = "non-finite" if bad[i] else "energy/enstrophy envelope"
             if check:
-                e_loc = F.fno_sample_errors(x, 3, ref, 3, 2, npix, I)
+                e_loc = F.fno_sample_errors(x, ch, ref, ch, 2, npix, I)
                 loc = active & ~fail & ~(e_loc <= self.tol)
                 for i in np.flatnonzero(loc):
                     reason[i] = f"local check {e_loc[i]:.3g} > {self.tol}"
@@ -302,19 +314,19 @@ class Rollout:
                 active[ids] = False
                 sol = new_solver([self.inst[i] for i in ids], self.params, seed_fields=False)
                 for q, i in enumerate(ids):
-                    sol.set_field_coarse(q, c.Nc, x_prev[i], 3)
+                    sol.set_field_coarse(q, c.Nc, x_prev[i], ch)
                 solvers.append((sol, ids))
                 if log:
                     log(f"step {s}: instances {ids} -> solver ({reason[ids[0]]})")
             for sol, ids in solvers:
                 sol.step(c.every)
                 for q, i in enumerate(ids):
-                    sol.field_coarse(q, c.Nc, x[i], 3)
+                    sol.field_coarse(q, c.Nc, x[i], ch)
             prev = nrm if prev is None else np.where(active[:, None], nrm, prev)
             if judge is not None:
                 tgt = judge(s + 1)
                 if tgt is not None:
-                    err[s] = F.fno_sample_errors(x, 3, tgt, tgt.shape[-1], 2, npix, I)
+                    err[s] = F.fno_sample_errors(x, ch, tgt, tgt.shape[-1], 2, npix, I)
             if log and (s + 1) % 50 == 0:
                 log(f"rollout step {s + 1}/{steps}: mean err {np.nanmean(err[s]):.3e}, "
                     f"{int(active.sum())} on the network")
@@ -344,14 +356,14 @@ def surrogate_step_seconds(net: F.FNO, checker: T.Solver, x, Nc: int, reps: int 
     with residual output in place, projection with the acceptance norms)."""
     torch = _torch()
     y = x.clone()
-    B = x.shape[0]
-    net.forward_ex(y, y, 3, True, B)
-    checker.project_coarse(Nc, y, 3, B, norms=True)
+    B, ch = x.shape[0], x.shape[-1]
+    net.forward_ex(y, y, ch, True, B)
+    checker.project_coarse(Nc, y, ch, B, norms=True)
     torch.cuda.synchronize()
     t0 = time.time()
     for _ in range(reps):
-        net.forward_ex(y, y, 3, True, B)
-        checker.project_coarse(Nc, y, 3, B, norms=True)
+        net.forward_ex(y, y, ch, True, B)
+        checker.project_coarse(Nc, y, ch, B, norms=True)
     torch.cuda.synchronize()
     return (time.time() - t0) / reps
 
@@ -378,6 +390,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--modes", type=int, default=16)
     ap.add_argument("--input-noise", type=float, default=0.0)
+    ap.add_argument("--scale-channel", action="store_true",
+                    help="a fourth input channel with the coarse grid spacing L/Nc of each instance")
     ap.add_argument("--threshold", type=float, default=0.1)
     ap.add_argument("--check-every", type=int, default=25)
     ap.add_argument("--report", default="surrogate_report.json")
@@ -389,12 +403,14 @@ def main(argv=None):
     wl = Wl.radius_sweep()
     inst = wl.instances
     params = Wl.workload_coefficients()
-    cfg = SurrogateConfig(batch=a.batch, lr=a.lr, modes=a.modes, input_noise=a.input_noise)
+    cfg = SurrogateConfig(batch=a.batch, lr=a.lr, modes=a.modes, input_noise=a.input_noise,
+                          cin=4 if a.scale_channel else 3)
     I, Nc = len(inst), cfg.Nc
+    spacing = [i.L / Nc for i in inst] if a.scale_channel else None
     masks = coarse_masks(inst, Nc, params)
     solver = new_solver(inst, params)
     if a.speed_only:
-        D = collect(solver, masks, 1, cfg.every, Nc, transient=a.transient)
+        D = collect(solver, masks, 1, cfg.every, Nc, transient=a.transient, spacing=spacing)
         net = F.FNO(width=cfg.width, modes=cfg.modes, layers=cfg.layers, cin=cfg.cin, cout=cfg.cout,
                     hidden=cfg.hidden, H=Nc, W=Nc, max_batch=I, seed=0)
         t_sur = surrogate_step_seconds(net, solver, D[0], Nc)
@@ -403,7 +419,7 @@ def main(argv=None):
             f"{t_sol / t_sur:.2f}x")
         return {"seconds_per_surrogate_step": t_sur, "seconds_per_solver_steps": t_sol}
     log(f"{I} instances, transient {a.transient} steps, {a.snapshots} snapshots every {cfg.every}")
-    D = collect(solver, masks, a.snapshots, cfg.every, Nc, transient=a.transient, log=log)
+    D = collect(solver, masks, a.snapshots, cfg.every, Nc, transient=a.transient, log=log, spacing=spacing)
     train_ids, test_ids = split_by_radius(I // 2)
     # training pairs: snapshots 0 .. train_until (the rollout starts after them)
     tr = Trainer(cfg, seed=0)
@@ -424,7 +440,8 @@ def main(argv=None):
     guarded = ro.run(D[t0], steps, judge=judge, log=log)
     # persistence for reference
     npix = Nc * Nc
-    pers = np.stack([F.fno_sample_errors(D[t0], 3, D[t0 + s + 1], 3, 2, npix, I) for s in range(steps)])
+    dch = D.shape[-1]
+    pers = np.stack([F.fno_sample_errors(D[t0], dch, D[t0 + s + 1], dch, 2, npix, I) for s in range(steps)])
     t_sur = surrogate_step_seconds(tr.net, solver, D[t0], Nc)
     t_sol = solver_step_seconds(solver, cfg.every)
     test = np.array(test_ids)
@@ -434,7 +451,7 @@ def main(argv=None):
         "instances": I, "coarse_grid": Nc, "solver_steps_per_surrogate_step": cfg.every,
         "network": dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, hidden=cfg.hidden,
                         params=int(tr.net.n), dtype="bf16 storage, fp32 accumulation",
-                        input_noise=cfg.input_noise),
+                        input_noise=cfg.input_noise, inputs="v_x, v_y, K" + (", dx" if a.scale_channel else "")),
         "data": dict(transient=a.transient, snapshots=a.snapshots, train_pairs=len(tr.pairs(Dtrain, train_ids)),
                      train_instances=train_ids, test_instances=test_ids),
         "training": dict(epochs=len(hist), seconds=hist[-1][2], loss_first=hist[0][1], loss_last=hist[-1][1],

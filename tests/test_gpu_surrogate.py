@@ -113,3 +113,29 @@ def test_rollout_is_judged_and_falls_back(data, trained):
     assert (res2.fallback_step == 0).all(), res2.fallback_step
     assert all(r == "non-finite" for r in res2.reason)
     assert np.isfinite(res2.err).all() and res2.err.max() < 0.05, res2.err
+
+
+def test_scale_channel_pipeline(data):
+    """With the grid-spacing channel the snapshots carry L/Nc as a constant
+    fourth channel beside the same (v_x, v_y, K); a 4-input network trains a
+    few batches and rolls out with finite errors."""
+    import torch
+    from paper_2304_03306_amd import surrogate as S
+    say("surrogate scale channel")
+    inst = data["inst"][:4]
+    masks = data["masks"][:4]
+    s = S.new_solver(inst, data["p"])
+    spacing = [i.L / 128 for i in inst]
+    D4 = S.collect(s, masks, 6, EVERY, 128, transient=TRANSIENT, spacing=spacing)
+    assert D4.shape[-1] == 4
+    for i in range(4):
+        assert torch.all(D4[:, i, :, :, 3] == np.float32(spacing[i]))
+    ref = data["D"][:6, :4]
+    assert float((D4[..., :3] - ref).norm() / ref.norm()) < 1e-5  # same trajectories (tuning may reorder sums)
+    cfg = S.SurrogateConfig(batch=8, cin=4)
+    tr = S.Trainer(cfg, seed=0)
+    hist = tr.train(D4, [0, 1, 2, 3], epochs=2, seed=1)
+    assert np.isfinite(hist[-1][1])
+    ro = S.Rollout(tr.net, cfg, inst, data["p"], s, check_every=0, envelope=float("inf"))
+    res = ro.run(D4[0], 3, judge=lambda k: D4[k] if k < D4.shape[0] else None)
+    assert np.isfinite(res.err).all()
