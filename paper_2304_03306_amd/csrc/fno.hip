@@ -665,13 +665,20 @@ __global__ void __launch_bounds__(256) k_yanalysis(const bf16* __restrict__ T1, 
   for (long long it = blockIdx.x; it < items; it += gridDim.x) {
     const int kx = (int)(it % m);
     const long long b = it / m;
+    {  // 2 blocks x 32 groups of 4 rows x 4 runs of 8 channels: a thread reads one
+       // 4 x 8 patch and writes each channel's 4 rows as one 8-byte run of [c][y]
+      const int part = tid >> 7, y0 = ((tid >> 2) & 31) * 4, c0 = (tid & 3) * 8;
+      const bf16* src = T1 + ((b * 2 * m + part * m + kx) * H + y0) * C + c0;
+      uint4 v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {  // 2 blocks x 128 rows x 4 runs of 8 channels
-      const int seg = tid + 256 * i, part = seg >> 9, y = (seg & 511) >> 2, c0 = (seg & 3) * 8;
-      const uint4 v = *(const uint4*)(T1 + ((b * 2 * m + part * m + kx) * H + y) * C + c0);
-      const bf16* e = (const bf16*)&v;
+      for (int r = 0; r < 4; ++r) v[r] = *(const uint4*)(src + r * C);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Rs[part][(c0 + q) * LD + y] = e[q];
+      for (int q = 0; q < 8; ++q) {
+        short4_t col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[r] = (short)((const bf16*)&v[r])[q];
+        *(short4_t*)(Rs[part] + (c0 + q) * LD + y0) = col;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -718,12 +725,19 @@ __global__ void __launch_bounds__(256) k_ysynth(const bf16* __restrict__ O, cons
   for (long long it = blockIdx.x; it < items; it += gridDim.x) {
     const int kx = (int)(it % m);
     const long long b = it / m;
-    {  // 2 parts x 32 ky x 4 runs of 8 channels
-      const int part = tid >> 7, ky = (tid >> 2) & 31, c0 = (tid & 3) * 8;
-      const uint4 v = *(const uint4*)(O + (((long long)kx * K + ky) * B + b) * 2 * C + part * C + c0);
-      const bf16* e = (const bf16*)&v;
+    if (tid < 64) {  // 2 parts x 8 groups of 4 ky x 4 runs of 8 channels, one 4 x 8 patch per thread
+      const int part = tid >> 5, ky0 = ((tid >> 2) & 7) * 4, c0 = (tid & 3) * 8;
+      uint4 v[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Os[part][(c0 + q) * kLDK + ky] = e[q];
+      for (int r = 0; r < 4; ++r)
+        v[r] = *(const uint4*)(O + (((long long)kx * K + ky0 + r) * B + b) * 2 * C + part * C + c0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        short4_t col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[r] = (short)((const bf16*)&v[r])[q];
+        *(short4_t*)(Os[part] + (c0 + q) * kLDK + ky0) = col;
+      }
     }
     __syncthreads();
     short4_t br[2][2], bi[2][2];
