@@ -26,8 +26,10 @@ from . import ttsh as T
 from . import workloads as W
 
 
-def run(radii, N=1024, L=40.96, steps=200_000, transient=50_000, every=200, seed=7, log=None) -> dict:
-    params = W.paper_coefficients()
+def run(radii, N=1024, L=40.96, steps=200_000, transient=50_000, every=200, seed=7, log=None,
+        scheme: str = "ifeuler", dt: float = 0.01) -> dict:
+    import dataclasses
+    params = dataclasses.replace(W.paper_coefficients(dt=dt), scheme=scheme)
     n = len(radii)
     s = T.Solver([N] * n, [L] * n, params, T.TTSH_FP32)
     try:
@@ -90,9 +92,12 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200_000)
     ap.add_argument("--transient", type=int, default=50_000)
     ap.add_argument("--every", type=int, default=200)
+    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2"])
+    ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--report", default="circle_report.json")
     a = ap.parse_args(argv)
-    rep = run(a.radii, a.N, a.L, a.steps, a.transient, a.every, log=lambda m: print(f"[circle] {m}", flush=True))
+    rep = run(a.radii, a.N, a.L, a.steps, a.transient, a.every, log=lambda m: print(f"[circle] {m}", flush=True),
+              scheme=a.scheme, dt=a.dt)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     for r in rep["radii"]:

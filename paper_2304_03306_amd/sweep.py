@@ -26,11 +26,12 @@ from . import ttsh as T
 from . import workloads as W
 
 
-def run(stages: int, steps: int, log=None, tune: bool = True) -> dict:
+def run(stages: int, steps: int, log=None, tune: bool = True, scheme: str = "ifeuler") -> dict:
+    import dataclasses
     wl = W.radius_sweep()
     inst = wl.instances
     n = len(inst)
-    params = W.workload_coefficients()
+    params = dataclasses.replace(W.workload_coefficients(), scheme=scheme)
     s = T.Solver([i.N for i in inst], [i.L for i in inst], params, T.TTSH_FP32)
     try:
         for q, i in enumerate(inst):
@@ -78,9 +79,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--stages", type=int, default=32)
     ap.add_argument("--steps", type=int, default=20_000)
+    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2"])
     ap.add_argument("--report", default="sweep_report.json")
     a = ap.parse_args(argv)
-    rep = run(a.stages, a.steps, log=lambda m: print(f"[sweep] {m}", flush=True))
+    rep = run(a.stages, a.steps, log=lambda m: print(f"[sweep] {m}", flush=True), scheme=a.scheme)
     with open(a.report, "w") as f:
         json.dump(rep, f, indent=1)
     print(f"[sweep] {a.stages} stages of {a.steps} steps; {rep['throughput']:.4e} pt*steps/s", flush=True)
