@@ -470,12 +470,13 @@ def test_runs_are_bitwise_deterministic(gpu):
 
 # ---- ETD2RK: two column-pass stages per step --------------------------------------------------
 @pytest.mark.parametrize("N,steps,prec,preset,tol", [(64, 1, 64, "paper", 1e-13), (128, 1000, 32, "workload", 1e-5),
-                                                     (128, 200, 32, "paper", 1e-5), (256, 50, 96, "paper", 1e-6)])
+                                                     (128, 200, 32, "paper", 1e-5), (256, 50, 96, "paper", 1e-6),
+                                                     (2048, 2, 32, "paper", 1e-6)])
 def test_etdrk2_matches_oracle(gpu, N, steps, prec, preset, tol):
     """The second-order exponential Runge-Kutta step (stage state, kept
     stage-1 forcing and k = 0 sums on the device) against the oracle's ETD2RK;
     the paper preset runs the gamma_w (vorticity source) path through both
-    stages."""
+    stages; 2048^2 takes the per-size column kernels."""
     import dataclasses
     say("etdrk2", N, steps, prec, preset)
     L = N * 0.5
