@@ -162,6 +162,17 @@ int ttsh_get_field_coarse(ttsh_ctx* ctx, int inst, int Nc, float* out, int64_t p
  * Synchronous.                                                              */
 int ttsh_order(ttsh_ctx* ctx, int inst, double cx, double cy, double* out);
 
+/* Psi_2 of instance inst with the regions of the two-chamber section (sec.
+ * "Dumbbell" geometry, order parameter of the two cavities): the nodes within
+ * D/2 of either cavity centre, (cx - D/2, cy) for the left one (nodes left of
+ * x = cx) and (cx + D/2, cy) for the right one (nodes at or right of x = cx),
+ * D the distance between the centres.  Otherwise as out[1] of ttsh_order:
+ * *psi2 = |w_l + w_r| / (|w_l| + |w_r|), or NaN if a region holds no node.
+ * The disk test rounds each operation of
+ * (x - c_x)^2 + (y - c_y)^2 <= (D/2)^2 separately (no fused multiply-add).
+ * D must be positive and finite (else EINVAL).  Synchronous.               */
+int ttsh_order_dumbbell(ttsh_ctx* ctx, int inst, double cx, double cy, double D, double* psi2);
+
 /* Vortex count of instance inst (the topological defects of the direction of
  * v, used to tell single vortices, pairs and disordered states apart): over
  * the grid cells whose four corner nodes all have K < kmax and |v| > vmin, the

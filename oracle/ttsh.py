@@ -490,18 +490,29 @@ def vortex_order(v: np.ndarray, L: float, center=(0.0, 0.0)) -> float:
     return float((num / den - 2.0 / math.pi) / (1.0 - 2.0 / math.pi))
 
 
-def vortex_order2(w: np.ndarray, L: float, split_x: float = 0.0) -> float:
+def vortex_order2(w: np.ndarray, L: float, split_x: float = 0.0, D: float = 0.0, center_y: float = 0.0) -> float:
     """Order parameter Psi_2 of the two-chamber (dumbbell) section: with
-    x_left / x_right the nodes of largest |omega| left of x = split_x and at or
-    right of it, |w(x_left) + w(x_right)| / (|w(x_left)| + |w(x_right)|); 1 for
-    co-rotating (ferromagnetic), 0 for counter-rotating vortices.  Ties go to
-    the first node in row-major order."""
+    x_left / x_right the nodes of largest |omega| in the left and right
+    regions, |w(x_left) + w(x_right)| / (|w(x_left)| + |w(x_right)|); 1 for
+    co-rotating (ferromagnetic), 0 for counter-rotating vortices.  Regions:
+    with D > 0 the paper's, the nodes within D/2 of either cavity centre
+    (split_x -+ D/2, center_y), the node where the two disks touch going to
+    the right one; with D = 0 the half-planes left of x = split_x and at or
+    right of it.  Ties go to the first node in row-major order; NaN when a
+    region holds no node."""
     N = w.shape[-1]
-    x, _ = node_coords(N, L)
+    x, y = node_coords(N, L)
     left = x < split_x
+    right = ~left
+    if D > 0:
+        r2 = (0.5 * D) ** 2
+        left = left & ((x - (split_x - 0.5 * D)) ** 2 + (y - center_y) ** 2 <= r2)
+        right = right & ((x - (split_x + 0.5 * D)) ** 2 + (y - center_y) ** 2 <= r2)
+    if not left.any() or not right.any():
+        return float("nan")
     aw = np.abs(w)
     iL = int(np.argmax(np.where(left, aw, -1.0)))
-    iR = int(np.argmax(np.where(left, -1.0, aw)))
+    iR = int(np.argmax(np.where(right, aw, -1.0)))
     wl, wr = w.flat[iL], w.flat[iR]
     return float(abs(wl + wr) / (abs(wl) + abs(wr)))
 

@@ -400,15 +400,27 @@ __global__ void __launch_bounds__(1024) k_vortex_count(const C2<double>* __restr
 }
 
 // Two-chamber order parameter from the vorticity in the real part of Z: the
-// nodes of largest |omega| left of x = cx and at or right of it (ties to the
-// lower index), |w_l + w_r| / (|w_l| + |w_r|).
+// nodes of largest |omega| in the left and right regions (ties to the lower
+// index), |w_l + w_r| / (|w_l| + |w_r|).  Regions: with D > 0 the nodes within
+// D/2 of (cx - D/2, cy) left of x = cx and within D/2 of (cx + D/2, cy) at or
+// right of it; with D <= 0 the two half-planes.  An empty region gives NaN.
+// The disk test rounds every product and sum separately (no fused
+// multiply-add), so that a node on a disk's rim falls on the same side as in
+// a plain evaluation of the same expression.
 __global__ void __launch_bounds__(1024) k_order_psi2(const C2<double>* __restrict__ Z, int N, double dx, double cx,
-                                                     double* __restrict__ out) {
+                                                     double cy, double D, double* __restrict__ out) {
+  const double r2 = __dmul_rn(0.5 * D, 0.5 * D);
+  const double cl = __dsub_rn(cx, 0.5 * D), cr = __dadd_rn(cx, 0.5 * D);
   double best[2] = {-1.0, -1.0};
   int at[2] = {0, 0};
   for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
-    const double x = ((i % N) - N / 2) * dx;
+    const double x = __dmul_rn((double)((i % N) - N / 2), dx);
     const int side = x < cx ? 0 : 1;
+    if (D > 0.0) {
+      const double y = __dmul_rn((double)((i / N) - N / 2), dx);
+      const double ex = __dsub_rn(x, side ? cr : cl), ey = __dsub_rn(y, cy);
+      if (__dadd_rn(__dmul_rn(ex, ex), __dmul_rn(ey, ey)) > r2) continue;
+    }
     const double a = fabs(Z[i].x);
     if (a > best[side]) {  // i grows per thread: the first of equal values is kept
       best[side] = a;
@@ -437,7 +449,7 @@ __global__ void __launch_bounds__(1024) k_order_psi2(const C2<double>* __restric
   }
   if (threadIdx.x == 0) {
     const double wl = Z[bi[0][0]].x, wr = Z[bi[1][0]].x;
-    out[1] = fabs(wl + wr) / (fabs(wl) + fabs(wr));
+    out[1] = (bv[0][0] < 0.0 || bv[1][0] < 0.0) ? __builtin_nan("") : fabs(wl + wr) / (fabs(wl) + fabs(wr));
   }
 }
 

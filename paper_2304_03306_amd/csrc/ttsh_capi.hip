@@ -825,15 +825,15 @@ int ttsh_project_coarse(ttsh_ctx* c, int N, float* v, int64_t pix_stride, int ba
   return TTSH_OK;
 }
 
-int ttsh_order(ttsh_ctx* c, int inst, double cx, double cy, double* out) {
-  int rc = check_inst(c, inst);
-  if (rc) return rc;
-  if (!out) return fail(TTSH_EINVAL, "null output");
+// Order parameters into dnorm[0] (Psi, from the velocity) and dnorm[1] (Psi_2,
+// from the vorticity), the first from_what of them skipped; the host receives
+// dnorm[from_what..1] in out[0..].
+static int order_impl(ttsh_ctx* c, int inst, double cx, double cy, double D, int from_what, double* out) {
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
   const int N = k.N, n = N * N;
   const double L = c->L[inst], dk = 2.0 * M_PI / L, dx = L / N;
-  for (int what = 0; what < 2; ++what) {
+  for (int what = from_what; what < 2; ++what) {
     if (c->prec == 32)
       hipLaunchKernelGGL(k_state_to_full<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
                          at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), (C2<double>*)c->scr0, N, dk, what);
@@ -847,12 +847,28 @@ int ttsh_order(ttsh_ctx* c, int inst, double cx, double cy, double* out) {
                          c->dnorm);
     else
       hipLaunchKernelGGL(k_order_psi2, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx,
-                         c->dnorm);
+                         cy, D, c->dnorm);
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipMemcpyAsync(out, c->dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(out, c->dnorm + from_what, (2 - from_what) * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return TTSH_OK;
+}
+
+int ttsh_order(ttsh_ctx* c, int inst, double cx, double cy, double* out) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!out) return fail(TTSH_EINVAL, "null output");
+  return order_impl(c, inst, cx, cy, 0.0, 0, out);
+}
+
+int ttsh_order_dumbbell(ttsh_ctx* c, int inst, double cx, double cy, double D, double* psi2) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!psi2) return fail(TTSH_EINVAL, "null output");
+  if (!(D > 0.0) || !std::isfinite(D)) return fail(TTSH_EINVAL, "D must be positive and finite");
+  return order_impl(c, inst, cx, cy, D, 1, psi2);
 }
 
 int ttsh_vortices(ttsh_ctx* c, int inst, double kmax, double vmin, int* out) {

@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_set_field_coarse": [vp, i32, i32, dp, i64],
             "ttsh_project_coarse": [vp, i32, dp, i64, i32, dp],
             "ttsh_order": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
+            "ttsh_order_dumbbell": [vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_vortices": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
@@ -183,6 +184,13 @@ def ttsh_order(ctx, inst, center=(0.0, 0.0)):
     out = (ctypes.c_double * 2)()
     _check(lib().ttsh_order(ctx, int(inst), float(center[0]), float(center[1]), ctypes.cast(out, ctypes.c_void_p)))
     return out[0], out[1]
+
+def ttsh_order_dumbbell(ctx, inst, D, center=(0.0, 0.0)):
+    """Psi_2 over the disks of radius D/2 about center -+ (D/2, 0)."""
+    out = ctypes.c_double()
+    _check(lib().ttsh_order_dumbbell(ctx, int(inst), float(center[0]), float(center[1]), float(D),
+                                     ctypes.cast(ctypes.pointer(out), ctypes.c_void_p)))
+    return out.value
 
 def ttsh_vortices(ctx, inst, kmax=0.5, vmin=0.0):
     """(vortex centres, saddles) of instance inst, see include/ttsh.h."""
@@ -329,6 +337,9 @@ class Solver:
 
     def order(self, inst, center=(0.0, 0.0)):
         return ttsh_order(self.ctx, inst, center)
+
+    def order_dumbbell(self, inst, D, center=(0.0, 0.0)):
+        return ttsh_order_dumbbell(self.ctx, inst, D, center)
 
     def vortices(self, inst, kmax=0.5, vmin=0.0):
         return ttsh_vortices(self.ctx, inst, kmax, vmin)

@@ -403,8 +403,9 @@ def test_failure_injection_nonfinite_input_and_unstable_mask(gpu):
 
 @pytest.mark.parametrize("prec", [32, 64])
 def test_order_parameters_match_oracle(gpu, prec):
-    """Psi and Psi_2 from the library equal the oracle's on the same state:
-    a 256^2 dumbbell instance after 300 steps and a circle after 200."""
+    """Psi and Psi_2 (half-planes and the two-chamber disks) from the library
+    equal the oracle's on the same state: a 256^2 dumbbell instance and a
+    circle after 300 steps."""
     say("order parameters", prec)
     p = O.workload_params()
     N, L = 256, 128.0
@@ -423,6 +424,18 @@ def test_order_parameters_match_oracle(gpu, prec):
         psi, psi2 = s.order(i, cen)
         assert abs(psi - O.vortex_order(v, L, cen)) < 1e-12
         assert abs(psi2 - O.vortex_order2(w, L, cen[0])) < 1e-12
+        # the two-chamber regions: disks of radius D/2 about the cavity centres
+        # (D = 40: the dumbbell's own; D = 25 and 8: smaller disks, nodes on the rims)
+        for D in (40.0, 25.0, 8.0):
+            got = s.order_dumbbell(i, D, cen)
+            want = O.vortex_order2(w, L, cen[0], D=D, center_y=cen[1])
+            assert abs(got - want) < 1e-12, (i, cen, D, got, want)
+    # a disk smaller than the node spacing that holds no node: NaN on both sides
+    got = s.order_dumbbell(0, 0.2, (0.25, 0.25))
+    assert np.isnan(got) and np.isnan(O.vortex_order2(w, L, 0.25, D=0.2, center_y=0.25))
+    with pytest.raises(gpu.TTSHError) as e:
+        s.order_dumbbell(0, 0.0)
+    assert e.value.code == gpu.TTSH_EINVAL
 
 
 @pytest.mark.parametrize("g", ["rot", "refl", "transpose"])

@@ -415,6 +415,15 @@ def test_vortex_order2_limits():
     # the split decides which peaks compete: past the right vortex the right
     # side holds only noise, so Psi_2 is ~1 whatever the vortices' signs
     assert O.vortex_order2(w_opp, L, split_x=30.0) > 0.99
+    # the paper's regions (the disks of radius D/2 about the cavity centres
+    # -+D/2): a stronger spike outside both disks (near the far wall) does not
+    # compete there, while the half-planes pick it up
+    spike = np.zeros((N, N))
+    spike[N // 2 + 20, 16] = -5.0  # (x, y) = (-16, 20): in the left half, outside the left disk
+    assert (x[N // 2 + 20, 16], y[N // 2 + 20, 16]) == (-16.0, 20.0)
+    assert abs(O.vortex_order2(w_same + spike, L, D=32.0) - 1.0) < 1e-12
+    assert O.vortex_order2(w_same + spike, L) < 0.9
+    assert abs(O.vortex_order2(w_opp + spike, L, D=32.0) - 0.3 / 1.7) < 5e-3
 
 
 # ---- second-order exponential Runge-Kutta (ETD2RK, Cox and Matthews 2002) -----------------
