@@ -552,6 +552,73 @@ def vortex_count(v: np.ndarray, K: np.ndarray, kmax: float, vmin: float):
     return int(n[n > 0].sum()), int(-n[n < 0].sum())
 
 
+# ---------------------------------------------------------------------------
+# Lyapunov exponents (Benettin / Shimada-Nagashima method, circle section's
+# characterisation of the transition): perturbed copies of the state are
+# advanced with the same step and re-orthonormalised by a QR decomposition.
+# ---------------------------------------------------------------------------
+def compact_weights(N: int) -> np.ndarray:
+    """Weights of the compact half spectrum [2M+1][M+1] under which the
+    weighted sum of |c|^2 is the full-spectrum sum (1 on the m_x = 0 column,
+    which holds both signs of m_y; 2 on m_x > 0, whose mirror images -m are
+    not stored)."""
+    M = N // 4
+    w = np.full((2 * M + 1, M + 1), 2.0)
+    w[:, 0] = 1.0
+    return w
+
+
+def lyap_inner(a: np.ndarray, b: np.ndarray, N: int) -> float:
+    """<a, b> of two compact states [2][2M+1][M+1]: sum over components and
+    stored modes of w Re(conj(a) b) — the L2 inner product of the real fields
+    over the grid nodes (Parseval, unitary DFT)."""
+    return float(np.sum(compact_weights(N)[None] * (np.conj(a) * b).real))
+
+
+def lyapunov_qr(base: np.ndarray, perts, eps: float, N: int):
+    """One re-orthonormalisation.  The deviations d_i = (X_i - X_0)/eps of
+    the perturbed states from the base state are factored as D = Q R (Q
+    orthonormal under lyap_inner, diag R > 0); returns (log R_ii, the new
+    states X_0 + eps Q_i).  The factorisation is numpy's Householder QR in the
+    coordinates sqrt(w) (Re, Im) of every stored entry."""
+    sw = np.sqrt(compact_weights(N))[None]
+    cols = [np.concatenate([((X - base) / eps * sw).real.ravel(), ((X - base) / eps * sw).imag.ravel()])
+            for X in perts]
+    Q, R = np.linalg.qr(np.stack(cols, axis=1))
+    sign = np.sign(np.diag(R))
+    Q = Q * sign[None]
+    r = np.abs(np.diag(R))
+    n = base.size
+    out = []
+    for i in range(len(perts)):
+        q = (Q[:n, i] + 1j * Q[n:, i]).reshape(base.shape) / sw
+        out.append(base + eps * q)
+    return np.log(r), out
+
+
+def lyapunov_run(vhat0: np.ndarray, perts0, K: np.ndarray, p: Params, L: float, eps: float, tau: int,
+                 intervals: int):
+    """Benettin's method on full spectra: the base state and the perturbed
+    states are each advanced tau steps with velocity_step (or the chosen
+    scheme), then lyapunov_qr on their compact forms; returns the per-interval
+    log R_ii, shape [intervals][p] (the exponents are their time averages
+    divided by tau * dt).  The perturbed states start from perts0 and are
+    first orthonormalised about vhat0."""
+    N = vhat0.shape[-1]
+    X0 = to_compact(vhat0)
+    _, Xs = lyapunov_qr(X0, [to_compact(q) for q in perts0], eps, N)
+    vb = from_compact(X0, N)
+    vs = [from_compact(X, N) for X in Xs]
+    logs = []
+    for _ in range(intervals):
+        vb = run_velocity(vb, K, p, L, tau)
+        vs = [run_velocity(v, K, p, L, tau) for v in vs]
+        lr, Xs = lyapunov_qr(to_compact(vb), [to_compact(v) for v in vs], eps, N)
+        logs.append(lr)
+        vs = [from_compact(X, N) for X in Xs]
+    return np.array(logs)
+
+
 def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
     """||a - b||_2 / ||b||_2 over all entries, FP64 sums."""
     a = np.asarray(a, dtype=np.float64)

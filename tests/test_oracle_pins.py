@@ -542,3 +542,66 @@ def test_vortex_count_defect_on_a_node():
     assert vort[:, N // 2, N // 2].tolist() == [0.0, 0.0]
     assert O.vortex_count(vort, disk, 0.5, 1e-12) == (1, 0)
     assert O.vortex_count(np.stack([x, -y]), disk, 0.5, 1e-12) == (0, 1)
+
+
+# ---- Lyapunov exponents (Benettin's method with QR re-orthonormalisation) --------------------
+def test_lyap_inner_is_the_real_space_inner_product():
+    """The weighted compact inner product equals sum_x v_a . v_b over the grid
+    nodes of the two real fields (Parseval with the unitary DFT): a dropped
+    weight on the m_x > 0 columns or a conjugation slip fails it."""
+    N, L = 32, 20.0
+    a = O.project_field(W.uniform_field(1, N, 1.0), L)
+    b = O.project_field(W.uniform_field(2, N, 1.0), L)
+    va, vb = O.field(a), O.field(b)
+    ca, cb = O.to_compact(a), O.to_compact(b)
+    assert abs(O.lyap_inner(ca, cb, N) - float(np.sum(va * vb))) < 1e-12 * float(np.sum(va * va))
+    assert abs(O.lyap_inner(ca, ca, N) - float(np.sum(va * va))) < 1e-12 * float(np.sum(va * va))
+
+
+def test_lyapunov_qr_orthonormal_and_triangular():
+    """After lyapunov_qr the deviations (X_i - X_0)/eps are orthonormal under
+    the real-space inner product, and the original deviations equal
+    sum_j R_ji q_j with R upper triangular, exp(log R_ii) on its diagonal."""
+    N, L, eps = 32, 20.0, 1e-3
+    X0 = O.to_compact(O.project_field(W.uniform_field(3, N, 1.0), L))
+    D = [O.to_compact(O.project_field(W.uniform_field(10 + i, N, 1.0), L)) for i in range(4)]
+    D[2] = D[2] + 0.9 * D[0]  # not orthogonal to begin with
+    logs, Xs = O.lyapunov_qr(X0, [X0 + eps * d for d in D], eps, N)
+    q = [(X - X0) / eps for X in Xs]
+    for i in range(4):
+        for j in range(4):
+            assert abs(O.lyap_inner(q[i], q[j], N) - (i == j)) < 1e-10
+    for i in range(4):
+        r = [O.lyap_inner(q[j], D[i], N) for j in range(4)]
+        assert all(abs(r[j]) < 1e-8 * abs(r[i]) for j in range(i + 1, 4))  # triangular
+        assert abs(math.log(r[i]) - logs[i]) < 1e-10
+        rec = sum(r[j] * q[j] for j in range(i + 1))
+        assert np.max(np.abs(rec - D[i])) < 1e-9 * np.max(np.abs(D[i]))
+
+
+def test_lyapunov_linear_spectrum_closed_form():
+    """With the nonlinear, advection and wall terms off, perturbations evolve
+    by the exact multiplier exp(L(k) dt) per step, so the exponents are the
+    largest values of L(k) = -alpha - Gamma0 k^2 - Gamma2 k^4 over the state
+    space, each with its multiplicity: a shell of modes with one |m| gives
+    two real directions per pair +-m (divergence-free velocity), k = 0 gives
+    two (the mean flow).  Box L = 2 pi 1.2: shell |m| = 1 (k^2 = 1/1.44,
+    4 directions) is the most unstable, then k = 0 (L = -alpha = 1, 2
+    directions), then the shell |m|^2 = 2 (0.46)."""
+    N, Lbox = 16, 2 * math.pi * 1.2
+    p = dataclasses.replace(O.workload_params(dt=0.05), beta=0.0, lambda0=0.0, gamma_v=0.0, gamma_w=0.0)
+    lam = lambda k2: -p.alpha - p.gamma0 * k2 - p.gamma2 * k2 * k2
+    k1 = 1.0 / 1.44
+    want = [lam(k1)] * 4 + [lam(0.0)] * 2
+    assert lam(2 * k1) < lam(0.0) < lam(k1) and all(lam(m2 * k1) < lam(2 * k1) for m2 in (4, 5, 8, 9))
+    # base: the zero state (a fixed point; with growth rates > 0 any other base
+    # would grow by e^48 over the run and swamp eps-sized differences)
+    v0 = np.zeros((2, N, N), dtype=np.complex128)
+    perts = [O.project_field(W.uniform_field(20 + i, N, 1e-3), Lbox) for i in range(6)]
+    tau = 20
+    logs = O.lyapunov_run(v0, perts, np.zeros((N, N)), p, Lbox, 1e-6, tau, 60)
+    got = logs[-1] / (tau * p.dt)
+    assert np.max(np.abs(got - np.array(want))) < 1e-8, got
+    # the time average converges to the same values (start-up transient / T)
+    avg = logs.mean(axis=0) / (tau * p.dt)
+    assert np.max(np.abs(avg - np.array(want))) < 0.05
