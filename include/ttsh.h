@@ -173,6 +173,26 @@ int ttsh_order(ttsh_ctx* ctx, int inst, double cx, double cy, double* out);
  * D must be positive and finite (else EINVAL).  Synchronous.               */
 int ttsh_order_dumbbell(ttsh_ctx* ctx, int inst, double cx, double cy, double D, double* psi2);
 
+/* Lyapunov exponents by Benettin's method (circle section, exponents of the
+ * transition: perturbed copies of the state advanced with the same step and
+ * re-orthonormalised by a QR decomposition).  Instances pert[0..p-1] hold
+ * perturbed copies of instance base (same grid size, distinct, not base;
+ * 1 <= p <= 16).  With d_v = (X_v - X_base)/eps the deviations of their
+ * compact states, the call factors D = Q R by modified Gram-Schmidt in FP64
+ * (in the order v = 0..p-1) under the inner product of the real fields
+ * (sum over the grid nodes of v_a . v_b, i.e. the compact spectrum with
+ * weight 1 on m_x = 0 and 2 on m_x > 0), writes X_v = X_base + eps q_v
+ * (rounded to the stored precision; X_base unchanged) and returns
+ * log_r[v] = log R_vv (host, [p]).  Calling it every tau steps and averaging
+ * log_r / (tau dt) gives the p largest exponents.  eps is absolute, in the
+ * units of the state's Parseval norm; it must be positive and finite
+ * (EINVAL), and small enough for linear growth yet above the rounding of
+ * the stored precision (FP64 states are the intended use).  A deviation with
+ * nothing left after the projections gives ENONFINITE (the perturbed states
+ * are then unspecified).  Uses a scratch of p FP64 compact states, grown on
+ * demand.  Synchronous.                                                     */
+int ttsh_lyap_qr(ttsh_ctx* ctx, int base, const int* pert, int p, double eps, double* log_r);
+
 /* Vortex count of instance inst (the topological defects of the direction of
  * v, used to tell single vortices, pairs and disordered states apart): over
  * the grid cells whose four corner nodes all have K < kmax and |v| > vmin, the

@@ -453,6 +453,81 @@ __global__ void __launch_bounds__(1024) k_order_psi2(const C2<double>* __restric
   }
 }
 
+// ---- Lyapunov re-orthonormalisation -------------------------------------------
+// Benettin's method (circle section: exponents of the transition): the
+// deviations d_v = (X_v - X_0)/eps of p perturbed states from the base state
+// are orthonormalised in order by modified Gram-Schmidt under the real-space
+// inner product (Parseval: weight 1 on the m_x = 0 column, 2 on m_x > 0, the
+// padding position excluded); logs[v] = log |d_v - projections| (the diagonal
+// of R in D = Q R) and X_v = X_0 + eps q_v, rounded to the stored precision.
+// One workgroup; thread t owns the entries t, t + 1024, ... of every vector,
+// so that vector updates need no synchronisation, and every sum is reduced
+// in a fixed order (results do not vary between runs).
+constexpr int kMaxLyap = 16;
+struct LyapArgs {
+  void* st[kMaxLyap];
+};
+
+__device__ __forceinline__ double block_sum_1024(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    red[16] = t;
+  }
+  __syncthreads();
+  const double r = red[16];
+  __syncthreads();  // red is reused by the next sum
+  return r;
+}
+
+template <class S>
+__global__ void __launch_bounds__(1024) k_lyap_qr(const C2<S>* __restrict__ base, LyapArgs a, int p, int N,
+                                                  double eps, C2<double>* __restrict__ q,
+                                                  double* __restrict__ logs) {
+  __shared__ double red[17];
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  const int n = 2 * MP * SP;
+  for (int v = 0; v < p; ++v) {
+    C2<S>* X = (C2<S>*)a.st[v];
+    C2<double>* qv = q + (size_t)v * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int pos = (i % (MP * SP)) % SP;
+      const C2<double> x = cvt<double>(X[i]), b = cvt<double>(base[i]);
+      qv[i] = pos > 2 * M ? mk(0.0, 0.0) : mk((x.x - b.x) / eps, (x.y - b.y) / eps);
+    }
+    for (int u = 0; u < v; ++u) {
+      const C2<double>* qu = q + (size_t)u * n;
+      double part = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double w = (i % (MP * SP)) / SP == 0 ? 1.0 : 2.0;
+        part += w * (qu[i].x * qv[i].x + qu[i].y * qv[i].y);
+      }
+      const double r = block_sum_1024(part, red);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) qv[i] = mk(qv[i].x - r * qu[i].x, qv[i].y - r * qu[i].y);
+    }
+    double part = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double w = (i % (MP * SP)) / SP == 0 ? 1.0 : 2.0;
+      part += w * (qv[i].x * qv[i].x + qv[i].y * qv[i].y);
+    }
+    const double rr = sqrt(block_sum_1024(part, red));
+    const double inv = 1.0 / rr;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int pos = (i % (MP * SP)) % SP;
+      const C2<double> qi = mk(qv[i].x * inv, qv[i].y * inv);
+      qv[i] = qi;
+      if (pos <= 2 * M) {
+        const C2<double> b = cvt<double>(base[i]);
+        X[i] = cvt<S>(mk(b.x + eps * qi.x, b.y + eps * qi.y));
+      }
+    }
+    if (threadIdx.x == 0) logs[v] = log(rr);
+  }
+}
+
 // ---- FP64 norms on the compact state -----------------------------------------
 // out[0] = sum_x |v|^2 (Parseval, unitary), out[1..2] = <v_x>, <v_y>,
 // out[3] = max |k . v_hat|, out[4] = 1 if any entry is non-finite.

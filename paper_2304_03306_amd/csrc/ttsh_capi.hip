@@ -137,6 +137,8 @@ struct ttsh_ctx {
   size_t pb_cap = 0;                     // bytes of each
   double* pnorm = nullptr;               // [pnorm_cap][2]
   int pnorm_cap = 0;
+  void* lyq = nullptr;                   // Lyapunov vectors: kMaxLyap logs, then [p][state] FP64
+  size_t lyq_cap = 0;                    // bytes
   int graph_steps = 50;
   int bs = 0;       // workgroup size of the column pass in use
   int bs_row = 0;   // workgroup size of the row pass in use
@@ -416,7 +418,7 @@ void free_ctx(ttsh_ctx* c) {
   if (c->scr0) hipFree(c->scr0);
   if (c->scr1) hipFree(c->scr1);
   if (c->dnorm) hipFree(c->dnorm);
-  for (void* p : {c->pb0, c->pb1, (void*)c->pnorm})
+  for (void* p : {c->pb0, c->pb1, (void*)c->pnorm, c->lyq})
     if (p) hipFree(p);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
@@ -869,6 +871,52 @@ int ttsh_order_dumbbell(ttsh_ctx* c, int inst, double cx, double cy, double D, d
   if (!psi2) return fail(TTSH_EINVAL, "null output");
   if (!(D > 0.0) || !std::isfinite(D)) return fail(TTSH_EINVAL, "D must be positive and finite");
   return order_impl(c, inst, cx, cy, D, 1, psi2);
+}
+
+int ttsh_lyap_qr(ttsh_ctx* c, int base, const int* pert, int p, double eps, double* log_r) {
+  int rc = check_inst(c, base);
+  if (rc) return rc;
+  if (!pert || !log_r) return fail(TTSH_EINVAL, "null argument");
+  if (p < 1 || p > kMaxLyap) return fail(TTSH_EINVAL, "p must be 1..16");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(TTSH_EINVAL, "eps must be positive and finite");
+  auto [ci, jb] = c->loc[base];
+  SizeClass& k = c->cls[ci];
+  const size_t es = c->prec == 32 ? sizeof(C2<float>) : sizeof(C2<double>);
+  LyapArgs a{};
+  for (int v = 0; v < p; ++v) {
+    if ((rc = check_inst(c, pert[v]))) return rc;
+    if (pert[v] == base) return fail(TTSH_EINVAL, "a perturbed instance is the base instance");
+    for (int u = 0; u < v; ++u)
+      if (pert[u] == pert[v]) return fail(TTSH_EINVAL, "perturbed instances must be distinct");
+    if (c->loc[pert[v]].first != ci) return fail(TTSH_EINVAL, "perturbed instances must have the base's grid size");
+    a.st[v] = (char*)k.st + (size_t)c->loc[pert[v]].second * k.sSt() * es;
+  }
+  const size_t n = k.sSt();
+  const size_t bytes = sizeof(double) * kMaxLyap + (size_t)p * n * sizeof(C2<double>);
+  if (bytes > c->lyq_cap) {
+    if (c->lyq) hipFree(c->lyq);
+    c->lyq = nullptr;
+    c->lyq_cap = 0;
+    if (hipMalloc(&c->lyq, bytes) != hipSuccess) return fail(TTSH_ENOMEM, "Lyapunov vectors");
+    c->lyq_cap = bytes;
+  }
+  double* dlogs = (double*)c->lyq;
+  C2<double>* q = (C2<double>*)((char*)c->lyq + sizeof(double) * kMaxLyap);
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_lyap_qr<float>, dim3(1), dim3(1024), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), jb), a, p, k.N, eps, q, dlogs);
+  else
+    hipLaunchKernelGGL(k_lyap_qr<double>, dim3(1), dim3(1024), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), jb), a, p, k.N, eps, q, dlogs);
+  HIPCHK(hipGetLastError());
+  for (int v = 0; v < p; ++v)
+    if ((rc = refresh_x(c, pert[v]))) return rc;
+  HIPCHK(hipMemcpyAsync(log_r, dlogs, p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int v = 0; v < p; ++v)
+    if (!std::isfinite(log_r[v]))
+      return fail(TTSH_ENONFINITE, "perturbation " + std::to_string(v) + " has no component left (degenerate or non-finite)");
+  return TTSH_OK;
 }
 
 int ttsh_vortices(ttsh_ctx* c, int inst, double kmax, double vmin, int* out) {

@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_order": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_order_dumbbell": [vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_vortices": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
+            "ttsh_lyap_qr": [vp, i32, vp, i32, ctypes.c_double, dp],
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
             "ttsh_step": [vp, i64],
@@ -191,6 +192,16 @@ def ttsh_order_dumbbell(ctx, inst, D, center=(0.0, 0.0)):
     _check(lib().ttsh_order_dumbbell(ctx, int(inst), float(center[0]), float(center[1]), float(D),
                                      ctypes.cast(ctypes.pointer(out), ctypes.c_void_p)))
     return out.value
+
+def ttsh_lyap_qr(ctx, base, pert, eps):
+    """log R_vv of the re-orthonormalised deviations of instances pert from
+    base (see include/ttsh.h); the perturbed states are rewritten."""
+    pert = [int(x) for x in pert]
+    idx = (ctypes.c_int * max(1, len(pert)))(*pert)
+    out = (ctypes.c_double * max(1, len(pert)))()
+    _check(lib().ttsh_lyap_qr(ctx, int(base), ctypes.cast(idx, ctypes.c_void_p), len(pert), float(eps),
+                              ctypes.cast(out, ctypes.c_void_p)))
+    return np.array(out[: len(pert)], dtype=np.float64)
 
 def ttsh_vortices(ctx, inst, kmax=0.5, vmin=0.0):
     """(vortex centres, saddles) of instance inst, see include/ttsh.h."""
@@ -340,6 +351,9 @@ class Solver:
 
     def order_dumbbell(self, inst, D, center=(0.0, 0.0)):
         return ttsh_order_dumbbell(self.ctx, inst, D, center)
+
+    def lyap_qr(self, base, pert, eps):
+        return ttsh_lyap_qr(self.ctx, base, pert, eps)
 
     def vortices(self, inst, kmax=0.5, vmin=0.0):
         return ttsh_vortices(self.ctx, inst, kmax, vmin)
