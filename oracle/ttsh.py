@@ -552,6 +552,21 @@ def vortex_count(v: np.ndarray, K: np.ndarray, kmax: float, vmin: float):
     return int(n[n > 0].sum()), int(-n[n < 0].sum())
 
 
+def temporal_psd(w_series, times, freqs) -> np.ndarray:
+    """Temporal power spectral density of the vorticity (circle section,
+    eq. (PSD)): S(f) = (1/N^2) sum_x |sum_t w(x, t) e^{-2 pi i f t}|^2 over
+    the sampled times t (frequency f in cycles per unit time, Omega = 2 pi f).
+    w_series: sequence of real [N][N] vorticity fields, one per time."""
+    w = np.asarray(w_series, dtype=np.float64)
+    N = w.shape[-1]
+    t = np.asarray(times, dtype=np.float64)
+    out = np.zeros(len(freqs))
+    for j, f in enumerate(freqs):
+        A = np.tensordot(np.exp(-2j * np.pi * f * t), w, axes=(0, 0))
+        out[j] = float(np.sum(np.abs(A) ** 2)) / (N * N)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Lyapunov exponents (Benettin / Shimada-Nagashima method, circle section's
 # characterisation of the transition): perturbed copies of the state are

@@ -605,3 +605,27 @@ def test_lyapunov_linear_spectrum_closed_form():
     # the time average converges to the same values (start-up transient / T)
     avg = logs.mean(axis=0) / (tau * p.dt)
     assert np.max(np.abs(avg - np.array(want))) < 0.05
+
+
+# ---- temporal power spectral density of the vorticity --------------------------------------
+def test_temporal_psd_closed_forms():
+    """S(f) of eq. (PSD) for fields whose time sums are known: a pattern
+    cos(k.x - 2 pi f0 t) sampled over whole periods gives (T/2)^2 at f = +-f0
+    and 0 at the other multiples of 1/(T dt); a constant field c gives
+    (c T)^2 at f = 0; S is even in f for real fields."""
+    N, L, T, dt = 16, 10.0, 40, 0.5
+    x, y = O.node_coords(N, L)
+    f0 = 3 / (T * dt)  # three periods over the record
+    times = np.arange(T) * dt
+    k = 2 * np.pi / L * np.array([2.0, 1.0])
+    series = [np.cos(k[0] * x + k[1] * y - 2 * np.pi * f0 * t) for t in times]
+    freqs = np.array([j / (T * dt) for j in range(-5, 6)])
+    S = O.temporal_psd(series, times, freqs)
+    want = np.where(np.isclose(np.abs(freqs), f0), (T / 2) ** 2, 0.0)
+    assert np.max(np.abs(S - want)) < 1e-9 * T * T
+    S0 = O.temporal_psd([np.full((N, N), 0.7)] * T, times, [0.0, 1 / (T * dt)])
+    assert abs(S0[0] - (0.7 * T) ** 2) < 1e-9 and abs(S0[1]) < 1e-9
+    rng = np.random.default_rng(4)
+    noise = [rng.standard_normal((N, N)) for _ in range(T)]
+    fr = np.array([0.013, 0.21, 0.37])
+    assert np.allclose(O.temporal_psd(noise, times, fr), O.temporal_psd(noise, times, -fr), rtol=1e-12)
