@@ -193,6 +193,24 @@ int ttsh_order_dumbbell(ttsh_ctx* ctx, int inst, double cx, double cy, double D,
  * demand.  Synchronous.                                                     */
 int ttsh_lyap_qr(ttsh_ctx* ctx, int base, const int* pert, int p, double eps, double* log_r);
 
+/* Temporal power spectral density of the vorticity (circle section, eq.
+ * (PSD)): S(f) = (1/N^2) sum_x |sum_t omega(x, t) e^{-2 pi i f t}|^2, the sum
+ * over the sampled times t at which ttsh_psd_accumulate is called, f in cycles
+ * per unit time (Omega = 2 pi f).  The sums are kept in the spectral domain
+ * (Parseval over x): acc is a caller-owned device buffer of
+ * nf * 2 * (N/4 + 1) * (N/2 + 2) complex doubles (16 bytes each), zeroed by
+ * the caller before the first sample; layout [nf][2][N/4+1][N/2+2] (+f, -f
+ * sums per stored mode).  ttsh_psd_accumulate adds instance inst's
+ * vorticity spectrum at time t, weighted by e^{-2 pi i f t}, for the nf
+ * frequencies freqs (host array, 1 <= nf <= 4096, finite; EINVAL otherwise);
+ * asynchronous on the context's stream (acc must stay valid until the work
+ * completes; accumulations into one buffer are ordered by the stream).
+ * ttsh_psd_finish reads a buffer built for grid size N and writes S[nf]
+ * (host); synchronous.  Results do not depend on the order of the samples
+ * beyond rounding, and are reproducible run to run.                        */
+int ttsh_psd_accumulate(ttsh_ctx* ctx, int inst, int nf, const double* freqs, double t, void* acc);
+int ttsh_psd_finish(ttsh_ctx* ctx, int N, int nf, const void* acc, double* S);
+
 /* Vortex count of instance inst (the topological defects of the direction of
  * v, used to tell single vortices, pairs and disordered states apart): over
  * the grid cells whose four corner nodes all have K < kmax and |v| > vmin, the

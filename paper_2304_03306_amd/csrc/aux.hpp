@@ -528,6 +528,68 @@ __global__ void __launch_bounds__(1024) k_lyap_qr(const C2<S>* __restrict__ base
   }
 }
 
+// ---- temporal power spectral density of the vorticity ----------------------------
+// Circle section, eq. (PSD): S(f) = (1/N^2) sum_x |sum_t w(x, t) e^{-2 pi i f t}|^2.
+// By Parseval over x (unitary DFT) the sum over nodes is the sum over all modes
+// k of |W(k, f)|^2 with W(k, f) = sum_t w_hat(k, t) e^{-2 pi i f t}, so the
+// accumulators live on the compact spectrum.  Only m_x >= 0 is stored; the
+// mirror mode -k of a column m_x > 0 has W(-k, f) = conj(W(k, -f)), so each
+// stored mode keeps two accumulators, at +f and at -f (the second is not used
+// on the m_x = 0 column, which holds both signs of m_y itself).
+// acc: [nf][2][M+1][2M+2] complex FP64, index 0 of the second axis for +f.
+constexpr int kMaxPsdFreqs = 4096;
+
+template <class S>
+__global__ void __launch_bounds__(256) k_psd_acc(const C2<S>* __restrict__ st, int N, double dk,
+                                                 const double* __restrict__ freqs, int nf, double t,
+                                                 C2<double>* __restrict__ acc) {
+  __shared__ double pc[256], ps[256];
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2, nm = MP * SP;
+  const int f0 = blockIdx.y * 256;
+  const int nfb = min(256, nf - f0);
+  if ((int)threadIdx.x < nfb) {
+    double sn, cs;
+    sincospi(2.0 * freqs[f0 + threadIdx.x] * t, &sn, &cs);  // e^{-2 pi i f t} = cs - i sn
+    pc[threadIdx.x] = cs;
+    ps[threadIdx.x] = sn;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nm) return;
+  const int mx = i / SP, pos = i % SP;
+  if (pos > 2 * M) return;
+  const int my = pos <= M ? pos : pos - (2 * M + 1);
+  const C2<double> vx = cvt<double>(st[i]), vy = cvt<double>(st[nm + i]);
+  const double kx = dk * mx, ky = dk * my;
+  // w_hat = i (k_x v_y - k_y v_x)
+  const double dxr = kx * vy.x - ky * vx.x, dxi = kx * vy.y - ky * vx.y;
+  const double wr = -dxi, wi = dxr;
+  for (int q = 0; q < nfb; ++q) {
+    const double c = pc[q], sn = ps[q];
+    C2<double>* a = acc + ((size_t)(f0 + q) * 2) * nm + i;
+    // w_hat (c - i sn) at +f, w_hat (c + i sn) at -f
+    const C2<double> p0 = a[0], p1 = a[nm];
+    a[0] = mk(p0.x + wr * c + wi * sn, p0.y + wi * c - wr * sn);
+    a[nm] = mk(p1.x + wr * c - wi * sn, p1.y + wi * c + wr * sn);
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_psd_finish(const C2<double>* __restrict__ acc, int N,
+                                                     double* __restrict__ S) {
+  __shared__ double red[17];
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2, nm = MP * SP;
+  const C2<double>* a = acc + (size_t)blockIdx.x * 2 * nm;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < nm; i += blockDim.x) {
+    const int mx = i / SP, pos = i % SP;
+    if (pos > 2 * M) continue;
+    part += a[i].x * a[i].x + a[i].y * a[i].y;
+    if (mx > 0) part += a[nm + i].x * a[nm + i].x + a[nm + i].y * a[nm + i].y;
+  }
+  const double tot = block_sum_1024(part, red);
+  if (threadIdx.x == 0) S[blockIdx.x] = tot / ((double)N * (double)N);
+}
+
 // ---- FP64 norms on the compact state -----------------------------------------
 // out[0] = sum_x |v|^2 (Parseval, unitary), out[1..2] = <v_x>, <v_y>,
 // out[3] = max |k . v_hat|, out[4] = 1 if any entry is non-finite.

@@ -139,6 +139,8 @@ struct ttsh_ctx {
   int pnorm_cap = 0;
   void* lyq = nullptr;                   // Lyapunov vectors: kMaxLyap logs, then [p][state] FP64
   size_t lyq_cap = 0;                    // bytes
+  double* psdf = nullptr;                // PSD frequencies [kMaxPsdFreqs], then S [kMaxPsdFreqs]
+  std::vector<double> psd_freqs;         // the frequencies in psdf
   int graph_steps = 50;
   int bs = 0;       // workgroup size of the column pass in use
   int bs_row = 0;   // workgroup size of the row pass in use
@@ -418,7 +420,7 @@ void free_ctx(ttsh_ctx* c) {
   if (c->scr0) hipFree(c->scr0);
   if (c->scr1) hipFree(c->scr1);
   if (c->dnorm) hipFree(c->dnorm);
-  for (void* p : {c->pb0, c->pb1, (void*)c->pnorm, c->lyq})
+  for (void* p : {c->pb0, c->pb1, (void*)c->pnorm, c->lyq, (void*)c->psdf})
     if (p) hipFree(p);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
@@ -916,6 +918,54 @@ int ttsh_lyap_qr(ttsh_ctx* c, int base, const int* pert, int p, double eps, doub
   for (int v = 0; v < p; ++v)
     if (!std::isfinite(log_r[v]))
       return fail(TTSH_ENONFINITE, "perturbation " + std::to_string(v) + " has no component left (degenerate or non-finite)");
+  return TTSH_OK;
+}
+
+int ttsh_psd_accumulate(ttsh_ctx* c, int inst, int nf, const double* freqs, double t, void* acc) {
+  int rc = check_inst(c, inst);
+  if (rc) return rc;
+  if (!freqs || !acc) return fail(TTSH_EINVAL, "null argument");
+  if (nf < 1 || nf > kMaxPsdFreqs) return fail(TTSH_EINVAL, "nf must be 1..4096");
+  if (!std::isfinite(t)) return fail(TTSH_EINVAL, "t must be finite");
+  for (int j = 0; j < nf; ++j)
+    if (!std::isfinite(freqs[j])) return fail(TTSH_EINVAL, "frequencies must be finite");
+  if (!c->psdf && hipMalloc((void**)&c->psdf, sizeof(double) * 2 * kMaxPsdFreqs) != hipSuccess)
+    return fail(TTSH_ENOMEM, "PSD frequencies");
+  if (c->psd_freqs.size() != (size_t)nf || !std::equal(freqs, freqs + nf, c->psd_freqs.begin())) {
+    HIPCHK(hipStreamSynchronize(c->stream));  // earlier launches may still read psdf
+    HIPCHK(hipMemcpy(c->psdf, freqs, sizeof(double) * nf, hipMemcpyHostToDevice));
+    c->psd_freqs.assign(freqs, freqs + nf);
+  }
+  auto [ci, j] = c->loc[inst];
+  SizeClass& k = c->cls[ci];
+  const int N = k.N, M = N / 4;
+  const int nm = (M + 1) * (2 * M + 2);
+  const double dk = 2.0 * M_PI / c->L[inst];
+  const dim3 grid((nm + 255) / 256, (nf + 255) / 256);
+  if (c->prec == 32)
+    hipLaunchKernelGGL(k_psd_acc<float>, grid, dim3(256), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), N, dk, c->psdf, nf, t,
+                       (C2<double>*)acc);
+  else
+    hipLaunchKernelGGL(k_psd_acc<double>, grid, dim3(256), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), N, dk, c->psdf, nf, t,
+                       (C2<double>*)acc);
+  HIPCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+int ttsh_psd_finish(ttsh_ctx* c, int N, int nf, const void* acc, double* S) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (!acc || !S) return fail(TTSH_EINVAL, "null argument");
+  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
+  if (nf < 1 || nf > kMaxPsdFreqs) return fail(TTSH_EINVAL, "nf must be 1..4096");
+  if (!c->psdf && hipMalloc((void**)&c->psdf, sizeof(double) * 2 * kMaxPsdFreqs) != hipSuccess)
+    return fail(TTSH_ENOMEM, "PSD frequencies");
+  double* dS = c->psdf + kMaxPsdFreqs;
+  hipLaunchKernelGGL(k_psd_finish, dim3(nf), dim3(1024), 0, c->stream, (const C2<double>*)acc, N, dS);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(S, dS, sizeof(double) * nf, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return TTSH_OK;
 }
 

@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
             "ttsh_order_dumbbell": [vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_vortices": [vp, i32, ctypes.c_double, ctypes.c_double, dp],
             "ttsh_lyap_qr": [vp, i32, vp, i32, ctypes.c_double, dp],
+            "ttsh_psd_accumulate": [vp, i32, i32, dp, ctypes.c_double, vp],
+            "ttsh_psd_finish": [vp, i32, i32, vp, dp],
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
             "ttsh_step": [vp, i64],
@@ -202,6 +204,23 @@ def ttsh_lyap_qr(ctx, base, pert, eps):
     _check(lib().ttsh_lyap_qr(ctx, int(base), ctypes.cast(idx, ctypes.c_void_p), len(pert), float(eps),
                               ctypes.cast(out, ctypes.c_void_p)))
     return np.array(out[: len(pert)], dtype=np.float64)
+
+def psd_buffer_len(N, nf):
+    """Float64 entries of a PSD accumulator for grid size N and nf
+    frequencies (see include/ttsh.h: nf * 2 * (N/4+1) * (N/2+2) complex)."""
+    return 2 * nf * 2 * (N // 4 + 1) * (N // 2 + 2)
+
+
+def ttsh_psd_accumulate(ctx, inst, freqs, t, acc):
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    _check(lib().ttsh_psd_accumulate(ctx, int(inst), len(f), f.ctypes.data_as(ctypes.c_void_p), float(t),
+                                     _dev_addr(acc)))
+
+
+def ttsh_psd_finish(ctx, N, nf, acc):
+    out = np.zeros(int(nf), dtype=np.float64)
+    _check(lib().ttsh_psd_finish(ctx, int(N), int(nf), _dev_addr(acc), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
 
 def ttsh_vortices(ctx, inst, kmax=0.5, vmin=0.0):
     """(vortex centres, saddles) of instance inst, see include/ttsh.h."""
@@ -354,6 +373,12 @@ class Solver:
 
     def lyap_qr(self, base, pert, eps):
         return ttsh_lyap_qr(self.ctx, base, pert, eps)
+
+    def psd_accumulate(self, inst, freqs, t, acc):
+        ttsh_psd_accumulate(self.ctx, inst, freqs, t, acc)
+
+    def psd_finish(self, N, nf, acc):
+        return ttsh_psd_finish(self.ctx, N, nf, acc)
 
     def vortices(self, inst, kmax=0.5, vmin=0.0):
         return ttsh_vortices(self.ctx, inst, kmax, vmin)
