@@ -397,8 +397,12 @@ __global__ void k_lift8(const bf16* __restrict__ x, const bf16* __restrict__ Pw,
 // u = h Q1 + Q1_b.  Computed transposed on the matrix cores (u^T = Q1^T h^T,
 // then y^T = Q2^T a^T) because the result layout of the first product (lane =
 // point column, 4 consecutive hidden rows) is exactly the operand layout the
-// second one needs.  A wavefront handles 16 points per iteration.
-template <int C, int HID>
+// second one needs.  A wavefront handles G groups of 16 points per iteration.
+#ifndef FNO_PROJ_GROUPS
+#define FNO_PROJ_GROUPS 4
+#endif
+constexpr int kProjGroups = FNO_PROJ_GROUPS;  // groups of 16 points per wavefront and iteration
+template <int C, int HID, int G>
 __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, const bf16* __restrict__ Q1,
                                                     const float* __restrict__ b1, const bf16* __restrict__ Q2,
                                                     const float* __restrict__ b2, int cout, float* __restrict__ y,
@@ -421,9 +425,8 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
       qb[hb][e] = l16 < cout ? (short)Q2[(16 * hb + q4 + e) * cout + l16] : (short)0;
     }
   }
-  // two independent groups of 16 points per iteration, for instruction-level
+  // G independent groups of 16 points per iteration, for instruction-level
   // parallelism between their MFMA and GELU chains
-  constexpr int G = 2;
   for (long long t = wave * G; t * 16 < npts; t += nwave * G) {
     long long p[G];
     bool ok[G];
@@ -1822,8 +1825,8 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
   if (proj_fused) {
     // h_L is [P][C] (inside h[L]), y and skip were range-checked above
     const long long tiles = (P + 15) / 16;
-    const long long blocks = std::min<long long>((tiles + 7) / 8, 8192);  // 4 waves x 2 groups
-    hipLaunchKernelGGL((k_proj_fused<32, 128>), dim3((unsigned)blocks), dim3(256), 0, c->s, c->h[c->L], c->Q1,
+    const long long blocks = std::min<long long>((tiles + 4 * kProjGroups - 1) / (4 * kProjGroups), 8192);
+    hipLaunchKernelGGL((k_proj_fused<32, 128, kProjGroups>), dim3((unsigned)blocks), dim3(256), 0, c->s, c->h[c->L], c->Q1,
                        c->theta + c->oQ1b, c->Q2, c->theta + c->oQ2b, c->cout, y, (long long)ys,
                        residual ? x : nullptr, (long long)c->cin, P);
     FCHK(hipGetLastError());
