@@ -101,3 +101,40 @@ def test_circle_driver_short_run(gpu):
     for r in rep["radii"]:
         assert np.isfinite(r["psi_mean"]) and np.isfinite(r["energy_mean"]) and r["energy_mean"] >= 0
     assert np.array(rep["psi_series"]).shape == (10, 2)
+    # the vorticity PSD on the record's frequency grid, non-negative
+    assert len(rep["psd_freqs"]) >= 1
+    for r in rep["radii"]:
+        assert len(r["vorticity_psd"]) == len(rep["psd_freqs"]) and min(r["vorticity_psd"]) >= 0
+
+
+def test_dumbbell_driver_short_run(gpu):
+    """The dumbbell driver on one radius and two distances: Psi_2 in [0, 1]
+    for every cell, one row per distance."""
+    from paper_2304_03306_amd import dumbbell
+    print("[case] dumbbell driver 256^2 x 2 distances", flush=True)
+    rep = dumbbell.run([3.14], [1.2, 1.8], seeds=1, N=256, L=20.48, steps=3000, transient=1000, every=500)
+    rows = rep["radii"][0]["runs"]
+    assert [r["D_over_R"] for r in rows] == [1.2, 1.8]
+    for r in rows:
+        assert 0.0 <= r["psi2_mean"] <= 1.0
+
+
+def test_hysteresis_driver_short_run(gpu):
+    """The ramp driver on three radii for three short stages: both ramps
+    recorded at every stage, Psi finite."""
+    from paper_2304_03306_amd import hysteresis
+    print("[case] hysteresis driver 256^2 x 3 radii", flush=True)
+    rep = hysteresis.run([5.2, 5.3, 5.4], steps=1000, every=100, N=256, L=20.48)
+    assert len(rep["record"]) == 3 and len(rep["radii"]) == 3
+    for r in rep["radii"]:
+        assert np.isfinite(r["up_psi"]) and np.isfinite(r["down_psi"])
+
+
+def test_lyapunov_driver_short_run(gpu):
+    """The Lyapunov driver on one radius, two copies, a few intervals: two
+    finite exponents."""
+    from paper_2304_03306_amd import lyapunov
+    print("[case] lyapunov driver 256^2 x 1 radius", flush=True)
+    rep = lyapunov.run([5.2], p=2, N=256, L=20.48, transient=500, tau=50, intervals=10)
+    ex = rep["radii"][0]["exponents"]
+    assert len(ex) == 2 and all(np.isfinite(ex))
