@@ -5,7 +5,10 @@ computation and mask-generation subsections), Appendix C (Algorithm 1, the
 integration scheme, and the text after it: unitary DFT, the exponential
 multiplier, the k = 0 rule of eq. (7), the 1/2-rule cutoff, the Hermitian
 correction, the stream function) and Appendix D (Algorithm 2, the automatic
-mask generator).
+mask generator).  The diagnostics follow the results sections: the order
+parameters Psi (circle) and Psi_2 (dumbbell, its regions of radius D/2), the
+temporal power spectral density of the vorticity (eq. (PSD)), a vortex count,
+and Lyapunov exponents by perturbed copies and QR re-orthonormalisation.
 
 General coefficient form.  The paper writes the model in the dimensionless
 (a, b, lambda, gamma_v, gamma_w) convention, eq. (2)/(4).  The workloads used
