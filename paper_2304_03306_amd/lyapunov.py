@@ -9,7 +9,9 @@ advanced by the same batched step; every tau steps ttsh_lyap_qr
 re-orthonormalises each radius's copies about its base on the device and
 returns log R_vv.  The exponents are the averages of log R_vv / (tau dt)
 over the measuring window; their spread over four consecutive sub-windows
-is reported as an error estimate.
+is reported as an error estimate.  With --start-from, every radius starts from
+the state settled at a larger radius (the oscillating branch), which inside
+the hysteresis window follows the downward branch instead of the vortex.
 
 The grid spacing is that of the circle runs (0.04) in a box of side 20.48, so
 the radii at which the exponents cross zero can differ from the paper's.
@@ -28,10 +30,25 @@ from . import ttsh as T
 from . import workloads as W
 
 
+def _settled_state(R, N, L, params, steps, seed):
+    """Compact FP64 state after `steps` steps from a random start at radius R
+    (the starting point of the downward branch)."""
+    s = T.Solver([N], [L], params, T.TTSH_FP64)
+    try:
+        s.mask_from_binary(0, W.binary_outside(N, L, [(0.0, 0.0)], [R]))
+        s.set_field(0, W.uniform_field(seed, N, 0.01))
+        s.step(steps)
+        s.sync()
+        return s.state(0)
+    finally:
+        s.close()
+
+
 def run(radii, p=4, N=512, L=20.48, transient=50_000, tau=100, intervals=1000, rel_eps=1e-6, seed=3,
-        log=None, dt: float = 0.01) -> dict:
+        log=None, dt: float = 0.01, start_from: float = 0.0) -> dict:
     params = dataclasses.replace(W.paper_coefficients(dt=dt))
     nr = len(radii)
+    start = _settled_state(start_from, N, L, params, transient, seed) if start_from > 0 else None
     n = nr * (1 + p)
     s = T.Solver([N] * n, [L] * n, params, T.TTSH_FP64)
     base = [r * (1 + p) for r in range(nr)]
@@ -41,7 +58,10 @@ def run(radii, p=4, N=512, L=20.48, transient=50_000, tau=100, intervals=1000, r
         for r, R in enumerate(radii):
             for q in [base[r]] + pert[r]:
                 s.mask_from_binary(q, W.binary_outside(N, L, [(0.0, 0.0)], [R]))
-            s.set_field(base[r], W.uniform_field(seed + r, N, 0.01))
+            if start is None:
+                s.set_field(base[r], W.uniform_field(seed + r, N, 0.01))
+            else:  # every base continues the state settled at the larger radius
+                s.set_state(base[r], start)
         s.tune(tau)
         t0 = time.time()
         s.step(transient)  # the copies run alongside; they are replaced below
@@ -75,7 +95,7 @@ def run(radii, p=4, N=512, L=20.48, transient=50_000, tau=100, intervals=1000, r
                         "psi_mean": float(psi[intervals // 5:, r].mean()),
                         "psi_std": float(psi[intervals // 5:, r].std())})
         return {"N": N, "L": L, "dt": dt, "p": p, "tau": tau, "intervals": intervals, "transient": transient,
-                "rel_eps": rel_eps, "precision": "FP64",
+                "rel_eps": rel_eps, "precision": "FP64", "start_from": start_from or None,
                 "coefficients": "paper preset (a, b, lambda, gamma_v, gamma_w) = (0.5, 1.6, 9, 40, 4)",
                 "mask": "Algorithm 2 from the binary outside-the-circle field",
                 "seconds": secs, "radii": out}
@@ -95,10 +115,12 @@ def main(argv=None):
     ap.add_argument("--tau", type=int, default=100)
     ap.add_argument("--intervals", type=int, default=1000)
     ap.add_argument("--rel-eps", type=float, default=1e-6)
+    ap.add_argument("--start-from", type=float, default=0.0,
+                    help="start every radius from the state settled at this radius (0: random starts)")
     ap.add_argument("--report", default="lyapunov_report.json")
     a = ap.parse_args(argv)
     rep = run(a.radii, a.p, a.N, a.L, a.transient, a.tau, a.intervals, a.rel_eps,
-              log=lambda m: print(f"[lyapunov] {m}", flush=True))
+              log=lambda m: print(f"[lyapunov] {m}", flush=True), start_from=a.start_from)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     print(f"[lyapunov] {len(a.radii) * (1 + a.p)} instances of {a.N}^2 (FP64), "
