@@ -276,11 +276,19 @@ __global__ void k_resample(const C2<S>* __restrict__ src, int Ns, C2<double>* __
 // ---- order parameters on the real-space fields ------------------------------
 // Vortex order parameter about (cx, cy) of the velocity in Z (real part v_x,
 // imaginary part v_y, node (i, j) at x = (j - N/2) dx, y = (i - N/2) dx):
-// sums of |e_theta . v| and |v| in FP64 in a fixed order (one workgroup).
+// sums of |e_theta . v| and |v| in FP64 in a fixed order.
+//
+// The reductions over the N^2 nodes here run in order_blocks(N) workgroups of
+// 1024 threads, each writing one partial result; a one-thread kernel combines
+// the partials in workgroup order, so that results do not vary between runs.
+inline int order_blocks(int N) {
+  const int b = N * N / 4096;
+  return b < 1 ? 1 : (b > 256 ? 256 : b);  // at most kOrderMaxBlocks
+}
 __global__ void __launch_bounds__(1024) k_order_psi(const C2<double>* __restrict__ Z, int N, double dx, double cx,
-                                                    double cy, double* __restrict__ out) {
+                                                    double cy, double* __restrict__ part) {
   double num = 0.0, den = 0.0;
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x) {
     const double x = ((i % N) - N / 2) * dx - cx, y = ((i / N) - N / 2) * dx - cy;
     const double r = sqrt(x * x + y * y);
     const C2<double> v = Z[i];
@@ -301,9 +309,27 @@ __global__ void __launch_bounds__(1024) k_order_psi(const C2<double>* __restrict
       a += red[w][0];
       b += red[w][1];
     }
-    const double two_pi = 2.0 / M_PI;
-    out[0] = (a / b - two_pi) / (1.0 - two_pi);
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
   }
+}
+// The combining kernels run one workgroup of 256 threads: the partials
+// (at most 256 per quantity) are staged in LDS in parallel, then one thread
+// takes them in workgroup order.
+constexpr int kOrderMaxBlocks = 256;
+__global__ void __launch_bounds__(256) k_order_psi_final(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out) {
+  __shared__ double ps[2 * kOrderMaxBlocks];
+  for (int q = threadIdx.x; q < 2 * nb; q += blockDim.x) ps[q] = part[q];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < nb; ++q) {
+    a += ps[2 * q];
+    b += ps[2 * q + 1];
+  }
+  const double two_pi = 2.0 / M_PI;
+  out[0] = (a / b - two_pi) / (1.0 - two_pi);
 }
 
 // Topological defects of the direction field of v = (Re Z, Im Z).  A node is
@@ -316,7 +342,8 @@ __global__ void __launch_bounds__(1024) k_order_psi(const C2<double>* __restrict
 // tests, a step to the next or previous quadrant is +-1, to the opposite one
 // +-2 with the sign of the cross product of the two vectors; the sum around
 // the loop is 4n.  out[0] = sum of n > 0 (vortex centres), out[1] = sum of |n|
-// over n < 0 (saddles).  One workgroup; integer sums, independent of order.
+// over n < 0 (saddles).  Integer sums (independent of order), one partial per
+// workgroup combined by k_vortex_final.
 __device__ __forceinline__ int quadrant(double x, double y) {
   if (x > 0.0 && y >= 0.0) return 0;
   if (x <= 0.0 && y > 0.0) return 1;
@@ -338,13 +365,13 @@ __device__ __forceinline__ int winding_quarters(const C2<double> (&w)[P]) {
 }
 template <class T>
 __global__ void __launch_bounds__(1024) k_vortex_count(const C2<double>* __restrict__ Z, const T* __restrict__ K,
-                                                       int N, double kmax, double vmin, int* __restrict__ out) {
+                                                       int N, double kmax, double vmin, int* __restrict__ part) {
   int pos = 0, neg = 0;
   const double v2 = vmin * vmin;
   auto inside = [&](int id) { return (double)K[id] < kmax; };
   auto fast = [&](const C2<double>& z) { return z.x * z.x + z.y * z.y > v2 && (z.x != 0.0 || z.y != 0.0); };
   const int m = N - 1;  // N is a power of two: (i + d) & m wraps
-  for (int c = threadIdx.x; c < N * N; c += blockDim.x) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N * N; c += gridDim.x * blockDim.x) {
     const int i = c / N, j = c % N;
     {  // the cell with lower-left corner (i, j)
       const int id[4] = {i * N + j, i * N + ((j + 1) & m), ((i + 1) & m) * N + ((j + 1) & m), ((i + 1) & m) * N + j};
@@ -394,9 +421,22 @@ __global__ void __launch_bounds__(1024) k_vortex_count(const C2<double>* __restr
       a += red[w][0];
       b += red[w][1];
     }
-    out[0] = a;
-    out[1] = b;
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
   }
+}
+__global__ void __launch_bounds__(256) k_vortex_final(const int* __restrict__ part, int nb, int* __restrict__ out) {
+  __shared__ int ps[2 * kOrderMaxBlocks];
+  for (int q = threadIdx.x; q < 2 * nb; q += blockDim.x) ps[q] = part[q];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int a = 0, b = 0;
+  for (int q = 0; q < nb; ++q) {
+    a += ps[2 * q];
+    b += ps[2 * q + 1];
+  }
+  out[0] = a;
+  out[1] = b;
 }
 
 // Two-chamber order parameter from the vorticity in the real part of Z: the
@@ -408,12 +448,12 @@ __global__ void __launch_bounds__(1024) k_vortex_count(const C2<double>* __restr
 // multiply-add), so that a node on a disk's rim falls on the same side as in
 // a plain evaluation of the same expression.
 __global__ void __launch_bounds__(1024) k_order_psi2(const C2<double>* __restrict__ Z, int N, double dx, double cx,
-                                                     double cy, double D, double* __restrict__ out) {
+                                                     double cy, double D, double* __restrict__ part) {
   const double r2 = __dmul_rn(0.5 * D, 0.5 * D);
   const double cl = __dsub_rn(cx, 0.5 * D), cr = __dadd_rn(cx, 0.5 * D);
   double best[2] = {-1.0, -1.0};
   int at[2] = {0, 0};
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N * N; i += gridDim.x * blockDim.x) {
     const double x = __dmul_rn((double)((i % N) - N / 2), dx);
     const int side = x < cx ? 0 : 1;
     if (D > 0.0) {
@@ -447,7 +487,39 @@ __global__ void __launch_bounds__(1024) k_order_psi2(const C2<double>* __restric
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // (best |w|, its node) per side; node indices < 2^53 are exact
+    part[4 * blockIdx.x] = bv[0][0];
+    part[4 * blockIdx.x + 1] = (double)bi[0][0];
+    part[4 * blockIdx.x + 2] = bv[1][0];
+    part[4 * blockIdx.x + 3] = (double)bi[1][0];
+  }
+}
+// larger |w| wins, equal values go to the lower node: the same choice in any
+// order, so the partials are combined by a tree in LDS
+__global__ void __launch_bounds__(256) k_order_psi2_final(const C2<double>* __restrict__ Z,
+                                                          const double* __restrict__ part, int nb,
+                                                          double* __restrict__ out) {
+  __shared__ double bv[2][kOrderMaxBlocks];
+  __shared__ long long bi[2][kOrderMaxBlocks];
+  const int t = threadIdx.x;
+  for (int sd = 0; sd < 2; ++sd) {
+    bv[sd][t] = t < nb ? part[4 * t + 2 * sd] : -1.0;
+    bi[sd][t] = t < nb ? (long long)part[4 * t + 2 * sd + 1] : 0;
+  }
+  __syncthreads();
+  for (int o = kOrderMaxBlocks / 2; o > 0; o >>= 1) {
+    if (t < o)
+      for (int sd = 0; sd < 2; ++sd) {
+        const double v = bv[sd][t + o];
+        const long long i = bi[sd][t + o];
+        if (v > bv[sd][t] || (v == bv[sd][t] && v >= 0.0 && i < bi[sd][t])) {
+          bv[sd][t] = v;
+          bi[sd][t] = i;
+        }
+      }
+    __syncthreads();
+  }
+  if (t == 0) {
     const double wl = Z[bi[0][0]].x, wr = Z[bi[1][0]].x;
     out[1] = (bv[0][0] < 0.0 || bv[1][0] < 0.0) ? __builtin_nan("") : fabs(wl + wr) / (fabs(wl) + fabs(wr));
   }

@@ -846,12 +846,19 @@ static int order_impl(ttsh_ctx* c, int inst, double cx, double cy, double D, int
                          at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), (C2<double>*)c->scr0, N, dk, what);
     HIPCHK(hipGetLastError());
     HIPCHK(size_ops(N)->fft2(c->scr0, 1, +1, 1, c->tw64[N], c->stream));
-    if (what == 0)
-      hipLaunchKernelGGL(k_order_psi, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx, cy,
-                         c->dnorm);
-    else
-      hipLaunchKernelGGL(k_order_psi2, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx,
-                         cy, D, c->dnorm);
+    // partials in scr1 (free here; at least 64^2 complex doubles, 4 per workgroup needed)
+    const int nb = order_blocks(N);
+    double* part = (double*)c->scr1;
+    if (what == 0) {
+      hipLaunchKernelGGL(k_order_psi, dim3(nb), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx, cy,
+                         part);
+      hipLaunchKernelGGL(k_order_psi_final, dim3(1), dim3(256), 0, c->stream, (const double*)part, nb, c->dnorm);
+    } else {
+      hipLaunchKernelGGL(k_order_psi2, dim3(nb), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0, N, dx, cx,
+                         cy, D, part);
+      hipLaunchKernelGGL(k_order_psi2_final, dim3(1), dim3(256), 0, c->stream, (const C2<double>*)c->scr0,
+                         (const double*)part, nb, c->dnorm);
+    }
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipMemcpyAsync(out, c->dnorm + from_what, (2 - from_what) * sizeof(double), hipMemcpyDeviceToHost,
@@ -987,12 +994,15 @@ int ttsh_vortices(ttsh_ctx* c, int inst, double kmax, double vmin, int* out) {
   HIPCHK(hipGetLastError());
   HIPCHK(size_ops(N)->fft2(c->scr0, 1, +1, 1, c->tw64[N], c->stream));
   int* dcount = reinterpret_cast<int*>(c->dnorm);  // [2], inside the norms scratch
+  const int nb = order_blocks(N);
+  int* part = (int*)c->scr1;  // per-workgroup partials (scr1 is free here)
   if (c->prec == 64)
-    hipLaunchKernelGGL(k_vortex_count<double>, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0,
-                       at<const double>(k.K, k.sK(), sizeof(double), j), N, kmax, vmin, dcount);
+    hipLaunchKernelGGL(k_vortex_count<double>, dim3(nb), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0,
+                       at<const double>(k.K, k.sK(), sizeof(double), j), N, kmax, vmin, part);
   else
-    hipLaunchKernelGGL(k_vortex_count<float>, dim3(1), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0,
-                       at<const float>(k.K, k.sK(), sizeof(float), j), N, kmax, vmin, dcount);
+    hipLaunchKernelGGL(k_vortex_count<float>, dim3(nb), dim3(1024), 0, c->stream, (const C2<double>*)c->scr0,
+                       at<const float>(k.K, k.sK(), sizeof(float), j), N, kmax, vmin, part);
+  hipLaunchKernelGGL(k_vortex_final, dim3(1), dim3(256), 0, c->stream, (const int*)part, nb, dcount);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(out, dcount, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
