@@ -32,13 +32,14 @@ def _perturbed_context(gpu, prec, N=64, L=32.0, p=4, steps=40, amp=1e-3):
     return s, par
 
 
-@pytest.mark.parametrize("prec", [64, 32])
-def test_lyap_qr_matches_oracle(gpu, prec):
+@pytest.mark.parametrize("prec,N", [(64, 64), (32, 64), (64, 512)])
+def test_lyap_qr_matches_oracle(gpu, prec, N):
     """log R_vv and the rewritten states equal the oracle's Householder QR
     of the same deviations; the re-orthonormalised copies then step like any
-    other state (the mixed-domain arrays are refreshed)."""
-    say("lyap_qr vs oracle", prec)
-    N, L, p = 64, 32.0, 4
+    other state (the mixed-domain arrays are refreshed).  512^2 is the size
+    the Lyapunov runs use."""
+    say("lyap_qr vs oracle", prec, N)
+    L, p = N / 2.0, 4
     s, par = _perturbed_context(gpu, prec, N, L, p)
     try:
         X0 = s.state(0)

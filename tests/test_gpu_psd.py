@@ -16,18 +16,20 @@ def say(*a):
 
 @pytest.mark.parametrize("prec", [64, 32])
 def test_psd_matches_oracle(gpu, prec):
-    """Two instances (a 64^2 circle, a 128^2 dumbbell) sampled 16 times, 25
-    steps apart: S(f) at frequencies on and off the record's grid, negative
-    ones and f = 0 equals the oracle's sum over nodes of the same vorticity
-    fields (read back from the states the library sampled)."""
+    """Three instances (a 64^2 circle, a 128^2 dumbbell, a 512^2 circle)
+    sampled 16 times, 25 steps apart: S(f) at frequencies on and off the
+    record's grid, negative ones and f = 0 equals the oracle's sum over nodes
+    of the same vorticity fields (read back from the states the library
+    sampled)."""
     import torch
     say("psd vs oracle", prec)
-    Ns, Ls = [64, 128], [32.0, 64.0]
+    Ns, Ls = [64, 128, 512], [32.0, 64.0, 256.0]
     par = O.workload_params()
     s = gpu.Solver(Ns, Ls, par, prec)
     try:
         s.mask_tanh(0, [(0.0, 0.0)], [10.0], 0.5)
         s.mask_tanh(1, [(-10.0, 0.0), (10.0, 0.0)], [12.0, 12.0], 0.5)
+        s.mask_tanh(2, [(0.0, 0.0)], [60.0], 0.5)
         for q, N in enumerate(Ns):
             s.set_field(q, W.uniform_field(30 + q, N, 0.1, prec))
         s.step(100)
@@ -35,7 +37,7 @@ def test_psd_matches_oracle(gpu, prec):
         dts = every * par.dt
         freqs = np.array([0.0, 1 / (T * dts), -1 / (T * dts), 0.37, 1.3, -0.9, 2.0, 0.05])
         accs = [torch.zeros(gpu.psd_buffer_len(N, len(freqs)), dtype=torch.float64, device="cuda") for N in Ns]
-        series = [[], []]
+        series = [[] for _ in Ns]
         times = []
         for n in range(T):
             t = n * dts
