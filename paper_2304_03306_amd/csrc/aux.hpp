@@ -532,13 +532,7 @@ __global__ void __launch_bounds__(256) k_order_psi2_final(const C2<double>* __re
 // inner product (Parseval: weight 1 on the m_x = 0 column, 2 on m_x > 0, the
 // padding position excluded); logs[v] = log |d_v - projections| (the diagonal
 // of R in D = Q R) and X_v = X_0 + eps q_v, rounded to the stored precision.
-// One workgroup; thread t owns the entries t, t + 1024, ... of every vector,
-// so that vector updates need no synchronisation, and every sum is reduced
-// in a fixed order (results do not vary between runs).
-constexpr int kMaxLyap = 16;
-struct LyapArgs {
-  void* st[kMaxLyap];
-};
+constexpr int kMaxLyap = 16;  // perturbed copies per call
 
 __device__ __forceinline__ double block_sum_1024(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -555,49 +549,88 @@ __device__ __forceinline__ double block_sum_1024(double v, double* red) {
   return r;
 }
 
+// The passes run over many workgroups of 1024 threads (thread g owns entry g
+// of every vector, so updates need no synchronisation); each pass ends with a
+// per-workgroup partial of the next inner product, and the next pass's
+// workgroups each add all the partials in workgroup order, so every
+// workgroup uses the same coefficient and results do not vary between runs.
+// Launches per perturbed state v: one k_lyap_init, v times k_lyap_axpy, one
+// k_lyap_scale.
+__device__ __forceinline__ double lyap_weight(int i, int MPSP, int SP, int M, bool& pad) {
+  const int r = i % MPSP;
+  pad = r % SP > 2 * M;
+  return r / SP == 0 ? 1.0 : 2.0;
+}
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int nb) {
+  double t = 0.0;
+  for (int q = 0; q < nb; ++q) t += part[q];
+  return t;
+}
+
+// q_v = (X_v - X_0)/eps; partial of <qd, q_v> (qd = null: of <q_v, q_v>)
 template <class S>
-__global__ void __launch_bounds__(1024) k_lyap_qr(const C2<S>* __restrict__ base, LyapArgs a, int p, int N,
-                                                  double eps, C2<double>* __restrict__ q,
-                                                  double* __restrict__ logs) {
+__global__ void __launch_bounds__(1024) k_lyap_init(const C2<S>* __restrict__ base, const C2<S>* __restrict__ X,
+                                                    int N, double eps, C2<double>* __restrict__ qv,
+                                                    const C2<double>* __restrict__ qd, double* __restrict__ part) {
   __shared__ double red[17];
-  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
-  const int n = 2 * MP * SP;
-  for (int v = 0; v < p; ++v) {
-    C2<S>* X = (C2<S>*)a.st[v];
-    C2<double>* qv = q + (size_t)v * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int pos = (i % (MP * SP)) % SP;
-      const C2<double> x = cvt<double>(X[i]), b = cvt<double>(base[i]);
-      qv[i] = pos > 2 * M ? mk(0.0, 0.0) : mk((x.x - b.x) / eps, (x.y - b.y) / eps);
-    }
-    for (int u = 0; u < v; ++u) {
-      const C2<double>* qu = q + (size_t)u * n;
-      double part = 0.0;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double w = (i % (MP * SP)) / SP == 0 ? 1.0 : 2.0;
-        part += w * (qu[i].x * qv[i].x + qu[i].y * qv[i].y);
-      }
-      const double r = block_sum_1024(part, red);
-      for (int i = threadIdx.x; i < n; i += blockDim.x) qv[i] = mk(qv[i].x - r * qu[i].x, qv[i].y - r * qu[i].y);
-    }
-    double part = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double w = (i % (MP * SP)) / SP == 0 ? 1.0 : 2.0;
-      part += w * (qv[i].x * qv[i].x + qv[i].y * qv[i].y);
-    }
-    const double rr = sqrt(block_sum_1024(part, red));
-    const double inv = 1.0 / rr;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int pos = (i % (MP * SP)) % SP;
-      const C2<double> qi = mk(qv[i].x * inv, qv[i].y * inv);
-      qv[i] = qi;
-      if (pos <= 2 * M) {
-        const C2<double> b = cvt<double>(base[i]);
-        X[i] = cvt<S>(mk(b.x + eps * qi.x, b.y + eps * qi.y));
-      }
-    }
-    if (threadIdx.x == 0) logs[v] = log(rr);
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2, n = 2 * MP * SP;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < n) {
+    bool pad;
+    const double w = lyap_weight(i, MP * SP, SP, M, pad);
+    const C2<double> x = cvt<double>(X[i]), b = cvt<double>(base[i]);
+    const C2<double> d = pad ? mk(0.0, 0.0) : mk((x.x - b.x) / eps, (x.y - b.y) / eps);
+    qv[i] = d;
+    const C2<double> o = qd ? qd[i] : d;
+    acc = w * (o.x * d.x + o.y * d.y);
   }
+  const double t = block_sum_1024(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// q_v -= r q_u with r = sum of part_in; partial of <qd, q_v> (qd = null: <q_v, q_v>)
+__global__ void __launch_bounds__(1024) k_lyap_axpy(C2<double>* __restrict__ qv, const C2<double>* __restrict__ qu,
+                                                    const double* __restrict__ part_in, int nb, int N,
+                                                    const C2<double>* __restrict__ qd, double* __restrict__ part) {
+  __shared__ double red[17];
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2, n = 2 * MP * SP;
+  const double r = sum_parts(part_in, nb);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (i < n) {
+    bool pad;
+    const double w = lyap_weight(i, MP * SP, SP, M, pad);
+    const C2<double> a = qv[i], u = qu[i];
+    const C2<double> d = mk(a.x - r * u.x, a.y - r * u.y);
+    qv[i] = d;
+    const C2<double> o = qd ? qd[i] : d;
+    acc = w * (o.x * d.x + o.y * d.y);
+  }
+  const double t = block_sum_1024(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// rr = sqrt(sum of part_in); q_v /= rr; X_v = X_0 + eps q_v; logv = log rr
+template <class S>
+__global__ void __launch_bounds__(1024) k_lyap_scale(const C2<S>* __restrict__ base, C2<S>* __restrict__ X,
+                                                     C2<double>* __restrict__ qv, const double* __restrict__ part_in,
+                                                     int nb, int N, double eps, double* __restrict__ logv) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2, n = 2 * MP * SP;
+  const double rr = sqrt(sum_parts(part_in, nb));
+  const double inv = 1.0 / rr;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    bool pad;
+    (void)lyap_weight(i, MP * SP, SP, M, pad);
+    const C2<double> q = mk(qv[i].x * inv, qv[i].y * inv);
+    qv[i] = q;
+    if (!pad) {
+      const C2<double> b = cvt<double>(base[i]);
+      X[i] = cvt<S>(mk(b.x + eps * q.x, b.y + eps * q.y));
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *logv = log(rr);
 }
 
 // ---- temporal power spectral density of the vorticity ----------------------------

@@ -891,17 +891,22 @@ int ttsh_lyap_qr(ttsh_ctx* c, int base, const int* pert, int p, double eps, doub
   auto [ci, jb] = c->loc[base];
   SizeClass& k = c->cls[ci];
   const size_t es = c->prec == 32 ? sizeof(C2<float>) : sizeof(C2<double>);
-  LyapArgs a{};
+  void* st[kMaxLyap];
   for (int v = 0; v < p; ++v) {
     if ((rc = check_inst(c, pert[v]))) return rc;
     if (pert[v] == base) return fail(TTSH_EINVAL, "a perturbed instance is the base instance");
     for (int u = 0; u < v; ++u)
       if (pert[u] == pert[v]) return fail(TTSH_EINVAL, "perturbed instances must be distinct");
     if (c->loc[pert[v]].first != ci) return fail(TTSH_EINVAL, "perturbed instances must have the base's grid size");
-    a.st[v] = (char*)k.st + (size_t)c->loc[pert[v]].second * k.sSt() * es;
+    st[v] = (char*)k.st + (size_t)c->loc[pert[v]].second * k.sSt() * es;
   }
-  const size_t n = k.sSt();
-  const size_t bytes = sizeof(double) * kMaxLyap + (size_t)p * n * sizeof(C2<double>);
+  const int N = k.N;
+  const size_t n = k.sSt();  // complex entries per state, both components
+  const int nb = (int)((n + 1023) / 1024);
+  // scratch: logs [kMaxLyap], two partial buffers [nb], then the p vectors
+  const size_t head = sizeof(double) * (kMaxLyap + 2 * (size_t)nb);
+  const size_t head_al = (head + 255) / 256 * 256;
+  const size_t bytes = head_al + (size_t)p * n * sizeof(C2<double>);
   if (bytes > c->lyq_cap) {
     if (c->lyq) hipFree(c->lyq);
     c->lyq = nullptr;
@@ -910,14 +915,36 @@ int ttsh_lyap_qr(ttsh_ctx* c, int base, const int* pert, int p, double eps, doub
     c->lyq_cap = bytes;
   }
   double* dlogs = (double*)c->lyq;
-  C2<double>* q = (C2<double>*)((char*)c->lyq + sizeof(double) * kMaxLyap);
-  if (c->prec == 32)
-    hipLaunchKernelGGL(k_lyap_qr<float>, dim3(1), dim3(1024), 0, c->stream,
-                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), jb), a, p, k.N, eps, q, dlogs);
-  else
-    hipLaunchKernelGGL(k_lyap_qr<double>, dim3(1), dim3(1024), 0, c->stream,
-                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), jb), a, p, k.N, eps, q, dlogs);
-  HIPCHK(hipGetLastError());
+  double* pa = dlogs + kMaxLyap;
+  double* pb = pa + nb;
+  C2<double>* q = (C2<double>*)((char*)c->lyq + head_al);
+  for (int v = 0; v < p; ++v) {
+    C2<double>* qv = q + (size_t)v * n;
+    const C2<double>* qd = v > 0 ? q : nullptr;  // first projection onto q_0, or the norm
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_lyap_init<float>, dim3(nb), dim3(1024), 0, c->stream,
+                         at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), jb), (const C2<float>*)st[v], N, eps,
+                         qv, qd, pa);
+    else
+      hipLaunchKernelGGL(k_lyap_init<double>, dim3(nb), dim3(1024), 0, c->stream,
+                         at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), jb), (const C2<double>*)st[v], N,
+                         eps, qv, qd, pa);
+    for (int u = 0; u < v; ++u) {
+      const C2<double>* nxt = u + 1 < v ? q + (size_t)(u + 1) * n : nullptr;
+      hipLaunchKernelGGL(k_lyap_axpy, dim3(nb), dim3(1024), 0, c->stream, qv, (const C2<double>*)(q + (size_t)u * n),
+                         (const double*)pa, nb, N, nxt, pb);
+      std::swap(pa, pb);
+    }
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_lyap_scale<float>, dim3(nb), dim3(1024), 0, c->stream,
+                         at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), jb), (C2<float>*)st[v], qv,
+                         (const double*)pa, nb, N, eps, dlogs + v);
+    else
+      hipLaunchKernelGGL(k_lyap_scale<double>, dim3(nb), dim3(1024), 0, c->stream,
+                         at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), jb), (C2<double>*)st[v], qv,
+                         (const double*)pa, nb, N, eps, dlogs + v);
+    HIPCHK(hipGetLastError());
+  }
   for (int v = 0; v < p; ++v)
     if ((rc = refresh_x(c, pert[v]))) return rc;
   HIPCHK(hipMemcpyAsync(log_r, dlogs, p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
