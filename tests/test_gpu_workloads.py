@@ -4,6 +4,7 @@ which calls only the oracle).  The bar is the FP32 target: relative L2 error
 <= 1e-5 at step 1000.  The FP64 oracle's own sensitivity at step 1000 for the
 512^2 circle (a twin run started 2^-24 away) is 1.1e-7, well below it.
 """
+import math
 import os
 
 import numpy as np
@@ -138,3 +139,37 @@ def test_lyapunov_driver_short_run(gpu):
     rep = lyapunov.run([5.2], p=2, N=256, L=20.48, transient=500, tau=50, intervals=10)
     ex = rep["radii"][0]["exponents"]
     assert len(ex) == 2 and all(np.isfinite(ex))
+
+
+@pytest.mark.parametrize("prec", [32])
+def test_diagnostics_match_oracle_1024(gpu, prec):
+    """At the circle driver's size (1024^2, the reductions at their full
+    spread of 256 workgroups): Psi, Psi_2 (half-planes and two-chamber disks)
+    and the vortex count of a paper-preset state in a circle of radius 5.6
+    (Algorithm 2 mask, 3000 steps from a seeded start) equal the oracle's on
+    the same real-space fields."""
+    from oracle import ttsh as O
+    print("[case] diagnostics 1024^2 vs oracle", flush=True)
+    N, L = 1024, 40.96
+    s = gpu.Solver([N], [L], W.paper_coefficients(), prec)
+    try:
+        s.mask_from_binary(0, W.binary_outside(N, L, [(0.0, 0.0)], [5.6]))
+        s.set_field(0, W.uniform_field(12, N, 0.01, prec))
+        s.step(3000)
+        s.sync()
+        vh = O.from_compact(s.state(0), N)
+        kx, ky, _, _ = O.grid(N, L)
+        v = O.field(vh)
+        w = O.field(O.vorticity_hat(vh, kx, ky)[None])[0]
+        for cen in ((0.0, 0.0), (0.3, -0.2)):
+            psi, psi2 = s.order(0, cen)
+            assert abs(psi - O.vortex_order(v, L, cen)) < 1e-12
+            assert abs(psi2 - O.vortex_order2(w, L, cen[0])) < 1e-12
+            for D in (3.0, 5.0):
+                assert abs(s.order_dumbbell(0, D, cen) - O.vortex_order2(w, L, cen[0], D=D, center_y=cen[1])) < 1e-12
+        vmin = 1e-3 * math.sqrt(s.norms(0)[0] / (N * N))
+        K = s.mask(0)
+        # on the real-space field the library computes (its own FP64 transform)
+        assert s.vortices(0, 0.5, vmin) == O.vortex_count(s.field(0), K, 0.5, vmin)
+    finally:
+        s.close()
