@@ -7,9 +7,9 @@ has settled; the same downwards from the oscillating state at the largest
 radius.  Here both ramps run at once, as two shift-register chains of
 instances of one context (one instance per radius and ramp, each with its own
 Algorithm 2 mask): after every stage instance j of the upward ramp takes the
-final state of instance j - 1 (ttsh_reseed, an exact copy on equal grids),
-the downward ramp likewise from j + 1, and the chain heads keep their own
-state.  After S stages instance j holds the state continued through the
+final state of instance j - 1 (ttsh_reseed, an exact copy on equal grids, or
+with --noise plus projected uniform noise), the downward ramp likewise from
+j + 1, and the chain heads keep their own state.  After S stages instance j holds the state continued through the
 radii before it on its ramp, as the sequential protocol would, with all
 instances busy.  Psi is sampled over the second half of every stage; the
 report gives, per ramp and radius, its mean and spread at the last stage
@@ -31,7 +31,8 @@ from . import ttsh as T
 from . import workloads as W
 
 
-def run(radii, stages=None, steps=40_000, every=100, N=512, L=20.48, seed=5, log=None, dt: float = 0.01) -> dict:
+def run(radii, stages=None, steps=40_000, every=100, N=512, L=20.48, seed=5, log=None, dt: float = 0.01,
+        noise: float = 0.0) -> dict:
     params = dataclasses.replace(W.paper_coefficients(dt=dt))
     nr = len(radii)
     stages = stages or nr
@@ -63,7 +64,11 @@ def run(radii, stages=None, steps=40_000, every=100, N=512, L=20.48, seed=5, log
             if st + 1 < stages:
                 dst = up[1:] + down[:-1]
                 src = up[:-1] + down[1:]
-                s.reseed(dst, src)
+                kick = None
+                if noise > 0:  # projected uniform noise on every hand-off
+                    rng = np.random.Generator(np.random.PCG64(seed + 7919 * (st + 1)))
+                    kick = rng.uniform(-noise, noise, size=(len(dst), 2, N, N))
+                s.reseed(dst, src, kick)
         s.sync()
         secs = time.time() - t0
         last = record[-1]
@@ -71,6 +76,7 @@ def run(radii, stages=None, steps=40_000, every=100, N=512, L=20.48, seed=5, log
                   "down_psi": last["mean"][down[j]], "down_std": last["std"][down[j]]}
                  for j, R in enumerate(radii)]
         return {"N": N, "L": L, "dt": dt, "steps_per_stage": steps, "stages": stages, "sample_every": every,
+                "handoff_noise": noise,
                 "coefficients": "paper preset (a, b, lambda, gamma_v, gamma_w) = (0.5, 1.6, 9, 40, 4)",
                 "mask": "Algorithm 2 from the binary outside-the-circle field",
                 "seconds": secs, "radii": table, "record": record}
@@ -89,10 +95,12 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--L", type=float, default=20.48)
+    ap.add_argument("--noise", type=float, default=0.0,
+                    help="amplitude of projected uniform noise added at every hand-off (0: exact copies)")
     ap.add_argument("--report", default="hysteresis_report.json")
     a = ap.parse_args(argv)
     rep = run(a.radii, a.stages or None, a.steps, a.every, a.N, a.L,
-              log=lambda m: print(f"[hysteresis] {m}", flush=True))
+              log=lambda m: print(f"[hysteresis] {m}", flush=True), noise=a.noise)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     print(f"[hysteresis] {2 * len(a.radii)} instances of {a.N}^2, {rep['stages']} stages of {a.steps} steps "
