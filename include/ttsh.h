@@ -102,8 +102,8 @@ enum {
 
 /* Create a context holding n_inst independent instances advanced together.
  *   N[i]   grid points per side of instance i: 64, 128, 256, 512, 1024 or 2048
- *          (2048 with TTSH_FP32 or TTSH_FP32_STATE64 only; its passes run with
- *          256-thread workgroups)
+ *          (2048: its passes run with 256-thread workgroups, in FP64 with
+ *          about 70 KB of LDS per workgroup)
  *   L[i]   box side of instance i (> 0)
  *   p      coefficients shared by all instances
  *   precision  TTSH_FP32, TTSH_FP64 or TTSH_FP32_STATE64

@@ -49,9 +49,9 @@ struct TileOf {
 // LDS bytes of one tile of size N; the launch allocates the largest over the
 // size classes present (dynamic LDS), so that a context without the small
 // grids, whose padded tiles need the most LDS, keeps a higher occupancy.
-// A tile needs at most 64 KB of LDS (FP64 transforms of 2048 points do not fit:
-// 0 here, and contexts ask for them are refused).
-constexpr size_t kMaxTileLds = 65536;
+// A tile may take up to the 160 KB of LDS one gfx950 workgroup can address
+// (FP64 transforms of 2048 points need about 70 KB); larger tiles give 0.
+constexpr size_t kMaxTileLds = 163840;
 template <class T, int BS, int N>
 constexpr size_t row_smem_n() {
   if constexpr (TileOf<N, BS>::ok) {

@@ -447,9 +447,6 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
   for (int i = 0; i < n_inst; ++i) {
     if (!size_ops(N[i])) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
     if (!(L[i] > 0) || !std::isfinite(L[i])) return fail(TTSH_EINVAL, "L must be > 0");
-    // FP64 transforms of 2048 points need more LDS than one workgroup has
-    if (N[i] == 2048 && precision == TTSH_FP64)
-      return fail(TTSH_EUNSUPPORTED, "N = 2048 needs FP32 transforms (TTSH_FP32 or TTSH_FP32_STATE64)");
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(TTSH_EHIP, "no HIP device available");

@@ -173,6 +173,22 @@ def test_fp32_steps(gpu, N, steps, prec, preset):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("preset", ["workload", "paper"])
+def test_fp64_2048_steps(gpu, preset):
+    """FP64 transforms at 2048^2 (tiles of about 70 KB of LDS per workgroup)
+    against the FP64 oracle after a few steps: agreement to rounding."""
+    say("fp64 2048 steps", preset)
+    N = 2048
+    L = N * 0.5
+    p = O.workload_params() if preset == "workload" else O.paper_params()
+    K = O.mask_tanh(N, L, [(0.0, 0.0)], [L / 4], 0.5)
+    v0 = W.uniform_field(9, N, 0.3, 64)
+    s, vh = run_pair(gpu, N, L, p, 64, K, v0, 3)
+    err = O.rel_l2(s.field(0), O.field(vh))
+    print("rel_l2", err)
+    assert err < 1e-12
+
+
 def test_graph_equals_eager(gpu):
     say("graph vs eager")
     N, L = 128, 64.0

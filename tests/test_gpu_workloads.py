@@ -125,7 +125,7 @@ def test_hysteresis_driver_short_run(gpu):
     recorded at every stage, Psi finite."""
     from paper_2304_03306_amd import hysteresis
     print("[case] hysteresis driver 256^2 x 3 radii", flush=True)
-    rep = hysteresis.run([5.2, 5.3, 5.4], steps=1000, every=100, N=256, L=20.48)
+    rep = hysteresis.run([5.2, 5.3, 5.4], steps=1000, every=100, N=256, L=20.48, noise=1e-3)
     assert len(rep["record"]) == 3 and len(rep["radii"]) == 3
     for r in rep["radii"]:
         assert np.isfinite(r["up_psi"]) and np.isfinite(r["down_psi"])
