@@ -1001,22 +1001,27 @@ __global__ void k_gather(float* __restrict__ dst, long long dch, const float* __
   dst[(s * npix + p) * dch + ch] = src[(idx[s] * npix + p) * sch + ch];
 }
 
-// per-sample sums of (y - t)^2 and t^2 (FP64), one block per sample
-// With ref non-null the second sum is of (t - ref)^2, ref holding the same
-// channels at pixel stride ref_s (the denominator of an increment loss).
-__global__ void __launch_bounds__(256) k_loss_sums(const float* __restrict__ y, const float* __restrict__ t,
-                                                   long long per, const float* __restrict__ ref, long long ref_s,
-                                                   int nch, double* __restrict__ out) {
+// per-sample sums of (y - t)^2 and t^2 (FP64), one block of 1024 threads per
+// sample, a thread per pixel (all its channels).  With ref non-null the second
+// sum is of (t - ref)^2, ref holding the same channels at pixel stride ref_s
+// (the denominator of an increment loss).
+__global__ void __launch_bounds__(1024) k_loss_sums(const float* __restrict__ y, const float* __restrict__ t,
+                                                    long long per, const float* __restrict__ ref, long long ref_s,
+                                                    int nch, double* __restrict__ out) {
   const long long base = (long long)blockIdx.x * per;
+  const long long npix = per / nch, pix0 = (long long)blockIdx.x * npix;
   double a = 0.0, b = 0.0;
-  for (long long i = threadIdx.x; i < per; i += blockDim.x) {
-    const double d = (double)y[base + i] - (double)t[base + i];
-    a += d * d;
-    double tv = (double)t[base + i];
-    if (ref) tv -= (double)ref[((base + i) / nch) * ref_s + (base + i) % nch];
-    b += tv * tv;
+  for (long long j = threadIdx.x; j < npix; j += blockDim.x) {
+    const long long e = base + j * nch;
+    for (int ch = 0; ch < nch; ++ch) {
+      const double d = (double)y[e + ch] - (double)t[e + ch];
+      a += d * d;
+      double tv = (double)t[e + ch];
+      if (ref) tv -= (double)ref[(pix0 + j) * ref_s + ch];
+      b += tv * tv;
+    }
   }
-  __shared__ double red[4][2];
+  __shared__ double red[16][2];
   a = ttsh::wave_sum_from(a, 1);
   b = ttsh::wave_sum_from(b, 1);
   if ((threadIdx.x & 63) == 0) {
@@ -1025,8 +1030,13 @@ __global__ void __launch_bounds__(256) k_loss_sums(const float* __restrict__ y, 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    out[2 * blockIdx.x] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
-    out[2 * blockIdx.x + 1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      sa += red[w][0];
+      sb += red[w][1];
+    }
+    out[2 * blockIdx.x] = sa;
+    out[2 * blockIdx.x + 1] = sb;
   }
 }
 
@@ -1867,7 +1877,7 @@ int fno_loss_ex(fno_ctx* c, const float* y, const float* t, const float* ref, in
   if (B < 1 || B > c->maxB) return ffail(TTSH_EINVAL, "batch out of range");
   if (ref && ref_stride < c->cout) return ffail(TTSH_EINVAL, "reference pixel stride smaller than cout");
   const long long per = (long long)c->H * c->W * c->cout;
-  hipLaunchKernelGGL(k_loss_sums, dim3(B), dim3(256), 0, c->s, y, t, per, ref, (long long)ref_stride, c->cout,
+  hipLaunchKernelGGL(k_loss_sums, dim3(B), dim3(1024), 0, c->s, y, t, per, ref, (long long)ref_stride, c->cout,
                      c->lsum);
   hipLaunchKernelGGL(k_loss_grad, dim3(nb(per * B)), dim3(256), 0, c->s, y, t, c->lsum, per, B, c->dy);
   FCHK(hipGetLastError());
