@@ -1141,6 +1141,53 @@ __global__ void __launch_bounds__(256) k_colsum_part8(const bf16* __restrict__ a
   }
 }
 
+// Weight gradient of the lifting layer for CIN <= 4 inputs and 32 outputs:
+// workgroup b sums x[p][k] dh[p][c] over the points of chunk b into
+// part[b][k][c] (k_reduce_parts then adds the chunks).  Thread t takes the
+// eight columns 8 (t % 4) .. 8 (t % 4) + 7 of every 64th point (one 16-byte
+// load of dh per point), and the 64 point lanes are added in order.  The
+// input channels are too few for the matrix-core tiles.
+template <int CIN>
+__global__ void __launch_bounds__(256) k_lift_wgrad_part(const bf16* __restrict__ x, const bf16* __restrict__ dh,
+                                                         long long P, long long chunk, float* __restrict__ part) {
+  constexpr int C = 32, LANES = 64;
+  const int cg = threadIdx.x & 3, lp = threadIdx.x >> 2;
+  const long long p0 = (long long)blockIdx.x * chunk;
+  const long long p1 = p0 + chunk < P ? p0 + chunk : P;
+  float acc[CIN][8];
+#pragma unroll
+  for (int k = 0; k < CIN; ++k)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[k][e] = 0.f;
+  for (long long p = p0 + lp; p < p1; p += LANES) {
+    const uint4 raw = *(const uint4*)(dh + p * C + 8 * cg);
+    const unsigned w[4] = {raw.x, raw.y, raw.z, raw.w};
+    float g[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      g[2 * e] = __uint_as_float(w[e] << 16);
+      g[2 * e + 1] = __uint_as_float(w[e] & 0xffff0000u);
+    }
+#pragma unroll
+    for (int k = 0; k < CIN; ++k) {
+      const float xv = bf2f(x[p * CIN + k]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[k][e] += xv * g[e];
+    }
+  }
+  __shared__ float red[LANES][CIN * C];
+#pragma unroll
+  for (int k = 0; k < CIN; ++k)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[lp][k * C + 8 * cg + e] = acc[k][e];
+  __syncthreads();
+  for (int o = threadIdx.x; o < CIN * C; o += blockDim.x) {
+    float t = 0.f;
+    for (int q = 0; q < LANES; ++q) t += red[q][o];
+    part[(long long)blockIdx.x * CIN * C + o] = t;
+  }
+}
+
 // out[j] = sum_c part[c][j] in a fixed order: 16 interleaved partial sums per
 // column (c = g, g + 16, ...), then added for g = 0..15; 16 columns per block
 __global__ void __launch_bounds__(256) k_reduce_parts(const float* __restrict__ part, int nparts, long long n,
@@ -1992,7 +2039,23 @@ int fno_backward(fno_ctx* c, int B) {
     std::swap(dh, dh_next);
   }
   // lift
-  if ((rc = wgrad(c, c->cin, C, P, c->xb, 1, c->cin, dh, C, 1, c->grad + c->oPw))) return rc;
+  if (C == 32 && c->cin >= 1 && c->cin <= 4 && ((uintptr_t)dh & 15) == 0) {
+    const long long nchunk = (P + kWgradChunk - 1) / kWgradChunk;
+    if ((size_t)(nchunk * c->cin * C) > c->part_n) return ffail(TTSH_ENOMEM, "fno partials buffer too small");
+    const dim3 g((unsigned)nchunk), t(256);
+    const bf16* xb = c->xb;
+    switch (c->cin) {
+      case 1: hipLaunchKernelGGL(k_lift_wgrad_part<1>, g, t, 0, c->s, xb, (const bf16*)dh, P, kWgradChunk, c->part); break;
+      case 2: hipLaunchKernelGGL(k_lift_wgrad_part<2>, g, t, 0, c->s, xb, (const bf16*)dh, P, kWgradChunk, c->part); break;
+      case 3: hipLaunchKernelGGL(k_lift_wgrad_part<3>, g, t, 0, c->s, xb, (const bf16*)dh, P, kWgradChunk, c->part); break;
+      default: hipLaunchKernelGGL(k_lift_wgrad_part<4>, g, t, 0, c->s, xb, (const bf16*)dh, P, kWgradChunk, c->part); break;
+    }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nb((long long)c->cin * C, 16)), dim3(256), 0, c->s, c->part,
+                       (int)nchunk, (long long)c->cin * C, c->grad + c->oPw);
+    FCHK(hipGetLastError());
+  } else if ((rc = wgrad(c, c->cin, C, P, c->xb, 1, c->cin, dh, C, 1, c->grad + c->oPw))) {
+    return rc;
+  }
   if ((rc = colsum(c, dh, P, C, c->grad + c->oPb))) return rc;
   return TTSH_OK;
 }
