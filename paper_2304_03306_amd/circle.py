@@ -20,6 +20,7 @@ statistics of the sampled series are host-side analysis of its output.
 from __future__ import annotations
 
 import json
+import os
 import time
 
 import numpy as np
@@ -127,6 +128,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     rep = run(a.radii, a.N, a.L, a.steps, a.transient, a.every, log=lambda m: print(f"[circle] {m}", flush=True),
               scheme=a.scheme, dt=a.dt, psd_fmax=a.psd_fmax)
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     for r in rep["radii"]:

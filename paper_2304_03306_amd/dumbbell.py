@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import dataclasses
 import json
+import os
 import time
 
 import numpy as np
@@ -102,6 +103,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     rep = run(a.radii, a.ratios, a.seeds, a.N, a.L, a.steps, a.transient, a.every,
               log=lambda m: print(f"[dumbbell] {m}", flush=True), scheme=a.scheme, dt=a.dt)
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     print(f"[dumbbell] {rep['instances']} instances of {a.N}^2, {a.steps} steps in {rep['seconds']:.1f} s", flush=True)

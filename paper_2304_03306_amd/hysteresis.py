@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import dataclasses
 import json
+import os
 import time
 
 import numpy as np
@@ -101,6 +102,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     rep = run(a.radii, a.stages or None, a.steps, a.every, a.N, a.L,
               log=lambda m: print(f"[hysteresis] {m}", flush=True), noise=a.noise)
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     print(f"[hysteresis] {2 * len(a.radii)} instances of {a.N}^2, {rep['stages']} stages of {a.steps} steps "

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import dataclasses
 import json
+import os
 import time
 
 import numpy as np
@@ -121,6 +122,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     rep = run(a.radii, a.p, a.N, a.L, a.transient, a.tau, a.intervals, a.rel_eps,
               log=lambda m: print(f"[lyapunov] {m}", flush=True), start_from=a.start_from)
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f)
     print(f"[lyapunov] {len(a.radii) * (1 + a.p)} instances of {a.N}^2 (FP64), "

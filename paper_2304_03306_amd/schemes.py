@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import dataclasses
 import json
+import os
 import time
 
 import numpy as np
@@ -99,6 +100,7 @@ def main(argv=None):
     ap.add_argument("--report", default="schemes_report.json")
     a = ap.parse_args(argv)
     rep = run(a.T, tuple(a.dts), log=lambda m: print(f"[schemes] {m}", flush=True))
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f, indent=1)
     return rep

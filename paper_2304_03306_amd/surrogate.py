@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 import time
 from typing import List, Optional, Sequence
 
@@ -470,6 +471,7 @@ def main(argv=None):
         "seconds_per_solver_20_steps": t_sol,
         "speedup_per_step": t_sol / t_sur,
     }
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f, indent=1)
     log(f"speedup {t_sol / t_sur:.2f}x per surrogate step ({t_sur * 1e3:.2f} ms vs {t_sol * 1e3:.2f} ms); "

@@ -18,6 +18,7 @@ calls and keeps the record.
 from __future__ import annotations
 
 import json
+import os
 import time
 
 import numpy as np
@@ -83,6 +84,7 @@ def main(argv=None):
     ap.add_argument("--report", default="sweep_report.json")
     a = ap.parse_args(argv)
     rep = run(a.stages, a.steps, log=lambda m: print(f"[sweep] {m}", flush=True), scheme=a.scheme)
+    os.makedirs(os.path.dirname(os.path.abspath(a.report)), exist_ok=True)
     with open(a.report, "w") as f:
         json.dump(rep, f, indent=1)
     print(f"[sweep] {a.stages} stages of {a.steps} steps; {rep['throughput']:.4e} pt*steps/s", flush=True)
