@@ -629,3 +629,54 @@ def test_temporal_psd_closed_forms():
     noise = [rng.standard_normal((N, N)) for _ in range(T)]
     fr = np.array([0.013, 0.21, 0.37])
     assert np.allclose(O.temporal_psd(noise, times, fr), O.temporal_psd(noise, times, -fr), rtol=1e-12)
+
+
+# ---- pins added for the diagnostics, the Algorithm 2 cutoff and the paper preset ------------------
+def test_norms_against_real_space_sums():
+    """norms(): Parseval sum, mean and max |k . v_hat| against quantities fixed
+    in real space.  A field made of a constant, a cosine along x in v_x only
+    and a divergence-free mode: sum |v|^2 and the mean are plain sums over the
+    nodes; the divergence d_x v_x = -A k sin(k x) has unitary spectrum of
+    modulus A k N / 2 at m = (+-m0, 0), so max |k . v_hat| = A k N / 2."""
+    N, L, A, m0 = 32, 20.0, 0.7, 3
+    x, y = O.node_coords(N, L)
+    k = 2 * math.pi * m0 / L
+    v = 0.2 * mode_field(N, L, 2, 1)
+    v[0] += 0.25 + A * np.cos(k * x)
+    v[1] += -0.4
+    vh = O.dft2(v)
+    e, mx, my, div = O.norms(vh, L)
+    assert abs(e - float(np.sum(v * v))) < 1e-12 * float(np.sum(v * v))
+    assert abs(mx - float(v[0].mean())) < 1e-15 and abs(my - float(v[1].mean())) < 1e-15
+    assert abs(mx - 0.25) < 1e-14 and abs(my + 0.4) < 1e-14
+    assert abs(div - A * k * N / 2) < 1e-12 * A * k * N
+    # a divergence-free field has no divergence left beyond rounding
+    _, _, _, div0 = O.norms(O.dft2(mode_field(N, L, 2, 1)), L)
+    assert div0 < 1e-13
+
+
+def test_alg2_cutoff_keeps_the_edge_and_drops_beyond():
+    """Algorithm 2 removes modes with k^2 > (pi/(4 dx))^2, i.e. m^2 > (N/8)^2
+    (strict): a mode with m^2 = (N/8)^2 survives, one with m^2 = (N/8)^2 + 1
+    does not.  With K_naive = c + a cos(edge) + b cos(beyond) the result is
+    therefore (c + a cos(edge))^2 exactly, up to rounding."""
+    N, L = 64, 64.0
+    x, y = O.node_coords(N, L)
+    g = 2 * math.pi / L
+    edge = np.cos(g * (8 * x))              # m = (8, 0): m^2 = 64 = (N/8)^2, kept
+    beyond = np.cos(g * (7 * x + 4 * y))    # m = (7, 4): m^2 = 65, removed
+    c, a, b = 0.5, 0.3, 0.2
+    K = O.mask_alg2(c + a * edge + b * beyond)
+    assert np.abs(K - (c + a * edge) ** 2).max() < 1e-14
+
+
+def test_paper_preset_is_table_one():
+    """The paper preset against the literal values of the table of parameters
+    (Appendix A): lambda = 9, a = 0.5, b = 1.6, gamma_v = 40, gamma_w = 4,
+    dt = 0.01; eq. (2)'s linear part a v - (1 + lap)^2 v has the symbol
+    a - (1 - k^2)^2."""
+    lam, a, b, gv, gw, dt = 9.0, 0.5, 1.6, 40.0, 4.0, 0.01
+    p = O.paper_params()
+    assert (p.lambda0, p.beta, p.gamma_v, p.gamma_w, p.dt, p.lambda1) == (lam, b, gv, gw, dt, 0.0)
+    k2 = np.array([0.0, 0.25, 1.0, 1.7, 4.0])
+    assert np.abs(O.linear_symbol(k2, p) - (a - (1.0 - k2) ** 2)).max() < 1e-14
