@@ -34,6 +34,7 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_radius_sweep.json")
+STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_step_kernels_radius_sweep.json")
 STEP_SOURCES = ("common.hpp", "fft.hpp", "step.hpp", "step_multi.hpp", "step_multi.hip")
 
 
@@ -110,6 +111,55 @@ def measured_traffic(kernel: str, block: int):
                 and ", false, " in name and (kernel == "row_multi" or ", 0, " in name)):
             return v["bytes"]
     return None
+
+
+def summarize_stats(stats_csv) -> dict:
+    """Mean duration per kernel name from a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+    kernels = {}
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            kernels[r["Name"]] = {"calls": int(r["Calls"]), "avg_us": float(r["AverageNs"]) / 1e3,
+                                  "min_us": float(r["MinNs"]) / 1e3, "max_us": float(r["MaxNs"]) / 1e3}
+    return {"source_sha256": step_source_hash(), "kernels": kernels}
+
+
+def recorded_avg_us(kernel: str, block: int):
+    """The rocprofv3 mean duration of the given step kernel from the committed
+    summary, or None if it is missing or the kernel sources changed since."""
+    try:
+        with open(STATS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != step_source_hash():
+        return None
+    for name, v in t.get("kernels", {}).items():
+        if (name.startswith(f"void ttsh::{kernel}<float") and name.endswith(f", {block}>(ttsh::MultiArgs)")
+                and ", false, " in name and (kernel == "row_multi" or ", 0, " in name)):
+            return v["avg_us"]
+    return None
+
+
+def stream_ceiling(torch, T, mib: int = 160, reps: int = 30):
+    """Rates of the library's streaming probe for several read:write mixes, on
+    arrays totalling about `mib` MiB (the size of one step pass's traffic) and
+    on 2 GiB (beyond the 256 MB last-level cache).  GB/s = bytes moved per
+    launch / mean launch time; the best workgroup count of a few is kept."""
+    out = {}
+    for total_mib in (mib, 2048):
+        for r, w in ((1, 1), (2, 1), (5, 2), (1, 0)):
+            arrays = r + w
+            elems = total_mib * (1 << 20) // (16 * arrays)
+            buf = torch.zeros((r + max(w, 1)) * elems * 4, dtype=torch.float32, device="cuda")
+            best = 0.0
+            for blocks in (2048, 8192, 32768):
+                us = T.ttsh_stream_bench(r, w, elems, blocks, reps if total_mib <= 256 else 5, buf)
+                best = max(best, arrays * elems * 16 / (us * 1e-6) / 1e9)
+            out[f"{total_mib}MiB_r{r}w{w}"] = round(best, 1)
+            del buf
+    torch.cuda.synchronize()
+    return out
 
 
 def kept_modes(N: int) -> int:
@@ -225,10 +275,19 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = autotuned)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (scale for the HBM byte counters)")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming-bandwidth probe")
+    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
+                    help="write the rocprofv3 mean durations of the step kernels (read back by later runs)")
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV", "COPY_MIB"),
                     help="write the HBM traffic summary of the step kernels from rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summary = summarize_stats(args.summarize_stats)
+        with open(STATS_FILE, "w") as f:
+            json.dump(summary, f, indent=1)
+        print(json.dumps(summary, indent=1))
+        return
     if args.summarize_pmc:
         a = args.summarize_pmc
         summary = summarize_pmc(a[0], a[1], a[2], a[3], int(a[4]))
@@ -285,7 +344,14 @@ def main():
         log(f"[bench] parity at step 1000: {parity}")
         reinit(s, W, wl)
 
+    # warm-up; a call whose length is not a whole number of graph chunks ends
+    # with a tail graph of its own length, so one untimed call of that tail
+    # captures it before the timed region
+    tail = args.steps % 50
+    warmup = args.warmup + tail
     s.step(args.warmup)
+    if tail:
+        s.step(tail)
     s.sync()
     dt = timed_steps(s, torch, args.steps)
     value = wl.points * args.steps / dt
@@ -311,6 +377,7 @@ def main():
     # the recorded counter summary is of the radius sweep in FP32
     traffic = measured_traffic(dom[0], dom[3]) if args.precision == 32 and args.workload == "sweep" else None
     achieved = dom[2] / (dom[1] * 1e-6) / 1e9
+    rocprof_us = recorded_avg_us(dom[0], dom[3]) if args.precision == 32 and args.workload == "sweep" else None
     step_bytes = row_b + col_b
     step_us = row_us + col_us
     log("[bench] kernels: " + ", ".join(f"{k[0]} {k[1]:.1f}us {k[2] / k[1] / 1e3:.0f}GB/s" for k in kern))
@@ -339,6 +406,11 @@ def main():
         log(f"[bench] plain 512^2: {plain['value']:.4e} pt*steps/s, {plain['ms_per_step'] * 1e3:.1f} us/step")
         ps.close()
 
+    stream = None
+    if not args.no_stream:
+        stream = stream_ceiling(torch, T)
+        log(f"[bench] streaming probe (GB/s): {stream}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_budget)
@@ -351,7 +423,7 @@ def main():
         "unit": "grid-pt·steps/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": warmup,
         "ms_per_step": 1e3 * dt / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
@@ -367,7 +439,10 @@ def main():
                    "parallelism": "single GPU, instances batched per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": dom[0], "block": dom[3], "avg_us": dom[1], "bytes_per_launch": dom[2]},
+                     "kernel": dom[0], "block": dom[3], "avg_us": dom[1], "bytes_per_launch": dom[2],
+                     "rocprof_avg_us": rocprof_us,
+                     "rocprof_frac": (dom[2] / (rocprof_us * 1e-6) / 1e9 / HBM_PEAK_GBS) if rocprof_us else None},
+        "stream_probe_GBps": stream,
         "step_hbm": {"algorithmic_bytes": step_bytes, "kernel_us": step_us,
                      "GBps": step_bytes / (step_us * 1e-6) / 1e9,
                      "frac": step_bytes / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,

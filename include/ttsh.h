@@ -135,7 +135,9 @@ int ttsh_mask_tanh(ttsh_ctx* ctx, int inst, int n_circ, const double* cx, const 
 int ttsh_mask_from_binary(ttsh_ctx* ctx, int inst, const uint8_t* K_naive, int where);
 
 /* Set the velocity of instance inst from a real field v [2][N][N] float64:
- * DFT, 1/2-rule cutoff, Leray projection (k != 0); the k = 0 mode is kept.  */
+ * DFT, 1/2-rule cutoff, Leray projection (k != 0); the k = 0 mode is kept.
+ * A field holding NaN or Inf is refused with TTSH_ENONFINITE before the
+ * instance is touched (its state stays as it was).  Synchronous.           */
 int ttsh_set_field(ttsh_ctx* ctx, int inst, const double* v, int where);
 
 /* Real velocity v [2][N][N] and, if omega is not NULL, vorticity omega [N][N]
@@ -252,20 +254,38 @@ int ttsh_set_state(ttsh_ctx* ctx, int inst, const double* vhat, int where);
 int ttsh_get_state(ttsh_ctx* ctx, int inst, double* vhat, int where);
 
 /* Advance every instance by nsteps >= 0 steps.  Asynchronous on the
- * context's stream; whole chunks of TTSH_OPT_GRAPH_STEPS steps replay a
- * captured HIP graph.                                                       */
+ * context's stream.  With TTSH_OPT_GRAPH_STEPS = G > 0, whole chunks of G
+ * steps replay one captured HIP graph and a remaining tail of r < G steps
+ * replays a graph of r steps (captured on first use and kept while calls end
+ * with the same tail); with G = 0 every kernel is launched directly.        */
 int ttsh_step(ttsh_ctx* ctx, int64_t nsteps);
 
-/* Continuation between stages (hysteresis protocol of the circle section):
- * for q = 0..n-1, simultaneously,
+/* Continuation between stages (hysteresis protocol of the circle section:
+ * each run starts from the final state of the previous one, with a small
+ * random kick): for q = 0..n-1, simultaneously,
  *   state[dst[q]] <- resample(state[src[q]]) + P DFT[noise_q]
  * where resample copies the spectrum by integer mode index (zero padding or
- * truncation between grid sizes, scaled by N_dst/N_src for the unitary DFT)
- * and noise_q [2][N_dst][N_dst] float64 is the q-th block of `noise` (blocks
- * stored back to back in the order of dst; noise may be NULL for none).
- * All sources are read before any destination is written.                   */
-int ttsh_reseed(ttsh_ctx* ctx, int n, const int* dst, const int* src, const double* noise,
-                int where);
+ * truncation between grid sizes, scaled by N_dst/N_src for the unitary DFT),
+ * P is the 1/2-rule cutoff plus the Leray projection (as in ttsh_set_field),
+ * and noise_q [2][N_dst][N_dst] is drawn on the device by the counter-based
+ * generator Philox-4x32-10 (Salmon et al., SC'11): key = (seed mod 2^32,
+ * seed >> 32), counter = (i N_dst + j, dst[q], 0, 0) for node (i, j), and
+ * output word c gives component c as noise_amp (2 u - 1), u = (word >> 8) 2^-24,
+ * evaluated in FP64 (uniform on [-noise_amp, noise_amp)).  noise_amp = 0 adds
+ * no noise.  dst and src are host arrays of instance indices; destinations
+ * must be distinct; a destination may also be a source (all sources are read
+ * before any destination is written).  Allocates a device scratch of the
+ * destinations' compact FP64 spectra for the call.  Synchronous.
+ * Errors: TTSH_EINVAL (indices, duplicates, non-finite noise_amp),
+ * TTSH_ENOMEM, TTSH_EHIP.                                                   */
+int ttsh_reseed(ttsh_ctx* ctx, int n, const int* dst, const int* src, double noise_amp, uint64_t seed);
+
+/* As ttsh_reseed, with caller-drawn noise: noise_q [2][N_dst][N_dst] float64
+ * is the q-th block of `noise` (blocks stored back to back in the order of
+ * dst; noise may be NULL for none), on the host (where = TTSH_HOST) or the
+ * device (TTSH_DEVICE).  Synchronous.                                       */
+int ttsh_reseed_field(ttsh_ctx* ctx, int n, const int* dst, const int* src, const double* noise,
+                      int where);
 
 /* FP64 diagnostics of instance inst (synchronous):
  * out[0] = sum_x |v|^2, out[1] = <v_x>, out[2] = <v_y>, out[3] = max |k . v_hat|. */
@@ -304,6 +324,17 @@ int ttsh_set_option(ttsh_ctx* ctx, int key, int64_t value);
  * iDFT.  precision 32 runs the library's FP32 transform (inputs rounded),
  * 64 the FP64 one.  Synchronous; in and out may alias.                      */
 int ttsh_fft2(const double* in, double* out, int N, int batch, int inverse, int precision);
+
+/* Streaming-bandwidth probe (measurement only; no part of the method): a
+ * kernel that reads `reads` arrays and writes `writes` arrays of `elems`
+ * 16-byte elements each, element by element, with `blocks` workgroups of 256
+ * threads; (reads, writes) is one of (1,1), (2,1), (3,1), (5,2), (1,0),
+ * (0,1).  buf is a caller-owned device buffer of (reads + max(writes, 1)) *
+ * elems * 16 bytes, 16-byte aligned, inputs first; a read-only run needs the
+ * buffer zero-filled.  One untimed launch, then `reps` launches back to back on
+ * the null stream between two HIP events; *us_out = mean microseconds per
+ * launch.  Synchronous.                                                     */
+int ttsh_stream_bench(int reads, int writes, int64_t elems, int blocks, int reps, void* buf, double* us_out);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* ttsh_last_error(void);

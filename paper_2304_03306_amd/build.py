@@ -49,6 +49,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> Path:
               for p in PRECS for b in BLOCKS]
     units.append((CSRC / "ttsh_capi.hip", OUT / "ttsh_capi.o", []))
     units.append((CSRC / "fno.hip", OUT / "fno.o", []))
+    units.append((CSRC / "stream.hip", OUT / "stream.o", []))
     cmds = [[HIPCC, *FLAGS, *extra, "-c", str(src), "-o", str(obj)] for src, obj, extra in units]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for cmd, fut in zip(cmds, [ex.submit(_run, c) for c in cmds]):

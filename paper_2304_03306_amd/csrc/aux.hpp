@@ -91,10 +91,48 @@ __global__ void k_mask_tanh(T* __restrict__ K, int N, double dx, Circles c, doub
   K[i] = (T)k;
 }
 
+// ---- counter-based noise (Philox-4x32-10) -------------------------------------
+// Philox-4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11): each round takes the 64-bit products of
+// counter words 0 and 2 with two fixed multipliers and forms
+// (hi(p1) ^ c1 ^ k0, lo(p1), hi(p0) ^ c3 ^ k1, lo(p0)); the key is advanced by
+// two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Continuation noise of one destination instance into Z = n_x + i n_y, [N][N]:
+// node (i, j) takes counter (i N + j, inst, 0, 0); word c gives component c as
+// amp (2 u - 1), u = (word >> 8) 2^-24, in FP64.
+__global__ void k_philox_noise(C2<double>* __restrict__ Z, int N, uint32_t inst, uint32_t k0, uint32_t k1,
+                               double amp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * N) return;
+  uint32_t c[4] = {(uint32_t)i, inst, 0u, 0u};
+  philox4x32_10(c, k0, k1);
+  const double ux = (double)(c[0] >> 8) * 0x1p-24;
+  const double uy = (double)(c[1] >> 8) * 0x1p-24;
+  Z[i] = mk(amp * (2.0 * ux - 1.0), amp * (2.0 * uy - 1.0));
+}
+
 // ---- state packing -----------------------------------------------------------
 // From Z = unnormalised 2D FFT of (v_x + i v_y): separate the two real fields,
 // scale to the unitary DFT, cut at m^2 > M^2, project (k != 0), optionally add
 // a compact FP64 spectrum `add` (same layout as the state), store the state.
+// Z may be null (no field: the state becomes `add`, or zero).
 // Thread per stored (component-pair) position.
 template <class S>
 __global__ void k_pack_state(const C2<double>* __restrict__ Z, const C2<double>* __restrict__ add,
@@ -106,7 +144,7 @@ __global__ void k_pack_state(const C2<double>* __restrict__ Z, const C2<double>*
   C2<double> ox = mk(0.0, 0.0), oy = mk(0.0, 0.0);
   if (pos <= 2 * M) {
     const int my = pos <= M ? pos : pos - (2 * M + 1);
-    if (mx * mx + my * my <= M * M) {
+    if (mx * mx + my * my <= M * M && Z) {
       const C2<double> zp = Z[(size_t)((my + N) % N) * N + mx];
       const C2<double> zm = Z[(size_t)((N - my) % N) * N + (N - mx) % N];
       const double s = 1.0 / N;
@@ -119,10 +157,10 @@ __global__ void k_pack_state(const C2<double>* __restrict__ Z, const C2<double>*
         ox = ox - cscale(d, (double)mx);
         oy = oy - cscale(d, (double)my);
       }
-      if (add) {
-        ox = ox + add[(0 * MP + mx) * SP + pos];
-        oy = oy + add[(1 * MP + mx) * SP + pos];
-      }
+    }
+    if (mx * mx + my * my <= M * M && add) {
+      ox = ox + add[(0 * MP + mx) * SP + pos];
+      oy = oy + add[(1 * MP + mx) * SP + pos];
     }
   }
   st[(0 * MP + mx) * SP + pos] = cvt<S>(ox);

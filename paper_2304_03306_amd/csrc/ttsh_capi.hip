@@ -147,8 +147,12 @@ struct ttsh_ctx {
   int opt_bs = 0;   // requested by TTSH_OPT_BLOCK (0 = chosen)
   int split_row = 0, split_col = 0;  // one launch per size class (TTSH_OPT_SPLIT)
   int guard = 1;
-  hipGraph_t graph = nullptr;
+  int device = 0;                        // HIP device current at creation
+  hipGraph_t graph = nullptr;            // graph_steps steps
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_rem = nullptr;        // rem_steps (< graph_steps) steps: the tail of the last call
+  hipGraphExec_t gexec_rem = nullptr;
+  int rem_steps = 0;
 };
 
 namespace {
@@ -156,8 +160,13 @@ namespace {
 void drop_graph(ttsh_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
+  if (c->gexec_rem) hipGraphExecDestroy(c->gexec_rem);
+  if (c->graph_rem) hipGraphDestroy(c->graph_rem);
   c->gexec = nullptr;
   c->graph = nullptr;
+  c->gexec_rem = nullptr;
+  c->graph_rem = nullptr;
+  c->rem_steps = 0;
 }
 
 int make_twiddles(int N, bool fp64, void** out) {
@@ -304,10 +313,10 @@ int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
   return TTSH_OK;
 }
 
-int build_graph(ttsh_ctx* c) {
-  drop_graph(c);
+// capture `steps` steps of every instance into a graph and instantiate it
+int build_graph(ttsh_ctx* c, int steps, hipGraph_t* graph, hipGraphExec_t* gexec) {
   HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_steps(c, c->graph_steps, c->cap);
+  int rc = enqueue_steps(c, steps, c->cap);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (rc != TTSH_OK) {
@@ -315,8 +324,8 @@ int build_graph(ttsh_ctx* c) {
     return rc;
   }
   if (e != hipSuccess) return fail(TTSH_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-  c->graph = g;
-  HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  *graph = g;
+  HIPCHK(hipGraphInstantiate(gexec, g, nullptr, nullptr, 0));
   return TTSH_OK;
 }
 
@@ -353,19 +362,20 @@ int refresh_x(ttsh_ctx* c, int inst) {
   return TTSH_OK;
 }
 
-// Z (FP64, scr0) holds the unnormalised FFT of v_x + i v_y; `add` optional.
-int pack_into_state(ttsh_ctx* c, int inst, const void* add) {
+// Z (FP64, e.g. scr0) holds the unnormalised FFT of v_x + i v_y, or is null
+// for no field; `add` optional.
+int pack_into_state(ttsh_ctx* c, int inst, const void* Z, const void* add) {
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
   const int N = k.N, M = N / 4;
   const size_t n = (size_t)(M + 1) * (2 * M + 2);
   if (c->prec == 32) {
     hipLaunchKernelGGL(k_pack_state<float>, dim3(nblk(n)), dim3(kB), 0, c->stream,
-                       (const C2<double>*)c->scr0, (const C2<double>*)add,
+                       (const C2<double>*)Z, (const C2<double>*)add,
                        at<C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), N);
   } else {
     hipLaunchKernelGGL(k_pack_state<double>, dim3(nblk(n)), dim3(kB), 0, c->stream,
-                       (const C2<double>*)c->scr0, (const C2<double>*)add,
+                       (const C2<double>*)Z, (const C2<double>*)add,
                        at<C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), N);
   }
   HIPCHK(hipGetLastError());
@@ -405,6 +415,87 @@ int norms_into(ttsh_ctx* c, int inst, double* dout) {
     hipLaunchKernelGGL(k_norms<double>, dim3(1), dim3(1024), 0, c->stream,
                        at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), k.N, dk, dout);
   HIPCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
+// ---- continuation (reseed) ----------------------------------------------------
+int reseed_check(ttsh_ctx* c, int n, const int* dst, const int* src) {
+  if (!c) return fail(TTSH_EINVAL, "null context");
+  if (n < 0 || (n > 0 && (!dst || !src))) return fail(TTSH_EINVAL, "bad reseed lists");
+  for (int q = 0; q < n; ++q) {
+    if (dst[q] < 0 || dst[q] >= c->n_inst || src[q] < 0 || src[q] >= c->n_inst)
+      return fail(TTSH_EINVAL, "reseed index out of range");
+    for (int r = 0; r < q; ++r)
+      if (dst[r] == dst[q]) return fail(TTSH_EINVAL, "duplicate reseed destination");
+  }
+  return TTSH_OK;
+}
+
+// compact FP64 spectra of every destination, back to back: the scratch a
+// reseed needs to read all sources before any destination is written
+size_t reseed_scratch_elems(const ttsh_ctx* c, int n, const int* dst) {
+  size_t e = 0;
+  for (int q = 0; q < n; ++q) {
+    const int Nd = c->N[dst[q]];
+    e += (size_t)2 * (Nd / 4 + 1) * (Nd / 2 + 2);
+  }
+  return e;
+}
+
+// the noise added at a reseed: caller fields (`fields`, [2][N][N] per
+// destination, back to back) or, if fields is null and amp != 0, the
+// device's Philox stream
+struct Noise {
+  const double* fields = nullptr;
+  int where = TTSH_HOST;
+  double amp = 0.0;
+  uint64_t seed = 0;
+};
+
+// state[dst[q]] <- resample(state[src[q]]) + P DFT(noise_q); `tmp` holds
+// reseed_scratch_elems complex doubles.  Asynchronous, except that host noise
+// fields are staged through scr1 one destination at a time.
+int reseed_impl(ttsh_ctx* c, int n, const int* dst, const int* src, const Noise& nz, C2<double>* tmp) {
+  // gather every resampled source first
+  size_t off = 0;
+  for (int q = 0; q < n; ++q) {
+    auto [cs, js] = c->loc[src[q]];
+    SizeClass& ks = c->cls[cs];
+    const int Nd = c->N[dst[q]];
+    const size_t cnt = (size_t)2 * (Nd / 4 + 1) * (Nd / 2 + 2);
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_resample<float>, dim3(nblk(cnt)), dim3(kB), 0, c->stream,
+                         at<const C2<float>>(ks.st, ks.sSt(), sizeof(C2<float>), js), ks.N, tmp + off, Nd);
+    else
+      hipLaunchKernelGGL(k_resample<double>, dim3(nblk(cnt)), dim3(kB), 0, c->stream,
+                         at<const C2<double>>(ks.st, ks.sSt(), sizeof(C2<double>), js), ks.N, tmp + off, Nd);
+    HIPCHK(hipGetLastError());
+    off += cnt;
+  }
+  off = 0;
+  size_t noff = 0;
+  for (int q = 0; q < n; ++q) {
+    const int Nd = c->N[dst[q]];
+    int rc;
+    const void* Z = nullptr;
+    if (nz.fields) {
+      const void* dev = nullptr;
+      if ((rc = stage_in(c, nz.fields + noff, sizeof(double) * 2 * Nd * Nd, nz.where, &dev))) return rc;
+      if ((rc = field_to_spectrum(c, Nd, (const double*)dev))) return rc;
+      noff += (size_t)2 * Nd * Nd;
+      Z = c->scr0;
+    } else if (nz.amp != 0.0) {
+      hipLaunchKernelGGL(k_philox_noise, dim3(nblk((size_t)Nd * Nd)), dim3(kB), 0, c->stream, (C2<double>*)c->scr0, Nd,
+                         (uint32_t)dst[q], (uint32_t)(nz.seed & 0xFFFFFFFFu), (uint32_t)(nz.seed >> 32), nz.amp);
+      HIPCHK(hipGetLastError());
+      HIPCHK(size_ops(Nd)->fft2(c->scr0, 1, -1, 1, c->tw64[Nd], c->stream));
+      Z = c->scr0;
+    }
+    if ((rc = pack_into_state(c, dst[q], Z, tmp + off))) return rc;
+    if ((rc = refresh_x(c, dst[q]))) return rc;
+    off += (size_t)2 * (Nd / 4 + 1) * (Nd / 2 + 2);
+    if (nz.fields && nz.where == TTSH_HOST) HIPCHK(hipStreamSynchronize(c->stream));
+  }
   return TTSH_OK;
 }
 
@@ -460,6 +551,10 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
   c->gw = p->gamma_w != 0.0;
   c->stream = (hipStream_t)stream;
   c->loc.resize(n_inst);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(TTSH_EHIP, "hipGetDevice failed");
+  }
   auto bail = [&](int rc) {
     free_ctx(c);
     return rc;
@@ -665,13 +760,17 @@ int ttsh_set_field(ttsh_ctx* c, int inst, const double* v, int where) {
   const void* dev = nullptr;
   if ((rc = stage_in(c, v, sizeof(double) * 2 * N * N, where, &dev))) return rc;
   if ((rc = field_to_spectrum(c, N, (const double*)dev))) return rc;
-  if ((rc = pack_into_state(c, inst, nullptr))) return rc;
-  if ((rc = refresh_x(c, inst))) return rc;
-  double h[5];
-  if ((rc = norms_into(c, inst, c->dnorm))) return rc;
-  HIPCHK(hipMemcpyAsync(h, c->dnorm, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  // the k = 0 entry of the transform is the sum of every input value, so it is
+  // finite exactly when the input holds no NaN or Inf (barring overflow of the
+  // sum, which is refused too); checked before the state is written
+  double z0[2];
+  HIPCHK(hipMemcpyAsync(z0, c->scr0, sizeof(z0), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (h[4] != 0.0) return fail(TTSH_ENONFINITE, "non-finite value in the input field");
+  if (!std::isfinite(z0[0]) || !std::isfinite(z0[1]))
+    return fail(TTSH_ENONFINITE, "non-finite value in the input field (state left unchanged)");
+  if ((rc = pack_into_state(c, inst, c->scr0, nullptr))) return rc;
+  if ((rc = refresh_x(c, inst))) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
   return TTSH_OK;
 }
 
@@ -1080,74 +1179,67 @@ int ttsh_get_state(ttsh_ctx* c, int inst, double* vhat, int where) {
 int ttsh_step(ttsh_ctx* c, int64_t nsteps) {
   if (!c) return fail(TTSH_EINVAL, "null context");
   if (nsteps < 0) return fail(TTSH_EINVAL, "nsteps must be >= 0");
+  if (c->graph_steps <= 0) return enqueue_steps(c, nsteps, c->stream);
   int rc;
   int64_t left = nsteps;
-  if (c->graph_steps > 0 && left >= c->graph_steps) {
-    if (!c->gexec && (rc = build_graph(c))) return rc;
+  if (left >= c->graph_steps) {
+    if (!c->gexec && (rc = build_graph(c, c->graph_steps, &c->graph, &c->gexec))) return rc;
     while (left >= c->graph_steps) {
       HIPCHK(hipGraphLaunch(c->gexec, c->stream));
       left -= c->graph_steps;
     }
   }
-  return enqueue_steps(c, left, c->stream);
+  if (left > 0) {
+    // the tail shorter than a chunk replays a graph of its own length, kept
+    // until a call ends with a different tail
+    if (c->gexec_rem && c->rem_steps != (int)left) {
+      hipGraphExecDestroy(c->gexec_rem);
+      hipGraphDestroy(c->graph_rem);
+      c->gexec_rem = nullptr;
+      c->graph_rem = nullptr;
+      c->rem_steps = 0;
+    }
+    if (!c->gexec_rem) {
+      if ((rc = build_graph(c, (int)left, &c->graph_rem, &c->gexec_rem))) return rc;
+      c->rem_steps = (int)left;
+    }
+    HIPCHK(hipGraphLaunch(c->gexec_rem, c->stream));
+  }
+  return TTSH_OK;
 }
 
-int ttsh_reseed(ttsh_ctx* c, int n, const int* dst, const int* src, const double* noise, int where) {
-  if (!c) return fail(TTSH_EINVAL, "null context");
-  if (n < 0 || (n > 0 && (!dst || !src))) return fail(TTSH_EINVAL, "bad reseed lists");
-  if (noise && where != TTSH_HOST && where != TTSH_DEVICE) return fail(TTSH_EINVAL, "bad where");
-  for (int q = 0; q < n; ++q) {
-    if (dst[q] < 0 || dst[q] >= c->n_inst || src[q] < 0 || src[q] >= c->n_inst)
-      return fail(TTSH_EINVAL, "reseed index out of range");
-    for (int r = 0; r < q; ++r)
-      if (dst[r] == dst[q]) return fail(TTSH_EINVAL, "duplicate reseed destination");
-  }
-  // gather every resampled source first
-  std::vector<size_t> off(n + 1, 0);
-  for (int q = 0; q < n; ++q) {
-    const int Nd = c->N[dst[q]];
-    off[q + 1] = off[q] + (size_t)2 * (Nd / 4 + 1) * (Nd / 2 + 2);
-  }
+int ttsh_reseed(ttsh_ctx* c, int n, const int* dst, const int* src, double noise_amp, uint64_t seed) {
+  int rc = reseed_check(c, n, dst, src);
+  if (rc) return rc;
+  if (!std::isfinite(noise_amp)) return fail(TTSH_EINVAL, "noise_amp must be finite");
   C2<double>* tmp = nullptr;
-  if (n > 0 && hipMalloc((void**)&tmp, off[n] * sizeof(C2<double>)) != hipSuccess)
+  const size_t need = reseed_scratch_elems(c, n, dst);
+  if (need > 0 && hipMalloc((void**)&tmp, need * sizeof(C2<double>)) != hipSuccess)
     return fail(TTSH_ENOMEM, "reseed scratch allocation failed");
-  auto done = [&](int rc) {
-    hipStreamSynchronize(c->stream);
-    if (tmp) hipFree(tmp);
-    return rc;
-  };
-  for (int q = 0; q < n; ++q) {
-    auto [cs, js] = c->loc[src[q]];
-    SizeClass& ks = c->cls[cs];
-    const int Nd = c->N[dst[q]];
-    const size_t cnt = off[q + 1] - off[q];
-    if (c->prec == 32)
-      hipLaunchKernelGGL(k_resample<float>, dim3(nblk(cnt)), dim3(kB), 0, c->stream,
-                         at<const C2<float>>(ks.st, ks.sSt(), sizeof(C2<float>), js), ks.N, tmp + off[q], Nd);
-    else
-      hipLaunchKernelGGL(k_resample<double>, dim3(nblk(cnt)), dim3(kB), 0, c->stream,
-                         at<const C2<double>>(ks.st, ks.sSt(), sizeof(C2<double>), js), ks.N, tmp + off[q], Nd);
-    if (hipGetLastError() != hipSuccess) return done(fail(TTSH_EHIP, "resample launch failed"));
-  }
-  size_t noff = 0;
-  for (int q = 0; q < n; ++q) {
-    const int Nd = c->N[dst[q]];
-    int rc;
-    if (noise) {
-      const double* blk = noise + noff;
-      const void* dev = nullptr;
-      if ((rc = stage_in(c, blk, sizeof(double) * 2 * Nd * Nd, where, &dev))) return done(rc);
-      if ((rc = field_to_spectrum(c, Nd, (const double*)dev))) return done(rc);
-      noff += (size_t)2 * Nd * Nd;
-    } else {
-      if (hipMemsetAsync(c->scr0, 0, sizeof(C2<double>) * Nd * Nd, c->stream) != hipSuccess)
-        return done(fail(TTSH_EHIP, "memset failed"));
-    }
-    if ((rc = pack_into_state(c, dst[q], tmp + off[q]))) return done(rc);
-    if ((rc = refresh_x(c, dst[q]))) return done(rc);
-    if (where == TTSH_HOST) hipStreamSynchronize(c->stream);
-  }
-  return done(TTSH_OK);
+  Noise nz;
+  nz.amp = noise_amp;
+  nz.seed = seed;
+  rc = reseed_impl(c, n, dst, src, nz, tmp);
+  hipStreamSynchronize(c->stream);
+  if (tmp) hipFree(tmp);
+  return rc;
+}
+
+int ttsh_reseed_field(ttsh_ctx* c, int n, const int* dst, const int* src, const double* noise, int where) {
+  int rc = reseed_check(c, n, dst, src);
+  if (rc) return rc;
+  if (noise && where != TTSH_HOST && where != TTSH_DEVICE) return fail(TTSH_EINVAL, "bad where");
+  C2<double>* tmp = nullptr;
+  const size_t need = reseed_scratch_elems(c, n, dst);
+  if (need > 0 && hipMalloc((void**)&tmp, need * sizeof(C2<double>)) != hipSuccess)
+    return fail(TTSH_ENOMEM, "reseed scratch allocation failed");
+  Noise nz;
+  nz.fields = noise;
+  nz.where = where;
+  rc = reseed_impl(c, n, dst, src, nz, tmp);
+  hipStreamSynchronize(c->stream);
+  if (tmp) hipFree(tmp);
+  return rc;
 }
 
 int ttsh_norms(ttsh_ctx* c, int inst, double out[4]) {

@@ -65,11 +65,9 @@ def run(radii, stages=None, steps=40_000, every=100, N=512, L=20.48, seed=5, log
             if st + 1 < stages:
                 dst = up[1:] + down[:-1]
                 src = up[:-1] + down[1:]
-                kick = None
-                if noise > 0:  # projected uniform noise on every hand-off
-                    rng = np.random.Generator(np.random.PCG64(seed + 7919 * (st + 1)))
-                    kick = rng.uniform(-noise, noise, size=(len(dst), 2, N, N))
-                s.reseed(dst, src, kick)
+                # projected uniform noise on every hand-off (none if noise == 0),
+                # drawn on the device
+                s.reseed(dst, src, noise, seed + 7919 * (st + 1))
         s.sync()
         secs = time.time() - t0
         last = record[-1]

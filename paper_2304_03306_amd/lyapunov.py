@@ -70,7 +70,7 @@ def run(radii, p=4, N=512, L=20.48, transient=50_000, tau=100, intervals=1000, r
         rng = np.random.Generator(np.random.PCG64(seed + 1000))
         dst = [q for r in range(nr) for q in pert[r]]
         src = [base[r] for r in range(nr) for _ in range(p)]
-        s.reseed(dst, src, rng.uniform(-1e-6, 1e-6, size=(len(dst), 2, N, N)))
+        s.reseed_field(dst, src, rng.uniform(-1e-6, 1e-6, size=(len(dst), 2, N, N)))
         eps = [rel_eps * np.sqrt(s.norms(b)[0]) for b in base]
         for r in range(nr):
             s.lyap_qr(base[r], pert[r], eps[r])

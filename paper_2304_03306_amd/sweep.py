@@ -59,9 +59,8 @@ def run(stages: int, steps: int, log=None, tune: bool = True, scheme: str = "ife
                 log(f"stage {st}: {steps} steps in {seconds[-1]:.2f} s; "
                     f"Psi up {np.round(psi[st, 0::2], 2).tolist()}")
             if st + 1 < stages:
-                noise = np.concatenate([W.uniform_field(W.noise_seed(st, q), inst[q].N, 1e-3, 32).ravel()
-                                        for q in range(n)])
-                s.reseed(list(range(n)), src, noise)
+                # U[-1e-3, 1e-3] noise per node, drawn on the device (Philox)
+                s.reseed(list(range(n)), src, 1e-3, W.stage_seed(st))
         radii = [inst[2 * j].radii[0] for j in range(n // 2)]
         return {"radii": radii, "stages": stages, "steps_per_stage": steps,
                 "psi_up": psi[:, 0::2].tolist(), "psi_down": psi[:, 1::2].tolist(),

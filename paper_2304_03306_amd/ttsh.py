@@ -67,7 +67,8 @@ def lib() -> ctypes.CDLL:
             "ttsh_set_state": [vp, i32, dp, i32],
             "ttsh_get_state": [vp, i32, dp, i32],
             "ttsh_step": [vp, i64],
-            "ttsh_reseed": [vp, i32, dp, dp, dp, i32],
+            "ttsh_reseed": [vp, i32, dp, dp, ctypes.c_double, ctypes.c_uint64],
+            "ttsh_reseed_field": [vp, i32, dp, dp, dp, i32],
             "ttsh_norms": [vp, i32, dp],
             "ttsh_sync": [vp],
             "ttsh_set_option": [vp, i32, i64],
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_pass_times": [vp, i64, dp],
             "ttsh_tune": [vp, i64, dp, dp],
             "ttsh_num_classes": [vp, dp],
+            "ttsh_stream_bench": [i32, i32, i64, i32, i32, vp, dp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -262,13 +264,26 @@ def ttsh_step(ctx, nsteps):
     return _check(lib().ttsh_step(ctx, int(nsteps)))
 
 
-def ttsh_reseed(ctx, dst, src, noise=None):
+def _index_lists(dst, src):
     n = len(dst)
+    if len(src) != n:
+        raise ValueError("dst and src must have the same length")
     d = (ctypes.c_int * n)(*[int(v) for v in dst])
     s = (ctypes.c_int * n)(*[int(v) for v in src])
+    return n, d, s
+
+
+def ttsh_reseed(ctx, dst, src, noise_amp=0.0, seed=0):
+    n, d, s = _index_lists(dst, src)
+    return _check(lib().ttsh_reseed(ctx, n, ctypes.cast(d, ctypes.c_void_p), ctypes.cast(s, ctypes.c_void_p),
+                                    float(noise_amp), int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+
+def ttsh_reseed_field(ctx, dst, src, noise=None):
+    n, d, s = _index_lists(dst, src)
     p, w, keep = _buf(noise, np.float64)
-    return _check(lib().ttsh_reseed(ctx, n, ctypes.cast(d, ctypes.c_void_p),
-                                    ctypes.cast(s, ctypes.c_void_p), p, w))
+    return _check(lib().ttsh_reseed_field(ctx, n, ctypes.cast(d, ctypes.c_void_p),
+                                          ctypes.cast(s, ctypes.c_void_p), p, w))
 
 
 def ttsh_norms(ctx, inst):
@@ -306,6 +321,24 @@ def ttsh_pass_times(ctx, nsteps):
     out = (ctypes.c_double * 2)()
     _check(lib().ttsh_pass_times(ctx, int(nsteps), ctypes.cast(out, ctypes.c_void_p)))
     return out[0], out[1]
+
+
+def ttsh_stream_bench(reads, writes, elems, blocks, reps, buf):
+    """Mean microseconds per launch of the streaming probe (reads, writes
+    arrays of `elems` 16-byte elements) on the device buffer `buf` (a torch
+    tensor or a device address) of at least (reads + max(writes, 1)) * elems
+    * 16 bytes."""
+    need = (reads + max(writes, 1)) * int(elems) * 16
+    if hasattr(buf, "data_ptr"):
+        if buf.numel() * buf.element_size() < need:
+            raise ValueError("stream buffer too small")
+        ptr = buf.data_ptr()
+    else:
+        ptr = int(buf)
+    out = ctypes.c_double()
+    _check(lib().ttsh_stream_bench(int(reads), int(writes), int(elems), int(blocks), int(reps),
+                                   ctypes.c_void_p(ptr), ctypes.byref(out)))
+    return out.value
 
 
 def ttsh_tune(ctx, nsteps):
@@ -411,8 +444,13 @@ class Solver:
     def option(self, key, value):
         ttsh_set_option(self.ctx, key, value)
 
-    def reseed(self, dst, src, noise=None):
-        ttsh_reseed(self.ctx, dst, src, noise)
+    def reseed(self, dst, src, noise_amp=0.0, seed=0):
+        """Continuation with device-drawn (Philox) noise of amplitude noise_amp."""
+        ttsh_reseed(self.ctx, dst, src, noise_amp, seed)
+
+    def reseed_field(self, dst, src, noise=None):
+        """Continuation with caller-drawn noise fields ([n][2][N][N] or flat)."""
+        ttsh_reseed_field(self.ctx, dst, src, noise)
 
     def tune(self, nsteps=20):
         return ttsh_tune(self.ctx, nsteps)

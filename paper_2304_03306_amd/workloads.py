@@ -9,7 +9,11 @@ same numbers.
 
 Random numbers: numpy's PCG64 generator seeded with the stated integer, one
 i.i.d. uniform draw per node and component, in FP64; a run in FP32 rounds the
-field to FP32 before either side sees it.
+field to FP32 before either side sees it.  The continuation noise that the
+library draws on the device comes from the counter-based Philox-4x32-10
+generator (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy
+as 1, 2, 3", SC'11); `philox4x32_10` below implements the same published
+definition in Python, so that the oracle side sees the same numbers.
 """
 from __future__ import annotations
 
@@ -42,6 +46,47 @@ def binary_outside(N: int, L: float, centers, radii) -> np.ndarray:
     for (cx, cy), R in zip(centers, radii):
         out &= np.sqrt((x - cx) ** 2 + (y - cy) ** 2) >= R
     return out.astype(np.uint8)
+
+
+# ---- Philox-4x32-10 ---------------------------------------------------------------
+_U32 = np.uint64(0xFFFFFFFF)
+_PHILOX_MUL = (np.uint64(0xD2511F53), np.uint64(0xCD9E8D57))
+_PHILOX_WEYL = (np.uint64(0x9E3779B9), np.uint64(0xBB67AE85))
+
+
+def philox4x32_10(ctr, key):
+    """Philox-4x32 with 10 rounds.  ctr: four equal-shape arrays (or ints) of
+    32-bit counter words; key: two 32-bit key words.  Each round multiplies
+    counter words 0 and 2 by the two multipliers into 64-bit products and
+    forms (hi(p1) ^ c1 ^ k0, lo(p1), hi(p0) ^ c3 ^ k1, lo(p0)); the key is
+    bumped by the two Weyl constants between rounds.  Returns the four output
+    words as uint64 arrays holding 32-bit values."""
+    c0, c1, c2, c3 = (np.asarray(c, dtype=np.uint64) & _U32 for c in ctr)
+    k0, k1 = np.uint64(int(key[0]) & 0xFFFFFFFF), np.uint64(int(key[1]) & 0xFFFFFFFF)
+    for r in range(10):
+        if r:
+            k0 = (k0 + _PHILOX_WEYL[0]) & _U32
+            k1 = (k1 + _PHILOX_WEYL[1]) & _U32
+        p0 = _PHILOX_MUL[0] * c0
+        p1 = _PHILOX_MUL[1] * c2
+        c0, c1, c2, c3 = (p1 >> np.uint64(32)) ^ c1 ^ k0, p1 & _U32, (p0 >> np.uint64(32)) ^ c3 ^ k1, p0 & _U32
+    return c0, c1, c2, c3
+
+
+def philox_noise(seed: int, instance: int, N: int, amp: float) -> np.ndarray:
+    """The continuation noise of ttsh_reseed for destination `instance`,
+    [2][N][N] float64: key = (seed mod 2^32, seed >> 32), counter = (i N + j,
+    instance, 0, 0) for node (i, j); output word c gives component c as
+    amp (2 u - 1) with u = (word >> 8) 2^-24, evaluated in FP64 (exact up to
+    the final multiplication by amp)."""
+    seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    idx = np.arange(N * N, dtype=np.uint64).reshape(N, N)
+    w = philox4x32_10((idx, np.uint64(instance), np.uint64(0), np.uint64(0)), (seed & 0xFFFFFFFF, seed >> 32))
+    out = np.empty((2, N, N))
+    for c in range(2):
+        u = (w[c] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+        out[c] = amp * (2.0 * u - 1.0)
+    return out
 
 
 @dataclasses.dataclass(frozen=True)
@@ -159,6 +204,7 @@ def dumbbells(n: int = 16, N: int = 1024) -> Workload:
     return Workload("dumbbell1024_fp32", 32, 0.01, 50_000, inst)
 
 
-def noise_seed(stage: int, instance: int) -> int:
-    """Seed of the reseed noise of one instance at one stage."""
-    return 1_000_003 * (stage + 1) + instance
+def stage_seed(stage: int) -> int:
+    """Seed of the continuation noise drawn after stage `stage` (the noise of
+    each destination instance is told apart by its index in the counter)."""
+    return 1_000_003 * (stage + 1)

@@ -26,7 +26,7 @@ def _perturbed_context(gpu, prec, N=64, L=32.0, p=4, steps=40, amp=1e-3):
         s.mask_tanh(q, [(0.0, 0.0)], [10.0], 0.5)
     s.set_field(0, W.uniform_field(7, N, 0.1, prec))
     noise = np.stack([W.uniform_field(100 + v, N, amp) for v in range(p)])
-    s.reseed(list(range(1, p + 1)), [0] * p, noise)
+    s.reseed_field(list(range(1, p + 1)), [0] * p, noise)
     s.step(steps)
     s.sync()
     return s, par
@@ -112,7 +112,7 @@ def test_lyapunov_linear_spectrum_on_device(gpu):
     s = gpu.Solver([N] * (p + 1), [Lbox] * (p + 1), par, 64)
     try:
         s.set_field(0, np.zeros((2, N, N)))
-        s.reseed(list(range(1, p + 1)), [0] * p, np.stack([W.uniform_field(20 + v, N, 1e-3) for v in range(p)]))
+        s.reseed_field(list(range(1, p + 1)), [0] * p, np.stack([W.uniform_field(20 + v, N, 1e-3) for v in range(p)]))
         s.lyap_qr(0, list(range(1, p + 1)), 1e-6)
         logs = []
         for _ in range(60):

@@ -146,7 +146,9 @@ def test_circle64_fp64_2000_steps(gpu):
     s.mask_tanh(0, inst.centers, inst.radii, inst.xi)
     s.set_field(0, v0)
     vh = O.project_field(v0, inst.L)
-    for upto, tol in ((1000, 1e-10), (2000, 2e-6)):
+    # step 2000: the measured error (6.9e-8) sits at the FP64 twin floor; the
+    # bound is 3x that floor
+    for upto, tol in ((1000, 1e-10), (2000, 2.1e-7)):
         s.step(1000)
         s.sync()
         vh = O.run_velocity(vh, K, p, inst.L, 1000)
@@ -196,16 +198,18 @@ def test_graph_equals_eager(gpu):
     K = O.mask_tanh(N, L, [(0.0, 0.0)], [16.0], 0.5)
     v0 = W.uniform_field(4, N, 0.2, 32)
     out = []
-    for g in (0, 7):
+    # whole chunks, tails of several lengths (each replays a graph of its own
+    # length, rebuilt when the tail changes) and a call shorter than a chunk
+    for g in (0, 7, 50):
         s = make(gpu, N, L, p, 32)
         s.option(gpu.TTSH_OPT_GRAPH_STEPS, g)
         s.set_mask(0, K)
         s.set_field(0, v0)
-        for _ in range(3):
-            s.step(23)
+        for n in (23, 17, 23, 50, 3, 3):
+            s.step(n)
             s.sync()
         out.append(s.state(0))
-    assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
 def test_resume_bitwise(gpu):
@@ -319,11 +323,47 @@ def test_reseed_matches_oracle(gpu):
     before = [O.from_compact(s.state(i), N) for i, N in enumerate(Ns)]
     dst, src = [0, 1, 2, 3], [1, 0, 3, 2]
     noise = [W.uniform_field(60 + q, Ns[d], 1e-3) for q, d in enumerate(dst)]
-    s.reseed(dst, src, np.concatenate([n.ravel() for n in noise]))
+    s.reseed_field(dst, src, np.concatenate([n.ravel() for n in noise]))
     for q, (d, sr) in enumerate(zip(dst, src)):
         want = O.resample(before[sr], Ns[d]) + O.project_field(noise[q], Ls[d])
         got = O.from_compact(s.state(d), Ns[d])
         assert np.abs(got - want).max() < 1e-12 * np.abs(want).max(), (d, sr)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_reseed_philox_matches_oracle(gpu, prec):
+    """Continuation with device noise: destination d takes resample(source) +
+    P DFT(noise_d), noise_d the Philox stream of (seed, d) that the
+    input-generator module reproduces in Python; mixed grid sizes, a swap, a
+    destination that is also its own source.  With noise_amp = 0 the copy is
+    the plain resample."""
+    say("reseed philox", prec)
+    p = O.workload_params()
+    Ns, Ls = [128, 256, 128, 64, 256], [64.0, 128.0, 64.0, 32.0, 128.0]
+    s = gpu.Solver(Ns, Ls, p, prec)
+    for i, (N, L) in enumerate(zip(Ns, Ls)):
+        s.mask_tanh(i, [(0.0, 0.0)], [L / 4], 0.5)
+        s.set_field(i, W.uniform_field(80 + i, N, 0.3, prec))
+    s.step(5)
+    s.sync()
+    before = [O.from_compact(s.state(i), N) for i, N in enumerate(Ns)]
+    dst, src = [0, 1, 2, 3, 4], [1, 0, 3, 2, 4]
+    amp, seed = 1e-3, (11 << 32) | 77
+    s.reseed(dst, src, amp, seed)
+    tol = 1e-12 if prec == 64 else 1e-6
+    for d, sr in zip(dst, src):
+        want = O.resample(before[sr], Ns[d]) + O.project_field(W.philox_noise(seed, d, Ns[d], amp), Ls[d])
+        got = O.from_compact(s.state(d), Ns[d])
+        assert np.abs(got - want).max() < tol * np.abs(want).max(), (d, sr)
+    # no noise: the plain mode-index copy
+    before = [O.from_compact(s.state(i), N) for i, N in enumerate(Ns)]
+    s.reseed([1, 3], [2, 4], 0.0, seed)
+    for d, sr in ((1, 2), (3, 4)):
+        want = O.resample(before[sr], Ns[d])
+        got = O.from_compact(s.state(d), Ns[d])
+        assert np.abs(got - want).max() < tol * np.abs(want).max(), (d, sr)
+    with pytest.raises(gpu.TTSHError):
+        s.reseed([0, 0], [1, 2], amp, seed)
 
 
 # ---- coarse fields (surrogate data path) ------------------------------------------
@@ -401,10 +441,18 @@ def test_failure_injection_nonfinite_input_and_unstable_mask(gpu):
     p = O.workload_params()
     s = make(gpu, N, L, p, 32)
     v = W.uniform_field(3, N, 0.1, 32)
-    v[1, 5, 7] = np.nan
-    with pytest.raises(gpu.TTSHError) as e:
-        s.set_field(0, v)
-    assert e.value.code == gpu.TTSH_ENONFINITE
+    s.set_field(0, v)
+    kept = s.state(0)
+    for bad_value in (np.nan, np.inf):
+        w = v.copy()
+        w[1, 5, 7] = bad_value
+        with pytest.raises(gpu.TTSHError) as e:
+            s.set_field(0, w)
+        assert e.value.code == gpu.TTSH_ENONFINITE
+        # the refused field left the instance as it was
+        assert np.array_equal(s.state(0), kept)
+    s.step(2)
+    s.sync()
     bad = dataclasses.replace(p, gamma_v=300.0)
     u = gpu.Solver([N, N], [L, L], bad, 32)
     u.set_mask(0, np.zeros((N, N)))

@@ -129,3 +129,30 @@ def test_pmc_summary_scaling_and_source_check(tmp_path, monkeypatch):
     s["source_sha256"] = "0" * 64
     out.write_text(json.dumps(s))
     assert bench.measured_traffic("row_multi", 64) is None
+
+
+def test_philox_known_answers():
+    """The Python Philox-4x32-10 against the published known-answer vectors of
+    the generator's authors (Salmon et al., SC'11, Random123 test set)."""
+    from paper_2304_03306_amd import workloads as W
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+             ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+             ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+              (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in cases:
+        assert tuple(int(w) for w in W.philox4x32_10(ctr, key)) == want
+
+
+def test_philox_noise_layout_and_range():
+    """philox_noise: node (i, j) uses counter (iN + j, instance, 0, 0), word c
+    gives component c; values lie in [-amp, amp) and are 24-bit grid values."""
+    from paper_2304_03306_amd import workloads as W
+    N, amp, seed, inst = 16, 1e-3, (7 << 32) | 5, 3
+    z = W.philox_noise(seed, inst, N, amp)
+    i, j = 5, 11
+    w = W.philox4x32_10((i * N + j, inst, 0, 0), (5, 7))
+    for c in range(2):
+        assert z[c, i, j] == amp * (2.0 * (int(w[c]) >> 8) * 2.0 ** -24 - 1.0)
+    assert z.min() >= -amp and z.max() < amp
+    assert not np.array_equal(z, W.philox_noise(seed, inst + 1, N, amp))
+    assert not np.array_equal(z, W.philox_noise(seed + 1, inst, N, amp))
