@@ -680,3 +680,123 @@ def test_paper_preset_is_table_one():
     assert (p.lambda0, p.beta, p.gamma_v, p.gamma_w, p.dt, p.lambda1) == (lam, b, gv, gw, dt, 0.0)
     k2 = np.array([0.0, 0.25, 1.0, 1.7, 4.0])
     assert np.abs(O.linear_symbol(k2, p) - (a - (1.0 - k2) ** 2)).max() < 1e-14
+
+
+# ---- fourth-order exponential Runge-Kutta (ETDRK4, Cox and Matthews 2002) ---------------------
+def test_phi_123_match_high_precision():
+    """phi_k(z) = sum_j z^j/(j+k)!, k = 1, 2, 3, against 40-digit evaluations
+    of their closed forms, across the series / recurrence switch at |z| = 1/2
+    and into the stiff range."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    z = np.array([0.0, 1e-12, -3e-6, 4e-3, -0.3, 0.49, -0.5, 0.51, -2.0, 1.25, -80.0, -5e3])
+    got = O.phi_123(z)
+    for i, zi in enumerate(z):
+        if zi == 0.0:
+            want = (1.0, 0.5, 1.0 / 6.0)
+        else:
+            q = mpmath.mpf(float(zi))
+            e = mpmath.expm1(q)
+            want = (float(e / q), float((e - q) / q ** 2), float((e - q - q * q / 2) / q ** 3))
+        for k in range(3):
+            assert abs(got[k][i] - want[k]) <= 1e-13 * abs(want[k]), (zi, k, got[k][i], want[k])
+
+
+def _etdrk4_scalar(z, w):
+    """Amplification of ETDRK4 on u' = (L + lam) u with z = L h, w = lam h,
+    worked out by hand from the scheme's four stages (phi functions from 40
+    digits): a = (e^{z/2} + q w) u with q = phi_1(z/2)/2, b = e^{z/2} u + q w a,
+    c = e^{z/2} a + q w (2 b - u), u' = e^z u + w (f1 u + 2 f2 (a + b) + f3 c)."""
+    import mpmath
+    mpmath.mp.dps = 40
+    Z, Wm = mpmath.mpf(z), mpmath.mpf(w)
+    ph = lambda k, x: sum(x ** j / mpmath.factorial(j + k) for j in range(60))
+    E, E2, q = mpmath.exp(Z), mpmath.exp(Z / 2), ph(1, Z / 2) / 2
+    f1 = ph(1, Z) - 3 * ph(2, Z) + 4 * ph(3, Z)
+    f2 = ph(2, Z) - 2 * ph(3, Z)
+    f3 = -ph(2, Z) + 4 * ph(3, Z)
+    A = E2 + q * Wm
+    B = E2 + q * Wm * A
+    C = E2 * A + q * Wm * (2 * B - 1)
+    return float(E + Wm * (f1 + 2 * f2 * (A + B) + f3 * C))
+
+
+def test_etdrk4_linear_forcing_closed_form():
+    """With a constant mask K = c and beta = lambda0 = 0 the forcing is the
+    linear -gamma_v c v, so every mode follows u_n = R^n u_0 with R the
+    scheme's scalar amplification (worked out by hand, above); and R^n tends
+    to the exact e^{(L - gamma_v c) t} at fourth order in h.  A stage fed the
+    wrong state or a swapped coefficient fails the first check."""
+    pytest.importorskip("mpmath")
+    N, L, c, n = 16, 2 * math.pi * 4.0, 0.3, 40
+    p = dataclasses.replace(zero_nl(O.workload_params()), gamma_v=50.0, dt=0.02, scheme="etdrk4")
+    v0 = O.project_field(mode_field(N, L, 1, 2) + mode_field(N, L, 3, 0, 0.5, 1.1), L)
+    vh = O.run_velocity(v0, np.full((N, N), c), p, L, n)
+    for mx, my in ((1, 2), (3, 0)):
+        k2 = (2 * math.pi / L) ** 2 * (mx * mx + my * my)
+        Lk = 1.0 + k2 - k2 * k2
+        R = _etdrk4_scalar(Lk * p.dt, -p.gamma_v * c * p.dt)
+        for comp in range(2):
+            if abs(v0[comp, my % N, mx]) > 0:
+                assert abs(vh[comp, my % N, mx] / v0[comp, my % N, mx] - R ** n) < 1e-12 * R ** n
+    # the hand-worked amplification is a fourth-order approximation of the exponential
+    Lk, lam, T = 1.0 + 0.5 - 0.25, -5.0, 0.4
+    err = [abs(_etdrk4_scalar(Lk * h, lam * h) ** round(T / h) - math.exp((Lk + lam) * T)) for h in (0.02, 0.01, 0.005)]
+    assert 15.0 < err[0] / err[1] < 18.0 and 15.0 < err[1] / err[2] < 17.5, err
+
+
+@pytest.mark.parametrize("k2,rate", [(0.5, 1.25), (2.0, 1.0 + 2.0 - 4.0)])
+def test_etdrk4_linear_modes_are_exact(k2, rate):
+    """With the forcing switched off every stage reduces to the exponential:
+    a single mode grows or decays at exactly L(k) (P3/P4)."""
+    N, n = 16, 200
+    p = dataclasses.replace(zero_nl(O.workload_params()), scheme="etdrk4")
+    L = 2 * math.pi * math.sqrt(2.0 / k2)
+    v0 = O.project_field(mode_field(N, L, 1, 1), L)
+    vh = O.run_velocity(v0, np.zeros((N, N)), p, L, n)
+    got = math.log(abs(vh[1, 1, 1]) / abs(v0[1, 1, 1])) / (n * p.dt)
+    assert abs(got - rate) < 1e-11, (got, rate)
+
+
+@pytest.mark.parametrize("preset", ["workload", "paper"])
+def test_etdrk4_fourth_order_convergence(preset):
+    """Errors against the finest run scale as dt^4: for dt = 8h, 4h, 2h against
+    h the differences are c (8^4 - 1, 4^4 - 1, 2^4 - 1) h^4, ratios 273 and 17
+    (a third-order slip gives 73 and 9).  The paper preset exercises the
+    gamma_w source."""
+    N, L = 16, 16.0
+    K = O.mask_tanh(N, L, [(0, 0)], [5.0], 0.5)
+    v0 = O.project_field(W.uniform_field(11, N, 0.8), L)
+    if preset == "workload":
+        base, T_end, dts = dataclasses.replace(O.workload_params(), gamma_v=10.0), 0.4, (0.02, 0.01, 0.005, 0.0025)
+    else:
+        base, T_end, dts = dataclasses.replace(O.paper_params(), gamma_v=10.0, gamma_w=2.0), 0.2, (0.01, 0.005, 0.0025, 0.00125)
+    out = {dt: O.run_velocity(v0, K, dataclasses.replace(base, dt=dt, scheme="etdrk4"), L, int(round(T_end / dt)))
+           for dt in dts}
+    e = [np.abs(out[dt] - out[dts[-1]]).max() for dt in dts[:3]]
+    assert 240.0 < e[0] / e[2] < 330.0 and 16.0 < e[1] / e[2] < 19.0, e
+
+
+def test_etdrk4_solves_the_same_equation_as_etdrk2():
+    """ETDRK4 at dt and ETD2RK at dt/4 approach the same solution: their
+    difference is below a tenth of ETD2RK's own change from dt to dt/4
+    (ETD2RK's error shrinks 16-fold, ETDRK4's is far smaller)."""
+    N, L, T_end, dt = 16, 16.0, 0.4, 0.01
+    K = O.mask_tanh(N, L, [(0, 0)], [5.0], 0.5)
+    v0 = O.project_field(W.uniform_field(11, N, 0.8), L)
+    base = dataclasses.replace(O.workload_params(), gamma_v=10.0)
+    e4 = O.run_velocity(v0, K, dataclasses.replace(base, dt=dt, scheme="etdrk4"), L, int(round(T_end / dt)))
+    e2a = O.run_velocity(v0, K, dataclasses.replace(base, dt=dt, scheme="etdrk2"), L, int(round(T_end / dt)))
+    e2b = O.run_velocity(v0, K, dataclasses.replace(base, dt=dt / 4, scheme="etdrk2"), L, int(round(4 * T_end / dt)))
+    assert np.abs(e4 - e2b).max() < 0.1 * np.abs(e2a - e2b).max()
+
+
+def test_etdrk4_stays_divergence_free_and_hermitian():
+    N, L = 32, 32.0
+    K = O.mask_tanh(N, L, [(0, 0)], [10.0], 0.5)
+    p = dataclasses.replace(O.workload_params(), scheme="etdrk4")
+    vh = O.project_field(W.uniform_field(13, N, 0.01), L)
+    kx, ky, _, _ = O.grid(N, L)
+    vh = O.run_velocity(vh, K, p, L, 600)
+    assert np.abs(kx * vh[0] + ky * vh[1]).max() < 1e-13 * np.abs(vh).max()
+    assert np.array_equal(vh, np.conj(O.reflect(vh)))
