@@ -71,8 +71,21 @@ enum { TTSH_HOST = 0, TTSH_DEVICE = 1 };
  *                 dt phi1(z) f(u), then u' = a + dt phi2(z) (f(a) - f(u)),
  *                 phi2(z) = (exp(z) - 1 - z)/z^2; two forcing evaluations
  *                 (twice the kernels) per step and, per instance, a second
- *                 state and the stage-1 forcing spectra on the device.     */
-enum { TTSH_IFEULER = 0, TTSH_ETD1 = 1, TTSH_IMEX = 2, TTSH_ETDRK2 = 3 };
+ *                 state and the stage-1 forcing spectra on the device.
+ *   TTSH_ETDRK4   fourth-order exponential Runge-Kutta (Cox and Matthews,
+ *                 ETDRK4): with h = dt,
+ *                   a = e^{z/2} u + (h/2) phi1(z/2) f(u)
+ *                   b = e^{z/2} u + (h/2) phi1(z/2) f(a)
+ *                   c = e^{z/2} a + (h/2) phi1(z/2) (2 f(b) - f(u))
+ *                   u' = e^z u + h [f1 f(u) + 2 f2 (f(a) + f(b)) + f3 f(c)],
+ *                 f1 = phi1 - 3 phi2 + 4 phi3, f2 = phi2 - 2 phi3,
+ *                 f3 = -phi2 + 4 phi3, phi3(z) = (e^z - 1 - z - z^2/2)/z^3;
+ *                 four forcing evaluations per step and, per instance, a
+ *                 second state and two kept forcing spectra.
+ * Every stage of the Runge-Kutta schemes applies Algorithm 1's rules
+ * (projection of the whole update, k = 0 rule on rhs1, 1/2-rule cutoff,
+ * Hermitian correction).                                                    */
+enum { TTSH_IFEULER = 0, TTSH_ETD1 = 1, TTSH_IMEX = 2, TTSH_ETDRK2 = 3, TTSH_ETDRK4 = 4 };
 
 /* Arithmetic of the step (precision argument of ttsh_create):
  *   TTSH_FP64         everything in FP64;
@@ -86,7 +99,7 @@ typedef struct {
   double gamma_v; /* velocity damping in the wall, -gamma_v K v  (eq. (4)) */
   double gamma_w; /* vorticity damping in the wall, -gamma_w K omega (eq. (4)) */
   double dt;
-  int scheme;     /* TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX or TTSH_ETDRK2 */
+  int scheme;     /* TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX, TTSH_ETDRK2 or TTSH_ETDRK4 */
 } ttsh_params;
 
 /* Options for ttsh_set_option. */
@@ -295,11 +308,13 @@ int ttsh_norms(ttsh_ctx* ctx, int inst, double out[4]);
  * TTSH_ENONFINITE if any instance holds NaN/Inf.                           */
 int ttsh_sync(ttsh_ctx* ctx);
 
-/* Measurement: advance every instance by nsteps >= 1 steps without graphs,
- * bracketing each of the two kernel launches of a step (row pass, column
- * pass; each covers every instance) with HIP events on the context's stream,
- * and return their mean durations in microseconds: out[0] = row pass,
- * out[1] = column pass.  Synchronous.                                      */
+/* Measurement: launch the row pass nsteps >= 1 times back to back, then the
+ * column pass (integrating-factor Euler form) nsteps times back to back, each
+ * run between two HIP events on the context's stream, and return the mean
+ * launch durations in microseconds: out[0] = row pass, out[1] = column pass
+ * (each launch covers every instance).  The row pass always reads the same
+ * fields; the column pass re-applies its update with the same forcing, so
+ * the state changes: save it first if it matters.  Synchronous.            */
 int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
 
 /* Autotuner: time nsteps steps with every usable workgroup size, each as one

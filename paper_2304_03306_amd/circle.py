@@ -120,7 +120,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200_000)
     ap.add_argument("--transient", type=int, default=50_000)
     ap.add_argument("--every", type=int, default=200)
-    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2"])
+    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2", "etdrk4"])
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--psd-fmax", type=float, default=0.1,
                     help="vorticity PSD up to this frequency (cycles per unit time; 0: off)")

@@ -74,6 +74,84 @@ __device__ __forceinline__ double phi2(double z) {
   return (expm1(z) - z) / (z * z);
 }
 
+// phi_1, phi_2, phi_3 at z (phi_k(z) = sum_j z^j/(j+k)!): below |z| = 1/2 the
+// series, 16 terms by Horner (the first term left out is below
+// 2^-16/16! < 1e-18 of the sum); elsewhere phi_1 = expm1(z)/z and the
+// recurrence phi_k = (phi_{k-1} - 1/(k-1)!)/z, whose subtractions then lose
+// at most a few bits
+struct InvFact {
+  double v[19];
+  constexpr InvFact() : v() {
+    double f = 1.0;
+    v[0] = 1.0;
+    for (int i = 1; i < 19; ++i) {
+      f *= i;
+      v[i] = 1.0 / f;
+    }
+  }
+};
+
+__device__ __forceinline__ void phi123(double z, double& p1, double& p2, double& p3) {
+  constexpr InvFact inv;
+  if (fabs(z) < 0.5) {
+    double a1 = inv.v[16], a2 = inv.v[17], a3 = inv.v[18];
+#pragma unroll
+    for (int j = 14; j >= 0; --j) {
+      a1 = fma(a1, z, inv.v[j + 1]);
+      a2 = fma(a2, z, inv.v[j + 2]);
+      a3 = fma(a3, z, inv.v[j + 3]);
+    }
+    p1 = a1;
+    p2 = a2;
+    p3 = a3;
+  } else {
+    p1 = expm1(z) / z;
+    p2 = (p1 - 1.0) / z;
+    p3 = (p2 - 0.5) / z;
+  }
+}
+
+// phi_1 alone, the same way
+__device__ __forceinline__ double phi1(double z) {
+  constexpr InvFact inv;
+  if (fabs(z) < 0.5) {
+    double a1 = inv.v[16];
+#pragma unroll
+    for (int j = 14; j >= 0; --j) a1 = fma(a1, z, inv.v[j + 1]);
+    return a1;
+  }
+  return expm1(z) / z;
+}
+
+// Weights of an ETDRK4 stage (Cox and Matthews 2002) at z = L dt: the stage
+// is  u_out = A base + dt (w_new F_new + w_u F(u) + w_acc (F(a) + F(b)))
+//   MODE 4 (a):  A = e^{z/2}, w_new = phi_1(z/2)/2                     (base u)
+//   MODE 5 (b):  A = e^{z/2}, w_new = phi_1(z/2)/2                     (base u)
+//   MODE 6 (c):  A = e^{z/2}, w_new = phi_1(z/2), w_u = -phi_1(z/2)/2  (base a)
+//   MODE 7 (u'): A = e^z, w_u = f1, w_acc = 2 f2, w_new = f3           (base u)
+//                with f1 = phi_1 - 3 phi_2 + 4 phi_3, f2 = phi_2 - 2 phi_3,
+//                f3 = -phi_2 + 4 phi_3 at z
+template <int MODE>
+__device__ __forceinline__ void etd4_weights(const LinCoef& c, double dk, int m2, double& A, double& wn, double& wu,
+                                             double& wa) {
+  const double k2 = dk * dk * (double)m2;
+  const double z = (-c.alpha - c.gamma0 * k2 - c.gamma2 * k2 * k2) * c.dt;
+  if constexpr (MODE == 7) {
+    double p1, p2, p3;
+    phi123(z, p1, p2, p3);
+    A = exp(z);
+    wu = p1 - 3.0 * p2 + 4.0 * p3;
+    wa = 2.0 * (p2 - 2.0 * p3);
+    wn = -p2 + 4.0 * p3;
+  } else {
+    A = exp(0.5 * z);
+    const double q = 0.5 * phi1(0.5 * z);
+    wn = MODE == 6 ? 2.0 * q : q;
+    wu = MODE == 6 ? -q : 0.0;
+    wa = 0.0;
+  }
+}
+
 // (A, B) of column MODE 0 (one-stage schemes) or of an ETD2RK stage
 // (MODE 2: A = e^z, B = phi_1(z); MODE 3: A = 1, B = phi_2(z))
 template <int MODE>
@@ -328,6 +406,14 @@ __device__ __forceinline__ void hermitian_fix(C2<double> (&u)[kFftE], C2<double>
 // stage state st2, and keeps its forcing spectra (compact, as the state:
 // [NFY][M+1][2M+2]) in fst and its k = 0 forcing sums in s1st; stage 2 reads
 // st2 and the kept values and writes st.
+// MODE 4..7: the four stages of ETDRK4 (weights in etd4_weights).  Per
+// instance fst holds two slots [2][NFY][M+1][2M+2] (slot 0: F(u), slot 1:
+// F(a) + F(b)) and s1st four k = 0 sums (the same two, x and y).  Stage a
+// (MODE 4) reads st, writes st2 = a and slot 0; stage b (5) reads st and
+// writes slot 1; stage c (6) reads st2 and slot 0 and adds to slot 1; the
+// last stage (7) reads st and both slots and writes st.  Stages b and c
+// leave no state behind: only their mixed-domain fields X, which the next
+// row pass turns into F(b) and F(c).
 template <int N, int TC, class T, class S, bool GW, int MODE>
 __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X,
                                          C2<S>* __restrict__ st, const T* __restrict__ rowsum,
@@ -355,9 +441,12 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
   const bool valid = mx <= M;
   const double dk = dkv[inst];
   C2<T>* L = reinterpret_cast<C2<T>*>(smem) + col * G::LS;
-  C2<S>* stp = (MODE == 3 ? st2 : st) + inst * 2 * MP * SP;         // state read
-  C2<S>* stq = (MODE == 2 ? st2 : st) + inst * 2 * MP * SP;         // state written
-  C2<T>* fsp = (MODE >= 2) ? fst + inst * NFY * MP * SP : nullptr;  // stage-1 forcing
+  constexpr int SLOTS = MODE >= 4 ? 2 : 1;                                  // kept forcing spectra
+  constexpr bool STORE = !(MODE == 5 || MODE == 6);                        // the stage keeps its state
+  C2<S>* stp = ((MODE == 3 || MODE == 6) ? st2 : st) + inst * 2 * MP * SP;  // state read
+  C2<S>* stq = ((MODE == 2 || MODE == 4) ? st2 : st) + inst * 2 * MP * SP;  // state written
+  C2<T>* fsp = (MODE >= 2) ? fst + inst * SLOTS * NFY * MP * SP : nullptr;  // kept forcing
+  double sux = 0.0, suy = 0.0, sax = 0.0, say = 0.0;                       // kept k = 0 sums
 
   C2<T> f[NFY][E];
   double s1x = 0.0, s1y = 0.0;
@@ -381,8 +470,25 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
         s1x += R[2 * w];
         s1y += R[2 * w + 1];
       }
+      double* s4 = MODE >= 4 ? s1st + 4 * inst : nullptr;
+      if constexpr (MODE == 6 || MODE == 7) {  // read before the barrier, written after it
+        sux = s4[0];
+        suy = s4[1];
+        sax = s4[2];
+        say = s4[3];
+      }
       __syncthreads();
-      if constexpr (MODE == 2) {
+      if constexpr (MODE == 4 || MODE == 5) {
+        if (tid == 0) {
+          s4[MODE == 4 ? 0 : 2] = s1x;
+          s4[MODE == 4 ? 1 : 3] = s1y;
+        }
+      } else if constexpr (MODE == 6) {
+        if (tid == 0) {
+          s4[2] = sax + s1x;
+          s4[3] = say + s1y;
+        }
+      } else if constexpr (MODE == 2) {
         if (tid == 0) {
           s1st[2 * inst] = s1x;
           s1st[2 * inst + 1] = s1y;
@@ -406,7 +512,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       if constexpr (GW) f[2][e] = valid ? Yp[mix_idx<N>(2, mx, t + e * TT)] : mk<T>(0, 0);
     }
     fft<N, -1, NFY>(f, L, t, tw);
-    if constexpr (MODE >= 2) {  // keep (stage 1) or subtract (stage 2) the stage-1 forcing
+    if constexpr (MODE == 2 || MODE == 3) {  // keep (stage 1) or subtract (stage 2) the stage-1 forcing
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int idx = t + e * TT;
@@ -440,7 +546,53 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
     if (valid && (lo || hi) && m2 <= M * M) {
       const C2<double> ux = cvt<double>(stp[(0 * MP + mx) * SP + pos]);
       const C2<double> uy = cvt<double>(stp[(1 * MP + mx) * SP + pos]);
-      if constexpr (MODE != 1) {
+      if constexpr (MODE >= 4) {
+        // ETDRK4 stage: the combination of the new forcing with the kept ones,
+        // kept spectra updated on the way
+        double A, wn, wu, wa;
+        etd4_weights<MODE>(lc, dk, m2, A, wn, wu, wa);
+        C2<double> g[NFY];
+#pragma unroll
+        for (int q = 0; q < NFY; ++q) {
+          C2<T>* s0 = fsp + (q * MP + mx) * SP + pos;
+          C2<T>* s1 = fsp + ((NFY + q) * MP + mx) * SP + pos;
+          const C2<T> fn = f[q][e];
+          g[q] = cscale(cvt<double>(fn), wn);
+          if constexpr (MODE == 4) *s0 = fn;
+          if constexpr (MODE == 5) *s1 = fn;
+          if constexpr (MODE == 6) {
+            g[q] = g[q] + cscale(cvt<double>(*s0), wu);
+            *s1 = *s1 + fn;
+          }
+          if constexpr (MODE == 7) g[q] = g[q] + cscale(cvt<double>(*s0), wu) + cscale(cvt<double>(*s1), wa);
+        }
+        const double dt_over_N = lc.dt_over_N;
+        if (m2 == 0) {
+          nx[e] = cscale(ux, A) + mk(dt_over_N * (wn * s1x + wu * sux + wa * sax), 0.0);
+          ny[e] = cscale(uy, A) + mk(dt_over_N * (wn * s1y + wu * suy + wa * say), 0.0);
+        } else {
+          double inv_m2;
+          {
+            const double dm = (double)m2;
+            double r = (double)__frcp_rn((float)m2);
+            r = r * (2.0 - dm * r);
+            inv_m2 = r * (2.0 - dm * r);
+          }
+          C2<double> qx = cscale(ux, A) + cscale(g[0], dt_over_N);
+          C2<double> qy = cscale(uy, A) + cscale(g[1], dt_over_N);
+          const double dmx = mx, dmy = my;
+          const C2<double> d = cscale(mk(dmx * qx.x + dmy * qy.x, dmx * qx.y + dmy * qy.y), inv_m2);
+          qx = qx - cscale(d, dmx);
+          qy = qy - cscale(d, dmy);
+          if constexpr (GW) {
+            const C2<double> gg = cscale(g[NFY - 1], dt_over_N * inv_m2 / dk);
+            qx = qx + mk(-dmy * gg.y, dmy * gg.x);
+            qy = qy + mk(dmx * gg.y, -dmx * gg.x);
+          }
+          nx[e] = qx;
+          ny[e] = qy;
+        }
+      } else if constexpr (MODE != 1) {
         const double dt_over_N = lc.dt_over_N;
         double A, B;
         linear_ab<MODE>(lc, dk, m2, A, B);
@@ -496,7 +648,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       nx[e] = cvt<double>(cvt<S>(nx[e]));
       ny[e] = cvt<double>(cvt<S>(ny[e]));
     }
-    if (valid) {
+    if (valid && STORE) {
       // modes outside the 1/2-rule disk stay zero in memory and are not rewritten
 #pragma unroll
       for (int e = 0; e < E; ++e) {

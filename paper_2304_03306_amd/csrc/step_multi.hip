@@ -53,7 +53,8 @@ void col_multi_launch(const MultiArgs& a, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((col_multi<T, S, GW, MODE, BS>), dim3(a.start[a.ncls]), dim3(BS), lds, s, a);
 }
 
-// mode: 0 one-stage step, 1 state -> X only, 2 / 3 the ETD2RK stages
+// mode: 0 one-stage step, 1 state -> X only, 2 / 3 the ETD2RK stages, 4..7
+// the ETDRK4 stages
 hipError_t col(const MultiArgs& a, int gw, int mode, hipStream_t s) {
   const size_t lds = gw && mode != 1 ? lds_bytes(a, col_smem_of<T, BS, true>) : lds_bytes(a, col_smem_of<T, BS, false>);
   if (lds == 0) return hipErrorInvalidValue;
@@ -65,6 +66,14 @@ hipError_t col(const MultiArgs& a, int gw, int mode, hipStream_t s) {
     case 5: col_multi_launch<true, 2>(a, lds, s); break;
     case 6: col_multi_launch<false, 3>(a, lds, s); break;
     case 7: col_multi_launch<true, 3>(a, lds, s); break;
+    case 8: col_multi_launch<false, 4>(a, lds, s); break;
+    case 9: col_multi_launch<true, 4>(a, lds, s); break;
+    case 10: col_multi_launch<false, 5>(a, lds, s); break;
+    case 11: col_multi_launch<true, 5>(a, lds, s); break;
+    case 12: col_multi_launch<false, 6>(a, lds, s); break;
+    case 13: col_multi_launch<true, 6>(a, lds, s); break;
+    case 14: col_multi_launch<false, 7>(a, lds, s); break;
+    case 15: col_multi_launch<true, 7>(a, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -111,6 +120,14 @@ hipError_t col_one_n(const MultiArgs& o, int gw, int mode, hipStream_t s) {
       case 5: col_one_launch<N, true, 2>(o, s); break;
       case 6: col_one_launch<N, false, 3>(o, s); break;
       case 7: col_one_launch<N, true, 3>(o, s); break;
+      case 8: col_one_launch<N, false, 4>(o, s); break;
+      case 9: col_one_launch<N, true, 4>(o, s); break;
+      case 10: col_one_launch<N, false, 5>(o, s); break;
+      case 11: col_one_launch<N, true, 5>(o, s); break;
+      case 12: col_one_launch<N, false, 6>(o, s); break;
+      case 13: col_one_launch<N, true, 6>(o, s); break;
+      case 14: col_one_launch<N, false, 7>(o, s); break;
+      case 15: col_one_launch<N, true, 7>(o, s); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

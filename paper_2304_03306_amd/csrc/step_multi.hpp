@@ -26,9 +26,9 @@ struct ClassArgs {
   void* rowsum;
   const double* dk;
   const void* tw;
-  void* st2;      // ETD2RK stage state (same layout as st), else null
-  void* fst;      // ETD2RK stage-1 forcing spectra, else null
-  double* s1st;   // ETD2RK stage-1 k = 0 forcing sums [n][2], else null
+  void* st2;      // ETD2RK / ETDRK4 stage state (same layout as st), else null
+  void* fst;      // kept forcing spectra of the exponential Runge-Kutta stages, else null
+  double* s1st;   // their k = 0 forcing sums ([n][2] ETD2RK, [n][4] ETDRK4), else null
 };
 
 struct MultiArgs {

@@ -97,7 +97,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100_000)
     ap.add_argument("--transient", type=int, default=60_000)
     ap.add_argument("--every", type=int, default=500)
-    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2"])
+    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2", "etdrk4"])
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--report", default="dumbbell_report.json")
     a = ap.parse_args(argv)

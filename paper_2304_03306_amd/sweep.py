@@ -79,7 +79,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--stages", type=int, default=32)
     ap.add_argument("--steps", type=int, default=20_000)
-    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2"])
+    ap.add_argument("--scheme", default="ifeuler", choices=["ifeuler", "etd1", "imex", "etdrk2", "etdrk4"])
     ap.add_argument("--report", default="sweep_report.json")
     a = ap.parse_args(argv)
     rep = run(a.stages, a.steps, log=lambda m: print(f"[sweep] {m}", flush=True), scheme=a.scheme)

@@ -17,10 +17,11 @@ LIB_PATH = Path(__file__).resolve().with_name("libttsh.so")
 
 TTSH_OK, TTSH_EINVAL, TTSH_EUNSUPPORTED, TTSH_EHIP, TTSH_ENONFINITE, TTSH_ENOMEM = 0, -1, -2, -3, -4, -5
 TTSH_HOST, TTSH_DEVICE = 0, 1
-TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX, TTSH_ETDRK2 = 0, 1, 2, 3
+TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX, TTSH_ETDRK2, TTSH_ETDRK4 = 0, 1, 2, 3, 4
 TTSH_FP32, TTSH_FP64, TTSH_FP32_STATE64 = 32, 64, 96
 TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD, TTSH_OPT_SPLIT = 1, 2, 4, 8
-SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX, "etdrk2": TTSH_ETDRK2}
+SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX, "etdrk2": TTSH_ETDRK2,
+           "etdrk4": TTSH_ETDRK4}
 
 
 class TTSHError(RuntimeError):

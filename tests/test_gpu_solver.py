@@ -119,7 +119,7 @@ def test_one_step_fp64(gpu, N):
     assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-13
 
 
-@pytest.mark.parametrize("scheme", ["ifeuler", "etd1", "imex", "etdrk2"])
+@pytest.mark.parametrize("scheme", ["ifeuler", "etd1", "imex", "etdrk2", "etdrk4"])
 def test_schemes_fp64(gpu, scheme):
     say("schemes", scheme)
     import dataclasses
@@ -588,6 +588,55 @@ def test_etdrk2_mixed_sizes(gpu, split):
         s.set_field(q, v0)
         refs.append(O.run_velocity(O.project_field(v0, L), K, p, L, 30))
     s.step(30)
+    s.sync()
+    for q in range(len(Ns)):
+        err = O.rel_l2(s.field(q), O.field(refs[q]))
+        assert err < 1e-12, (q, err)
+
+
+# ---- ETDRK4: four column-pass stages per step --------------------------------------------------
+@pytest.mark.parametrize("N,steps,prec,preset,tol", [(64, 1, 64, "paper", 1e-13), (64, 30, 64, "workload", 1e-12),
+                                                     (128, 500, 32, "workload", 1e-5), (128, 100, 32, "paper", 1e-5),
+                                                     (256, 30, 96, "paper", 1e-6), (2048, 1, 32, "paper", 1e-6)])
+def test_etdrk4_matches_oracle(gpu, N, steps, prec, preset, tol):
+    """The fourth-order exponential Runge-Kutta step (stage state a, kept F(u)
+    and F(a) + F(b) spectra and their k = 0 sums on the device) against the
+    oracle's ETDRK4; the paper preset runs the gamma_w source through all four
+    stages; 2048^2 takes the per-size column kernels."""
+    import dataclasses
+    say("etdrk4", N, steps, prec, preset)
+    L = N * 0.5
+    base = O.paper_params() if preset == "paper" else O.workload_params()
+    p = dataclasses.replace(base, scheme="etdrk4")
+    K = O.mask_tanh(N, L, [(0.0, 0.0)], [L / 4], 0.5)
+    v0 = W.uniform_field(19, N, 0.01 if preset == "workload" else 0.3)
+    if prec == 32:
+        v0 = v0.astype(np.float32).astype(np.float64)
+    s, vh = run_pair(gpu, N, L, p, prec, K, v0, steps)
+    err = O.rel_l2(s.field(0), O.field(vh))
+    print("etdrk4 rel_l2", err, flush=True)
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_etdrk4_mixed_sizes(gpu, split):
+    """Two grid sizes in one context (multi-size launch, or one launch per size
+    class): every instance's stage state, two kept forcing slots and four
+    k = 0 sums sit at its own offset."""
+    import dataclasses
+    say("etdrk4 mixed sizes split", split)
+    p = dataclasses.replace(O.paper_params(), scheme="etdrk4")
+    Ns, Ls = [128, 256, 128], [64.0, 96.0, 48.0]
+    s = gpu.Solver(Ns, Ls, p, 64)
+    s.option(gpu.TTSH_OPT_SPLIT, split)
+    refs = []
+    for q, (N, L) in enumerate(zip(Ns, Ls)):
+        K = O.mask_tanh(N, L, [(0.0, 0.0)], [L / 4], 0.5)
+        v0 = W.uniform_field(45 + q, N, 0.3)
+        s.set_mask(q, K)
+        s.set_field(q, v0)
+        refs.append(O.run_velocity(O.project_field(v0, L), K, p, L, 10))
+    s.step(10)
     s.sync()
     for q in range(len(Ns)):
         err = O.rel_l2(s.field(q), O.field(refs[q]))
