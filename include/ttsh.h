@@ -293,6 +293,24 @@ int ttsh_step(ttsh_ctx* ctx, int64_t nsteps);
  * TTSH_ENOMEM, TTSH_EHIP.                                                   */
 int ttsh_reseed(ttsh_ctx* ctx, int n, const int* dst, const int* src, double noise_amp, uint64_t seed);
 
+/* ttsh_reseed without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, the same kernels and the same
+ * result bit for bit; the destinations' resampled spectra go to a fixed
+ * 64 MiB scratch in the library's device memory instead of a per-call
+ * buffer, so the destinations' compact FP64 spectra, 32 (N_dst/4 + 1)
+ * (N_dst/2 + 2) bytes each, may total at most 64 MiB (TTSH_EINVAL
+ * otherwise, before any work is queued): the radius sweep's 64 destinations
+ * (12 x 128^2, 16 x 256^2, 36 x 512^2) take 41.5 MiB; 15 destinations of
+ * 1024^2 fit, 16 do not.
+ * The scratch is shared by every call on one GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (two contexts on different
+ * streams, or two threads) race; order them on one stream or synchronise.
+ * Asynchronous on the context's stream (no synchronisation, no host
+ * staging).                                                               */
+int ttsh_reseed_noalloc(ttsh_ctx* ctx, int n, const int* dst, const int* src, double noise_amp,
+                        uint64_t seed);
+
 /* As ttsh_reseed, with caller-drawn noise: noise_q [2][N_dst][N_dst] float64
  * is the q-th block of `noise` (blocks stored back to back in the order of
  * dst; noise may be NULL for none), on the host (where = TTSH_HOST) or the

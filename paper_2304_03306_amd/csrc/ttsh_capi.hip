@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,16 @@
 #include "step_multi.hpp"
 
 using namespace ttsh;
+
+// Scratch of ttsh_reseed_noalloc: the destinations' resampled compact FP64
+// spectra of one call, back to back.  It lives in the code object's device
+// memory, so the call allocates nothing; every GPU that loads the library
+// holds its own copy until the process ends.  In host code the name `scratch`
+// is a host-side stand-in, not a device address: the runtime gives each
+// device's address through hipGetSymbolAddress (see resolve_scratch), and
+// only that address is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace ttsh {
 const SizeOps* ops_64();
@@ -78,6 +89,28 @@ int record_error(int code, const char* msg) {
   return code;
 }
 }  // namespace ttsh
+
+namespace {
+
+// device address of `scratch` per HIP device, taken once per device with that
+// device current (at the first ttsh_create there)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(TTSH_EUNSUPPORTED, "device index beyond the scratch address table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return TTSH_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(TTSH_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = p;
+  return TTSH_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -561,6 +594,10 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return fail(TTSH_EHIP, "hipGetDevice failed");
+  }
+  if (int rc = resolve_scratch(c->device)) {
+    delete c;
+    return rc;
   }
   auto bail = [&](int rc) {
     free_ctx(c);
@@ -1230,6 +1267,22 @@ int ttsh_reseed(ttsh_ctx* c, int n, const int* dst, const int* src, double noise
   hipStreamSynchronize(c->stream);
   if (tmp) hipFree(tmp);
   return rc;
+}
+
+int ttsh_reseed_noalloc(ttsh_ctx* c, int n, const int* dst, const int* src, double noise_amp, uint64_t seed) {
+  int rc = reseed_check(c, n, dst, src);
+  if (rc) return rc;
+  if (!std::isfinite(noise_amp)) return fail(TTSH_EINVAL, "noise_amp must be finite");
+  const size_t need = reseed_scratch_elems(c, n, dst) * sizeof(C2<double>);
+  if (need > kNoAllocScratchBytes)
+    return fail(TTSH_EINVAL, "the destinations' spectra (" + std::to_string(need) +
+                                 " bytes) exceed the 64 MiB scratch of ttsh_reseed_noalloc");
+  void* ptr = g_scratch_ptr[c->device];
+  if (!ptr) return fail(TTSH_EHIP, "scratch address not resolved for the context's device");
+  Noise nz;
+  nz.amp = noise_amp;
+  nz.seed = seed;
+  return reseed_impl(c, n, dst, src, nz, (C2<double>*)ptr);
 }
 
 int ttsh_reseed_field(ttsh_ctx* c, int n, const int* dst, const int* src, const double* noise, int where) {

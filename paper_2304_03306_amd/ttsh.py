@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
             "ttsh_step": [vp, i64],
             "ttsh_reseed": [vp, i32, dp, dp, ctypes.c_double, ctypes.c_uint64],
             "ttsh_reseed_field": [vp, i32, dp, dp, dp, i32],
+            "ttsh_reseed_noalloc": [vp, i32, dp, dp, ctypes.c_double, ctypes.c_uint64],
             "ttsh_norms": [vp, i32, dp],
             "ttsh_sync": [vp],
             "ttsh_set_option": [vp, i32, i64],
@@ -278,6 +279,13 @@ def ttsh_reseed(ctx, dst, src, noise_amp=0.0, seed=0):
     n, d, s = _index_lists(dst, src)
     return _check(lib().ttsh_reseed(ctx, n, ctypes.cast(d, ctypes.c_void_p), ctypes.cast(s, ctypes.c_void_p),
                                     float(noise_amp), int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+
+def ttsh_reseed_noalloc(ctx, dst, src, noise_amp=0.0, seed=0):
+    n, d, s = _index_lists(dst, src)
+    return _check(lib().ttsh_reseed_noalloc(ctx, n, ctypes.cast(d, ctypes.c_void_p),
+                                            ctypes.cast(s, ctypes.c_void_p), float(noise_amp),
+                                            int(seed) & 0xFFFFFFFFFFFFFFFF))
 
 
 def ttsh_reseed_field(ctx, dst, src, noise=None):
