@@ -35,7 +35,7 @@ def log(*a):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_step_kernels_radius_sweep.json")
 STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_step_kernels_radius_sweep.json")
-STEP_SOURCES = ("common.hpp", "fft.hpp", "step.hpp", "step_multi.hpp", "step_multi.hip")
+STEP_SOURCES = ("common.hpp", "fft.hpp", "step.hpp", "step_multi.hpp", "step_multi.hip", "step_sched.hip")
 
 
 def step_source_hash() -> str:
@@ -96,8 +96,17 @@ def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
             "copy_mib": copy_mib, "kernels": kernels}
 
 
-def measured_traffic(kernel: str, block: int):
-    """Bytes per launch of the given step kernel from the committed counter
+def kernel_name(pass_: str, block: int, sched: int, state_bytes: int = 8) -> str:
+    """The profiler's name of a multi-size step kernel of the FP32 transforms
+    (no vorticity damping; column pass in its one-stage form)."""
+    if pass_ == "row":
+        return f"void ttsh::row_multi<float, false, {block}, {sched}>(ttsh::MultiArgs)"
+    S = "float" if state_bytes == 8 else "double"
+    return f"void ttsh::col_multi<float, {S}, false, 0, {block}, {sched}>(ttsh::MultiArgs)"
+
+
+def measured_traffic(name: str):
+    """Bytes per launch of the named step kernel from the committed counter
     summary, or None if it is missing or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -106,11 +115,8 @@ def measured_traffic(kernel: str, block: int):
         return None
     if t.get("source_sha256") != step_source_hash():
         return None
-    for name, v in t.get("kernels", {}).items():
-        if (name.startswith(f"void ttsh::{kernel}<float") and name.endswith(f", {block}>(ttsh::MultiArgs)")
-                and ", false, " in name and (kernel == "row_multi" or ", 0, " in name)):
-            return v["bytes"]
-    return None
+    v = t.get("kernels", {}).get(name)
+    return v["bytes"] if v else None
 
 
 def summarize_stats(stats_csv) -> dict:
@@ -124,8 +130,8 @@ def summarize_stats(stats_csv) -> dict:
     return {"source_sha256": step_source_hash(), "kernels": kernels}
 
 
-def recorded_avg_us(kernel: str, block: int):
-    """The rocprofv3 mean duration of the given step kernel from the committed
+def recorded_avg_us(name: str):
+    """The rocprofv3 mean duration of the named step kernel from the committed
     summary, or None if it is missing or the kernel sources changed since."""
     try:
         with open(STATS_FILE) as f:
@@ -134,11 +140,8 @@ def recorded_avg_us(kernel: str, block: int):
         return None
     if t.get("source_sha256") != step_source_hash():
         return None
-    for name, v in t.get("kernels", {}).items():
-        if (name.startswith(f"void ttsh::{kernel}<float") and name.endswith(f", {block}>(ttsh::MultiArgs)")
-                and ", false, " in name and (kernel == "row_multi" or ", 0, " in name)):
-            return v["avg_us"]
-    return None
+    v = t.get("kernels", {}).get(name)
+    return v["avg_us"] if v else None
 
 
 def stream_ceiling(torch, T, mib: int = 160, reps: int = 30):
@@ -273,6 +276,9 @@ def main():
     ap.add_argument("--precision", type=int, default=32, choices=[32, 96],
                     help="32: FP32 state; 96: FP64 state (FP32 transforms in both)")
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = autotuned)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON cache of tuner results (default: the package's tuning_cache.json)")
+    ap.add_argument("--retune", action="store_true", help="tune even if the cache holds a choice")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (scale for the HBM byte counters)")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming-bandwidth probe")
@@ -325,15 +331,19 @@ def main():
     log(f"[bench] workload {wl.name}: {len(wl.instances)} instances, {wl.points} points/step")
     state_bytes = 8 if args.precision == 32 else 16
     s = setup(T, W, wl, params, args.precision)
-    s.option(T.TTSH_OPT_GUARD, 0)
+    # the NaN/Inf guard stays on, as in production runs: the step graphs carry a
+    # check of every instance each 50 steps and ttsh_sync checks once more
+    from paper_2304_03306_amd import tuning
+    cache = args.tuning_cache or tuning.DEFAULT_CACHE
     if args.block:
         s.option(T.TTSH_OPT_BLOCK, args.block)
-        block, split = (args.block, args.block), (0, 0)
+        cfg = s.get_tuning()
     else:
-        cfg, tuned_us = s.tune(20)
-        block, split = cfg[:2], cfg[2:]
-        log(f"[bench] autotuned (row, column) workgroup sizes {block}, one launch per grid size {split} "
-            f"({tuned_us:.1f} us/step)")
+        cfg, tuned_us, hit = tuning.autotune(s, 20, cache, retune=args.retune)
+        log(f"[bench] {'tuning from the cache' if hit else 'autotuned'}: (row, column) workgroup sizes "
+            f"{cfg[:2]}, one launch per grid size {cfg[2:4]}, transform schedules {cfg[4:6]}"
+            + (f" ({tuned_us:.1f} us/step when tuned)" if tuned_us else ""))
+    block, split, sched = tuple(cfg[0:2]), tuple(cfg[2:4]), tuple(cfg[4:6])
 
     parity = {}
     if not args.no_parity and args.workload == "sweep":
@@ -358,7 +368,6 @@ def main():
     log(f"[bench] {args.steps} steps in {dt:.3f} s: {value:.4e} pt*steps/s")
     finite = True
     try:
-        s.option(T.TTSH_OPT_GUARD, 1)
         s.sync()
     except T.TTSHError:
         finite = False
@@ -371,13 +380,15 @@ def main():
     row_b = sum(pass_bytes(N, state_bytes)[0] * n for N, n in counts.items())
     col_b = sum(pass_bytes(N, state_bytes)[1] * n for N, n in counts.items())
     # kernel names as the profiler shows them: one launch per grid size runs row_one / col_one
-    kern = [("row_one" if split[0] else "row_multi", row_us, row_b, block[0]),
-            ("col_one" if split[1] else "col_multi", col_us, col_b, block[1])]
+    kern = [("row_one" if split[0] else "row_multi", row_us, row_b, block[0], sched[0], "row"),
+            ("col_one" if split[1] else "col_multi", col_us, col_b, block[1], sched[1], "col")]
     dom = max(kern, key=lambda k: k[1])
-    # the recorded counter summary is of the radius sweep in FP32
-    traffic = measured_traffic(dom[0], dom[3]) if args.precision == 32 and args.workload == "sweep" else None
+    # the recorded counter and duration summaries are of the radius sweep
+    recorded = args.workload == "sweep" and not split[kern.index(dom)]
+    dom_name = kernel_name(dom[5], dom[3], dom[4], state_bytes) if recorded else None
+    traffic = measured_traffic(dom_name) if recorded and args.precision == 32 else None
     achieved = dom[2] / (dom[1] * 1e-6) / 1e9
-    rocprof_us = recorded_avg_us(dom[0], dom[3]) if args.precision == 32 and args.workload == "sweep" else None
+    rocprof_us = recorded_avg_us(dom_name) if recorded else None
     step_bytes = row_b + col_b
     step_us = row_us + col_us
     log("[bench] kernels: " + ", ".join(f"{k[0]} {k[1]:.1f}us {k[2] / k[1] / 1e3:.0f}GB/s" for k in kern))
@@ -387,8 +398,7 @@ def main():
     if not args.no_plain:
         pw = W.circle_fp32_512()
         ps = setup(T, W, pw, params, args.precision)
-        ps.option(T.TTSH_OPT_GUARD, 0)
-        pcfg, _ = ps.tune(20)
+        pcfg, _, _ = tuning.autotune(ps, 20, cache, retune=args.retune)
         pblock = pcfg[:2]
         perr = None
         if not args.no_parity:
@@ -433,13 +443,14 @@ def main():
         "config": {"workload": wl.name, "instances": len(wl.instances),
                    "grids": " + ".join(f"{counts[N]}x{N}^2" for N in sizes),
                    "points_per_step": wl.points, "dt": params.dt, "block": block,
-                   "launch_per_grid_size": split,
+                   "launch_per_grid_size": split, "transform_schedule": sched,
                    "precision": ("FP32 transforms and state" if args.precision == 32 else
                                  "FP32 transforms, FP64 state") + ", FP64 k-space update",
                    "parallelism": "single GPU, instances batched per grid size"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": dom[0], "block": dom[3], "avg_us": dom[1], "bytes_per_launch": dom[2],
+                     "kernel": dom_name or dom[0], "block": dom[3], "schedule": dom[4], "avg_us": dom[1],
+                     "bytes_per_launch": dom[2],
                      "rocprof_avg_us": rocprof_us,
                      "rocprof_frac": (dom[2] / (rocprof_us * 1e-6) / 1e9 / HBM_PEAK_GBS) if rocprof_us else None},
         "stream_probe_GBps": stream,

@@ -108,9 +108,14 @@ enum {
   TTSH_OPT_BLOCK = 2,       /* workgroup size of the step kernels: 64, 128 or 256
                                (8 x size >= largest N), 0 = chosen from the batch */
   TTSH_OPT_GUARD = 4,       /* 1: ttsh_sync checks the state for NaN/Inf; default 1 */
-  TTSH_OPT_SPLIT = 8        /* bit 0: row pass, bit 1: column pass launched once per grid
+  TTSH_OPT_SPLIT = 8,       /* bit 0: row pass, bit 1: column pass launched once per grid
                                size (kernels compiled for that size) instead of once for
                                all sizes; default 0 */
+  TTSH_OPT_GUARD_EVERY = 16 /* with the guard on: steps between the NaN/Inf checks that
+                               ttsh_step queues (part of the captured graphs; one launch
+                               per grid size over all its instances, flags kept on the
+                               device until ttsh_sync reports them); 0 = check only in
+                               ttsh_sync; default 50 */
 };
 
 /* Create a context holding n_inst independent instances advanced together.
@@ -322,8 +327,10 @@ int ttsh_reseed_field(ttsh_ctx* ctx, int n, const int* dst, const int* src, cons
  * out[0] = sum_x |v|^2, out[1] = <v_x>, out[2] = <v_y>, out[3] = max |k . v_hat|. */
 int ttsh_norms(ttsh_ctx* ctx, int inst, double out[4]);
 
-/* Wait for the context's queued work; with TTSH_OPT_GUARD set, return
- * TTSH_ENONFINITE if any instance holds NaN/Inf.                           */
+/* Wait for the context's queued work; with TTSH_OPT_GUARD set, check every
+ * instance's state once more and return TTSH_ENONFINITE if that check or any
+ * check queued by ttsh_step since the last ttsh_sync found NaN/Inf (the
+ * message names the lowest such instance); the flags are then cleared.     */
 int ttsh_sync(ttsh_ctx* ctx);
 
 /* Measurement: launch the row pass nsteps >= 1 times back to back, then the
@@ -335,15 +342,38 @@ int ttsh_sync(ttsh_ctx* ctx);
  * the state changes: save it first if it matters.  Synchronous.            */
 int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
 
-/* Autotuner: time nsteps steps with every usable workgroup size, each as one
- * launch for all grid sizes and as one launch per grid size (HIP events,
- * after two warm-up steps), keep the fastest configuration for each of the
- * two passes independently, and restore the state the context had before the
- * call.  cfg_out (4 ints, may be NULL): row-pass size, column-pass size,
- * row-pass split (0/1), column-pass split (0/1); us_out: microseconds per step
- * of that choice (may be NULL).  A later TTSH_OPT_BLOCK / TTSH_OPT_SPLIT
- * overrides it.  Synchronous.                                               */
+/* Autotuner: for each of the two passes of a step, independently, time
+ * nsteps back-to-back launches (as ttsh_pass_times, after two warm-up steps)
+ * of every candidate configuration, in two rounds over all candidates, and
+ * keep the fastest (each candidate's faster round):
+ *   workgroup size 64, 128 or 256 (the rows or columns per tile follow:
+ *   size / (N/8) for a grid of N points);
+ *   one launch for all grid sizes, or one launch per grid size;
+ *   with one launch for all sizes in the FP32 arithmetic, the transform
+ *   schedule: the LDS padding (one slot per 8, 16 or 32 entries) and, for
+ *   grids that are not a power of 8, whether the leftover radix (2 or 4)
+ *   runs first or last (schedule code 2 * log2(padding period) + first:
+ *   6, 7, 8 (the default: padding 16, radix last), 9, 10, 11).
+ * The state the context had before the call is restored.  cfg_out (6 ints,
+ * may be NULL): row-pass size, column-pass size, row split (0/1), column
+ * split (0/1), row schedule, column schedule (the layout of
+ * ttsh_set_tuning); us_out (may be NULL): microseconds per step of that
+ * choice.  A later TTSH_OPT_BLOCK / TTSH_OPT_SPLIT overrides it.
+ * Synchronous.                                                              */
 int ttsh_tune(ttsh_ctx* ctx, int64_t nsteps, int* cfg_out, double* us_out);
+
+/* The launch configuration in use (6 ints, as cfg_out of ttsh_tune), and
+ * setting one found earlier (for instance from a cache of tuner results)
+ * without timing anything.  set: TTSH_EINVAL if a size does not fit the
+ * context, a split flag is not 0/1, or a schedule is unknown or used where
+ * only the default exists (FP64 or FP32-state-64 arithmetic, one launch per
+ * grid size, grids of 2048).                                               */
+int ttsh_get_tuning(ttsh_ctx* ctx, int* cfg);
+int ttsh_set_tuning(ttsh_ctx* ctx, const int* cfg);
+
+/* Name of the current HIP device's architecture (e.g. "gfx950:sramecc+:xnack-")
+ * into out (NUL-terminated, at most n bytes); the key of tuner caches.     */
+int ttsh_device_arch(char* out, int n);
 
 /* Number of distinct grid sizes (size classes) in the context; their sizes in
  * increasing order go to N_out (may be NULL).                               */

@@ -19,6 +19,7 @@ LIB = HERE / "libttsh.so"
 SIZES = (64, 128, 256, 512, 1024, 2048)
 PRECS = (32, 64, 96)
 BLOCKS = (64, 128, 256)
+SCHED_VARIANTS = (6, 10, 9, 7, 11)  # kSchedVariants of csrc/launch.hpp
 ARCH = os.environ.get("TTSH_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -47,6 +48,9 @@ def build(jobs: int | None = None, verbose: bool = True) -> Path:
     units = [(CSRC / "kernels_n.hip", OUT / f"kernels_{n}.o", [f"-DTTSH_N={n}"]) for n in SIZES]
     units += [(CSRC / "step_multi.hip", OUT / f"step_{p}_{b}.o", [f"-DTTSH_PREC={p}", f"-DTTSH_BS={b}"])
               for p in PRECS for b in BLOCKS]
+    # the FP32 step passes with the other transform schedules the autotuner tries
+    units += [(CSRC / "step_sched.hip", OUT / f"sched_{b}_{s}.o", [f"-DTTSH_BS={b}", f"-DTTSH_SCH={s}"])
+              for b in BLOCKS for s in SCHED_VARIANTS]
     units.append((CSRC / "ttsh_capi.hip", OUT / "ttsh_capi.o", []))
     units.append((CSRC / "fno.hip", OUT / "fno.o", []))
     units.append((CSRC / "stream.hip", OUT / "stream.o", []))

@@ -734,14 +734,19 @@ __global__ void __launch_bounds__(1024) k_psd_finish(const C2<double>* __restric
 }
 
 // ---- FP64 norms on the compact state -----------------------------------------
+// Over kNormBlocks workgroups of 256 threads, each writing one partial
+// [5] (sum of |v|^2 with the Parseval weights, max |k . v_hat|, non-finite
+// flag, and, from workgroup 0, the k = 0 entries); k_norms_final combines the
+// partials in workgroup order, so results do not vary between runs:
 // out[0] = sum_x |v|^2 (Parseval, unitary), out[1..2] = <v_x>, <v_y>,
 // out[3] = max |k . v_hat|, out[4] = 1 if any entry is non-finite.
+constexpr int kNormBlocks = 64;
 template <class S>
-__global__ void __launch_bounds__(1024) k_norms(const C2<S>* __restrict__ st, int N, double dk,
-                                                double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_norms(const C2<S>* __restrict__ st, int N, double dk,
+                                               double* __restrict__ part) {
   const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
   double e = 0.0, dv = 0.0, bad = 0.0;
-  for (int i = threadIdx.x; i < MP * SP; i += blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < MP * SP; i += gridDim.x * blockDim.x) {
     const int mx = i / SP, pos = i % SP;
     if (pos > 2 * M) continue;
     const int my = pos <= M ? pos : pos - (2 * M + 1);
@@ -754,7 +759,7 @@ __global__ void __launch_bounds__(1024) k_norms(const C2<S>* __restrict__ st, in
     const C2<double> d = mk(mx * a.x + my * b.x, mx * a.y + my * b.y);
     dv = fmax(dv, dk * sqrt(d.x * d.x + d.y * d.y));
   }
-  __shared__ double red[16][3];
+  __shared__ double red[4][3];
   for (int o = 1; o < 64; o <<= 1) {
     e += __shfl_xor(e, o, 64);
     dv = fmax(dv, __shfl_xor(dv, o, 64));
@@ -773,14 +778,52 @@ __global__ void __launch_bounds__(1024) k_norms(const C2<S>* __restrict__ st, in
       D0 = fmax(D0, red[w][1]);
       B0 = fmax(B0, red[w][2]);
     }
-    const C2<double> a0 = cvt<double>(st[0]);
-    const C2<double> b0 = cvt<double>(st[MP * SP]);
-    out[0] = E0;
-    out[1] = a0.x / N;
-    out[2] = b0.x / N;
-    out[3] = D0;
-    out[4] = B0;
+    double* o = part + 5 * blockIdx.x;
+    o[0] = E0;
+    o[1] = D0;
+    o[2] = B0;
+    if (blockIdx.x == 0) {
+      o[3] = cvt<double>(st[0]).x / N;
+      o[4] = cvt<double>(st[MP * SP]).x / N;
+    }
   }
+}
+
+__global__ void k_norms_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double E0 = 0.0, D0 = 0.0, B0 = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    E0 += part[5 * b];
+    D0 = fmax(D0, part[5 * b + 1]);
+    B0 = fmax(B0, part[5 * b + 2]);
+  }
+  out[0] = E0;
+  out[1] = part[3];
+  out[2] = part[4];
+  out[3] = D0;
+  out[4] = B0;
+}
+
+// ---- non-finite guard over every instance of a size class --------------------
+// flags[i] = 1 if instance i of the class holds a NaN or Inf among its stored
+// modes (workgroup (x, i) scans part of instance i; every writer stores the
+// same value, so no atomics are needed).  The flags are cleared by k_fill_int.
+template <class S>
+__global__ void __launch_bounds__(256) k_guard(const C2<S>* __restrict__ st, int N, int* __restrict__ flags) {
+  const int M = N / 4, MP = M + 1, SP = 2 * M + 2;
+  const size_t per = (size_t)2 * MP * SP;
+  const C2<S>* s = st + (size_t)blockIdx.y * per;
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+    const C2<S> v = s[i];
+    bad |= !isfinite((double)v.x) || !isfinite((double)v.y);
+  }
+  if (bad) flags[blockIdx.y] = 1;
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace ttsh

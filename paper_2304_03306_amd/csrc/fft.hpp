@@ -30,17 +30,38 @@ namespace ttsh {
 
 constexpr int kFftE = 8;  // elements per thread
 
-// LDS index with one pad slot every 2^TTSH_PAD_SHIFT entries (breaks the
-// strided scatter of the first stage across banks).  One slot per 16 was the
-// fastest of 1 per 4..64 in measurements of both step passes on gfx950.
-#ifndef TTSH_PAD_SHIFT
-#define TTSH_PAD_SHIFT 4
-#endif
-__host__ __device__ constexpr int lds_pad(int j) { return j + (j >> TTSH_PAD_SHIFT); }
-template <int N>
+// Schedule of a transform, one int SCH = 2 PAD + SMALL_FIRST:
+//   PAD          the LDS index gets one pad slot every 2^PAD entries (breaks
+//                the strided scatter of the stages across banks);
+//   SMALL_FIRST  for N not a power of 8, whether the radix left over after
+//                the radix-8 stages (2 or 4) runs as the first stage or the
+//                last one.
+// The default (one slot per 16, small radix last) was the fastest of the
+// hand-measured settings on gfx950; the autotuner also tries PAD = 3, 5 and
+// the small radix first for the time-step kernels.  The schedule changes
+// neither the result's layout nor, for the padding, its arithmetic.
+constexpr int sched_code(int pad, bool small_first) { return 2 * pad + (small_first ? 1 : 0); }
+constexpr int kSchedDefault = sched_code(4, false);
+constexpr int sched_pad(int sch) { return sch >> 1; }
+constexpr bool sched_small_first(int sch) { return (sch & 1) != 0; }
+
+template <int SCH = kSchedDefault>
+__host__ __device__ constexpr int lds_pad(int j) { return j + (j >> sched_pad(SCH)); }
+template <int N, int SCH = kSchedDefault>
 struct Padded {
-  static constexpr int value = N + (N >> TTSH_PAD_SHIFT);
+  static constexpr int value = N + (N >> sched_pad(SCH));
 };
+
+// radix of the stage that follows stages whose radices multiply to P
+template <int N, int SCH>
+constexpr int stage_radix(int P) {
+  int l2 = 0;
+  while ((1 << l2) < N) ++l2;
+  const int small = 1 << (l2 % 3);  // 1, 2 or 4
+  if (sched_small_first(SCH) && small > 1) return P == 1 ? small : 8;
+  const int rem = N / P;
+  return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2);
+}
 
 #ifndef TTSH_FFT_SLOTS
 #define TTSH_FFT_SLOTS 2
@@ -104,15 +125,15 @@ struct Dft<8, DIR, T> {
 // ---- one Stockham stage, recursing into the next ---------------------------
 // v[f][e] holds element t + e*TT of transform f.  `lds` points at this group's
 // fft_slots(NF) regions of Padded<N> entries each.  `tw[j]` = e^{-2 pi i j / N}.
-template <int N, int DIR, int NF, int P, class T>
+template <int N, int DIR, int NF, int P, class T, int SCH>
 struct FftStage {
   static constexpr int E = kFftE;
   static constexpr int TT = N / E;
-  static constexpr int REM = N / P;
-  static constexpr int R = (REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : 2);
+  static constexpr int R = stage_radix<N, SCH>(P);
+  static_assert(R == 2 || R == 4 || R == 8, "radix");
   static constexpr int NB = E / R;  // butterflies per thread in this stage
   static constexpr bool LAST = (P * R == N);
-  static constexpr int NP = Padded<N>::value;
+  static constexpr int NP = Padded<N, SCH>::value;
 
   // twiddle multiplication and radix-R DFT of the NB butterflies of transform
   // f; the outputs go back to registers (last stage) or to LDS region `slot`
@@ -140,14 +161,14 @@ struct FftStage {
       } else {
         const int j0 = (i - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) slot[lds_pad(j0 + r * P)] = u[r];
+        for (int r = 0; r < R; ++r) slot[lds_pad<SCH>(j0 + r * P)] = u[r];
       }
     }
   }
 
   __device__ static __forceinline__ void gather(C2<T> (&v)[NF][E], int f, const C2<T>* slot, int t) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[f][e] = slot[lds_pad(t + e * TT)];
+    for (int e = 0; e < E; ++e) v[f][e] = slot[lds_pad<SCH>(t + e * TT)];
   }
 
   __device__ static __forceinline__ void run(C2<T> (&v)[NF][E], C2<T>* lds, int t,
@@ -163,7 +184,7 @@ struct FftStage {
 #pragma unroll
       for (int f = 0; f < NF; ++f) gather(v, f, lds + f * NP, t);
       __syncthreads();
-      FftStage<N, DIR, NF, P * R, T>::run(v, lds, t, tw);
+      FftStage<N, DIR, NF, P * R, T, SCH>::run(v, lds, t, tw);
     } else {
       // transform f uses slot f % NS; the barrier after writing f also orders
       // every read of f - NS (issued before it) ahead of the reuse of its slot
@@ -174,17 +195,17 @@ struct FftStage {
         gather(v, f, lds + (f % NS) * NP, t);
       }
       __syncthreads();
-      FftStage<N, DIR, NF, P * R, T>::run(v, lds, t, tw);
+      FftStage<N, DIR, NF, P * R, T, SCH>::run(v, lds, t, tw);
     }
   }
 };
 
 // Unnormalised transform(s): out[m] = sum_n in[n] e^{DIR 2 pi i m n / N}.
-template <int N, int DIR, int NF, class T>
+template <int N, int DIR, int NF, int SCH = kSchedDefault, class T>
 __device__ __forceinline__ void fft(C2<T> (&v)[NF][kFftE], C2<T>* lds, int t,
                                     const C2<T>* __restrict__ tw) {
   static_assert(N >= 64 && (N & (N - 1)) == 0, "N must be a power of two >= 64");
-  FftStage<N, DIR, NF, 1, T>::run(v, lds, t, tw);
+  FftStage<N, DIR, NF, 1, T, SCH>::run(v, lds, t, tw);
 }
 
 }  // namespace ttsh

@@ -27,6 +27,17 @@ struct MultiOps {
   hipError_t (*col_split)(const MultiArgs&, int gw, int mode, hipStream_t);
 };
 
+// The FP32 row pass and one-stage column pass with a non-default transform
+// schedule, one launch over every size class (autotuner candidates).
+struct SchedOps {
+  hipError_t (*row)(const MultiArgs&, int gw, hipStream_t);
+  hipError_t (*col)(const MultiArgs&, int gw, hipStream_t);
+};
+// schedules compiled besides the default, in the order the autotuner tries them
+constexpr int kNumSchedVariants = 5;
+constexpr int kSchedVariants[kNumSchedVariants] = {6, 10, 9, 7, 11};  // 2 PAD + SMALL_FIRST
+const SchedOps* sched_ops(int bs, int sch);  // null for the default schedule or an unknown one
+
 const SizeOps* size_ops(int N);
 // record `msg` as the calling thread's last error (ttsh_last_error) and return code
 int record_error(int code, const char* msg);

@@ -181,14 +181,14 @@ struct RowCoef {
   T beta, gamma_v, lambda0, gamma_w;
 };
 
-template <int N>
+template <int N, int SCH = kSchedDefault>
 struct Geo {
   static constexpr int E = kFftE;
   static constexpr int TT = N / E;       // threads per transform
   static constexpr int M = N / 4;        // dealiasing radius
   static constexpr int MP = M + 1;       // stored columns m_x = 0..M
   static constexpr int SP = 2 * M + 2;   // stored positions per state column
-  static constexpr int NP = Padded<N>::value;
+  static constexpr int NP = Padded<N, SCH>::value;
   static constexpr int MP4 = (MP + 3) / 4 * 4;  // mixed-domain columns, padded
   // LDS stride between transform groups that share a wavefront: TTSH_LDS_OFF
   // complex entries off a multiple of 32 (chosen by measuring LDS bank
@@ -212,25 +212,25 @@ __device__ __forceinline__ C2<T> pack_pq(C2<T> p, C2<T> q) {
 // row pass: RP row pairs per workgroup, TT threads per pair; `tile` selects
 // rows 2 RP tile .. 2 RP (tile + 1) - 1 of instance `inst`
 // ---------------------------------------------------------------------------
-template <int N, int RP, class T>
+template <int N, int RP, class T, int SCH = kSchedDefault>
 struct RowSmem {
-  static constexpr size_t lds = (size_t)RP * Geo<N>::LS * sizeof(C2<T>);
-  static constexpr size_t bytes = lds + (size_t)(RP * Geo<N>::TT / 64) * RP * 4 * sizeof(T);
+  static constexpr size_t lds = (size_t)RP * Geo<N, SCH>::LS * sizeof(C2<T>);
+  static constexpr size_t bytes = lds + (size_t)(RP * Geo<N, SCH>::TT / 64) * RP * 4 * sizeof(T);
 };
 
-template <int N, int RP, class T, bool GW>
+template <int N, int RP, class T, bool GW, int SCH = kSchedDefault>
 __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __restrict__ Y,
                                          const T* __restrict__ K, T* __restrict__ rowsum,
                                          const C2<T>* __restrict__ tw, const RowCoef<T>& c,
                                          size_t inst, int tile, unsigned char* smem) {
-  using G = Geo<N>;
+  using G = Geo<N, SCH>;
   constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, NP = G::NP;
   constexpr int NFY = GW ? 3 : 2;
   constexpr int NT = RP * TT;
   constexpr int NW = NT / 64;
   static_assert(NT % 64 == 0, "row pass needs whole wavefronts");
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem);
-  T(*red)[RP][4] = reinterpret_cast<T(*)[RP][4]>(smem + RowSmem<N, RP, T>::lds);
+  T(*red)[RP][4] = reinterpret_cast<T(*)[RP][4]>(smem + RowSmem<N, RP, T, SCH>::lds);
 
   const int tid = threadIdx.x;
   const int lane = tid % RP;
@@ -275,7 +275,7 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     z[1][e] = pack_pq(a.b, b.b);  // v_x + i v_y, row y0+1
     z[2][e] = pack_pq(w.a, w.b);  // omega(y0) + i omega(y0+1)
   }
-  fft<N, +1, 3>(z, L, t, tw);
+  fft<N, +1, 3, SCH>(z, L, t, tw);
 
   // mask rows, loaded after the inverse transforms: issued before them they
   // would hold 16 registers through the transforms (the row pass ran ~5 %
@@ -306,7 +306,7 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     if constexpr (GW)
       wv[NFY - 1][e] = mk(-c.gamma_w * kr[0][e] * z[2][e].x, -c.gamma_w * kr[1][e] * z[2][e].y);
   }
-  fft<N, -1, NFY>(wv, L, t, tw);
+  fft<N, -1, NFY, SCH>(wv, L, t, tw);
 
   // Outputs.  The forcing rows are stored unsplit, straight from registers:
   // Y[0][m][y] = W_y(m) and Y[1][m][y] = W_y(N - m) (m = 0..M) with
@@ -341,7 +341,7 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int idx = t + e * TT;
-      if (idx <= M || idx >= N - M) L[lds_pad(idx)] = wv[2][e];
+      if (idx <= M || idx >= N - M) L[lds_pad<SCH>(idx)] = wv[2][e];
     }
   }
   __syncthreads();
@@ -351,8 +351,8 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     for (int e = 0; e <= M / TT; ++e) {
       const int m = t + e * TT;
       if (m <= M) {
-        const C2<T> Wm = L[lds_pad(m)];
-        const C2<T> Wn = L[lds_pad((N - m) & (N - 1))];
+        const C2<T> Wm = L[lds_pad<SCH>(m)];
+        const C2<T> Wn = L[lds_pad<SCH>((N - m) & (N - 1))];
         Yp[mix_idx<N>(2, m, y0)] = mk(h * (Wm.x + Wn.x), h * (Wm.y - Wn.y));
         Yp[mix_idx<N>(2, m, y0 + 1)] = mk(h * (Wm.y + Wn.y), -h * (Wm.x - Wn.x));
       }
@@ -376,9 +376,9 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
 // column pass: TC columns per workgroup, TT threads per column
 // MODE 0: full step;  MODE 1: only state -> X (after the state was set)
 // ---------------------------------------------------------------------------
-template <int N, int TC, class T, bool GW>
+template <int N, int TC, class T, bool GW, int SCH = kSchedDefault>
 struct ColSmem {
-  static constexpr size_t fft = (size_t)TC * Geo<N>::LS * sizeof(C2<T>);
+  static constexpr size_t fft = (size_t)TC * Geo<N, SCH>::LS * sizeof(C2<T>);
   static constexpr size_t herm = (size_t)N * sizeof(C2<double>);
   static constexpr size_t bytes = fft > herm ? fft : herm;
 };
@@ -414,7 +414,7 @@ __device__ __forceinline__ void hermitian_fix(C2<double> (&u)[kFftE], C2<double>
 // last stage (7) reads st and both slots and writes st.  Stages b and c
 // leave no state behind: only their mixed-domain fields X, which the next
 // row pass turns into F(b) and F(c).
-template <int N, int TC, class T, class S, bool GW, int MODE>
+template <int N, int TC, class T, class S, bool GW, int MODE, int SCH = kSchedDefault>
 __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __restrict__ X,
                                          C2<S>* __restrict__ st, const T* __restrict__ rowsum,
                                          const double* __restrict__ dkv,
@@ -422,7 +422,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
                                          size_t inst, int tile, unsigned char* smem,
                                          C2<S>* __restrict__ st2 = nullptr, C2<T>* __restrict__ fst = nullptr,
                                          double* __restrict__ s1st = nullptr) {
-  using G = Geo<N>;
+  using G = Geo<N, SCH>;
   constexpr int E = G::E, TT = G::TT, M = G::M, MP = G::MP, SP = G::SP, NP = G::NP;
   constexpr int NFY = GW ? 3 : 2;
   constexpr int NT = TC * TT;
@@ -511,7 +511,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       f[1][e] = mk(h * (w0.y + w1.y), -h * (w0.x - w1.x));  // row transform of N_y
       if constexpr (GW) f[2][e] = valid ? Yp[mix_idx<N>(2, mx, t + e * TT)] : mk<T>(0, 0);
     }
-    fft<N, -1, NFY>(f, L, t, tw);
+    fft<N, -1, NFY, SCH>(f, L, t, tw);
     if constexpr (MODE == 2 || MODE == 3) {  // keep (stage 1) or subtract (stage 2) the stage-1 forcing
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -676,7 +676,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
     z[1][e] = cvt<T>(cscale(ny[e], sN));
     z[2][e] = cvt<T>(mk(-cw.y * dk * sN, cw.x * dk * sN));
   }
-  fft<N, +1, 3>(z, L, t, tw);
+  fft<N, +1, 3, SCH>(z, L, t, tw);
   if (valid) {
     C2<T>* Xp = X + inst * 3 * G::MP4 * N;
 #pragma unroll

@@ -52,35 +52,35 @@ struct TileOf {
 // A tile may take up to the 160 KB of LDS one gfx950 workgroup can address
 // (FP64 transforms of 2048 points need about 70 KB); larger tiles give 0.
 constexpr size_t kMaxTileLds = 163840;
-template <class T, int BS, int N>
+template <class T, int BS, int N, int SCH = kSchedDefault>
 constexpr size_t row_smem_n() {
   if constexpr (TileOf<N, BS>::ok) {
-    constexpr size_t b = RowSmem<N, TileOf<N, BS>::R, T>::bytes;
+    constexpr size_t b = RowSmem<N, TileOf<N, BS>::R, T, SCH>::bytes;
     return b <= kMaxTileLds ? b : 0;
   } else {
     return 0;
   }
 }
-template <class T, int BS, bool GW, int N>
+template <class T, int BS, bool GW, int N, int SCH = kSchedDefault>
 constexpr size_t col_smem_n() {
   if constexpr (TileOf<N, BS>::ok) {
-    constexpr size_t b = ColSmem<N, TileOf<N, BS>::R, T, GW>::bytes;
+    constexpr size_t b = ColSmem<N, TileOf<N, BS>::R, T, GW, SCH>::bytes;
     return b <= kMaxTileLds ? b : 0;
   } else {
     return 0;
   }
 }
-template <class T, int BS>
+template <class T, int BS, int SCH = kSchedDefault>
 constexpr size_t row_smem_of(int N) {
-  return N == 64 ? row_smem_n<T, BS, 64>() : N == 128 ? row_smem_n<T, BS, 128>()
-       : N == 256 ? row_smem_n<T, BS, 256>() : N == 512 ? row_smem_n<T, BS, 512>()
-       : N == 1024 ? row_smem_n<T, BS, 1024>() : N == 2048 ? row_smem_n<T, BS, 2048>() : 0;
+  return N == 64 ? row_smem_n<T, BS, 64, SCH>() : N == 128 ? row_smem_n<T, BS, 128, SCH>()
+       : N == 256 ? row_smem_n<T, BS, 256, SCH>() : N == 512 ? row_smem_n<T, BS, 512, SCH>()
+       : N == 1024 ? row_smem_n<T, BS, 1024, SCH>() : N == 2048 ? row_smem_n<T, BS, 2048, SCH>() : 0;
 }
-template <class T, int BS, bool GW>
+template <class T, int BS, bool GW, int SCH = kSchedDefault>
 constexpr size_t col_smem_of(int N) {
-  return N == 64 ? col_smem_n<T, BS, GW, 64>() : N == 128 ? col_smem_n<T, BS, GW, 128>()
-       : N == 256 ? col_smem_n<T, BS, GW, 256>() : N == 512 ? col_smem_n<T, BS, GW, 512>()
-       : N == 1024 ? col_smem_n<T, BS, GW, 1024>() : N == 2048 ? col_smem_n<T, BS, GW, 2048>() : 0;
+  return N == 64 ? col_smem_n<T, BS, GW, 64, SCH>() : N == 128 ? col_smem_n<T, BS, GW, 128, SCH>()
+       : N == 256 ? col_smem_n<T, BS, GW, 256, SCH>() : N == 512 ? col_smem_n<T, BS, GW, 512, SCH>()
+       : N == 1024 ? col_smem_n<T, BS, GW, 1024, SCH>() : N == 2048 ? col_smem_n<T, BS, GW, 2048, SCH>() : 0;
 }
 
 // Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
@@ -100,15 +100,15 @@ __device__ __forceinline__ int class_of(const MultiArgs& a, int b) {
   return ci;
 }
 
-template <int N, class T, bool GW, int BS>
+template <int N, class T, bool GW, int BS, int SCH = kSchedDefault>
 __device__ __forceinline__ void row_go(const ClassArgs& d, const RowCoef<T>& c, int inst, int tile,
                                        unsigned char* smem) {
-  if constexpr (row_smem_n<T, BS, N>() > 0)
-    row_body<N, TileOf<N, BS>::R, T, GW>((const C2<T>*)d.X_in, (C2<T>*)d.Y, (const T*)d.K,
-                                         (T*)d.rowsum, (const C2<T>*)d.tw, c, inst, tile, smem);
+  if constexpr (row_smem_n<T, BS, N, SCH>() > 0)
+    row_body<N, TileOf<N, BS>::R, T, GW, SCH>((const C2<T>*)d.X_in, (C2<T>*)d.Y, (const T*)d.K,
+                                              (T*)d.rowsum, (const C2<T>*)d.tw, c, inst, tile, smem);
 }
 
-template <class T, bool GW, int BS>
+template <class T, bool GW, int BS, int SCH = kSchedDefault>
 __global__ void __launch_bounds__(BS) row_multi(MultiArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -119,28 +119,28 @@ __global__ void __launch_bounds__(BS) row_multi(MultiArgs a) {
   const int tile = local - inst * d.tiles;
   const RowCoef<T> c{(T)a.beta, (T)a.gamma_v, (T)a.lambda0, (T)a.gamma_w};
   switch (d.N) {
-    case 64: row_go<64, T, GW, BS>(d, c, inst, tile, smem); break;
-    case 128: row_go<128, T, GW, BS>(d, c, inst, tile, smem); break;
-    case 256: row_go<256, T, GW, BS>(d, c, inst, tile, smem); break;
-    case 512: row_go<512, T, GW, BS>(d, c, inst, tile, smem); break;
-    case 1024: row_go<1024, T, GW, BS>(d, c, inst, tile, smem); break;
+    case 64: row_go<64, T, GW, BS, SCH>(d, c, inst, tile, smem); break;
+    case 128: row_go<128, T, GW, BS, SCH>(d, c, inst, tile, smem); break;
+    case 256: row_go<256, T, GW, BS, SCH>(d, c, inst, tile, smem); break;
+    case 512: row_go<512, T, GW, BS, SCH>(d, c, inst, tile, smem); break;
+    case 1024: row_go<1024, T, GW, BS, SCH>(d, c, inst, tile, smem); break;
     default: break;
   }
 }
 
-template <int N, class T, class S, bool GW, int MODE, int BS>
+template <int N, class T, class S, bool GW, int MODE, int BS, int SCH = kSchedDefault>
 __device__ __forceinline__ void col_go(const ClassArgs& d, const LinCoef& lc, int inst, int tile,
                                        unsigned char* smem) {
-  if constexpr (col_smem_n<T, BS, GW, N>() > 0) {
+  if constexpr (col_smem_n<T, BS, GW, N, SCH>() > 0) {
     LinCoef l = lc;
     l.dt_over_N = lc.dt / N;  // the unnormalised forward FFT carries N x the unitary DFT
-    col_body<N, TileOf<N, BS>::R, T, S, GW, MODE>((const C2<T>*)d.Y, (C2<T>*)d.X_out, (C2<S>*)d.st,
+    col_body<N, TileOf<N, BS>::R, T, S, GW, MODE, SCH>((const C2<T>*)d.Y, (C2<T>*)d.X_out, (C2<S>*)d.st,
                                                   (const T*)d.rowsum, d.dk, (const C2<T>*)d.tw, l,
                                                   inst, tile, smem, (C2<S>*)d.st2, (C2<T>*)d.fst, d.s1st);
   }
 }
 
-template <class T, class S, bool GW, int MODE, int BS>
+template <class T, class S, bool GW, int MODE, int BS, int SCH = kSchedDefault>
 __global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -150,11 +150,11 @@ __global__ void __launch_bounds__(BS) col_multi(MultiArgs a) {
   const int inst = local / d.tiles;
   const int tile = local - inst * d.tiles;
   switch (d.N) {
-    case 64: col_go<64, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
-    case 128: col_go<128, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
-    case 256: col_go<256, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
-    case 512: col_go<512, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
-    case 1024: col_go<1024, T, S, GW, MODE, BS>(d, a.lc, inst, tile, smem); break;
+    case 64: col_go<64, T, S, GW, MODE, BS, SCH>(d, a.lc, inst, tile, smem); break;
+    case 128: col_go<128, T, S, GW, MODE, BS, SCH>(d, a.lc, inst, tile, smem); break;
+    case 256: col_go<256, T, S, GW, MODE, BS, SCH>(d, a.lc, inst, tile, smem); break;
+    case 512: col_go<512, T, S, GW, MODE, BS, SCH>(d, a.lc, inst, tile, smem); break;
+    case 1024: col_go<1024, T, S, GW, MODE, BS, SCH>(d, a.lc, inst, tile, smem); break;
     default: break;
   }
 }

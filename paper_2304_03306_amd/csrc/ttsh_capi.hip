@@ -7,6 +7,7 @@
 // into a HIP graph and replayed on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -56,6 +57,27 @@ TTSH_DECL(32)
 TTSH_DECL(64)
 TTSH_DECL(96)
 #undef TTSH_DECL
+#define TTSH_DECL_SCHED(b)                 \
+  const SchedOps* sched_ops_##b##_6();   \
+  const SchedOps* sched_ops_##b##_10();  \
+  const SchedOps* sched_ops_##b##_9();   \
+  const SchedOps* sched_ops_##b##_7();   \
+  const SchedOps* sched_ops_##b##_11();
+TTSH_DECL_SCHED(64)
+TTSH_DECL_SCHED(128)
+TTSH_DECL_SCHED(256)
+#undef TTSH_DECL_SCHED
+const SchedOps* sched_ops(int bs, int sch) {
+  switch (bs * 100 + sch) {
+#define TTSH_CASE(b, s) \
+  case b * 100 + s: return sched_ops_##b##_##s();
+    TTSH_CASE(64, 6) TTSH_CASE(64, 10) TTSH_CASE(64, 9) TTSH_CASE(64, 7) TTSH_CASE(64, 11)
+    TTSH_CASE(128, 6) TTSH_CASE(128, 10) TTSH_CASE(128, 9) TTSH_CASE(128, 7) TTSH_CASE(128, 11)
+    TTSH_CASE(256, 6) TTSH_CASE(256, 10) TTSH_CASE(256, 9) TTSH_CASE(256, 7) TTSH_CASE(256, 11)
+#undef TTSH_CASE
+    default: return nullptr;
+  }
+}
 const MultiOps* multi_ops(int prec, int bs) {
   switch (prec * 1000 + bs) {
     case 32064: return multi_ops_32_64();
@@ -138,6 +160,7 @@ struct SizeClass {
   void* st2 = nullptr;   // ETD2RK / ETDRK4: stage state (as st), kept forcing spectra, k = 0 sums
   void* fst = nullptr;
   double* s1st = nullptr;
+  int* gflags = nullptr;  // the class's guard flags, in the order of ids (inside the context's dflags)
   // per-instance strides in elements
   // mixed-domain arrays hold M+1 columns padded to a multiple of 4
   size_t mp4() const { return (size_t)((N / 4 + 1 + 3) / 4 * 4); }
@@ -166,7 +189,9 @@ struct ttsh_ctx {
   std::map<int, void*> tw32;             // FP32 twiddles per N
   void* scr0 = nullptr;                  // FP64 complex N^2 of the largest N
   void* scr1 = nullptr;
-  double* dnorm = nullptr;               // [n_inst][5]
+  double* dnorm = nullptr;               // [n_inst][5]; kNormBlocks x 5 partials follow
+  int* dflags = nullptr;                 // [n_inst] non-finite flags of the guard
+  int guard_every = 50;                  // steps between guard checks inside ttsh_step (0: only at ttsh_sync)
   void* pb0 = nullptr;                   // batched coarse-field spectra (grown on demand)
   void* pb1 = nullptr;
   size_t pb_cap = 0;                     // bytes of each
@@ -181,6 +206,8 @@ struct ttsh_ctx {
   int bs_row = 0;   // workgroup size of the row pass in use
   int opt_bs = 0;   // requested by TTSH_OPT_BLOCK (0 = chosen)
   int split_row = 0, split_col = 0;  // one launch per size class (TTSH_OPT_SPLIT)
+  int sched_row = kSchedDefault;     // transform schedule of the row pass (multi-size launch, FP32)
+  int sched_col = kSchedDefault;     // and of the one-stage column pass
   int guard = 1;
   int device = 0;                        // HIP device current at creation
   hipGraph_t graph = nullptr;            // graph_steps steps
@@ -325,14 +352,26 @@ MultiArgs multi_args(ttsh_ctx* c, int row, int inst) {
 // kernels are not compiled for that size)
 bool must_split(const ttsh_ctx* c) { return max_N(c) > 1024; }
 
+// a non-default transform schedule exists for the multi-size launches of the
+// FP32 arithmetic (row pass, one-stage column pass)
+bool sched_usable(const ttsh_ctx* c, int split) { return c->prec == 32 && !split && !must_split(c); }
+
 hipError_t launch_row(ttsh_ctx* c, const MultiArgs& m, hipStream_t s) {
+  const bool split = c->split_row || must_split(c);
+  if (c->sched_row != kSchedDefault && sched_usable(c, split))
+    return sched_ops(c->bs_row, c->sched_row)->row(m, c->gw, s);
   const MultiOps* o = multi_ops(c->prec == 64 ? 64 : 32, c->bs_row);
-  return c->split_row || must_split(c) ? o->row_split(m, c->gw, s) : o->row(m, c->gw, s);
+  return split ? o->row_split(m, c->gw, s) : o->row(m, c->gw, s);
 }
 hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) {
+  const bool split = c->split_col || must_split(c);
+  if (mode == 0 && c->sched_col != kSchedDefault && sched_usable(c, split))
+    return sched_ops(c->bs, c->sched_col)->col(m, c->gw, s);
   const MultiOps* o = multi_ops(c->prec, c->bs);
-  return c->split_col || must_split(c) ? o->col_split(m, c->gw, mode, s) : o->col(m, c->gw, mode, s);
+  return split ? o->col_split(m, c->gw, mode, s) : o->col(m, c->gw, mode, s);
 }
+
+hipError_t launch_guard(ttsh_ctx* c, hipStream_t s);
 
 int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
   if (n <= 0) return TTSH_OK;
@@ -349,6 +388,9 @@ int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
       HIPCHK(launch_row(c, r, s));
       HIPCHK(launch_col(c, q, modes[j], s));
     }
+    // the guard after every guard_every steps of this sequence (inside a
+    // captured chunk of G steps: after steps guard_every, 2 guard_every, ...)
+    if (c->guard && c->guard_every > 0 && (i + 1) % c->guard_every == 0) HIPCHK(launch_guard(c, s));
   }
   return TTSH_OK;
 }
@@ -448,14 +490,34 @@ int norms_into(ttsh_ctx* c, int inst, double* dout) {
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
   const double dk = 2.0 * M_PI / c->L[inst];
+  double* part = c->dnorm + 5 * c->n_inst;
   if (c->prec == 32)
-    hipLaunchKernelGGL(k_norms<float>, dim3(1), dim3(1024), 0, c->stream,
-                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), k.N, dk, dout);
+    hipLaunchKernelGGL(k_norms<float>, dim3(kNormBlocks), dim3(256), 0, c->stream,
+                       at<const C2<float>>(k.st, k.sSt(), sizeof(C2<float>), j), k.N, dk, part);
   else
-    hipLaunchKernelGGL(k_norms<double>, dim3(1), dim3(1024), 0, c->stream,
-                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), k.N, dk, dout);
+    hipLaunchKernelGGL(k_norms<double>, dim3(kNormBlocks), dim3(256), 0, c->stream,
+                       at<const C2<double>>(k.st, k.sSt(), sizeof(C2<double>), j), k.N, dk, part);
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(64), 0, c->stream, (const double*)part, kNormBlocks, dout);
   HIPCHK(hipGetLastError());
   return TTSH_OK;
+}
+
+// the non-finite guard over every instance: sets the flags of the instances
+// that hold NaN or Inf (ttsh_sync reads and clears them); the flags of a
+// class are stored in the class's instance order
+hipError_t launch_guard(ttsh_ctx* c, hipStream_t s) {
+  for (auto& k : c->cls) {
+    const int n = (int)k.ids.size();
+    const size_t per = (size_t)2 * (k.N / 4 + 1) * (k.N / 2 + 2);
+    const dim3 grid((unsigned)std::min<size_t>((per + 2047) / 2048, 64), (unsigned)n);
+    if (c->prec == 32)
+      hipLaunchKernelGGL(k_guard<float>, grid, dim3(256), 0, s, (const C2<float>*)k.st, k.N, k.gflags);
+    else
+      hipLaunchKernelGGL(k_guard<double>, grid, dim3(256), 0, s, (const C2<double>*)k.st, k.N, k.gflags);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---- continuation (reseed) ----------------------------------------------------
@@ -551,6 +613,7 @@ void free_ctx(ttsh_ctx* c) {
   if (c->scr0) hipFree(c->scr0);
   if (c->scr1) hipFree(c->scr1);
   if (c->dnorm) hipFree(c->dnorm);
+  if (c->dflags) hipFree(c->dflags);
   for (void* p : {c->pb0, c->pb1, (void*)c->pnorm, c->lyq, (void*)c->psdf})
     if (p) hipFree(p);
   if (c->cap) hipStreamDestroy(c->cap);
@@ -655,8 +718,17 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
   const int Nmax = sizes.back();
   if (hipMalloc(&c->scr0, sizeof(double) * 2 * Nmax * Nmax) != hipSuccess ||
       hipMalloc(&c->scr1, sizeof(double) * 2 * Nmax * Nmax) != hipSuccess ||
-      hipMalloc((void**)&c->dnorm, sizeof(double) * 5 * n_inst) != hipSuccess)
+      hipMalloc((void**)&c->dnorm, sizeof(double) * 5 * ((size_t)n_inst + kNormBlocks)) != hipSuccess ||
+      hipMalloc((void**)&c->dflags, sizeof(int) * n_inst) != hipSuccess)
     return bail(fail(TTSH_ENOMEM, "scratch allocation failed"));
+  if (hipMemset(c->dflags, 0, sizeof(int) * n_inst) != hipSuccess) return bail(fail(TTSH_EHIP, "hipMemset failed"));
+  {
+    int off = 0;
+    for (auto& k : c->cls) {
+      k.gflags = c->dflags + off;
+      off += (int)k.ids.size();
+    }
+  }
   if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(TTSH_EHIP, "stream creation failed"));
   if (sizes.size() > (size_t)kMaxClasses) return bail(fail(TTSH_EUNSUPPORTED, "too many grid sizes"));
@@ -694,6 +766,10 @@ int ttsh_set_option(ttsh_ctx* c, int key, int64_t value) {
       break;
     case TTSH_OPT_GUARD:
       c->guard = value != 0;
+      break;
+    case TTSH_OPT_GUARD_EVERY:
+      if (value < 0 || value > 1000000) return fail(TTSH_EINVAL, "guard interval out of range");
+      c->guard_every = (int)value;
       break;
     default:
       return fail(TTSH_EINVAL, "unknown option");
@@ -1319,15 +1395,25 @@ int ttsh_sync(ttsh_ctx* c) {
   if (!c) return fail(TTSH_EINVAL, "null context");
   HIPCHK(hipStreamSynchronize(c->stream));
   if (!c->guard) return TTSH_OK;
-  for (int i = 0; i < c->n_inst; ++i) {
-    int rc = norms_into(c, i, c->dnorm + 5 * i);
-    if (rc) return rc;
-  }
-  std::vector<double> h(5 * c->n_inst);
-  HIPCHK(hipMemcpyAsync(h.data(), c->dnorm, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  // a last check of the current states on top of the ones the steps ran,
+  // then read and clear the flags
+  HIPCHK(launch_guard(c, c->stream));
+  std::vector<int> h(c->n_inst);
+  HIPCHK(hipMemcpyAsync(h.data(), c->dflags, sizeof(int) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  hipLaunchKernelGGL(k_fill_int, dim3(nblk(c->n_inst)), dim3(kB), 0, c->stream, c->dflags, c->n_inst, 0);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
-  for (int i = 0; i < c->n_inst; ++i)
-    if (h[5 * i + 4] != 0.0) return fail(TTSH_ENONFINITE, "non-finite value in instance " + std::to_string(i));
+  int first = -1, bad = 0;
+  for (auto& k : c->cls)
+    for (size_t j = 0; j < k.ids.size(); ++j)
+      if (h[(size_t)(k.gflags - c->dflags) + j]) {
+        ++bad;
+        if (first < 0 || k.ids[j] < first) first = k.ids[j];
+      }
+  if (bad) {
+    return fail(TTSH_ENONFINITE, "non-finite value in instance " + std::to_string(first) +
+                                     (bad > 1 ? " (and " + std::to_string(bad - 1) + " more)" : std::string()));
+  }
   return TTSH_OK;
 }
 
@@ -1397,48 +1483,107 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
   };
   int rc = TTSH_OK;
   if (copy_all(true) != hipSuccess) rc = fail(TTSH_EHIP, "tuner save failed");
-  const int keep_bs = c->bs, keep_row = c->bs_row, keep_sr = c->split_row, keep_sc = c->split_col;
-  int best_row = 0, best_col = 0, best_sr = 0, best_sc = 0;
+  const int keep[6] = {c->bs_row, c->bs, c->split_row, c->split_col, c->sched_row, c->sched_col};
+  int best_row[3] = {0, 0, kSchedDefault}, best_col[3] = {0, 0, kSchedDefault};  // bs, split, schedule
   double row_us = 0.0, col_us = 0.0;
-  for (int split = must_split(c) ? 1 : 0; split < 2 && rc == TTSH_OK; ++split) {
+  // every candidate is timed in two rounds (all candidates once, then all
+  // again) and keeps its faster time, which evens out drifts of the clock
+  struct Cand {
+    int bs, split, sch;
+    double row, col;
+  };
+  std::vector<Cand> cands;
+  for (int split = must_split(c) ? 1 : 0; split < 2; ++split)
     for (int bs : {64, 128, 256}) {
-      if (rc != TTSH_OK || !bs_valid(c, bs)) continue;
-      c->bs = c->bs_row = bs;
-      c->split_row = c->split_col = split;
+      if (!bs_valid(c, bs)) continue;
+      const int nsch = sched_usable(c, split) ? 1 + kNumSchedVariants : 1;
+      for (int q = 0; q < nsch; ++q) cands.push_back({bs, split, q == 0 ? kSchedDefault : kSchedVariants[q - 1], 1e30, 1e30});
+    }
+  for (int round = 0; round < 2 && rc == TTSH_OK; ++round)
+    for (Cand& k : cands) {
+      c->bs = c->bs_row = k.bs;
+      c->split_row = c->split_col = k.split;
+      c->sched_row = c->sched_col = k.sch;
       double t[2];
       if (enqueue_steps(c, 2, c->stream) != TTSH_OK) { rc = TTSH_EHIP; break; }  // warm-up
       if ((rc = ttsh_pass_times(c, nsteps, t)) != TTSH_OK) break;
-      if (!best_row || t[0] < row_us) { best_row = bs; best_sr = split; row_us = t[0]; }
-      if (!best_col || t[1] < col_us) { best_col = bs; best_sc = split; col_us = t[1]; }
+      k.row = std::min(k.row, t[0]);
+      k.col = std::min(k.col, t[1]);
     }
+  for (const Cand& k : cands) {
+    if (!best_row[0] || k.row < row_us) { best_row[0] = k.bs; best_row[1] = k.split; best_row[2] = k.sch; row_us = k.row; }
+    if (!best_col[0] || k.col < col_us) { best_col[0] = k.bs; best_col[1] = k.split; best_col[2] = k.sch; col_us = k.col; }
   }
   if (copy_all(false) != hipSuccess && rc == TTSH_OK) rc = fail(TTSH_EHIP, "tuner restore failed");
   hipStreamSynchronize(c->stream);
   hipFree(buf);
-  if (rc != TTSH_OK || !best_row) {
-    c->bs = keep_bs;
-    c->bs_row = keep_row;
-    c->split_row = keep_sr;
-    c->split_col = keep_sc;
+  if (rc != TTSH_OK || !best_row[0]) {
+    c->bs_row = keep[0];
+    c->bs = keep[1];
+    c->split_row = keep[2];
+    c->split_col = keep[3];
+    c->sched_row = keep[4];
+    c->sched_col = keep[5];
     return rc ? rc : fail(TTSH_EUNSUPPORTED, "no workgroup size to tune");
   }
-  // the two passes are tuned independently (the data layout does not depend
-  // on the workgroup size)
-  c->bs_row = best_row;
-  c->bs = best_col;
-  c->split_row = best_sr;
-  c->split_col = best_sc;
+  // the two passes are tuned independently (the data layout depends on
+  // neither the workgroup size nor the transform schedule)
+  c->bs_row = best_row[0];
+  c->split_row = best_row[1];
+  c->sched_row = best_row[2];
+  c->bs = best_col[0];
+  c->split_col = best_col[1];
+  c->sched_col = best_col[2];
   c->opt_bs = 0;
   drop_graph(c);
-  const int best = best_col;
-  const double best_us = row_us + col_us;
   if (cfg_out) {
-    cfg_out[0] = best_row;
-    cfg_out[1] = best;
-    cfg_out[2] = best_sr;
-    cfg_out[3] = best_sc;
+    const int cfg[6] = {best_row[0], best_col[0], best_row[1], best_col[1], best_row[2], best_col[2]};
+    std::copy(cfg, cfg + 6, cfg_out);
   }
-  if (us_out) *us_out = best_us;
+  if (us_out) *us_out = row_us + col_us;
+  return TTSH_OK;
+}
+
+int ttsh_device_arch(char* out, int n) {
+  if (!out || n < 1) return fail(TTSH_EINVAL, "null or empty output");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(TTSH_EHIP, "no HIP device available");
+  std::snprintf(out, (size_t)n, "%s", prop.gcnArchName);
+  return TTSH_OK;
+}
+
+int ttsh_get_tuning(ttsh_ctx* c, int* cfg) {
+  if (!c || !cfg) return fail(TTSH_EINVAL, "null argument");
+  const int v[6] = {c->bs_row, c->bs, c->split_row || must_split(c), c->split_col || must_split(c), c->sched_row,
+                    c->sched_col};
+  std::copy(v, v + 6, cfg);
+  return TTSH_OK;
+}
+
+int ttsh_set_tuning(ttsh_ctx* c, const int* cfg) {
+  if (!c || !cfg) return fail(TTSH_EINVAL, "null argument");
+  for (int q = 0; q < 2; ++q)
+    if (!bs_valid(c, cfg[q])) return fail(TTSH_EINVAL, "workgroup size not usable for this context");
+  for (int q = 2; q < 4; ++q)
+    if (cfg[q] != 0 && cfg[q] != 1) return fail(TTSH_EINVAL, "split flags must be 0 or 1");
+  for (int q = 4; q < 6; ++q) {
+    const int sch = cfg[q];
+    const bool known = sch == kSchedDefault || std::find(kSchedVariants, kSchedVariants + kNumSchedVariants, sch) !=
+                                                   kSchedVariants + kNumSchedVariants;
+    if (!known) return fail(TTSH_EINVAL, "unknown transform schedule");
+    if (sch != kSchedDefault && !sched_usable(c, cfg[q - 2]))
+      return fail(TTSH_EINVAL, "a non-default schedule needs the FP32 arithmetic and the multi-size launch");
+  }
+  c->bs_row = cfg[0];
+  c->bs = cfg[1];
+  c->split_row = cfg[2];
+  c->split_col = cfg[3];
+  c->sched_row = cfg[4];
+  c->sched_col = cfg[5];
+  c->opt_bs = 0;
+  drop_graph(c);
   return TTSH_OK;
 }
 

@@ -19,7 +19,7 @@ TTSH_OK, TTSH_EINVAL, TTSH_EUNSUPPORTED, TTSH_EHIP, TTSH_ENONFINITE, TTSH_ENOMEM
 TTSH_HOST, TTSH_DEVICE = 0, 1
 TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX, TTSH_ETDRK2, TTSH_ETDRK4 = 0, 1, 2, 3, 4
 TTSH_FP32, TTSH_FP64, TTSH_FP32_STATE64 = 32, 64, 96
-TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD, TTSH_OPT_SPLIT = 1, 2, 4, 8
+TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD, TTSH_OPT_SPLIT, TTSH_OPT_GUARD_EVERY = 1, 2, 4, 8, 16
 SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX, "etdrk2": TTSH_ETDRK2,
            "etdrk4": TTSH_ETDRK4}
 
@@ -77,6 +77,9 @@ def lib() -> ctypes.CDLL:
             "ttsh_fft2": [dp, dp, i32, i32, i32, i32],
             "ttsh_pass_times": [vp, i64, dp],
             "ttsh_tune": [vp, i64, dp, dp],
+            "ttsh_get_tuning": [vp, dp],
+            "ttsh_set_tuning": [vp, dp],
+            "ttsh_device_arch": [dp, i32],
             "ttsh_num_classes": [vp, dp],
             "ttsh_stream_bench": [i32, i32, i64, i32, i32, vp, dp],
         }
@@ -352,12 +355,32 @@ def ttsh_stream_bench(reads, writes, elems, blocks, reps, buf):
 
 def ttsh_tune(ctx, nsteps):
     """Pick the fastest launch configuration of each pass; returns
-    ((row_size, col_size, row_split, col_split), us_per_step)."""
-    cfg = (ctypes.c_int * 4)()
+    ((row_size, col_size, row_split, col_split, row_schedule, col_schedule),
+    us_per_step)."""
+    cfg = (ctypes.c_int * 6)()
     us = ctypes.c_double()
     _check(lib().ttsh_tune(ctx, int(nsteps), ctypes.cast(cfg, ctypes.c_void_p),
                            ctypes.cast(ctypes.byref(us), ctypes.c_void_p)))
     return tuple(cfg), us.value
+
+
+def ttsh_get_tuning(ctx):
+    cfg = (ctypes.c_int * 6)()
+    _check(lib().ttsh_get_tuning(ctx, ctypes.cast(cfg, ctypes.c_void_p)))
+    return tuple(cfg)
+
+
+def ttsh_set_tuning(ctx, cfg):
+    if len(cfg) != 6:
+        raise ValueError("a tuning is 6 ints")
+    arr = (ctypes.c_int * 6)(*[int(v) for v in cfg])
+    return _check(lib().ttsh_set_tuning(ctx, ctypes.cast(arr, ctypes.c_void_p)))
+
+
+def ttsh_device_arch():
+    buf = ctypes.create_string_buffer(128)
+    _check(lib().ttsh_device_arch(ctypes.cast(buf, ctypes.c_void_p), 128))
+    return buf.value.decode()
 
 
 def ttsh_last_error() -> str:
@@ -371,6 +394,8 @@ class Solver:
     def __init__(self, N, L, params, precision=TTSH_FP32, stream=None):
         self.N = [int(n) for n in N]
         self.L = [float(x) for x in L]
+        self.precision = int(precision)
+        self.gw = float(getattr(params, "gamma_w", 0.0)) != 0.0
         self.ctx = ttsh_create(self.N, self.L, params, precision, stream)
 
     def close(self):
@@ -463,6 +488,12 @@ class Solver:
 
     def tune(self, nsteps=20):
         return ttsh_tune(self.ctx, nsteps)
+
+    def get_tuning(self):
+        return ttsh_get_tuning(self.ctx)
+
+    def set_tuning(self, cfg):
+        ttsh_set_tuning(self.ctx, cfg)
 
     def pass_times(self, nsteps=50):
         return ttsh_pass_times(self.ctx, nsteps)

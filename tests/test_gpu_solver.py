@@ -292,9 +292,10 @@ def test_block_sizes_agree_and_tuner_restores_state(gpu):
             s.set_field(i, W.uniform_field(40 + i, N, 0.2, 32))
         if bs == 128 and split == 0:
             before = [s.state(i) for i in range(3)]
-            (brow, bcol, srow, scol), us = s.tune(3)
+            (brow, bcol, srow, scol, hrow, hcol), us = s.tune(3)
             assert brow in (64, 128, 256) and bcol in (64, 128, 256) and us > 0
-            assert srow in (0, 1) and scol in (0, 1)
+            assert srow in (0, 1) and scol in (0, 1) and hrow in range(6, 12) and hcol in range(6, 12)
+            assert s.get_tuning() == (brow, bcol, srow, scol, hrow, hcol)
             for i in range(3):
                 assert np.array_equal(s.state(i), before[i])
         s.step(20)
@@ -306,6 +307,50 @@ def test_block_sizes_agree_and_tuner_restores_state(gpu):
     # a per-size launch runs the same tile code as the multi-size launch
     for a, b in zip(out[(64, 3)], out[(64, 0)]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("sched", [6, 7, 8, 9, 10, 11])
+def test_transform_schedules_match_oracle(gpu, sched):
+    """Every transform schedule the autotuner may pick (LDS padding one slot
+    per 8/16/32 entries; for 128^2 and 256^2 the leftover radix first or
+    last), for both passes of a multi-size FP32 context, against the FP64
+    oracle after 40 steps; and a cached choice is applied as it was stored."""
+    from paper_2304_03306_amd import tuning
+    say("schedule", sched)
+    p = O.workload_params()
+    Ns, Ls = [128, 256, 512], [64.0, 96.0, 160.0]
+    s = gpu.Solver(Ns, Ls, p, 32)
+    refs = []
+    for i, (N, L) in enumerate(zip(Ns, Ls)):
+        K = O.mask_tanh(N, L, [(0.0, 0.0)], [L / 4], 0.5)
+        v0 = W.uniform_field(120 + i, N, 0.2, 32)
+        s.set_mask(i, K)
+        s.set_field(i, v0)
+        refs.append(O.run_velocity(O.project_field(v0, L), K, p, L, 40))
+    cfg = (64, 128, 0, 0, sched, sched)
+    s.set_tuning(cfg)
+    assert s.get_tuning() == cfg
+    s.step(40)
+    s.sync()
+    for i in range(3):
+        err = O.rel_l2(s.field(i), O.field(refs[i]))
+        assert err < 2e-6, (i, err)
+    # the cache hands the same choice to a new context without tuning
+    import tempfile, os
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "c.json")
+        tuning.store(tuning.cache_key(Ns, 32, False, gpu.ttsh_device_arch()), cfg, 1.0, path)
+        t = gpu.Solver(Ns, Ls, p, 32)
+        got, _, hit = tuning.autotune(t, 3, path)
+        assert hit and got == cfg and t.get_tuning() == cfg
+        t.close()
+    # schedules other than the default exist only for FP32 multi-size launches
+    f64 = gpu.Solver(Ns, Ls, p, 64)
+    if sched != 8:
+        with pytest.raises(gpu.TTSHError):
+            f64.set_tuning((64, 128, 0, 0, sched, sched))
+    f64.close()
+    s.close()
 
 
 def test_reseed_matches_oracle(gpu):
@@ -454,15 +499,23 @@ def test_failure_injection_nonfinite_input_and_unstable_mask(gpu):
     s.step(2)
     s.sync()
     bad = dataclasses.replace(p, gamma_v=300.0)
-    u = gpu.Solver([N, N], [L, L], bad, 32)
-    u.set_mask(0, np.zeros((N, N)))
-    u.set_mask(1, np.ones((N, N)))
-    u.set_field(0, W.uniform_field(4, N, 0.1, 32))
-    u.set_field(1, W.uniform_field(5, N, 0.1, 32))
-    u.step(300)
-    with pytest.raises(gpu.TTSHError) as e:
-        u.sync()
-    assert e.value.code == gpu.TTSH_ENONFINITE and "instance 1" in str(e.value)
+    # checks queued inside the step graphs (every 10 or 50 steps) or only the
+    # one in ttsh_sync: the unstable instance is reported either way
+    for every in (10, 50, 0):
+        u = gpu.Solver([N, N, 2 * N], [L, L, 2 * L], bad, 32)
+        u.option(gpu.TTSH_OPT_GUARD_EVERY, every)
+        u.set_mask(0, np.zeros((N, N)))
+        u.set_mask(1, np.ones((N, N)))
+        u.set_mask(2, np.zeros((2 * N, 2 * N)))
+        u.set_field(0, W.uniform_field(4, N, 0.1, 32))
+        u.set_field(1, W.uniform_field(5, N, 0.1, 32))
+        u.set_field(2, W.uniform_field(6, 2 * N, 0.1, 32))
+        u.step(300)
+        with pytest.raises(gpu.TTSHError) as e:
+            u.sync()
+        assert e.value.code == gpu.TTSH_ENONFINITE and "instance 1" in str(e.value), (every, str(e.value))
+        assert "more" not in str(e.value)
+        u.close()
 
 
 @pytest.mark.parametrize("prec", [32, 64])

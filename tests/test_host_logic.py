@@ -110,8 +110,10 @@ def test_pmc_summary_scaling_and_source_check(tmp_path, monkeypatch):
             f.write('"Kernel_Name","Counter_Name","Counter_Value"\n')
             for k, c, v in rows:
                 f.write(f'"{k}","{c}",{v}\n')
-    row = "void ttsh::row_multi<float, false, 64>(ttsh::MultiArgs)"
-    col = "void ttsh::col_multi<float, float, false, 0, 128>(ttsh::MultiArgs)"
+    row = bench.kernel_name("row", 64, 8)
+    col = bench.kernel_name("col", 128, 9)
+    assert row == "void ttsh::row_multi<float, false, 64, 8>(ttsh::MultiArgs)"
+    assert col == "void ttsh::col_multi<float, float, false, 0, 128, 9>(ttsh::MultiArgs)"
     csv(tmp_path / "f.csv", [(row, "FETCH_SIZE", 100.0), (row, "FETCH_SIZE", 300.0), (col, "FETCH_SIZE", 50.0)])
     csv(tmp_path / "w.csv", [(row, "WRITE_SIZE", 40.0), (col, "WRITE_SIZE", 80.0)])
     csv(tmp_path / "cf.csv", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0)])  # 1 MiB read, counted half
@@ -123,12 +125,12 @@ def test_pmc_summary_scaling_and_source_check(tmp_path, monkeypatch):
     out = tmp_path / "t.json"
     out.write_text(json.dumps(s))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
-    assert bench.measured_traffic("row_multi", 64) == s["kernels"][row]["bytes"]
-    assert bench.measured_traffic("col_multi", 128) == s["kernels"][col]["bytes"]
-    assert bench.measured_traffic("row_multi", 128) is None
+    assert bench.measured_traffic(row) == s["kernels"][row]["bytes"]
+    assert bench.measured_traffic(col) == s["kernels"][col]["bytes"]
+    assert bench.measured_traffic(bench.kernel_name("row", 128, 8)) is None
     s["source_sha256"] = "0" * 64
     out.write_text(json.dumps(s))
-    assert bench.measured_traffic("row_multi", 64) is None
+    assert bench.measured_traffic(row) is None
 
 
 def test_philox_known_answers():
@@ -156,3 +158,51 @@ def test_philox_noise_layout_and_range():
     assert z.min() >= -amp and z.max() < amp
     assert not np.array_equal(z, W.philox_noise(seed, inst + 1, N, amp))
     assert not np.array_equal(z, W.philox_noise(seed + 1, inst, N, amp))
+
+
+def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    """The tuner cache: the key ignores instance order, a stored choice is
+    read back and applied without tuning, a miss tunes and records, and a
+    malformed file reads as empty."""
+    from paper_2304_03306_amd import tuning, ttsh as T
+    monkeypatch.setattr(T, "ttsh_device_arch", lambda: "gfx950:test")
+    k1 = tuning.cache_key([512, 128, 512, 256], 32, False, "gfx950:test")
+    k2 = tuning.cache_key([256, 512, 128, 512], 32, False, "gfx950:test")
+    assert k1 == k2 == "gfx950:test|p32|gw0|1x128,1x256,2x512"
+    assert tuning.cache_key([512], 32, True, "a") != tuning.cache_key([512], 64, True, "a")
+
+    class FakeSolver:
+        N, precision, gw = [512, 128], 32, False
+
+        def __init__(self):
+            self.tuned = 0
+            self.applied = None
+
+        def tune(self, n):
+            self.tuned += 1
+            return (64, 256, 0, 0, 9, 8), 77.5
+
+        def set_tuning(self, cfg):
+            self.applied = tuple(cfg)
+
+    path = tmp_path / "cache.json"
+    a = FakeSolver()
+    cfg, us, hit = tuning.autotune(a, 5, path)
+    assert (cfg, us, hit) == ((64, 256, 0, 0, 9, 8), 77.5, False) and a.tuned == 1
+    b = FakeSolver()
+    cfg, us, hit = tuning.autotune(b, 5, path)
+    assert hit and b.tuned == 0 and b.applied == (64, 256, 0, 0, 9, 8) and us == 77.5
+    c = FakeSolver()
+    tuning.autotune(c, 5, path, retune=True)
+    assert c.tuned == 1
+    path.write_text("{not json")
+    assert tuning.load(path) == {}
+    d = FakeSolver()
+    _, _, hit = tuning.autotune(d, 5, path)
+    assert not hit and d.tuned == 1 and json_keys(path) == [tuning.cache_key(d.N, 32, False, "gfx950:test")]
+
+
+def json_keys(path):
+    import json
+    with open(path) as f:
+        return sorted(json.load(f))
