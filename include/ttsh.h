@@ -119,9 +119,13 @@ enum {
 };
 
 /* Create a context holding n_inst independent instances advanced together.
- *   N[i]   grid points per side of instance i: 64, 128, 256, 512, 1024 or 2048
- *          (2048: its passes run with 256-thread workgroups, in FP64 with
- *          about 70 KB of LDS per workgroup)
+ *   N[i]   grid points per side of instance i: 64, 128, 256, 512, 1024, 2048,
+ *          4096 or 8192 (2048: its passes run with 256-thread workgroups, in
+ *          FP64 with about 70 KB of LDS per workgroup; 4096 and 8192, the
+ *          paper's production sizes: N/8 threads per workgroup, one row pair
+ *          or column each, up to 139 KB of LDS; 8192 needs TTSH_FP32 or
+ *          TTSH_FP32_STATE64, else TTSH_EUNSUPPORTED).  Contexts with a grid
+ *          above 1024 launch every pass once per grid size.
  *   L[i]   box side of instance i (> 0)
  *   p      coefficients shared by all instances
  *   precision  TTSH_FP32, TTSH_FP64 or TTSH_FP32_STATE64

@@ -16,7 +16,9 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 OUT = HERE / "_build"
 LIB = HERE / "libttsh.so"
-SIZES = (64, 128, 256, 512, 1024, 2048)
+SIZES = (64, 128, 256, 512, 1024, 2048, 4096, 8192)
+# the production sizes' step passes: (N, arithmetic) pairs whose tiles fit the LDS
+BIG = ((4096, 32), (4096, 64), (4096, 96), (8192, 32), (8192, 96))
 PRECS = (32, 64, 96)
 BLOCKS = (64, 128, 256)
 SCHED_VARIANTS = (6, 10, 9, 7, 11)  # kSchedVariants of csrc/launch.hpp
@@ -51,6 +53,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> Path:
     # the FP32 step passes with the other transform schedules the autotuner tries
     units += [(CSRC / "step_sched.hip", OUT / f"sched_{b}_{s}.o", [f"-DTTSH_BS={b}", f"-DTTSH_SCH={s}"])
               for b in BLOCKS for s in SCHED_VARIANTS]
+    units += [(CSRC / "step_big.hip", OUT / f"big_{n}_{p}.o", [f"-DTTSH_N={n}", f"-DTTSH_PREC={p}"]) for n, p in BIG]
     units.append((CSRC / "ttsh_capi.hip", OUT / "ttsh_capi.o", []))
     units.append((CSRC / "fno.hip", OUT / "fno.o", []))
     units.append((CSRC / "stream.hip", OUT / "stream.o", []))

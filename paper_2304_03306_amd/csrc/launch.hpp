@@ -38,6 +38,15 @@ constexpr int kNumSchedVariants = 5;
 constexpr int kSchedVariants[kNumSchedVariants] = {6, 10, 9, 7, 11};  // 2 PAD + SMALL_FIRST
 const SchedOps* sched_ops(int bs, int sch);  // null for the default schedule or an unknown one
 
+// The passes of one size class of the paper's production sizes (4096, 8192),
+// whose workgroups have N/8 threads: `o` holds that class alone (c[0]).
+struct BigOps {
+  hipError_t (*row)(const MultiArgs& o, int gw, hipStream_t);
+  hipError_t (*col)(const MultiArgs& o, int gw, int mode, hipStream_t);
+};
+constexpr int kMaxBlockN = 2048;  // the largest size served by the 64..256-thread kernels
+const BigOps* big_ops(int N, int prec);  // null where the tiles do not fit (8192 in FP64)
+
 const SizeOps* size_ops(int N);
 // record `msg` as the calling thread's last error (ttsh_last_error) and return code
 int record_error(int code, const char* msg);

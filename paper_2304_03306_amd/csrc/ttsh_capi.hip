@@ -38,6 +38,23 @@ const SizeOps* ops_256();
 const SizeOps* ops_512();
 const SizeOps* ops_1024();
 const SizeOps* ops_2048();
+const SizeOps* ops_4096();
+const SizeOps* ops_8192();
+const BigOps* big_ops_4096_32();
+const BigOps* big_ops_4096_64();
+const BigOps* big_ops_4096_96();
+const BigOps* big_ops_8192_32();
+const BigOps* big_ops_8192_96();
+const BigOps* big_ops(int N, int prec) {
+  switch (N * 100 + prec) {
+    case 409632: return big_ops_4096_32();
+    case 409664: return big_ops_4096_64();
+    case 409696: return big_ops_4096_96();
+    case 819232: return big_ops_8192_32();
+    case 819296: return big_ops_8192_96();
+    default: return nullptr;
+  }
+}
 const SizeOps* size_ops(int N) {
   switch (N) {
     case 64: return ops_64();
@@ -46,6 +63,8 @@ const SizeOps* size_ops(int N) {
     case 512: return ops_512();
     case 1024: return ops_1024();
     case 2048: return ops_2048();
+    case 4096: return ops_4096();
+    case 8192: return ops_8192();
     default: return nullptr;
   }
 }
@@ -263,13 +282,27 @@ bool tiles_fit(int N, int gw) {
   return row_smem_of<T, BS>(N) > 0 && col_smem_of<T, BS, false>(N) > 0 && (!gw || col_smem_of<T, BS, true>(N) > 0);
 }
 
+// the largest size served by the 64..256-thread kernels (0 if none)
+int max_small_N(const ttsh_ctx* c) {
+  int m = 0;
+  for (auto& k : c->cls)
+    if (k.N <= kMaxBlockN) m = std::max(m, k.N);
+  return m;
+}
+
+// workgroup size of a class's tiles in one pass: the chosen size, or N/8 for
+// the production sizes (one row pair or column per workgroup)
+int class_bs(const ttsh_ctx* c, int N, int row) { return N > kMaxBlockN ? N / 8 : (row ? c->bs_row : c->bs); }
+
 // A workgroup of bs threads carries one transform of length N with N/8
-// threads, so bs is usable when 8 bs >= N for every size class and every
-// class's tiles fit the LDS limit (FP64 tiles of many small columns do not).
+// threads, so bs is usable when 8 bs >= N for every size class up to 2048
+// and every such class's tiles fit the LDS limit (FP64 tiles of many small
+// columns do not); larger classes have workgroups of their own size.
 bool bs_valid(const ttsh_ctx* c, int bs) {
-  if (!(bs == 64 || bs == 128 || bs == 256) || 8 * bs < max_N(c)) return false;
+  if (!(bs == 64 || bs == 128 || bs == 256) || 8 * bs < max_small_N(c)) return false;
   const bool f64 = c->prec == 64;
   for (auto& k : c->cls) {
+    if (k.N > kMaxBlockN) continue;
     bool ok = false;
     if (bs == 64) ok = f64 ? tiles_fit<double, 64>(k.N, c->gw) : tiles_fit<float, 64>(k.N, c->gw);
     if (bs == 128) ok = f64 ? tiles_fit<double, 128>(k.N, c->gw) : tiles_fit<float, 128>(k.N, c->gw);
@@ -302,7 +335,7 @@ int choose_bs(ttsh_ctx* c) {
 ClassArgs class_args(ttsh_ctx* c, SizeClass& k, int first, int count, int row) {
   ClassArgs a{};
   const size_t er = elem_real(c->prec), es = elem_state(c->prec);
-  const int R = (row ? c->bs_row : c->bs) / (k.N / 8);
+  const int R = class_bs(c, k.N, row) / (k.N / 8);
   a.N = k.N;
   a.n = count;
   a.tiles = row ? k.N / (2 * R) : (k.N / 4 + 1 + R - 1) / R;
@@ -356,19 +389,43 @@ bool must_split(const ttsh_ctx* c) { return max_N(c) > 1024; }
 // FP32 arithmetic (row pass, one-stage column pass)
 bool sched_usable(const ttsh_ctx* c, int split) { return c->prec == 32 && !split && !must_split(c); }
 
+// the launch arguments of class q of m alone
+MultiArgs only_class(const MultiArgs& m, int q) {
+  MultiArgs o = m;
+  o.ncls = 1;
+  o.c[0] = m.c[q];
+  o.start[0] = 0;
+  o.start[1] = m.start[q + 1] - m.start[q];
+  return o;
+}
+
 hipError_t launch_row(ttsh_ctx* c, const MultiArgs& m, hipStream_t s) {
   const bool split = c->split_row || must_split(c);
   if (c->sched_row != kSchedDefault && sched_usable(c, split))
     return sched_ops(c->bs_row, c->sched_row)->row(m, c->gw, s);
-  const MultiOps* o = multi_ops(c->prec == 64 ? 64 : 32, c->bs_row);
-  return split ? o->row_split(m, c->gw, s) : o->row(m, c->gw, s);
+  const int tp = c->prec == 64 ? 64 : 32;  // the row pass depends on the transform precision only
+  const MultiOps* o = multi_ops(tp, c->bs_row);
+  if (!split) return o->row(m, c->gw, s);
+  for (int q = 0; q < m.ncls; ++q) {
+    const MultiArgs a = only_class(m, q);
+    const hipError_t e = a.c[0].N > kMaxBlockN ? big_ops(a.c[0].N, tp)->row(a, c->gw, s) : o->row_split(a, c->gw, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) {
   const bool split = c->split_col || must_split(c);
   if (mode == 0 && c->sched_col != kSchedDefault && sched_usable(c, split))
     return sched_ops(c->bs, c->sched_col)->col(m, c->gw, s);
   const MultiOps* o = multi_ops(c->prec, c->bs);
-  return split ? o->col_split(m, c->gw, mode, s) : o->col(m, c->gw, mode, s);
+  if (!split) return o->col(m, c->gw, mode, s);
+  for (int q = 0; q < m.ncls; ++q) {
+    const MultiArgs a = only_class(m, q);
+    const hipError_t e =
+        a.c[0].N > kMaxBlockN ? big_ops(a.c[0].N, c->prec)->col(a, c->gw, mode, s) : o->col_split(a, c->gw, mode, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_guard(ttsh_ctx* c, hipStream_t s);
@@ -639,7 +696,10 @@ int ttsh_create(ttsh_ctx** out, int n_inst, const int* N, const double* L, const
     if (!std::isfinite(v)) return fail(TTSH_EINVAL, "non-finite coefficient");
   if (!(p->dt > 0)) return fail(TTSH_EINVAL, "dt must be > 0");
   for (int i = 0; i < n_inst; ++i) {
-    if (!size_ops(N[i])) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
+    if (!size_ops(N[i]))
+      return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048, 4096, 8192");
+    if (N[i] > kMaxBlockN && !big_ops(N[i], precision))
+      return fail(TTSH_EUNSUPPORTED, "8192 points per side need FP32 transforms (TTSH_FP32 or TTSH_FP32_STATE64)");
     if (!(L[i] > 0) || !std::isfinite(L[i])) return fail(TTSH_EINVAL, "L must be > 0");
   }
   int ndev = 0;
@@ -930,7 +990,7 @@ int ttsh_get_field_coarse(ttsh_ctx* c, int inst, int Nc, float* out, int64_t pix
   if (rc) return rc;
   if (!out) return fail(TTSH_EINVAL, "null output");
   if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
-  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024, 2048");
+  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024, 2048, 4096, 8192");
   if (Nc > max_N(c)) return fail(TTSH_EINVAL, "Nc larger than the context's largest grid");
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
@@ -962,7 +1022,7 @@ int ttsh_set_field_coarse(ttsh_ctx* c, int inst, int Nc, const float* v, int64_t
   if (rc) return rc;
   if (!v) return fail(TTSH_EINVAL, "null input");
   if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
-  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024, 2048");
+  if (!size_ops(Nc)) return fail(TTSH_EUNSUPPORTED, "Nc must be one of 64, 128, 256, 512, 1024, 2048, 4096, 8192");
   if (Nc > max_N(c)) return fail(TTSH_EINVAL, "Nc larger than the context's largest grid");
   auto [ci, j] = c->loc[inst];
   SizeClass& k = c->cls[ci];
@@ -996,7 +1056,7 @@ int ttsh_project_coarse(ttsh_ctx* c, int N, float* v, int64_t pix_stride, int ba
   if (!v) return fail(TTSH_EINVAL, "null field");
   if (pix_stride < 2) return fail(TTSH_EINVAL, "pix_stride must be >= 2");
   if (batch < 1) return fail(TTSH_EINVAL, "batch must be >= 1");
-  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
+  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048, 4096, 8192");
   const size_t n = (size_t)batch * N * N;
   if (n > (size_t)INT32_MAX) return fail(TTSH_EINVAL, "batch too large");
   const size_t bytes = n * sizeof(C2<double>);
@@ -1207,7 +1267,7 @@ int ttsh_psd_accumulate(ttsh_ctx* c, int inst, int nf, const double* freqs, doub
 int ttsh_psd_finish(ttsh_ctx* c, int N, int nf, const void* acc, double* S) {
   if (!c) return fail(TTSH_EINVAL, "null context");
   if (!acc || !S) return fail(TTSH_EINVAL, "null argument");
-  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
+  if (!size_ops(N)) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048, 4096, 8192");
   if (nf < 1 || nf > kMaxPsdFreqs) return fail(TTSH_EINVAL, "nf must be 1..4096");
   if (!c->psdf && hipMalloc((void**)&c->psdf, sizeof(double) * 2 * kMaxPsdFreqs) != hipSuccess)
     return fail(TTSH_ENOMEM, "PSD frequencies");
@@ -1590,7 +1650,7 @@ int ttsh_set_tuning(ttsh_ctx* c, const int* cfg) {
 int ttsh_fft2(const double* in, double* out, int N, int batch, int inverse, int precision) {
   if (!in || !out) return fail(TTSH_EINVAL, "null pointer");
   const SizeOps* ops = size_ops(N);
-  if (!ops) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048");
+  if (!ops) return fail(TTSH_EUNSUPPORTED, "N must be one of 64, 128, 256, 512, 1024, 2048, 4096, 8192");
   if (batch < 1) return fail(TTSH_EINVAL, "batch must be >= 1");
   if (precision != 32 && precision != 64) return fail(TTSH_EINVAL, "precision must be 32 or 64");
   int ndev = 0;

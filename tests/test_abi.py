@@ -41,9 +41,12 @@ def test_rejects_bad_arguments_before_device_work(lib):
     L = (ctypes.c_double * 1)(10.0)
     assert lib.ttsh_create(ctypes.byref(ctx), 1, N, L, ctypes.byref(p), 32, None) == ttsh.TTSH_EUNSUPPORTED
     assert "N must be" in ttsh.ttsh_last_error()
-    N[0] = 4096
+    N[0] = 16384
     assert lib.ttsh_create(ctypes.byref(ctx), 1, N, L, ctypes.byref(p), 64, None) == ttsh.TTSH_EUNSUPPORTED
     assert "N must be" in ttsh.ttsh_last_error()
+    N[0] = 8192  # FP64 transforms of 8192 points do not fit one workgroup's LDS
+    assert lib.ttsh_create(ctypes.byref(ctx), 1, N, L, ctypes.byref(p), 64, None) == ttsh.TTSH_EUNSUPPORTED
+    assert "FP32 transforms" in ttsh.ttsh_last_error()
     N[0] = 64
     assert lib.ttsh_create(ctypes.byref(ctx), 0, N, L, ctypes.byref(p), 32, None) == ttsh.TTSH_EINVAL
     assert lib.ttsh_create(ctypes.byref(ctx), 1, N, L, ctypes.byref(p), 16, None) == ttsh.TTSH_EINVAL

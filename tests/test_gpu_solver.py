@@ -41,6 +41,59 @@ def test_fft2_matches_numpy(gpu, N, prec, tol):
         assert err < tol, (inv, err)
 
 
+@pytest.mark.parametrize("N,prec,tol", [(4096, 64, 2e-14), (4096, 32, 3e-6), (8192, 64, 2e-14), (8192, 32, 3e-6)])
+def test_fft2_production_sizes(gpu, N, prec, tol):
+    """The library's transform at the paper's production sizes (one 512- or
+    1024-thread workgroup per row or column), against numpy."""
+    import torch
+    say("fft2 production size", N, prec)
+    rng = np.random.default_rng(N + prec)
+    x = rng.standard_normal((1, N, N)) + 1j * rng.standard_normal((1, N, N))
+    if prec == 32:
+        x = x.astype(np.complex64).astype(np.complex128)
+    dev = torch.from_numpy(x.view(np.float64).copy()).cuda()
+    out = torch.empty_like(dev)
+    gpu.ttsh_fft2(dev, out, N, 1, 0, prec)
+    got = out.cpu().numpy().view(np.complex128).reshape(1, N, N)
+    ref = O.dft2(x)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("Ns,prec,preset,steps,tol", [((4096,), 64, "paper", 2, 1e-12),
+                                                      ((4096,), 32, "workload", 2, 2e-6),
+                                                      ((8192, 512), 32, "paper", 1, 2e-6)])
+def test_production_sizes_step_matches_oracle(gpu, Ns, prec, preset, steps, tol):
+    """Time steps at the paper's production sizes (its grid of 8192^2 at
+    dx = 0.005 and the same box at 4096^2) against the FP64 oracle; the
+    context with 8192^2 also holds a 512^2 instance, so every pass launches
+    once per size class, the large one with 1024-thread workgroups."""
+    import dataclasses
+    say("production sizes", Ns, prec, preset, steps)
+    base = O.paper_params() if preset == "paper" else O.workload_params()
+    Ls = [N * (0.005 if preset == "paper" else 0.5) for N in Ns]
+    s = gpu.Solver(list(Ns), Ls, base, prec)
+    refs = []
+    for i, (N, L) in enumerate(zip(Ns, Ls)):
+        R, xi = (L / 4, 4 * L / N) if preset == "paper" else (L / 4, 0.5)
+        K = O.mask_tanh(N, L, [(0.0, 0.0)], [R], xi)
+        v0 = W.uniform_field(30 + i, N, 0.3, prec)
+        s.mask_tanh(i, [(0.0, 0.0)], [R], xi)
+        s.set_field(i, v0)
+        vh = O.project_field(v0, L)
+        for _ in range(steps):
+            vh = O.velocity_step(vh, K, base, L)
+        refs.append(vh)
+        del K, v0
+    s.step(steps)
+    s.sync()
+    for i in range(len(Ns)):
+        err = O.rel_l2(s.field(i), O.field(refs[i]))
+        print("production size", Ns[i], "rel_l2", err, flush=True)
+        assert err < tol, (Ns[i], err)
+    s.close()
+
+
 # ---- state set / get ----------------------------------------------------------------
 @pytest.mark.parametrize("N", [64, 256])
 def test_set_field_projects_like_oracle(gpu, N):
