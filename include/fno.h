@@ -56,7 +56,40 @@ void fno_destroy(fno_ctx* ctx);
  * Returns TTSH_EINVAL for an unknown option. */
 #define FNO_OPT_STAGED_GEMM 1
 #define FNO_OPT_SPECIALIZED 2
+/* FNO_OPT_CAPTURE: keep each stage's BF16 intermediates per layer (for
+ * stage-level tests; buffers of a few times the activations, allocated on
+ * the first use), read with fno_capture.  Off by default. */
+#define FNO_OPT_CAPTURE 3
 int fno_set_option(fno_ctx* ctx, int option, int value);
+
+/* Items of fno_capture, BF16 values read back as float32 (n elements from the
+ * start; layouts for B samples, C channels, m modes, P = B H W points):
+ *   FNO_CAP_XB   the input as BF16 [P][cin]                    (layer ignored)
+ *   FNO_CAP_H    h_l, l = 0..layers [P][C] (l = layers: the projection input)
+ *   FNO_CAP_Z    pre-activation z_l of a non-last layer [P][C] (training forward)
+ *   FNO_CAP_T1   k_x transform of h_l: [B][2m][H][C], rows k_x (real) then m + k_x
+ *                (imaginary), unnormalised, e^{-i k_x x}
+ *   FNO_CAP_G    retained modes F_l: [m][4m][B][C] (k_x; rows q < 2m real parts of
+ *                k_y = q or q - 2m, rows 2m + q imaginary parts)
+ *   FNO_CAP_O    mixed modes R_l F_l: [m][2m][B][2C] (k_x; k_y rows; real C then
+ *                imaginary C)
+ *   FNO_CAP_T2   k_y synthesis of O: [B][H][2m][C] (k_x real, m + k_x imaginary)
+ *   backward, per layer l, from the last fno_backward:
+ *   FNO_CAP_DZ   dl/dz_l [P][C];  FNO_CAP_BT1 its k_x transform with the
+ *                inverse weights (1 or 2)/(HW), as T1;  FNO_CAP_GG its retained
+ *                modes, as G;  FNO_CAP_GF their adjoint mix R_l^H, as O;
+ *                FNO_CAP_BT2 the k_y synthesis of GF, as T2;  FNO_CAP_DH the
+ *                gradient the layer hands down: dl/dh_l (l = 0), or
+ *                dl/dh_l times GELU'(z_{l-1}) (= dl/dz_{l-1}, l > 0)
+ *   FNO_CAP_DHL  dl/dh_layers from the projection [P][C]
+ *   FNO_CAP_DY   dl/dy as the backward pass takes it, BF16 [P][cout] (no capture
+ *                needed; the last fno_loss)                                    */
+enum {
+  FNO_CAP_XB = 0, FNO_CAP_H = 1, FNO_CAP_Z = 2, FNO_CAP_T1 = 3, FNO_CAP_G = 4, FNO_CAP_O = 5, FNO_CAP_T2 = 6,
+  FNO_CAP_DZ = 10, FNO_CAP_BT1 = 11, FNO_CAP_GG = 12, FNO_CAP_GF = 13, FNO_CAP_BT2 = 14, FNO_CAP_DH = 15,
+  FNO_CAP_DHL = 16, FNO_CAP_DY = 17
+};
+int fno_capture(fno_ctx* ctx, int what, int layer, float* out, int64_t n);
 
 /* Number of float32 parameters (the length of the vectors below). */
 int64_t fno_num_params(fno_ctx* ctx);

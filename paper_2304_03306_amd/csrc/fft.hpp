@@ -21,7 +21,8 @@
 // and lets more waves stay resident on a CU.
 //
 // All threads of the workgroup must call these functions (they contain
-// __syncthreads); threads that carry no useful data just transform zeros.
+// workgroup barriers, or wavefront-scope ordering for one-wavefront
+// workgroups); threads that carry no useful data just transform zeros.
 #pragma once
 
 #include "common.hpp"
@@ -122,10 +123,27 @@ struct Dft<8, DIR, T> {
   }
 };
 
+// Orders the LDS accesses between the stages of a transform group.  With
+// WAVE, the group's workgroup is a single wavefront: the LDS unit executes one
+// wavefront's instructions in issue order, so a store is seen by every later
+// load of the same wavefront without a barrier or a wait for the store to
+// complete; a wavefront-scope fence (which emits no instruction) keeps the
+// compiler from moving the loads above the stores.  Otherwise a workgroup
+// barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // ---- one Stockham stage, recursing into the next ---------------------------
 // v[f][e] holds element t + e*TT of transform f.  `lds` points at this group's
 // fft_slots(NF) regions of Padded<N> entries each.  `tw[j]` = e^{-2 pi i j / N}.
-template <int N, int DIR, int NF, int P, class T, int SCH>
+template <int N, int DIR, int NF, int P, class T, int SCH, bool WAVE>
 struct FftStage {
   static constexpr int E = kFftE;
   static constexpr int TT = N / E;
@@ -180,32 +198,33 @@ struct FftStage {
     } else if constexpr (NS == NF) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) butterflies(v, f, lds + f * NP, t, tw);
-      __syncthreads();
+      lds_sync<WAVE>();
 #pragma unroll
       for (int f = 0; f < NF; ++f) gather(v, f, lds + f * NP, t);
-      __syncthreads();
-      FftStage<N, DIR, NF, P * R, T, SCH>::run(v, lds, t, tw);
+      lds_sync<WAVE>();
+      FftStage<N, DIR, NF, P * R, T, SCH, WAVE>::run(v, lds, t, tw);
     } else {
       // transform f uses slot f % NS; the barrier after writing f also orders
       // every read of f - NS (issued before it) ahead of the reuse of its slot
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         butterflies(v, f, lds + (f % NS) * NP, t, tw);
-        __syncthreads();
+        lds_sync<WAVE>();
         gather(v, f, lds + (f % NS) * NP, t);
       }
-      __syncthreads();
-      FftStage<N, DIR, NF, P * R, T, SCH>::run(v, lds, t, tw);
+      lds_sync<WAVE>();
+      FftStage<N, DIR, NF, P * R, T, SCH, WAVE>::run(v, lds, t, tw);
     }
   }
 };
 
 // Unnormalised transform(s): out[m] = sum_n in[n] e^{DIR 2 pi i m n / N}.
-template <int N, int DIR, int NF, int SCH = kSchedDefault, class T>
+// WAVE: the calling workgroup is one wavefront (see lds_sync).
+template <int N, int DIR, int NF, int SCH = kSchedDefault, bool WAVE = false, class T>
 __device__ __forceinline__ void fft(C2<T> (&v)[NF][kFftE], C2<T>* lds, int t,
                                     const C2<T>* __restrict__ tw) {
   static_assert(N >= 64 && (N & (N - 1)) == 0, "N must be a power of two >= 64");
-  FftStage<N, DIR, NF, 1, T, SCH>::run(v, lds, t, tw);
+  FftStage<N, DIR, NF, 1, T, SCH, WAVE>::run(v, lds, t, tw);
 }
 
 }  // namespace ttsh

@@ -1276,6 +1276,12 @@ struct fno_ctx {
   int staged_gemm = 1;        // GEMMs whose operands allow it stage them through LDS
   int specialized = 1;        // kernels for C = 32, 2m = 32 and W = 128 (layer tail) / H = 128 (k_y steps)
   bool proj_train_fused = false;  // the last training forward left no hidden layer (fused backward)
+  // stage capture (FNO_OPT_CAPTURE, for stage-level tests): per layer, the
+  // intermediates that later layers overwrite, copied as they are produced
+  bool capture = false;
+  bf16 *capT1[16] = {}, *capO[16] = {}, *capT2[16] = {};                       // forward
+  bf16 *capDZ[16] = {}, *capBT1[16] = {}, *capGG[16] = {}, *capGF[16] = {}, *capBT2[16] = {}, *capDH[16] = {};
+  bf16* capDHL = nullptr;                                                      // dl/dh_L from the projection
   std::vector<void*> allocs;
   std::vector<std::pair<const char*, size_t>> extents;  // (start, bytes) of every buffer
 };
@@ -1625,6 +1631,18 @@ int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, const bf16* WbT, boo
 
 long long pts(const fno_ctx* c, int B) { return (long long)B * c->H * c->W; }
 
+// element counts of the captured buffers at the maximum batch
+long long cap_len_T(const fno_ctx* c) { return (long long)c->maxB * 2 * c->m * c->H * c->C; }  // T1, T2
+long long cap_len_O(const fno_ctx* c) { return (long long)c->m * 2 * c->m * c->maxB * 2 * c->C; }  // O, gF, gG
+long long cap_len_P(const fno_ctx* c) { return pts(c, c->maxB) * c->C; }  // dz, dh
+
+// copy n elements of src into a capture slot when capturing (stream-ordered)
+int cap_copy(fno_ctx* c, bf16* dst, const bf16* src, long long n) {
+  if (!c->capture || !dst) return TTSH_OK;
+  FCHK(hipMemcpyAsync(dst, src, (size_t)n * sizeof(bf16), hipMemcpyDeviceToDevice, c->s));
+  return TTSH_OK;
+}
+
 // points per partial product of a weight gradient: short enough that the
 // partial products (one wavefront per 32 x 32 tile each) fill the chip
 constexpr long long kWgradChunk = 1024;
@@ -1810,7 +1828,58 @@ int fno_set_option(fno_ctx* c, int option, int value) {
   if (!c) return ffail(TTSH_EINVAL, "null context");
   if (option == FNO_OPT_STAGED_GEMM) c->staged_gemm = value != 0;
   else if (option == FNO_OPT_SPECIALIZED) c->specialized = value != 0;
-  else return ffail(TTSH_EINVAL, "unknown option");
+  else if (option == FNO_OPT_CAPTURE) {
+    if (value && !c->capT1[0]) {  // buffers are allocated once, on first use
+      int rc;
+      const long long nT = cap_len_T(c), nO = cap_len_O(c), nP = cap_len_P(c);
+      for (int l = 0; l < c->L; ++l)
+        if ((rc = alloc(c, &c->capT1[l], nT)) || (rc = alloc(c, &c->capO[l], nO)) || (rc = alloc(c, &c->capT2[l], nT)) ||
+            (rc = alloc(c, &c->capDZ[l], nP)) || (rc = alloc(c, &c->capBT1[l], nT)) ||
+            (rc = alloc(c, &c->capGG[l], nO)) || (rc = alloc(c, &c->capGF[l], nO)) ||
+            (rc = alloc(c, &c->capBT2[l], nT)) || (rc = alloc(c, &c->capDH[l], nP)))
+          return rc;
+      if ((rc = alloc(c, &c->capDHL, nP))) return rc;
+    }
+    c->capture = value != 0;
+  } else {
+    return ffail(TTSH_EINVAL, "unknown option");
+  }
+  return TTSH_OK;
+}
+
+int fno_capture(fno_ctx* c, int what, int layer, float* out, int64_t n) {
+  if (!c || !out) return ffail(TTSH_EINVAL, "null argument");
+  if (!c->capT1[0]) return ffail(TTSH_EINVAL, "capture was never enabled");
+  const bool per_layer = what != FNO_CAP_XB && what != FNO_CAP_DHL && what != FNO_CAP_H && what != FNO_CAP_DY;
+  if (what == FNO_CAP_H ? (layer < 0 || layer > c->L) : (per_layer && (layer < 0 || layer >= c->L)))
+    return ffail(TTSH_EINVAL, "layer out of range");
+  const bf16* src = nullptr;
+  long long len = 0;
+  const long long nT = cap_len_T(c), nO = cap_len_O(c), nP = cap_len_P(c);
+  switch (what) {
+    case FNO_CAP_XB: src = c->xb; len = pts(c, c->maxB) * c->cin; break;
+    case FNO_CAP_H: src = c->h[layer]; len = nP; break;
+    case FNO_CAP_Z: src = c->z[layer]; len = layer < c->L - 1 ? nP : 0; break;
+    case FNO_CAP_T1: src = c->capT1[layer]; len = nT; break;
+    case FNO_CAP_G: src = c->G[layer]; len = (long long)c->m * 4 * c->m * c->maxB * c->C; break;
+    case FNO_CAP_O: src = c->capO[layer]; len = nO; break;
+    case FNO_CAP_T2: src = c->capT2[layer]; len = nT; break;
+    case FNO_CAP_DZ: src = c->capDZ[layer]; len = nP; break;
+    case FNO_CAP_BT1: src = c->capBT1[layer]; len = nT; break;
+    case FNO_CAP_GG: src = c->capGG[layer]; len = nO; break;
+    case FNO_CAP_GF: src = c->capGF[layer]; len = nO; break;
+    case FNO_CAP_BT2: src = c->capBT2[layer]; len = nT; break;
+    case FNO_CAP_DH: src = c->capDH[layer]; len = nP; break;
+    case FNO_CAP_DHL: src = c->capDHL; len = nP; break;
+    case FNO_CAP_DY: src = c->dy; len = pts(c, c->maxB) * c->cout; break;
+    default: return ffail(TTSH_EINVAL, "unknown capture item");
+  }
+  if (!src || len == 0) return ffail(TTSH_EINVAL, "nothing captured for this item");
+  if (n < 1 || n > len) return ffail(TTSH_EINVAL, "element count out of range");
+  std::vector<bf16> h((size_t)n);
+  FCHK(hipStreamSynchronize(c->s));
+  FCHK(hipMemcpy(h.data(), src, (size_t)n * sizeof(bf16), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) out[i] = bf2f(h[(size_t)i]);
   return TTSH_OK;
 }
 
@@ -1850,9 +1919,12 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     // with the fused tail (and lift), the previous step already left T1 (the k_x step of h_l)
     if (l == 0 ? !fuse_lift : !fuse)
       if ((rc = spectral_analysis_x(c, c->h[l], c->Dx, B))) return rc;
+    if ((rc = cap_copy(c, c->capT1[l], c->T1, (long long)B * 2 * m * H * C))) return rc;
     if ((rc = spectral_analysis_y(c, c->G[l], B))) return rc;
     if ((rc = spectral_mix(c, c->G[l], c->Wb[l], c->WbT[l], false, c->O, B))) return rc;
+    if ((rc = cap_copy(c, c->capO[l], c->O, (long long)m * 2 * m * B * 2 * C))) return rc;
     if ((rc = spectral_synth_y(c, c->O, B))) return rc;
+    if ((rc = cap_copy(c, c->capT2[l], c->T2, (long long)B * H * 2 * m * C))) return rc;
     if (fuse) {
       if ((rc = layer_tail(c, l, B, train != 0))) return rc;
       continue;
@@ -1977,6 +2049,7 @@ int fno_backward(fno_ctx* c, int B) {
   d.C = c->dh0; d.c_bf16 = 1; d.rC = C; d.cC = 1;
   if ((rc = cgemm(c, d))) return rc;
   }
+  if ((rc = cap_copy(c, c->capDHL, c->dh0, P * C))) return rc;
   // with the specialized kernels each layer's backward tail leaves the next
   // gradient already multiplied by GELU' (in dh) and its k_x transform (in T1)
   const bool fuse_b = tail_fusable(c);
@@ -1989,13 +2062,18 @@ int fno_backward(fno_ctx* c, int B) {
       hipLaunchKernelGGL(k_gelu_back, dim3(nb((P * C + 7) / 8)), dim3(256), 0, c->s, dh, c->z[l], c->dz, P * C);
       FCHK(hipGetLastError());
       dz = c->dz;
+      // the gradient layer l + 1 hands down, in the fused tail's form dl/dz_l
+      if ((rc = cap_copy(c, c->capDH[l + 1], dz, P * C))) return rc;
     }
+    if ((rc = cap_copy(c, c->capDZ[l], dz, P * C))) return rc;
     if ((rc = wgrad(c, C, C, P, c->h[l], 1, C, dz, C, 1, c->grad + c->oW[l]))) return rc;
     if ((rc = colsum(c, dz, P, C, c->grad + c->ob[l]))) return rc;
     // g_G = (w/(HW)) trunc rfft2(dz)
     if (!fuse_b || l == c->L - 1)
       if ((rc = spectral_analysis_x(c, dz, c->DxG, B))) return rc;
+    if ((rc = cap_copy(c, c->capBT1[l], c->T1, (long long)B * 2 * m * H * C))) return rc;
     if ((rc = spectral_analysis_y(c, c->gG, B))) return rc;
+    if ((rc = cap_copy(c, c->capGG[l], c->gG, (long long)m * 4 * m * B * C))) return rc;
     // dR per mode (kx, q): dR_r = F_r^T gG_r + F_i^T gG_i ; dR_i = F_r^T gG_i - F_i^T gG_r
     const long long nR = 2LL * m * m * C * C;
     for (int part = 0; part < 2; ++part) {
@@ -2019,9 +2097,12 @@ int fno_backward(fno_ctx* c, int B) {
     }
     // g_F = g_G Wb^T  (into gF, mode layout [m][2m][B][2C])
     if ((rc = spectral_mix(c, c->gG, c->Wb[l], c->WbT[l], true, c->gF, B))) return rc;
+    if ((rc = cap_copy(c, c->capGF[l], c->gF, (long long)m * 2 * m * B * 2 * C))) return rc;
     if ((rc = spectral_synth_y(c, c->gF, B))) return rc;
+    if ((rc = cap_copy(c, c->capBT2[l], c->T2, (long long)B * H * 2 * m * C))) return rc;
     if (fuse_b) {
       if ((rc = layer_tail_back(c, l, B, dz, dh_next))) return rc;
+      if ((rc = cap_copy(c, c->capDH[l], dh_next, P * C))) return rc;
       std::swap(dh, dh_next);
       continue;
     }
@@ -2036,6 +2117,7 @@ int fno_backward(fno_ctx* c, int B) {
     e.C = dh_next; e.c_bf16 = 1;
     e.sC1 = (long long)H * W * C; e.sC2 = (long long)W * C; e.rC = C; e.cC = 1;
     if ((rc = cgemm(c, e))) return rc;
+    if (l == 0 && (rc = cap_copy(c, c->capDH[0], dh_next, P * C))) return rc;
     std::swap(dh, dh_next);
   }
   // lift

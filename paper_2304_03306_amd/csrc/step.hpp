@@ -275,7 +275,7 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     z[1][e] = pack_pq(a.b, b.b);  // v_x + i v_y, row y0+1
     z[2][e] = pack_pq(w.a, w.b);  // omega(y0) + i omega(y0+1)
   }
-  fft<N, +1, 3, SCH>(z, L, t, tw);
+  fft<N, +1, 3, SCH, NT == 64>(z, L, t, tw);
 
   // mask rows, loaded after the inverse transforms: issued before them they
   // would hold 16 registers through the transforms (the row pass ran ~5 %
@@ -306,7 +306,7 @@ __device__ __forceinline__ void row_body(const C2<T>* __restrict__ X, C2<T>* __r
     if constexpr (GW)
       wv[NFY - 1][e] = mk(-c.gamma_w * kr[0][e] * z[2][e].x, -c.gamma_w * kr[1][e] * z[2][e].y);
   }
-  fft<N, -1, NFY, SCH>(wv, L, t, tw);
+  fft<N, -1, NFY, SCH, NT == 64>(wv, L, t, tw);
 
   // Outputs.  The forcing rows are stored unsplit, straight from registers:
   // Y[0][m][y] = W_y(m) and Y[1][m][y] = W_y(N - m) (m = 0..M) with
@@ -511,7 +511,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
       f[1][e] = mk(h * (w0.y + w1.y), -h * (w0.x - w1.x));  // row transform of N_y
       if constexpr (GW) f[2][e] = valid ? Yp[mix_idx<N>(2, mx, t + e * TT)] : mk<T>(0, 0);
     }
-    fft<N, -1, NFY, SCH>(f, L, t, tw);
+    fft<N, -1, NFY, SCH, NT == 64>(f, L, t, tw);
     if constexpr (MODE == 2 || MODE == 3) {  // keep (stage 1) or subtract (stage 2) the stage-1 forcing
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -676,7 +676,7 @@ __device__ __forceinline__ void col_body(const C2<T>* __restrict__ Y, C2<T>* __r
     z[1][e] = cvt<T>(cscale(ny[e], sN));
     z[2][e] = cvt<T>(mk(-cw.y * dk * sN, cw.x * dk * sN));
   }
-  fft<N, +1, 3, SCH>(z, L, t, tw);
+  fft<N, +1, 3, SCH, NT == 64>(z, L, t, tw);
   if (valid) {
     C2<T>* Xp = X + inst * 3 * G::MP4 * N;
 #pragma unroll

@@ -13,6 +13,9 @@ _sig_done = False
 
 FNO_OPT_STAGED_GEMM = 1
 FNO_OPT_SPECIALIZED = 2
+FNO_OPT_CAPTURE = 3
+(FNO_CAP_XB, FNO_CAP_H, FNO_CAP_Z, FNO_CAP_T1, FNO_CAP_G, FNO_CAP_O, FNO_CAP_T2) = range(7)
+(FNO_CAP_DZ, FNO_CAP_BT1, FNO_CAP_GG, FNO_CAP_GF, FNO_CAP_BT2, FNO_CAP_DH, FNO_CAP_DHL, FNO_CAP_DY) = range(10, 18)
 
 
 def lib():
@@ -27,6 +30,7 @@ def lib():
             "fno_get_params": ([vp, vp], ctypes.c_int),
             "fno_get_grads": ([vp, vp], ctypes.c_int),
             "fno_set_option": ([vp, i32, i32], ctypes.c_int),
+            "fno_capture": ([vp, i32, i32, vp, i64], ctypes.c_int),
             "fno_forward": ([vp, vp, vp, i32, i32], ctypes.c_int),
             "fno_forward_ex": ([vp, vp, vp, i64, i32, i32, i32], ctypes.c_int),
             "fno_gather": ([vp, vp, i64, vp, i64, i32, i64, vp, i32], ctypes.c_int),
@@ -108,6 +112,12 @@ class FNO:
         a = np.empty(self.n, dtype=np.float32)
         _check(lib().fno_get_grads(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
         return a
+
+    def capture(self, what: int, layer: int, n: int) -> np.ndarray:
+        """The first n captured BF16 values of an item (FNO_CAP_*), float64."""
+        out = np.empty(int(n), dtype=np.float32)
+        _check(lib().fno_capture(self.ctx, int(what), int(layer), out.ctypes.data_as(ctypes.c_void_p), int(n)))
+        return out.astype(np.float64)
 
     def set_option(self, option: int, value: int):
         _check(lib().fno_set_option(self.ctx, int(option), int(value)))
