@@ -33,6 +33,7 @@ def cases():
         "sweep_R24_256": sweep[14],    # radius 8 + 72*7/31 = 24.26, 256^2
         "sweep_R80_512": sweep[62],    # radius 80, 512^2
         "dumbbell_d40_1024": db[0],
+        "dumbbell_d80_1024": db[15],   # centre distance 80, the last of the 16
     }
 
 

@@ -4,7 +4,9 @@ hand-written backward pass, the Adam step, and a short training run.
 
 Tolerances: BF16 has an 8-bit significand (relative rounding 2^-9); the
 network chains ~20 BF16-rounded intermediates, so outputs and gradients are
-compared by relative L2 at the 1e-2 to 5e-2 level, FP32 Adam at 1e-6."""
+compared by relative L2, with bounds about twice the measured errors (5e-3
+to 8e-3), FP32 Adam at 1e-6.  Each stage on its own is checked to BF16
+rounding in test_gpu_fno_stages.py."""
 import numpy as np
 import pytest
 
@@ -102,7 +104,7 @@ def test_forward_matches_oracle(gpu):
     ref = F.forward(p, x.astype(np.float64), SMALL)
     err = rel(y.cpu().numpy(), ref)
     print("forward rel", err)
-    assert err < 3e-2
+    assert err < 1.2e-2  # measured 5.4e-3
 
 
 def test_backward_matches_oracle(gpu):
@@ -127,7 +129,7 @@ def test_backward_matches_oracle(gpu):
     for k in go:
         e = rel(g[k], go[k])
         print(k, "grad rel", e)
-        assert e < 6e-2, (k, e)
+        assert e < 1.2e-2, (k, e)  # measured <= 5.0e-3
 
 
 def test_adam_step_matches_oracle(gpu):
@@ -239,7 +241,8 @@ def test_fused_inference_projection_matches_training_path(gpu):
     a, b = y1.cpu().numpy().astype(np.float64), y2.cpu().numpy().astype(np.float64)
     assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
     ref = F.forward(p, x.astype(np.float64), cfg)
-    assert rel(a, ref) < 3e-2
+    print("fused projection rel", rel(a, ref), flush=True)
+    assert rel(a, ref) < 1.5e-2
     net.forward_ex(xd, xd, cfg.cin, True, B)
     got = xd.cpu().numpy().astype(np.float64)
     want = x[..., :2].astype(np.float64) + a
@@ -286,13 +289,13 @@ def test_specialized_kernels_match_oracle_and_general_path(gpu):
     y1, yt1, l1, g1 = out[1]
     y0, yt0, l0, g0 = out[0]
     print("fused/oracle", rel(y1, yo), "fused/unfused", rel(y1, y0), flush=True)
-    assert rel(y1, yo) < 3e-2 and rel(yt1, yo) < 3e-2
-    assert rel(y1, y0) < 1e-2 and rel(yt1, yt0) < 1e-2
+    assert rel(y1, yo) < 1.6e-2 and rel(yt1, yo) < 1.6e-2  # measured 7.8e-3
+    assert rel(y1, y0) < 2e-3 and rel(yt1, yt0) < 2e-3  # measured 5.6e-4
     assert abs(l1 - lo) < 2e-2 * lo
     for k in go:
         e, d = rel(g1[k], go[k]), rel(g1[k], g0[k])
         print(k, "grad rel", e, "vs unfused", d, flush=True)
-        assert e < 6e-2 and d < 3e-2, (k, e, d)
+        assert e < 1.6e-2 and d < 3e-3, (k, e, d)  # measured <= 7.8e-3 and 1.0e-3
 
 
 def test_increment_loss_and_its_gradient(gpu):
@@ -327,7 +330,8 @@ def test_increment_loss_and_its_gradient(gpu):
     go = F.backward(p, cache, gy, SMALL)
     for k in go:
         e = rel(g[k], go[k])
-        assert e < 6e-2, (k, e)
+        print(k, "grad rel (change-normalised loss)", e, flush=True)
+        assert e < 1.2e-2, (k, e)
 
 
 def test_perturb_is_bounded_reproducible_and_channel_limited(gpu):

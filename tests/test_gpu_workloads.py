@@ -70,7 +70,11 @@ def test_dumbbells_step1000(gpu):
     s.step(1000)
     s.sync()
     err = spectral_rel_l2(s.state(0), ref)
-    print("rel_l2", err)
+    print("d = 40 rel_l2", err)
+    assert err <= 1e-5
+    # the other end of the distance range: centre distance 80, instance 15
+    err = spectral_rel_l2(s.state(15), ref_state("dumbbell_d80_1024"))
+    print("d = 80 rel_l2", err)
     assert err <= 1e-5
     norms = [s.norms(q) for q in range(16)]
     # divergence of the stored FP32 spectrum: rounding of a projected FP64 update
