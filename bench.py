@@ -341,9 +341,11 @@ def main():
     else:
         cfg, tuned_us, hit = tuning.autotune(s, 20, cache, retune=args.retune)
         log(f"[bench] {'tuning from the cache' if hit else 'autotuned'}: (row, column) workgroup sizes "
-            f"{cfg[:2]}, one launch per grid size {cfg[2:4]}, transform schedules {cfg[4:6]}"
+            f"{cfg[:2]}, one launch per grid size {cfg[2:4]}, transform schedules {cfg[4:6]}, "
+            f"concurrent instance groups {cfg[6] if len(cfg) > 6 else 1}"
             + (f" ({tuned_us:.1f} us/step when tuned)" if tuned_us else ""))
-    block, split, sched = tuple(cfg[0:2]), tuple(cfg[2:4]), tuple(cfg[4:6])
+        cfg = s.get_tuning()
+    block, split, sched, groups = tuple(cfg[0:2]), tuple(cfg[2:4]), tuple(cfg[4:6]), int(cfg[6])
 
     parity = {}
     if not args.no_parity and args.workload == "sweep":
@@ -372,7 +374,11 @@ def main():
     except T.TTSHError:
         finite = False
 
-    # per-kernel durations from HIP events on the library's stream
+    # per-kernel durations from HIP events on the library's stream: every
+    # instance in one launch, launches back to back and alone on the GPU (with
+    # two instance groups the step's launches cover half the instances each
+    # and overlap, so their own durations say nothing about one kernel; the
+    # whole step's rate is in step_hbm)
     row_us, col_us = T.ttsh_pass_times(s.ctx, args.prof_steps)
     counts = {}
     for i in wl.instances:
@@ -444,6 +450,7 @@ def main():
                    "grids": " + ".join(f"{counts[N]}x{N}^2" for N in sizes),
                    "points_per_step": wl.points, "dt": params.dt, "block": block,
                    "launch_per_grid_size": split, "transform_schedule": sched,
+                   "concurrent_groups": groups,
                    "precision": ("FP32 transforms and state" if args.precision == 32 else
                                  "FP32 transforms, FP64 state") + ", FP64 k-space update",
                    "parallelism": "single GPU, instances batched per grid size"},
@@ -457,7 +464,9 @@ def main():
         "step_hbm": {"algorithmic_bytes": step_bytes, "kernel_us": step_us,
                      "GBps": step_bytes / (step_us * 1e-6) / 1e9,
                      "frac": step_bytes / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                     "wall_GBps": step_bytes * args.steps / dt / 1e9},
+                     "wall_GBps": step_bytes * args.steps / dt / 1e9,
+                     "wall_frac": step_bytes * args.steps / dt / 1e9 / HBM_PEAK_GBS,
+                     "concurrent_groups": groups},
         "parity": {"rel_l2_step1000_vs_fp64_oracle": parity, "all_finite": finite},
         "plain": plain,
         "cpu_baseline": cpu,

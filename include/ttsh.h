@@ -111,11 +111,18 @@ enum {
   TTSH_OPT_SPLIT = 8,       /* bit 0: row pass, bit 1: column pass launched once per grid
                                size (kernels compiled for that size) instead of once for
                                all sizes; default 0 */
-  TTSH_OPT_GUARD_EVERY = 16 /* with the guard on: steps between the NaN/Inf checks that
+  TTSH_OPT_GUARD_EVERY = 16,/* with the guard on: steps between the NaN/Inf checks that
                                ttsh_step queues (part of the captured graphs; one launch
                                per grid size over all its instances, flags kept on the
                                device until ttsh_sync reports them); 0 = check only in
                                ttsh_sync; default 50 */
+  TTSH_OPT_GROUPS = 17      /* 1 or 2: instance groups that ttsh_step advances
+                               concurrently.  With 2, every grid size's instances are
+                               split into two halves (in instance order), each half
+                               stepping with its own launches, graphs and stream, so
+                               that one half's row pass runs beside the other half's
+                               column pass; results are the same bit for bit.
+                               Default 1; ttsh_tune chooses. */
 };
 
 /* Create a context holding n_inst independent instances advanced together.
@@ -279,7 +286,11 @@ int ttsh_get_state(ttsh_ctx* ctx, int inst, double* vhat, int where);
  * context's stream.  With TTSH_OPT_GRAPH_STEPS = G > 0, whole chunks of G
  * steps replay one captured HIP graph and a remaining tail of r < G steps
  * replays a graph of r steps (captured on first use and kept while calls end
- * with the same tail); with G = 0 every kernel is launched directly.        */
+ * with the same tail); with G = 0 every kernel is launched directly.  With
+ * TTSH_OPT_GROUPS = 2 each instance group replays graphs of its own on a
+ * stream the library owns; those streams start after the work queued on the
+ * context's stream before the call, and the context's stream waits for them
+ * at the end of the call, so the ordering is that of a single stream.      */
 int ttsh_step(ttsh_ctx* ctx, int64_t nsteps);
 
 /* Continuation between stages (hysteresis protocol of the circle section:
@@ -358,20 +369,24 @@ int ttsh_pass_times(ttsh_ctx* ctx, int64_t nsteps, double* out);
  *   grids that are not a power of 8, whether the leftover radix (2 or 4)
  *   runs first or last (schedule code 2 * log2(padding period) + first:
  *   6, 7, 8 (the default: padding 16, radix last), 9, 10, 11).
- * The state the context had before the call is restored.  cfg_out (6 ints,
+ * Then whole steps (replayed as ttsh_step runs them, nsteps per candidate,
+ * two rounds) decide between the column-pass sizes (each with its fastest
+ * split and schedule) and between one and two concurrent instance groups
+ * (TTSH_OPT_GROUPS), the row pass keeping its choice.
+ * The state the context had before the call is restored.  cfg_out (7 ints,
  * may be NULL): row-pass size, column-pass size, row split (0/1), column
- * split (0/1), row schedule, column schedule (the layout of
- * ttsh_set_tuning); us_out (may be NULL): microseconds per step of that
- * choice.  A later TTSH_OPT_BLOCK / TTSH_OPT_SPLIT overrides it.
- * Synchronous.                                                              */
+ * split (0/1), row schedule, column schedule, groups (the layout of
+ * ttsh_set_tuning); us_out (may be NULL): microseconds per whole step of that
+ * choice.  A later TTSH_OPT_BLOCK / TTSH_OPT_SPLIT / TTSH_OPT_GROUPS
+ * overrides it.  Synchronous.                                               */
 int ttsh_tune(ttsh_ctx* ctx, int64_t nsteps, int* cfg_out, double* us_out);
 
-/* The launch configuration in use (6 ints, as cfg_out of ttsh_tune), and
+/* The launch configuration in use (7 ints, as cfg_out of ttsh_tune), and
  * setting one found earlier (for instance from a cache of tuner results)
  * without timing anything.  set: TTSH_EINVAL if a size does not fit the
- * context, a split flag is not 0/1, or a schedule is unknown or used where
+ * context, a split flag is not 0/1, a schedule is unknown or used where
  * only the default exists (FP64 or FP32-state-64 arithmetic, one launch per
- * grid size, grids of 2048).                                               */
+ * grid size, grids of 2048), or groups is not 1 or 2.                      */
 int ttsh_get_tuning(ttsh_ctx* ctx, int* cfg);
 int ttsh_set_tuning(ttsh_ctx* ctx, const int* cfg);
 

@@ -29,6 +29,7 @@ using namespace ttsh;
 // device's address through hipGetSymbolAddress (see resolve_scratch), and
 // only that address is passed to kernels.
 constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxGroups = 2;  // concurrent instance groups of ttsh_step
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace ttsh {
@@ -234,19 +235,37 @@ struct ttsh_ctx {
   hipGraph_t graph_rem = nullptr;        // rem_steps (< graph_steps) steps: the tail of the last call
   hipGraphExec_t gexec_rem = nullptr;
   int rem_steps = 0;
+  // Concurrent instance groups (TTSH_OPT_GROUPS): with groups = 2 every size
+  // class is split into two halves, and each half steps on a stream of its
+  // own with graphs of its own, so that the row pass of one half runs on the
+  // GPU beside the column pass of the other (the two passes are bound by
+  // different units: the transforms' arithmetic and the memory traffic).
+  int groups = 1;
+  hipStream_t gstream[kMaxGroups] = {};
+  hipEvent_t gfork = nullptr;
+  hipEvent_t gjoin[kMaxGroups] = {};
+  hipGraph_t ggraph[kMaxGroups] = {};
+  hipGraphExec_t ggexec[kMaxGroups] = {};
+  hipGraph_t ggraph_rem[kMaxGroups] = {};
+  hipGraphExec_t ggexec_rem[kMaxGroups] = {};
 };
 
 namespace {
 
+void drop_one(hipGraph_t& g, hipGraphExec_t& x) {
+  if (x) (void)hipGraphExecDestroy(x);
+  if (g) (void)hipGraphDestroy(g);
+  x = nullptr;
+  g = nullptr;
+}
+
 void drop_graph(ttsh_ctx* c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  if (c->gexec_rem) hipGraphExecDestroy(c->gexec_rem);
-  if (c->graph_rem) hipGraphDestroy(c->graph_rem);
-  c->gexec = nullptr;
-  c->graph = nullptr;
-  c->gexec_rem = nullptr;
-  c->graph_rem = nullptr;
+  drop_one(c->graph, c->gexec);
+  drop_one(c->graph_rem, c->gexec_rem);
+  for (int g = 0; g < kMaxGroups; ++g) {
+    drop_one(c->ggraph[g], c->ggexec[g]);
+    drop_one(c->ggraph_rem[g], c->ggexec_rem[g]);
+  }
   c->rem_steps = 0;
 }
 
@@ -356,6 +375,35 @@ ClassArgs class_args(ttsh_ctx* c, SizeClass& k, int first, int count, int row) {
   return a;
 }
 
+// instances [first, end) of class k that belong to group g of G (contiguous
+// halves of the class, so that both groups carry every grid size)
+std::pair<int, int> group_range(const SizeClass& k, int g, int G) {
+  const int n = (int)k.ids.size();
+  return {(int)((int64_t)n * g / G), (int)((int64_t)n * (g + 1) / G)};
+}
+
+// Launch arguments of one pass over group g of G (classes without instances
+// in the group are left out; ncls = 0 if the group is empty).
+MultiArgs group_args(ttsh_ctx* c, int row, int g, int G) {
+  MultiArgs m{};
+  m.beta = c->p.beta;
+  m.gamma_v = c->p.gamma_v;
+  m.lambda0 = c->p.lambda0;
+  m.gamma_w = c->p.gamma_w;
+  m.lc = LinCoef{c->p.alpha, c->p.gamma0, c->p.gamma2, c->p.dt, 0.0, c->p.scheme};
+  int blocks = 0;
+  for (auto& k : c->cls) {
+    const auto [first, end] = group_range(k, g, G);
+    if (end <= first) continue;
+    ClassArgs a = class_args(c, k, first, end - first, row);
+    m.start[m.ncls] = blocks;
+    m.c[m.ncls++] = a;
+    blocks += a.tiles * (end - first);
+  }
+  m.start[m.ncls] = blocks;
+  return m;
+}
+
 // Launch arguments of one pass: all instances (inst < 0) or one instance.
 MultiArgs multi_args(ttsh_ctx* c, int row, int inst) {
   MultiArgs m{};
@@ -428,11 +476,13 @@ hipError_t launch_col(ttsh_ctx* c, const MultiArgs& m, int mode, hipStream_t s) 
   return hipSuccess;
 }
 
-hipError_t launch_guard(ttsh_ctx* c, hipStream_t s);
+hipError_t launch_guard(ttsh_ctx* c, hipStream_t s, int g = 0, int G = 1);
 
-int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
+// n steps of group g of G on stream s
+int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s, int g = 0, int G = 1) {
   if (n <= 0) return TTSH_OK;
-  const MultiArgs r = multi_args(c, 1, -1), q = multi_args(c, 0, -1);
+  const MultiArgs r = group_args(c, 1, g, G), q = group_args(c, 0, g, G);
+  if (r.ncls == 0) return TTSH_OK;
   // column-pass modes of one step, each after a row pass that evaluates the
   // forcing of the state the previous one left in X
   static const int one[] = {0}, etd2[] = {2, 3}, etd4[] = {4, 5, 6, 7};
@@ -447,19 +497,19 @@ int enqueue_steps(ttsh_ctx* c, int64_t n, hipStream_t s) {
     }
     // the guard after every guard_every steps of this sequence (inside a
     // captured chunk of G steps: after steps guard_every, 2 guard_every, ...)
-    if (c->guard && c->guard_every > 0 && (i + 1) % c->guard_every == 0) HIPCHK(launch_guard(c, s));
+    if (c->guard && c->guard_every > 0 && (i + 1) % c->guard_every == 0) HIPCHK(launch_guard(c, s, g, G));
   }
   return TTSH_OK;
 }
 
-// capture `steps` steps of every instance into a graph and instantiate it
-int build_graph(ttsh_ctx* c, int steps, hipGraph_t* graph, hipGraphExec_t* gexec) {
+// capture `steps` steps of group g of G into a graph and instantiate it
+int build_graph(ttsh_ctx* c, int steps, hipGraph_t* graph, hipGraphExec_t* gexec, int grp = 0, int G = 1) {
   HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_steps(c, steps, c->cap);
+  int rc = enqueue_steps(c, steps, c->cap, grp, G);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (rc != TTSH_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return fail(TTSH_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -562,19 +612,74 @@ int norms_into(ttsh_ctx* c, int inst, double* dout) {
 // the non-finite guard over every instance: sets the flags of the instances
 // that hold NaN or Inf (ttsh_sync reads and clears them); the flags of a
 // class are stored in the class's instance order
-hipError_t launch_guard(ttsh_ctx* c, hipStream_t s) {
+hipError_t launch_guard(ttsh_ctx* c, hipStream_t s, int g, int G) {
   for (auto& k : c->cls) {
-    const int n = (int)k.ids.size();
+    const auto [first, end] = group_range(k, g, G);
+    if (end <= first) continue;
     const size_t per = (size_t)2 * (k.N / 4 + 1) * (k.N / 2 + 2);
-    const dim3 grid((unsigned)std::min<size_t>((per + 2047) / 2048, 64), (unsigned)n);
+    const dim3 grid((unsigned)std::min<size_t>((per + 2047) / 2048, 64), (unsigned)(end - first));
     if (c->prec == 32)
-      hipLaunchKernelGGL(k_guard<float>, grid, dim3(256), 0, s, (const C2<float>*)k.st, k.N, k.gflags);
+      hipLaunchKernelGGL(k_guard<float>, grid, dim3(256), 0, s, (const C2<float>*)k.st + first * per, k.N,
+                         k.gflags + first);
     else
-      hipLaunchKernelGGL(k_guard<double>, grid, dim3(256), 0, s, (const C2<double>*)k.st, k.N, k.gflags);
+      hipLaunchKernelGGL(k_guard<double>, grid, dim3(256), 0, s, (const C2<double>*)k.st + first * per, k.N,
+                         k.gflags + first);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// streams and events of the concurrent groups, made on first use
+int ensure_groups(ttsh_ctx* c) {
+  if (!c->gfork && hipEventCreateWithFlags(&c->gfork, hipEventDisableTiming) != hipSuccess)
+    return fail(TTSH_EHIP, "event creation failed");
+  for (int g = 0; g < c->groups; ++g) {
+    if (!c->gstream[g] && hipStreamCreateWithFlags(&c->gstream[g], hipStreamNonBlocking) != hipSuccess)
+      return fail(TTSH_EHIP, "stream creation failed");
+    if (!c->gjoin[g] && hipEventCreateWithFlags(&c->gjoin[g], hipEventDisableTiming) != hipSuccess)
+      return fail(TTSH_EHIP, "event creation failed");
+  }
+  return TTSH_OK;
+}
+
+// ttsh_step with the instances in c->groups groups: the group streams wait
+// for the work queued on the context's stream, replay their graphs chunk by
+// chunk (each group its own), and the context's stream waits for all of
+// them, so that the call is ordered like a single-stream one
+int step_groups(ttsh_ctx* c, int64_t nsteps) {
+  if (nsteps == 0) return TTSH_OK;
+  int rc = ensure_groups(c);
+  if (rc) return rc;
+  const int G = c->groups;
+  HIPCHK(hipEventRecord(c->gfork, c->stream));
+  for (int g = 0; g < G; ++g) HIPCHK(hipStreamWaitEvent(c->gstream[g], c->gfork, 0));
+  if (c->graph_steps <= 0) {
+    for (int g = 0; g < G; ++g)
+      if ((rc = enqueue_steps(c, nsteps, c->gstream[g], g, G))) return rc;
+  } else {
+    int64_t left = nsteps;
+    if (left >= c->graph_steps) {
+      for (int g = 0; g < G; ++g)
+        if (!c->ggexec[g] && (rc = build_graph(c, c->graph_steps, &c->ggraph[g], &c->ggexec[g], g, G))) return rc;
+      for (; left >= c->graph_steps; left -= c->graph_steps)
+        for (int g = 0; g < G; ++g) HIPCHK(hipGraphLaunch(c->ggexec[g], c->gstream[g]));
+    }
+    if (left > 0) {
+      if (c->rem_steps != (int)left)
+        for (int g = 0; g < G; ++g) drop_one(c->ggraph_rem[g], c->ggexec_rem[g]);
+      for (int g = 0; g < G; ++g)
+        if (!c->ggexec_rem[g] && (rc = build_graph(c, (int)left, &c->ggraph_rem[g], &c->ggexec_rem[g], g, G)))
+          return rc;
+      c->rem_steps = (int)left;
+      for (int g = 0; g < G; ++g) HIPCHK(hipGraphLaunch(c->ggexec_rem[g], c->gstream[g]));
+    }
+  }
+  for (int g = 0; g < G; ++g) {
+    HIPCHK(hipEventRecord(c->gjoin[g], c->gstream[g]));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->gjoin[g], 0));
+  }
+  return TTSH_OK;
 }
 
 // ---- continuation (reseed) ----------------------------------------------------
@@ -674,6 +779,11 @@ void free_ctx(ttsh_ctx* c) {
   for (void* p : {c->pb0, c->pb1, (void*)c->pnorm, c->lyq, (void*)c->psdf})
     if (p) hipFree(p);
   if (c->cap) hipStreamDestroy(c->cap);
+  for (int g = 0; g < kMaxGroups; ++g) {
+    if (c->gstream[g]) hipStreamDestroy(c->gstream[g]);
+    if (c->gjoin[g]) hipEventDestroy(c->gjoin[g]);
+  }
+  if (c->gfork) hipEventDestroy(c->gfork);
   delete c;
 }
 
@@ -830,6 +940,10 @@ int ttsh_set_option(ttsh_ctx* c, int key, int64_t value) {
     case TTSH_OPT_GUARD_EVERY:
       if (value < 0 || value > 1000000) return fail(TTSH_EINVAL, "guard interval out of range");
       c->guard_every = (int)value;
+      break;
+    case TTSH_OPT_GROUPS:
+      if (value < 1 || value > kMaxGroups) return fail(TTSH_EINVAL, "groups must be 1 or 2");
+      c->groups = (int)value;
       break;
     default:
       return fail(TTSH_EINVAL, "unknown option");
@@ -1359,6 +1473,7 @@ int ttsh_get_state(ttsh_ctx* c, int inst, double* vhat, int where) {
 int ttsh_step(ttsh_ctx* c, int64_t nsteps) {
   if (!c) return fail(TTSH_EINVAL, "null context");
   if (nsteps < 0) return fail(TTSH_EINVAL, "nsteps must be >= 0");
+  if (c->groups > 1) return step_groups(c, nsteps);
   if (c->graph_steps <= 0) return enqueue_steps(c, nsteps, c->stream);
   int rc;
   int64_t left = nsteps;
@@ -1543,7 +1658,7 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
   };
   int rc = TTSH_OK;
   if (copy_all(true) != hipSuccess) rc = fail(TTSH_EHIP, "tuner save failed");
-  const int keep[6] = {c->bs_row, c->bs, c->split_row, c->split_col, c->sched_row, c->sched_col};
+  const int keep[7] = {c->bs_row, c->bs, c->split_row, c->split_col, c->sched_row, c->sched_col, c->groups};
   int best_row[3] = {0, 0, kSchedDefault}, best_col[3] = {0, 0, kSchedDefault};  // bs, split, schedule
   double row_us = 0.0, col_us = 0.0;
   // every candidate is timed in two rounds (all candidates once, then all
@@ -1574,6 +1689,73 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
     if (!best_row[0] || k.row < row_us) { best_row[0] = k.bs; best_row[1] = k.split; best_row[2] = k.sch; row_us = k.row; }
     if (!best_col[0] || k.col < col_us) { best_col[0] = k.bs; best_col[1] = k.split; best_col[2] = k.sch; col_us = k.col; }
   }
+  // Whole steps decide the column workgroup size and the number of
+  // concurrent groups: with two groups the row pass of one runs beside the
+  // column pass of the other, and the column size that is fastest alone need
+  // not be the one that shares the GPU best.  The row pass keeps its choice;
+  // each column size brings its fastest (split, schedule); each candidate is
+  // replayed as ttsh_step runs it (graphs, group streams), two rounds.
+  int best_groups = 1;
+  double step_us = row_us + col_us;
+  // the per-pass runs re-applied column updates with fixed forcing (unstable
+  // modes may have overflowed): whole steps start from the saved state, with
+  // the guard off so that they leave no flags for the next ttsh_sync
+  if (rc == TTSH_OK && copy_all(false) != hipSuccess) rc = fail(TTSH_EHIP, "tuner restore failed");
+  const int keep_guard = c->guard;
+  c->guard = 0;
+  if (rc == TTSH_OK && best_row[0]) {
+    struct Whole {
+      int bs, split, sch, groups;
+      double us;
+    };
+    std::vector<Whole> whole;
+    for (int bs : {64, 128, 256}) {
+      const Cand* b = nullptr;
+      for (const Cand& k : cands)
+        if (k.bs == bs && (!b || k.col < b->col)) b = &k;
+      if (!b) continue;
+      for (int G = 1; G <= std::min(kMaxGroups, c->n_inst); ++G) whole.push_back({bs, b->split, b->sch, G, 1e30});
+    }
+    hipEvent_t w0 = nullptr, w1 = nullptr;
+    if (hipEventCreate(&w0) != hipSuccess || hipEventCreate(&w1) != hipSuccess)
+      rc = fail(TTSH_EHIP, "event creation failed");
+    for (int round = 0; round < 2 && rc == TTSH_OK; ++round)
+      for (Whole& w : whole) {
+        c->bs_row = best_row[0];
+        c->split_row = best_row[1];
+        c->sched_row = best_row[2];
+        c->bs = w.bs;
+        c->split_col = w.split;
+        c->sched_col = w.sch;
+        c->groups = w.groups;
+        drop_graph(c);
+        if ((rc = ttsh_step(c, nsteps)) != TTSH_OK) break;  // captures the graphs
+        hipEventRecord(w0, c->stream);
+        if ((rc = ttsh_step(c, nsteps)) != TTSH_OK) break;
+        hipEventRecord(w1, c->stream);
+        if (hipEventSynchronize(w1) != hipSuccess) {
+          rc = fail(TTSH_EHIP, "sync failed");
+          break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, w0, w1);
+        w.us = std::min(w.us, 1000.0 * ms / (double)nsteps);
+      }
+    if (w0) hipEventDestroy(w0);
+    if (w1) hipEventDestroy(w1);
+    const Whole* win = nullptr;
+    for (const Whole& w : whole)
+      if (!win || w.us < win->us) win = &w;
+    if (rc == TTSH_OK && win) {
+      best_col[0] = win->bs;
+      best_col[1] = win->split;
+      best_col[2] = win->sch;
+      best_groups = win->groups;
+      step_us = win->us;
+    }
+    drop_graph(c);
+  }
+  c->guard = keep_guard;
   if (copy_all(false) != hipSuccess && rc == TTSH_OK) rc = fail(TTSH_EHIP, "tuner restore failed");
   hipStreamSynchronize(c->stream);
   hipFree(buf);
@@ -1584,6 +1766,8 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
     c->split_col = keep[3];
     c->sched_row = keep[4];
     c->sched_col = keep[5];
+    c->groups = keep[6];
+    drop_graph(c);
     return rc ? rc : fail(TTSH_EUNSUPPORTED, "no workgroup size to tune");
   }
   // the two passes are tuned independently (the data layout depends on
@@ -1594,13 +1778,14 @@ int ttsh_tune(ttsh_ctx* c, int64_t nsteps, int* cfg_out, double* us_out) {
   c->bs = best_col[0];
   c->split_col = best_col[1];
   c->sched_col = best_col[2];
+  c->groups = best_groups;
   c->opt_bs = 0;
   drop_graph(c);
   if (cfg_out) {
-    const int cfg[6] = {best_row[0], best_col[0], best_row[1], best_col[1], best_row[2], best_col[2]};
-    std::copy(cfg, cfg + 6, cfg_out);
+    const int cfg[7] = {best_row[0], best_col[0], best_row[1], best_col[1], best_row[2], best_col[2], best_groups};
+    std::copy(cfg, cfg + 7, cfg_out);
   }
-  if (us_out) *us_out = row_us + col_us;
+  if (us_out) *us_out = step_us;
   return TTSH_OK;
 }
 
@@ -1616,9 +1801,9 @@ int ttsh_device_arch(char* out, int n) {
 
 int ttsh_get_tuning(ttsh_ctx* c, int* cfg) {
   if (!c || !cfg) return fail(TTSH_EINVAL, "null argument");
-  const int v[6] = {c->bs_row, c->bs, c->split_row || must_split(c), c->split_col || must_split(c), c->sched_row,
-                    c->sched_col};
-  std::copy(v, v + 6, cfg);
+  const int v[7] = {c->bs_row, c->bs, c->split_row || must_split(c), c->split_col || must_split(c), c->sched_row,
+                    c->sched_col, c->groups};
+  std::copy(v, v + 7, cfg);
   return TTSH_OK;
 }
 
@@ -1636,12 +1821,14 @@ int ttsh_set_tuning(ttsh_ctx* c, const int* cfg) {
     if (sch != kSchedDefault && !sched_usable(c, cfg[q - 2]))
       return fail(TTSH_EINVAL, "a non-default schedule needs the FP32 arithmetic and the multi-size launch");
   }
+  if (cfg[6] < 1 || cfg[6] > kMaxGroups) return fail(TTSH_EINVAL, "groups must be 1 or 2");
   c->bs_row = cfg[0];
   c->bs = cfg[1];
   c->split_row = cfg[2];
   c->split_col = cfg[3];
   c->sched_row = cfg[4];
   c->sched_col = cfg[5];
+  c->groups = cfg[6];
   c->opt_bs = 0;
   drop_graph(c);
   return TTSH_OK;

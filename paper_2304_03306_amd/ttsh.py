@@ -20,6 +20,8 @@ TTSH_HOST, TTSH_DEVICE = 0, 1
 TTSH_IFEULER, TTSH_ETD1, TTSH_IMEX, TTSH_ETDRK2, TTSH_ETDRK4 = 0, 1, 2, 3, 4
 TTSH_FP32, TTSH_FP64, TTSH_FP32_STATE64 = 32, 64, 96
 TTSH_OPT_GRAPH_STEPS, TTSH_OPT_BLOCK, TTSH_OPT_GUARD, TTSH_OPT_SPLIT, TTSH_OPT_GUARD_EVERY = 1, 2, 4, 8, 16
+TTSH_OPT_GROUPS = 17
+TUNING_INTS = 7  # row size, column size, row split, column split, row schedule, column schedule, groups
 SCHEMES = {"ifeuler": TTSH_IFEULER, "etd1": TTSH_ETD1, "imex": TTSH_IMEX, "etdrk2": TTSH_ETDRK2,
            "etdrk4": TTSH_ETDRK4}
 
@@ -354,10 +356,9 @@ def ttsh_stream_bench(reads, writes, elems, blocks, reps, buf):
 
 
 def ttsh_tune(ctx, nsteps):
-    """Pick the fastest launch configuration of each pass; returns
-    ((row_size, col_size, row_split, col_split, row_schedule, col_schedule),
-    us_per_step)."""
-    cfg = (ctypes.c_int * 6)()
+    """Pick the fastest launch configuration; returns ((row_size, col_size,
+    row_split, col_split, row_schedule, col_schedule, groups), us_per_step)."""
+    cfg = (ctypes.c_int * TUNING_INTS)()
     us = ctypes.c_double()
     _check(lib().ttsh_tune(ctx, int(nsteps), ctypes.cast(cfg, ctypes.c_void_p),
                            ctypes.cast(ctypes.byref(us), ctypes.c_void_p)))
@@ -365,15 +366,20 @@ def ttsh_tune(ctx, nsteps):
 
 
 def ttsh_get_tuning(ctx):
-    cfg = (ctypes.c_int * 6)()
+    cfg = (ctypes.c_int * TUNING_INTS)()
     _check(lib().ttsh_get_tuning(ctx, ctypes.cast(cfg, ctypes.c_void_p)))
     return tuple(cfg)
 
 
 def ttsh_set_tuning(ctx, cfg):
-    if len(cfg) != 6:
-        raise ValueError("a tuning is 6 ints")
-    arr = (ctypes.c_int * 6)(*[int(v) for v in cfg])
+    """Set a configuration of TUNING_INTS ints; one of 6 (without the group
+    count) means one group."""
+    cfg = [int(v) for v in cfg]
+    if len(cfg) == TUNING_INTS - 1:
+        cfg.append(1)
+    if len(cfg) != TUNING_INTS:
+        raise ValueError(f"a tuning is {TUNING_INTS} ints")
+    arr = (ctypes.c_int * TUNING_INTS)(*cfg)
     return _check(lib().ttsh_set_tuning(ctx, ctypes.cast(arr, ctypes.c_void_p)))
 
 

@@ -2,12 +2,14 @@
 
 ttsh_tune times the candidate launch configurations of the two step passes
 (workgroup size, one launch for all grid sizes or one per size, transform
-schedule) and keeps the fastest; the choice depends only on the mix of grid
-sizes, the arithmetic, whether the vorticity-damping term is on, and the
-device.  This module keeps a JSON file of choices under that key, so that a
-later run sets the configuration (ttsh_set_tuning) without timing anything.
+schedule, one or two concurrent instance groups) and keeps the fastest; the
+choice depends only on the mix of grid sizes, the arithmetic, whether the
+vorticity-damping term is on, and the device.  This module keeps a JSON file
+of choices under that key, so that a later run sets the configuration
+(ttsh_set_tuning) without timing anything.
 
-The file maps key -> {"cfg": [6 ints, as ttsh_tune], "us_per_step": float}.
+The file maps key -> {"cfg": [7 ints, as ttsh_tune], "us_per_step": float
+(whole steps)}; a cfg of 6 ints (without the group count) means one group.
 A missing or unreadable file reads as empty; writes replace the file
 atomically.
 """

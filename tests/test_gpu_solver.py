@@ -345,10 +345,11 @@ def test_block_sizes_agree_and_tuner_restores_state(gpu):
             s.set_field(i, W.uniform_field(40 + i, N, 0.2, 32))
         if bs == 128 and split == 0:
             before = [s.state(i) for i in range(3)]
-            (brow, bcol, srow, scol, hrow, hcol), us = s.tune(3)
+            (brow, bcol, srow, scol, hrow, hcol, groups), us = s.tune(3)
             assert brow in (64, 128, 256) and bcol in (64, 128, 256) and us > 0
             assert srow in (0, 1) and scol in (0, 1) and hrow in range(6, 12) and hcol in range(6, 12)
-            assert s.get_tuning() == (brow, bcol, srow, scol, hrow, hcol)
+            assert groups in (1, 2)
+            assert s.get_tuning() == (brow, bcol, srow, scol, hrow, hcol, groups)
             for i in range(3):
                 assert np.array_equal(s.state(i), before[i])
         s.step(20)
@@ -380,7 +381,7 @@ def test_transform_schedules_match_oracle(gpu, sched):
         s.set_mask(i, K)
         s.set_field(i, v0)
         refs.append(O.run_velocity(O.project_field(v0, L), K, p, L, 40))
-    cfg = (64, 128, 0, 0, sched, sched)
+    cfg = (64, 128, 0, 0, sched, sched, 1)
     s.set_tuning(cfg)
     assert s.get_tuning() == cfg
     s.step(40)
@@ -401,7 +402,7 @@ def test_transform_schedules_match_oracle(gpu, sched):
     f64 = gpu.Solver(Ns, Ls, p, 64)
     if sched != 8:
         with pytest.raises(gpu.TTSHError):
-            f64.set_tuning((64, 128, 0, 0, sched, sched))
+            f64.set_tuning((64, 128, 0, 0, sched, sched, 1))
     f64.close()
     s.close()
 
@@ -807,3 +808,65 @@ def test_vortex_count_matches_oracle(gpu, prec):
     want = O.vortex_count(v, s.mask(1), 0.5, vmin)
     print("counts", got, want, flush=True)
     assert got == want
+
+
+@pytest.mark.parametrize("scheme,graph", [("ifeuler", 50), ("ifeuler", 0), ("etdrk2", 50), ("etdrk4", 7)])
+def test_groups_equal_one_stream(gpu, scheme, graph):
+    """Two concurrent instance groups (every grid size split in halves, each
+    half on its own stream and graphs) give the single-stream result bit for
+    bit: each instance runs the same tile code either way.  Calls of 50 + 23
+    steps cover whole graph chunks and a tail; a class of one instance leaves
+    that grid size out of one group."""
+    import dataclasses
+    say("groups", scheme, graph)
+    p = dataclasses.replace(O.workload_params(), scheme=scheme)
+    Ns, Ls = [256, 128, 512, 128, 256, 128], [100.0, 64.0, 256.0, 70.0, 90.0, 60.0]
+    out = {}
+    for groups in (1, 2):
+        s = gpu.Solver(Ns, Ls, p, 32)
+        s.option(gpu.TTSH_OPT_GRAPH_STEPS, graph)
+        s.set_tuning((64, 128, 0, 0, 8, 8, groups))
+        assert s.get_tuning()[6] == groups
+        for i, (N, L) in enumerate(zip(Ns, Ls)):
+            s.mask_tanh(i, [(0.0, 0.0)], [L / 4], 0.5)
+            s.set_field(i, W.uniform_field(70 + i, N, 0.2, 32))
+        s.step(50)
+        s.step(23)
+        s.sync()
+        out[groups] = [s.state(i) for i in range(len(Ns))]
+        s.close()
+    for i, (a, b) in enumerate(zip(out[1], out[2])):
+        assert np.array_equal(a, b), i
+
+
+def test_groups_guard_and_options(gpu):
+    """With two groups, the guard checks queued on a group's stream flag the
+    instance that overflowed (the unstable explicit mask term of the
+    failure-injection test, K = 1 and gamma_v dt = 3, on instance 3, which
+    the second group steps), and ttsh_sync names it; the option and tuning
+    setters refuse group counts other than 1 and 2."""
+    import dataclasses
+    say("groups guard")
+    N, L = 64, 32.0
+    bad = dataclasses.replace(O.workload_params(), gamma_v=300.0)
+    for every in (10, 0):
+        u = gpu.Solver([N, N, 2 * N, 2 * N], [L, L, 2 * L, 2 * L], bad, 32)
+        u.option(gpu.TTSH_OPT_GROUPS, 2)
+        u.option(gpu.TTSH_OPT_GUARD_EVERY, every)
+        for i in range(4):
+            n = u.N[i]
+            u.set_mask(i, np.ones((n, n)) if i == 3 else np.zeros((n, n)))
+            u.set_field(i, W.uniform_field(84 + i, n, 0.1, 32))
+        u.step(300)
+        with pytest.raises(gpu.TTSHError) as e:
+            u.sync()
+        assert e.value.code == gpu.TTSH_ENONFINITE and "instance 3" in str(e.value), (every, str(e.value))
+        assert "more" not in str(e.value)
+        u.close()
+    s = gpu.Solver([N, N], [L, L], O.workload_params(), 32)
+    for v in (0, 3):
+        with pytest.raises(gpu.TTSHError):
+            s.option(gpu.TTSH_OPT_GROUPS, v)
+        with pytest.raises(gpu.TTSHError):
+            s.set_tuning((64, 64, 0, 0, 8, 8, v))
+    s.close()
