@@ -279,6 +279,9 @@ def main():
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON cache of tuner results (default: the package's tuning_cache.json)")
     ap.add_argument("--retune", action="store_true", help="tune even if the cache holds a choice")
+    ap.add_argument("--groups", type=int, default=0, choices=[0, 1, 2],
+                    help="concurrent instance groups of the step (0 = the tuned choice); 1 gives "
+                         "profiles whose step kernels run alone, as the roofline's per-kernel figure")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (scale for the HBM byte counters)")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming-bandwidth probe")
@@ -344,6 +347,9 @@ def main():
             f"{cfg[:2]}, one launch per grid size {cfg[2:4]}, transform schedules {cfg[4:6]}, "
             f"concurrent instance groups {cfg[6] if len(cfg) > 6 else 1}"
             + (f" ({tuned_us:.1f} us/step when tuned)" if tuned_us else ""))
+        cfg = s.get_tuning()
+    if args.groups:
+        s.option(T.TTSH_OPT_GROUPS, args.groups)
         cfg = s.get_tuning()
     block, split, sched, groups = tuple(cfg[0:2]), tuple(cfg[2:4]), tuple(cfg[4:6]), int(cfg[6])
 
