@@ -71,8 +71,26 @@ __device__ inline float norm_cdf(float x) {
   const float h = 0.5f * erfc_half(fabsf(x));
   return x >= 0.f ? 1.0f - h : h;
 }
-// exact (erf) GELU x Phi(x) and its derivative Phi(x) + x phi(x)
-__device__ inline float gelu(float x) { return x * norm_cdf(x); }
+// Phi(-a) = erfc(a / sqrt 2) / 2 for a >= 0, the same formula with the factor
+// 1/2 taken into the polynomial: (2^{1/16} p)^-16 = p^-16 / 2, so the
+// coefficients are 2^{1/16} times those of erfc_half
+__device__ inline float half_erfc_half(float a) {
+  constexpr double r = 0.70710678118654752440, s = 1.04427378242741384032;  // 2^(1/16)
+  constexpr float c0 = (float)s, c1 = (float)(s * 0.0705230784 * r), c2 = (float)(s * 0.0422820123 * r * r),
+                  c3 = (float)(s * 0.0092705272 * r * r * r), c4 = (float)(s * 0.0001520143 * r * r * r * r),
+                  c5 = (float)(s * 0.0002765672 * r * r * r * r * r),
+                  c6 = (float)(s * 0.0000430638 * r * r * r * r * r * r);
+  const float p = fmaf(a, fmaf(a, fmaf(a, fmaf(a, fmaf(a, fmaf(a, c6, c5), c4), c3), c2), c1), c0);
+  const float q = __builtin_amdgcn_rcpf(p), q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
+  return q8 * q8;
+}
+// exact (erf) GELU x Phi(x) = max(x, 0) - |x| Phi(-|x|) (for x < 0, x Phi(x) =
+// -|x| Phi(-|x|); for x >= 0, x (1 - Phi(-x))): one max and one fma around the
+// tail probability; and its derivative Phi(x) + x phi(x)
+__device__ inline float gelu(float x) {
+  const float a = fabsf(x);
+  return fmaf(-a, half_erfc_half(a), fmaxf(x, 0.f));
+}
 __device__ inline float gelu_grad(float x) {
   return norm_cdf(x) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
@@ -527,6 +545,24 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
     }
   }
 
+  // Without LIFT, the next row's activation fragments and T2 piece are loaded
+  // at the top of each iteration (into a2n, t2n), so that their latency
+  // overlaps the current row's work instead of starting each iteration.
+  const int tj = tid >> 3, tc0 = (tid & 7) * 4;  // this thread's piece of T2[b][y]
+  short4_t a2n[2][2];
+  uint2 t2n = {0u, 0u};
+  if constexpr (!LIFT) {
+    const long long r0 = blockIdx.x;
+    if (r0 < rows) {
+      const bf16* hp = h + r0 * (W * C);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+          a2n[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+      t2n = *(const uint2*)(T2 + r0 * (J * C) + tj * C + tc0);
+    }
+  }
   for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
     float4_t acc[2][2];
     if constexpr (LIFT) {
@@ -542,19 +578,26 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
           acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, pw[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       }
     } else {
-      const bf16* hp = h + row * (W * C);
       short4_t a2[2][2];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-          a2[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+        for (int kk = 0; kk < 2; ++kk) a2[s][kk] = a2n[s][kk];
+      const uint2 v = t2n;
+      const long long rn = row + gridDim.x;
+      if (rn < rows) {
+        const bf16* hp = h + rn * (W * C);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int kk = 0; kk < 2; ++kk)
+            a2n[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+        t2n = *(const uint2*)(T2 + rn * (J * C) + tj * C + tc0);
+      }
       {  // T2[b][y] (J x C) into LDS as [c][j]
-        const int j = tid >> 3, c0 = (tid & 7) * 4;
-        const uint2 v = *(const uint2*)(T2 + row * (J * C) + j * C + c0);
         const bf16* e = (const bf16*)&v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ts[(c0 + q) * kLDK + j] = e[q];
+        for (int q = 0; q < 4; ++q) Ts[(tc0 + q) * kLDK + tj] = e[q];
       }
       __syncthreads();
 #pragma unroll
