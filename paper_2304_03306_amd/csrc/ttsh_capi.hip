@@ -259,7 +259,13 @@ void drop_one(hipGraph_t& g, hipGraphExec_t& x) {
   g = nullptr;
 }
 
+// Executable graphs may still run from an earlier asynchronous ttsh_step: the
+// graphs are only destroyed after the context's stream, which every step call
+// ends on (the group streams join it), has drained.
 void drop_graph(ttsh_ctx* c) {
+  bool any = c->gexec || c->gexec_rem;
+  for (int g = 0; g < kMaxGroups; ++g) any = any || c->ggexec[g] || c->ggexec_rem[g];
+  if (any) (void)hipStreamSynchronize(c->stream);
   drop_one(c->graph, c->gexec);
   drop_one(c->graph_rem, c->gexec_rem);
   for (int g = 0; g < kMaxGroups; ++g) {
@@ -666,8 +672,14 @@ int step_groups(ttsh_ctx* c, int64_t nsteps) {
         for (int g = 0; g < G; ++g) HIPCHK(hipGraphLaunch(c->ggexec[g], c->gstream[g]));
     }
     if (left > 0) {
-      if (c->rem_steps != (int)left)
+      if (c->rem_steps != (int)left) {
+        // an old tail may still run from an earlier call, whose end the
+        // context's stream has joined; this call's work is queued behind it
+        bool old = false;
+        for (int g = 0; g < G; ++g) old = old || c->ggexec_rem[g];
+        if (old) HIPCHK(hipStreamSynchronize(c->stream));
         for (int g = 0; g < G; ++g) drop_one(c->ggraph_rem[g], c->ggexec_rem[g]);
+      }
       for (int g = 0; g < G; ++g)
         if (!c->ggexec_rem[g] && (rc = build_graph(c, (int)left, &c->ggraph_rem[g], &c->ggexec_rem[g], g, G)))
           return rc;
@@ -1488,10 +1500,9 @@ int ttsh_step(ttsh_ctx* c, int64_t nsteps) {
     // the tail shorter than a chunk replays a graph of its own length, kept
     // until a call ends with a different tail
     if (c->gexec_rem && c->rem_steps != (int)left) {
-      hipGraphExecDestroy(c->gexec_rem);
-      hipGraphDestroy(c->graph_rem);
-      c->gexec_rem = nullptr;
-      c->graph_rem = nullptr;
+      // the old tail may still run from the previous call (stream order): wait
+      HIPCHK(hipStreamSynchronize(c->stream));
+      drop_one(c->graph_rem, c->gexec_rem);
       c->rem_steps = 0;
     }
     if (!c->gexec_rem) {
