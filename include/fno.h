@@ -141,6 +141,20 @@ int fno_forward_ex(fno_ctx* ctx, const float* x, float* y, int64_t y_pix_stride,
 int fno_gather(fno_ctx* ctx, float* dst, int64_t dst_ch, const float* src, int64_t src_ch, int nch,
                int64_t npix, const int64_t* idx, int n);
 
+/* fno_gather of square samples (n_side x n_side pixels, n_side even) with a
+ * symmetry of the square per sample, for training-set augmentation (the
+ * equation is isotropic and has no handedness, so a rotated or reflected
+ * solution is a solution; a mask centred on the grid centre stays a valid
+ * mask): sym[s] in 0..7 is the element g of the dihedral group D4, r = g & 3
+ * quarter turns counterclockwise followed, if g & 4, by the reflection
+ * y -> -y, about the node (n_side/2, n_side/2) of the periodic grid (rows y,
+ * columns x).  Destination node x' takes source node M_g^-1 x'; channels 0
+ * and 1 are a vector (v_x, v_y) and are multiplied by M_g; other channels are
+ * copied.  idx and sym are host arrays.  Synchronous; n <= max_batch.
+ * TTSH_EINVAL for odd n_side or sym outside 0..7.                          */
+int fno_gather_d4(fno_ctx* ctx, float* dst, int64_t dst_ch, const float* src, int64_t src_ch, int nch,
+                  int n_side, const int64_t* idx, const int* sym, int n);
+
 /* Add uniform noise amp * U[-1, 1) to channels 0..nch-1 of npix pixels of
  * x (device float32, pixel stride pix_stride); the noise is a counter-based
  * SplitMix64 stream of (seed, element index), reproducible for any launch

@@ -1044,6 +1044,46 @@ __global__ void k_gather(float* __restrict__ dst, long long dch, const float* __
   dst[(s * npix + p) * dch + ch] = src[(idx[s] * npix + p) * sch + ch];
 }
 
+// k_gather with a symmetry of the square grid per sample: sample s takes the
+// element g = sym[s] of the dihedral group D4 (r = g & 3 quarter turns
+// counterclockwise, then with g & 4 the reflection y -> -y), about the grid
+// centre (n/2, n/2) on the n x n periodic grid.  The destination node x' takes
+// the source node M_g^-1 x' and the vector formed by channels 0 and 1 is
+// multiplied by M_g; the other channels are copied.
+__global__ void k_gather_d4(float* __restrict__ dst, long long dch, const float* __restrict__ src, long long sch,
+                            int nch, int n, const long long* __restrict__ idx, const int* __restrict__ sym,
+                            long long tot) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const long long npix = (long long)n * n;
+  const long long s = i / npix, p = i % npix;
+  const int y = (int)(p / n), x = (int)(p % n), h = n / 2;
+  const int g = sym[s], r = g & 3;
+  // source position: reflect the destination position if asked, then turn
+  // it back r quarter turns ((a, b) -> (b, -a) each)
+  int a = x - h, b = y - h;
+  if (g & 4) b = -b;
+  for (int q = 0; q < r; ++q) {
+    const int t = a;
+    a = b;
+    b = -t;
+  }
+  const int xs = (a + h + n) % n, ys = (b + h + n) % n;
+  const float* sp = src + (idx[s] * npix + (long long)ys * n + xs) * sch;
+  float* dp = dst + (s * npix + p) * dch;
+  // the vector: r quarter turns ((u, v) -> (-v, u) each), then the reflection
+  float u = sp[0], v = nch > 1 ? sp[1] : 0.f;
+  for (int q = 0; q < r; ++q) {
+    const float t = u;
+    u = -v;
+    v = t;
+  }
+  if (g & 4) v = -v;
+  dp[0] = u;
+  if (nch > 1) dp[1] = v;
+  for (int c = 2; c < nch; ++c) dp[c] = sp[c];
+}
+
 // per-sample sums of (y - t)^2 and t^2 (FP64), one block of 1024 threads per
 // sample, a thread per pixel (all its channels).  With ref non-null the second
 // sum is of (t - ref)^2, ref holding the same channels at pixel stride ref_s
@@ -1316,6 +1356,7 @@ struct fno_ctx {
   size_t part_n = 0;
   double* lsum = nullptr;
   long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
+  int* gsym = nullptr;        // symmetry elements of fno_gather_d4 [max_batch]
   int staged_gemm = 1;        // GEMMs whose operands allow it stage them through LDS
   int specialized = 1;        // kernels for C = 32, 2m = 32 and W = 128 (layer tail) / H = 128 (k_y steps)
   bool proj_train_fused = false;  // the last training forward left no hidden layer (fused backward)
@@ -1794,7 +1835,7 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
       (rc = alloc(c, &c->dh1, (size_t)(P * C))) || (rc = alloc(c, &c->dz, (size_t)(P * C))) ||
       (rc = alloc(c, &c->gG, (size_t)modesz)) || (rc = alloc(c, &c->gF, (size_t)modesz)) ||
       (rc = alloc(c, &c->du, (size_t)(P * hidden))) || (rc = alloc(c, &c->lsum, (size_t)(2 * max_batch))) ||
-      (rc = alloc(c, &c->gidx, (size_t)max_batch)))
+      (rc = alloc(c, &c->gidx, (size_t)max_batch)) || (rc = alloc(c, &c->gsym, (size_t)max_batch)))
     return bail(rc);
   for (int l = 0; l <= layers; ++l)
     if ((rc = alloc(c, &c->h[l], (size_t)(P * C)))) return bail(rc);
@@ -2211,6 +2252,25 @@ int fno_gather(fno_ctx* c, float* dst, int64_t dch, const float* src, int64_t sc
                      (long long)npix, c->gidx, tot);
   FCHK(hipGetLastError());
   FCHK(hipStreamSynchronize(c->s));  // idx is read from pageable host memory
+  return TTSH_OK;
+}
+
+int fno_gather_d4(fno_ctx* c, float* dst, int64_t dch, const float* src, int64_t sch, int nch, int n_side,
+                  const int64_t* idx, const int* sym, int n) {
+  if (!c || !dst || !src || !idx || !sym) return ffail(TTSH_EINVAL, "null argument");
+  if (n < 1 || n > c->maxB) return ffail(TTSH_EINVAL, "sample count out of range");
+  if (nch < 1 || dch < nch || sch < nch || n_side < 2 || n_side % 2) return ffail(TTSH_EINVAL, "invalid sizes");
+  for (int s = 0; s < n; ++s) {
+    if (idx[s] < 0) return ffail(TTSH_EINVAL, "negative sample index");
+    if (sym[s] < 0 || sym[s] > 7) return ffail(TTSH_EINVAL, "symmetry element must be in 0..7");
+  }
+  FCHK(hipMemcpyAsync(c->gidx, idx, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->s));
+  FCHK(hipMemcpyAsync(c->gsym, sym, sizeof(int) * n, hipMemcpyHostToDevice, c->s));
+  const long long tot = (long long)n * n_side * n_side;
+  hipLaunchKernelGGL(k_gather_d4, dim3(nb(tot)), dim3(256), 0, c->s, dst, (long long)dch, src, (long long)sch, nch,
+                     n_side, c->gidx, c->gsym, tot);
+  FCHK(hipGetLastError());
+  FCHK(hipStreamSynchronize(c->s));  // idx and sym are read from pageable host memory
   return TTSH_OK;
 }
 

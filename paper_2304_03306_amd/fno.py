@@ -34,6 +34,7 @@ def lib():
             "fno_forward": ([vp, vp, vp, i32, i32], ctypes.c_int),
             "fno_forward_ex": ([vp, vp, vp, i64, i32, i32, i32], ctypes.c_int),
             "fno_gather": ([vp, vp, i64, vp, i64, i32, i64, vp, i32], ctypes.c_int),
+            "fno_gather_d4": ([vp, vp, i64, vp, i64, i32, i32, vp, vp, i32], ctypes.c_int),
             "fno_perturb": ([vp, vp, i64, i32, i64, f32, u64], ctypes.c_int),
             "fno_sample_errors": ([vp, i64, vp, i64, i32, i64, i32, vp], ctypes.c_int),
             "fno_loss": ([vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -133,6 +134,20 @@ class FNO:
 
     def perturb(self, x, pix_stride, nch, npix, amp, seed):
         _check(lib().fno_perturb(self.ctx, _ptr(x), int(pix_stride), int(nch), int(npix), float(amp), int(seed)))
+
+    def gather_d4(self, dst, dst_ch, src, src_ch, nch, n_side, idx, sym):
+        """gather of square samples with the D4 symmetry sym[s] (0..7) applied
+        to sample s (fno_gather_d4)."""
+        ix = np.ascontiguousarray(idx, dtype=np.int64)
+        sy = np.ascontiguousarray(sym, dtype=np.int32)
+        npix = n_side * n_side
+        if ix.size != sy.size:
+            raise ValueError("one symmetry element per sample")
+        if ix.size and int(ix.max()) * npix * src_ch + npix * src_ch > src.numel():
+            raise ValueError("sample index beyond the source")
+        _check(lib().fno_gather_d4(self.ctx, _ptr(dst), int(dst_ch), _ptr(src), int(src_ch), int(nch), int(n_side),
+                                   ix.ctypes.data_as(ctypes.c_void_p), sy.ctypes.data_as(ctypes.c_void_p),
+                                   int(ix.size)))
 
     def gather(self, dst, dst_ch, src, src_ch, nch, npix, idx):
         """Copy samples idx (host int64 indices) of src into dst."""

@@ -50,6 +50,7 @@ class SurrogateConfig:
     cout: int = 2
     increment_loss: bool = False  # normalise the loss by the change over the step (fno_loss_ex)
     input_noise: float = 0.0      # uniform perturbation of the input velocity in training
+    augment: bool = True          # a random symmetry of the square per training sample (fno_gather_d4)
 
 
 def _torch():
@@ -148,6 +149,7 @@ class Trainer:
         self.tb = torch.empty((cfg.batch, n, n, cfg.cout), dtype=torch.float32, device="cuda")
         self.yb = torch.empty_like(self.tb)
         self.step_count = 0
+        self.rng = np.random.default_rng(seed + 7919)  # the augmentation's symmetry elements
 
     def pairs(self, D, ids: Sequence[int]) -> np.ndarray:
         """Flat sample indices (into D viewed as [n_snap * I]) of every input
@@ -161,8 +163,14 @@ class Trainer:
         npix = c.Nc * c.Nc
         B = len(idx)
         dch = D.shape[-1]
-        self.net.gather(self.xb, c.cin, D, dch, c.cin, npix, idx)
-        self.net.gather(self.tb, c.cout, D, dch, c.cout, npix, idx + I)
+        if c.augment:
+            # the same rotation or reflection for a sample's input and target
+            sym = self.rng.integers(0, 8, B)
+            self.net.gather_d4(self.xb, c.cin, D, dch, c.cin, c.Nc, idx, sym)
+            self.net.gather_d4(self.tb, c.cout, D, dch, c.cout, c.Nc, idx + I, sym)
+        else:
+            self.net.gather(self.xb, c.cin, D, dch, c.cin, npix, idx)
+            self.net.gather(self.tb, c.cout, D, dch, c.cout, npix, idx + I)
         if c.input_noise > 0:
             self.net.perturb(self.xb, c.cin, c.cout, B * npix, c.input_noise, self.step_count + 1)
         self.net.forward_ex(self.xb, self.yb, c.cout, True, B, train=True)
@@ -393,6 +401,10 @@ def main(argv=None):
     ap.add_argument("--input-noise", type=float, default=0.0)
     ap.add_argument("--scale-channel", action="store_true",
                     help="a fourth input channel with the coarse grid spacing L/Nc of each instance")
+    ap.add_argument("--no-augment", action="store_true",
+                    help="train without the random rotation or reflection of the square per sample (by default "
+                         "each training sample takes one: the circles sit on the grid centre, and the equation "
+                         "has no preferred direction or handedness)")
     ap.add_argument("--threshold", type=float, default=0.1)
     ap.add_argument("--check-every", type=int, default=25)
     ap.add_argument("--report", default="surrogate_report.json")
@@ -405,7 +417,7 @@ def main(argv=None):
     inst = wl.instances
     params = Wl.workload_coefficients()
     cfg = SurrogateConfig(batch=a.batch, lr=a.lr, modes=a.modes, input_noise=a.input_noise,
-                          cin=4 if a.scale_channel else 3)
+                          cin=4 if a.scale_channel else 3, augment=not a.no_augment)
     I, Nc = len(inst), cfg.Nc
     spacing = [i.L / Nc for i in inst] if a.scale_channel else None
     masks = coarse_masks(inst, Nc, params)
@@ -452,7 +464,8 @@ def main(argv=None):
         "instances": I, "coarse_grid": Nc, "solver_steps_per_surrogate_step": cfg.every,
         "network": dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, hidden=cfg.hidden,
                         params=int(tr.net.n), dtype="bf16 storage, fp32 accumulation",
-                        input_noise=cfg.input_noise, inputs="v_x, v_y, K" + (", dx" if a.scale_channel else "")),
+                        input_noise=cfg.input_noise, augment=cfg.augment,
+                        inputs="v_x, v_y, K" + (", dx" if a.scale_channel else "")),
         "data": dict(transient=a.transient, snapshots=a.snapshots, train_pairs=len(tr.pairs(Dtrain, train_ids)),
                      train_instances=train_ids, test_instances=test_ids),
         "training": dict(epochs=len(hist), seconds=hist[-1][2], loss_first=hist[0][1], loss_last=hist[-1][1],

@@ -380,3 +380,55 @@ def test_gelu_matches_exact_erf_form(gpu):
     ref = F.forward(pq, np.zeros((1, 16, 16, 1)), cfg)
     got = y.cpu().numpy().astype(np.float64)
     assert np.abs(got - ref).max() <= 2e-2 * max(1.0, np.abs(ref).max())
+
+
+def test_gather_d4_applies_the_square_symmetries(gpu):
+    """fno_gather_d4 against the definition written with the 2 x 2 matrices:
+    for g = (r quarter turns counterclockwise, then the reflection y -> -y if
+    g & 4), M_g = F^f R^r with R = [[0, -1], [1, 0]], F = diag(1, -1); the
+    destination node x' (relative to the centre node n/2) takes the source
+    node M_g^-1 x' (periodic), channels 0-1 become M_g times the source vector,
+    channel 2 is copied; every element exactly.  Also: the four quarter turns
+    compose to the identity, and odd sides and elements outside 0..7 are
+    refused."""
+    import torch
+    from paper_2304_03306_amd.ttsh import TTSHError
+    say("fno gather d4")
+    n, h, C = SMALL.H, SMALL.H // 2, 3
+    net, _ = make_net(gpu, SMALL, 8, seed=21)
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((5, n, n, C)).astype(np.float32)
+    src = torch.from_numpy(x.copy()).cuda()
+    idx = np.array([3, 0, 4, 1, 2, 3, 0, 2])
+    sym = np.arange(8)
+    dst = torch.zeros((8, n, n, C), dtype=torch.float32, device="cuda")
+    net.gather_d4(dst, C, src, C, C, n, idx, sym)
+    got = dst.cpu().numpy()
+    R = np.array([[0, -1], [1, 0]])
+    F_ = np.diag([1, -1])
+    for s in range(8):
+        g = int(sym[s])
+        M = np.linalg.matrix_power(R, g & 3)
+        if g & 4:
+            M = F_ @ M
+        Minv = np.rint(np.linalg.inv(M)).astype(int)
+        want = np.empty((n, n, C), dtype=np.float32)
+        for yp in range(n):
+            for xp in range(n):
+                a, b = Minv @ np.array([xp - h, yp - h])
+                xs, ys = (a + h) % n, (b + h) % n
+                v = x[idx[s], ys, xs]
+                want[yp, xp, :2] = (M @ v[:2].astype(np.float64)).astype(np.float32)
+                want[yp, xp, 2] = v[2]
+        assert np.array_equal(got[s], want), s
+    # a quarter turn four times over is the identity
+    cur = torch.from_numpy(x[:1].copy()).cuda()
+    for _ in range(4):
+        nxt = torch.empty_like(cur)
+        net.gather_d4(nxt, C, cur, C, C, n, [0], [1])
+        cur = nxt
+    assert np.array_equal(cur.cpu().numpy(), x[:1])
+    with pytest.raises(TTSHError):
+        net.gather_d4(dst, C, src, C, C, n, [0], [8])
+    with pytest.raises(TTSHError):
+        net.gather_d4(dst, C, src, C, C, n - 1, [0], [0])
