@@ -122,6 +122,7 @@ enum {
                                stepping with its own launches, graphs and stream, so
                                that one half's row pass runs beside the other half's
                                column pass; results are the same bit for bit.
+                               2 needs at least two instances (TTSH_EINVAL).
                                Default 1; ttsh_tune chooses. */
 };
 

@@ -649,17 +649,9 @@ int ensure_groups(ttsh_ctx* c) {
   return TTSH_OK;
 }
 
-// ttsh_step with the instances in c->groups groups: the group streams wait
-// for the work queued on the context's stream, replay their graphs chunk by
-// chunk (each group its own), and the context's stream waits for all of
-// them, so that the call is ordered like a single-stream one
-int step_groups(ttsh_ctx* c, int64_t nsteps) {
-  if (nsteps == 0) return TTSH_OK;
-  int rc = ensure_groups(c);
-  if (rc) return rc;
-  const int G = c->groups;
-  HIPCHK(hipEventRecord(c->gfork, c->stream));
-  for (int g = 0; g < G; ++g) HIPCHK(hipStreamWaitEvent(c->gstream[g], c->gfork, 0));
+// the work of step_groups between the fork and the join
+int step_groups_body(ttsh_ctx* c, int64_t nsteps, int G) {
+  int rc;
   if (c->graph_steps <= 0) {
     for (int g = 0; g < G; ++g)
       if ((rc = enqueue_steps(c, nsteps, c->gstream[g], g, G))) return rc;
@@ -687,11 +679,29 @@ int step_groups(ttsh_ctx* c, int64_t nsteps) {
       for (int g = 0; g < G; ++g) HIPCHK(hipGraphLaunch(c->ggexec_rem[g], c->gstream[g]));
     }
   }
-  for (int g = 0; g < G; ++g) {
-    HIPCHK(hipEventRecord(c->gjoin[g], c->gstream[g]));
-    HIPCHK(hipStreamWaitEvent(c->stream, c->gjoin[g], 0));
-  }
   return TTSH_OK;
+}
+
+// ttsh_step with the instances in c->groups groups: the group streams wait
+// for the work queued on the context's stream, replay their graphs chunk by
+// chunk (each group its own), and the context's stream waits for all of
+// them, so that the call is ordered like a single-stream one.  The join is
+// queued on every path after the fork, so that whatever was launched on a
+// group stream before an error is still ordered ahead of later work.
+int step_groups(ttsh_ctx* c, int64_t nsteps) {
+  if (nsteps == 0) return TTSH_OK;
+  int rc = ensure_groups(c);
+  if (rc) return rc;
+  const int G = c->groups;
+  HIPCHK(hipEventRecord(c->gfork, c->stream));
+  for (int g = 0; g < G; ++g) HIPCHK(hipStreamWaitEvent(c->gstream[g], c->gfork, 0));
+  rc = step_groups_body(c, nsteps, G);
+  for (int g = 0; g < G; ++g) {
+    const hipError_t e1 = hipEventRecord(c->gjoin[g], c->gstream[g]);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(c->stream, c->gjoin[g], 0) : e1;
+    if (e2 != hipSuccess && rc == TTSH_OK) rc = fail(TTSH_EHIP, std::string("stream join: ") + hipGetErrorString(e2));
+  }
+  return rc;
 }
 
 // ---- continuation (reseed) ----------------------------------------------------
@@ -955,6 +965,7 @@ int ttsh_set_option(ttsh_ctx* c, int key, int64_t value) {
       break;
     case TTSH_OPT_GROUPS:
       if (value < 1 || value > kMaxGroups) return fail(TTSH_EINVAL, "groups must be 1 or 2");
+      if (value > c->n_inst) return fail(TTSH_EINVAL, "two groups need at least two instances");
       c->groups = (int)value;
       break;
     default:
@@ -1833,6 +1844,7 @@ int ttsh_set_tuning(ttsh_ctx* c, const int* cfg) {
       return fail(TTSH_EINVAL, "a non-default schedule needs the FP32 arithmetic and the multi-size launch");
   }
   if (cfg[6] < 1 || cfg[6] > kMaxGroups) return fail(TTSH_EINVAL, "groups must be 1 or 2");
+  if (cfg[6] > c->n_inst) return fail(TTSH_EINVAL, "two groups need at least two instances");
   c->bs_row = cfg[0];
   c->bs = cfg[1];
   c->split_row = cfg[2];

@@ -870,3 +870,10 @@ def test_groups_guard_and_options(gpu):
         with pytest.raises(gpu.TTSHError):
             s.set_tuning((64, 64, 0, 0, 8, 8, v))
     s.close()
+    # two groups of one instance would leave a group empty
+    one = gpu.Solver([N], [L], O.workload_params(), 32)
+    with pytest.raises(gpu.TTSHError):
+        one.option(gpu.TTSH_OPT_GROUPS, 2)
+    with pytest.raises(gpu.TTSHError):
+        one.set_tuning((64, 64, 0, 0, 8, 8, 2))
+    one.close()
