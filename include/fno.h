@@ -56,6 +56,12 @@ void fno_destroy(fno_ctx* ctx);
  * Returns TTSH_EINVAL for an unknown option. */
 #define FNO_OPT_STAGED_GEMM 1
 #define FNO_OPT_SPECIALIZED 2
+/* FNO_OPT_TAIL_PROJ: with the specialized kernels, the last Fourier layer's
+ * tail (1x1 convolution, inverse k_x transform, bias) fused with the
+ * projection, so that h_layers is formed on chip and written to memory only
+ * for the training backward or the stage capture.  On by default; the same
+ * bits as the unfused pair. */
+#define FNO_OPT_TAIL_PROJ 4
 /* FNO_OPT_CAPTURE: keep each stage's BF16 intermediates per layer (for
  * stage-level tests; buffers of a few times the activations, allocated on
  * the first use), read with fno_capture.  Off by default. */
@@ -66,6 +72,7 @@ int fno_set_option(fno_ctx* ctx, int option, int value);
  * start; layouts for B samples, C channels, m modes, P = B H W points):
  *   FNO_CAP_XB   the input as BF16 [P][cin]                    (layer ignored)
  *   FNO_CAP_H    h_l, l = 0..layers [P][C] (l = layers: the projection input)
+ *                (every h_l of the last forward run with capture on)
  *   FNO_CAP_Z    pre-activation z_l of a non-last layer [P][C] (training forward)
  *   FNO_CAP_T1   k_x transform of h_l: [B][2m][H][C], rows k_x (real) then m + k_x
  *                (imaginary), unnormalised, e^{-i k_x x}

@@ -1,7 +1,7 @@
 // Fourier-neural-operator surrogate on gfx950 (interface: include/fno.h).
 //
 // Every dense piece of the network goes through one strided, batched GEMM on
-// the matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
+// the matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
 // accumulation): the pruned 2D DFTs as products with small DFT matrices (only
 // m of W/2+1 k_x columns and 2m of H k_y rows are ever needed), the per-mode
 // complex channel mixing as real block products [Re, Im] [[R_r, R_i],
@@ -122,9 +122,32 @@ struct GemmArgs {
 };
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 __device__ inline short4_t pack4(float a, float b, float c, float d) {
   return __builtin_bit_cast(short4_t, uint2v_t{pack2(a, b), pack2(c, d)});
+}
+// The matrix-core products.  gfx950's v_mfma_f32_16x16x32_bf16 (mfma32)
+// takes 32 along k per instruction, eight per lane: lane l holds row l%16 of
+// the first operand and column l%16 of the second, both at the eight k slots
+// of lane group l/16, and receives rows 4(l/16)..+3 of column l%16 of the
+// 16 x 16 result.  Which k a slot carries is the caller's choice, as long as
+// both operands agree: most callers give group g the run k = 8g..8g+7 (one
+// 16-byte load per operand); where an operand is the result of an earlier
+// product (four consecutive rows per lane), the two halves of a slot group
+// are the two 16-row halves, k = 4g..4g+3 and 16+4g..16+4g+3 (cat8).  The
+// 16-deep form (mfma16: k = 4(l/16)..+3) serves only contractions that are
+// 16 deep.
+__device__ inline float4_t mfma32(short8_t a, short8_t b, float4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+__device__ inline float4_t mfma16(short4_t a, short4_t b, float4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ inline short8_t cat8(short4_t lo, short4_t hi) {
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 __device__ inline short4_t load_frag(const bf16* base, long long r, long long c, int row, int k0,
@@ -139,31 +162,30 @@ __device__ inline short4_t load_frag(const bf16* base, long long r, long long c,
   return v;
 }
 
-// One wavefront computes one 32 x 32 tile of C as 2 x 2 MFMA 16 x 16 blocks.
-// MFMA 16x16x16 operand layout (lane l): first operand row l%16, k =
-// 4(l/16)..+3; second operand column l%16, same k; result column l%16, rows
-// 4(l/16)..+3.  The product is formed transposed (C^T = B^T A^T: the B
-// fragment goes first), so that lane l ends up with row l%16 of the block and
-// four consecutive columns 4(l/16)..+3: one vector store per block when C's
-// columns are contiguous.
+// One wavefront computes one 32 x 32 tile of C as 2 x 2 MFMA 16 x 16 blocks,
+// 32 along k per step (lane group g: k = k0 + 8g..+7, zero past K).  The
+// product is formed transposed (C^T = B^T A^T: the B fragment goes first), so
+// that lane l ends up with row l%16 of the block and four consecutive columns
+// 4(l/16)..+3: one vector store per block when C's columns are contiguous.
 __device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, int b1, int b2,
                                  int i0, int j0, int lane, float4_t (&acc)[2][2]) {
   const bf16* pa = A.p + b1 * A.s1 + b2 * A.s2;
   const bf16* pb = B.p + b1 * B.s1 + b2 * B.s2;
-  const int rl = lane & 15, kq = (lane >> 4) * 4;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    short4_t a[2], b[2];
+  const int rl = lane & 15, kq = (lane >> 4) * 8;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    short8_t a[2], b[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      a[s] = load_frag(pa, A.r, A.c, i0 + 16 * s + rl, k0 + kq, M, K, A.kvec);
+      a[s] = cat8(load_frag(pa, A.r, A.c, i0 + 16 * s + rl, k0 + kq, M, K, A.kvec),
+                  load_frag(pa, A.r, A.c, i0 + 16 * s + rl, k0 + kq + 4, M, K, A.kvec));
       // B[k][j]: treat as rows j with stride B.c, columns k with stride B.r
-      b[s] = load_frag(pb, B.c, B.r, j0 + 16 * s + rl, k0 + kq, N, K, B.kvec);
+      b[s] = cat8(load_frag(pb, B.c, B.r, j0 + 16 * s + rl, k0 + kq, N, K, B.kvec),
+                  load_frag(pb, B.c, B.r, j0 + 16 * s + rl, k0 + kq + 4, N, K, B.kvec));
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
-        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[t], a[s], acc[s][t], 0, 0, 0);
+      for (int t = 0; t < 2; ++t) acc[s][t] = mfma32(b[t], a[s], acc[s][t]);
   }
 }
 
@@ -172,7 +194,7 @@ __device__ inline void gemm_part(const Op& A, const Op& B, int K, int M, int N, 
 // whichever dimension is contiguous: FA = 0 when A's rows run along k, 1 when
 // its columns do (A given transposed); FB = 0 when B's rows run along n, 1
 // when along k.  LDS holds A as [m][k] and B as [n][k] (k contiguous, what the
-// MFMA fragments read 4 at a time), so the operands whose memory runs along
+// MFMA fragments read 8 at a time), so the operands whose memory runs along
 // the other dimension are transposed on their way in.  The launcher checks
 // unit strides, multiples of 8 and 16-byte alignment.
 constexpr int kKC = 32, kLDK = 40;  // k chunk, LDS row stride (bf16) with padding
@@ -208,26 +230,22 @@ __device__ inline void gemm_part_lds(const Op& A, const Op& B, int K, int M, int
                                      bf16* __restrict__ Bt) {
   const bf16* pa = A.p + b1 * A.s1 + b2 * A.s2;
   const bf16* pb = B.p + b1 * B.s1 + b2 * B.s2;
-  const int rl = lane & 15, kq = (lane >> 4) * 4;
+  const int rl = lane & 15, kq = (lane >> 4) * 8;
   for (int k0 = 0; k0 < K; k0 += kKC) {
     // A(i, k) at pa + i * A.r + k * A.c;  B(k, j) at pb + k * B.r + j * B.c
     stage_block<FA == 0>(pa, A.r, A.c, i0, M, k0, K, lane, As);
     stage_block<FB == 1>(pb, B.c, B.r, j0, N, k0, K, lane, Bt);
     wave_lds_sync();
+    short8_t a[2], b[2];
 #pragma unroll
-    for (int kk = 0; kk < kKC; kk += 16) {
-      short4_t a[2], b[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        a[s] = *(const short4_t*)(As + (16 * s + rl) * kLDK + kk + kq);
-        b[s] = *(const short4_t*)(Bt + (16 * s + rl) * kLDK + kk + kq);
-      }
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[t], a[s], acc[s][t], 0, 0, 0);
+    for (int s = 0; s < 2; ++s) {
+      a[s] = *(const short8_t*)(As + (16 * s + rl) * kLDK + kq);
+      b[s] = *(const short8_t*)(Bt + (16 * s + rl) * kLDK + kq);
     }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[s][t] = mfma32(b[t], a[s], acc[s][t]);
     wave_lds_sync();  // the next chunk overwrites the staging buffers
   }
 }
@@ -426,21 +444,26 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
                                                     const float* __restrict__ b2, int cout, float* __restrict__ y,
                                                     long long ys, const float* __restrict__ skip, long long skip_r,
                                                     long long npts) {
-  constexpr int HB = HID / 16, KB = C / 16;
-  const int lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  // k slots: the first product runs over channels k = 32 kb + 8 g + e; the
+  // second over the hidden pair (2 P, 2 P + 1) of 16-row blocks, slot (g, e)
+  // carrying hidden row 32 P + 16 (e / 4) + 4 g + e % 4 (what two results of
+  // the first product hold, cat8)
+  static_assert(C % 32 == 0 && HID % 32 == 0, "k in steps of 32");
+  constexpr int HB = HID / 16, KB = C / 32;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, g4 = lane >> 4, q4 = g4 * 4, q8 = g4 * 8;
   const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6), nwave = (long long)gridDim.x * 4;
-  short4_t qa[HB][KB], qb[HB];
+  short8_t qa[HB][KB], qb[HB / 2];
   float bias1[HB][4];
 #pragma unroll
   for (int hb = 0; hb < HB; ++hb) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) qa[hb][kb][e] = (short)Q1[(16 * kb + q4 + e) * HID + 16 * hb + l16];
+      for (int e = 0; e < 8; ++e) qa[hb][kb][e] = (short)Q1[(32 * kb + q8 + e) * HID + 16 * hb + l16];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       bias1[hb][e] = b1[16 * hb + q4 + e];
-      qb[hb][e] = l16 < cout ? (short)Q2[(16 * hb + q4 + e) * cout + l16] : (short)0;
+      qb[hb / 2][4 * (hb & 1) + e] = l16 < cout ? (short)Q2[(16 * hb + q4 + e) * cout + l16] : (short)0;
     }
   }
   // G independent groups of 16 points per iteration, for instruction-level
@@ -448,29 +471,34 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
   for (long long t = wave * G; t * 16 < npts; t += nwave * G) {
     long long p[G];
     bool ok[G];
-    short4_t hv[G][KB];
+    short8_t hv[G][KB];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       p[g] = (t + g) * 16 + l16;
       ok[g] = p[g] < npts;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb)
-        hv[g][kb] = ok[g] ? *(const short4_t*)(h + p[g] * C + 16 * kb + q4) : short4_t{0, 0, 0, 0};
+        hv[g][kb] = ok[g] ? *(const short8_t*)(h + p[g] * C + 32 * kb + q8) : short8_t{0, 0, 0, 0, 0, 0, 0, 0};
     }
     float4_t acc2[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) acc2[g] = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int hb = 0; hb < HB; ++hb) {
+    for (int hp = 0; hp < HB / 2; ++hp) {
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        short4_t av[2];
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa[hb][kb], hv[g][kb], acc, 0, 0, 0);
-        const short4_t av = pack4(gelu(acc[0] + bias1[hb][0]), gelu(acc[1] + bias1[hb][1]),
-                                  gelu(acc[2] + bias1[hb][2]), gelu(acc[3] + bias1[hb][3]));
-        acc2[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qb[hb], av, acc2[g], 0, 0, 0);
+        for (int hh = 0; hh < 2; ++hh) {
+          const int hb = 2 * hp + hh;
+          float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) acc = mfma32(qa[hb][kb], hv[g][kb], acc);
+          // the bias is added after the product, as the unfused path does
+          av[hh] = pack4(gelu(acc[0] + bias1[hb][0]), gelu(acc[1] + bias1[hb][1]), gelu(acc[2] + bias1[hb][2]),
+                         gelu(acc[3] + bias1[hb][3]));
+        }
+        acc2[g] = mfma32(qb[hp], cat8(av[0], av[1]), acc2[g]);
       }
     }
 #pragma unroll
@@ -521,20 +549,24 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
   __shared__ __align__(16) bf16 Os[4][32 * kLDK];  // per wavefront output tile [x][c]
   __shared__ float Rs[NEXT ? 4 : 1][J][C + 1];     // partial k_x transforms [wave][j][c]
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int q8 = (lane >> 4) * 8;
   const int tid = threadIdx.x;
-  // row-independent operands, held in registers
-  short4_t a1[2][2], b2[2][2], a3[2][2], pw[2];
+  // row-independent operands, held in registers.  k slots: j = q8..q8+7 for
+  // Ax, channels q8..q8+7 for Wl; for Dx the points 32 w + {q4..q4+3,
+  // 16+q4..16+q4+3}, the two result halves the k_x transform takes (cat8)
+  short8_t a1[2], b2[2], a3[2];
+  short4_t pw[2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < 2; ++s) {
+    if constexpr (!LIFT) {
+      a1[s] = *(const short8_t*)(Ax + (32 * w + 16 * s + l16) * J + q8);
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      if constexpr (!LIFT) {
-        a1[s][kk] = *(const short4_t*)(Ax + (32 * w + 16 * s + l16) * J + 16 * kk + q4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) b2[s][kk][e] = (short)Wl[(16 * kk + q4 + e) * C + 16 * s + l16];
-      }
-      if constexpr (NEXT) a3[s][kk] = *(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + 16 * kk + q4);
+      for (int e = 0; e < 8; ++e) b2[s][e] = (short)Wl[(q8 + e) * C + 16 * s + l16];
     }
+    if constexpr (NEXT)
+      a3[s] = cat8(*(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + q4),
+                   *(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + 16 + q4));
+  }
   float bc[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -549,17 +581,14 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
   // at the top of each iteration (into a2n, t2n), so that their latency
   // overlaps the current row's work instead of starting each iteration.
   const int tj = tid >> 3, tc0 = (tid & 7) * 4;  // this thread's piece of T2[b][y]
-  short4_t a2n[2][2];
+  short8_t a2n[2];
   uint2 t2n = {0u, 0u};
   if constexpr (!LIFT) {
     const long long r0 = blockIdx.x;
     if (r0 < rows) {
       const bf16* hp = h + r0 * (W * C);
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-          a2n[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+      for (int s = 0; s < 2; ++s) a2n[s] = *(const short8_t*)(hp + (32 * w + 16 * s + l16) * C + q8);
       t2n = *(const uint2*)(T2 + r0 * (J * C) + tj * C + tc0);
     }
   }
@@ -574,24 +603,18 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) xa[e] = q4 + e < cin ? (short)xr[q4 + e] : (short)0;
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, pw[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        for (int t = 0; t < 2; ++t) acc[s][t] = mfma16(xa, pw[t], float4_t{0.f, 0.f, 0.f, 0.f});
       }
     } else {
-      short4_t a2[2][2];
+      short8_t a2[2];
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) a2[s][kk] = a2n[s][kk];
+      for (int s = 0; s < 2; ++s) a2[s] = a2n[s];
       const uint2 v = t2n;
       const long long rn = row + gridDim.x;
       if (rn < rows) {
         const bf16* hp = h + rn * (W * C);
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int kk = 0; kk < 2; ++kk)
-            a2n[s][kk] = *(const short4_t*)(hp + (32 * w + 16 * s + l16) * C + 16 * kk + q4);
+        for (int s = 0; s < 2; ++s) a2n[s] = *(const short8_t*)(hp + (32 * w + 16 * s + l16) * C + q8);
         t2n = *(const uint2*)(T2 + rn * (J * C) + tj * C + tc0);
       }
       {  // T2[b][y] (J x C) into LDS as [c][j]
@@ -604,13 +627,9 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          acc[s][t] = float4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kk = 0; kk < 2; ++kk) {
-            const short4_t b1 = *(const short4_t*)(Ts + (16 * t + l16) * kLDK + 16 * kk + q4);
-            acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[s][kk], b1, acc[s][t], 0, 0, 0);
-            acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[s][kk], b2[t][kk], acc[s][t], 0, 0, 0);
-          }
+          const short8_t b1 = *(const short8_t*)(Ts + (16 * t + l16) * kLDK + q8);
+          acc[s][t] = mfma32(a1[s], b1, float4_t{0.f, 0.f, 0.f, 0.f});
+          acc[s][t] = mfma32(a2[s], b2[t], acc[s][t]);
         }
     }
     // acc[s][t][e] = out[x = 32 w + 16 s + q4 + e][c = 16 t + l16]
@@ -665,9 +684,7 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          float4_t p = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int s = 0; s < 2; ++s) p = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[r][s], b3[s][t], p, 0, 0, 0);
+          const float4_t p = mfma32(a3[r], cat8(b3[0][t], b3[1][t]), float4_t{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
           for (int e = 0; e < 4; ++e) Rs[w][16 * r + q4 + e][16 * t + l16] = p[e];
         }
@@ -688,6 +705,134 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
   }
 }
 
+// The last Fourier layer's tail fused with the projection (C = 32, 2m = 32,
+// W = 128, hidden HID): per image row (b, y) and wavefront (32 points x),
+//   out[x][c] = sum_j Ax[x][j] T2[b][y][j][c] + sum_k h[b][y][x][k] Wl[k][c] + bias[c]
+// (the last layer has no activation) is rounded to BF16 into the wavefront's
+// LDS tile -- the values the unfused path stores as h_L -- and stored to hn
+// only when hn is given (the training backward reads h_L); then, for the two
+// groups of 16 points, y[p][o] = sum_j GELU(u[p][j]) Q2[j][o] + b2[o] (+ skip)
+// with u = out Q1 + b1, formed as k_proj_fused forms it (same products and
+// order, so the two paths give the same bits).  The projection's GELUs bound
+// the kernel; the tail's memory traffic runs beneath them and h_L makes no
+// round trip through memory.
+template <int HID>
+__global__ void __launch_bounds__(256, 3) k_tail_proj(const bf16* __restrict__ h, const bf16* __restrict__ T2,
+                                                   const bf16* __restrict__ Ax, const bf16* __restrict__ Wl,
+                                                   const float* __restrict__ bias, bf16* __restrict__ hn,
+                                                   const bf16* __restrict__ Q1, const float* __restrict__ b1,
+                                                   const bf16* __restrict__ Q2, const float* __restrict__ b2,
+                                                   int cout, float* __restrict__ y, long long ys,
+                                                   const float* __restrict__ skip, long long skip_r, long long rows) {
+  constexpr int C = 32, J = 32, W = 128, HB = HID / 16;
+  static_assert(HID % 32 == 0, "hidden width in steps of 32");
+  __shared__ __align__(16) bf16 Ts[C * kLDK];      // T2 block transposed: [c][j]
+  __shared__ __align__(16) bf16 Os[4][32 * kLDK];  // per wavefront output tile [x][c]
+  __shared__ __align__(16) float B1s[HID];          // the hidden layer's bias
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int q8 = (lane >> 4) * 8;
+  const int tid = threadIdx.x;
+  // the tail's operands (k slots as in k_layer_tail) and the projection's (as in k_proj_fused)
+  short8_t ax[2], wl[2], qa[HB], qb[HB / 2];
+  float bc[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    ax[s] = *(const short8_t*)(Ax + (32 * w + 16 * s + l16) * J + q8);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wl[s][e] = (short)Wl[(q8 + e) * C + 16 * s + l16];
+    bc[s] = bias[16 * s + l16];
+  }
+#pragma unroll
+  for (int hb = 0; hb < HB; ++hb) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) qa[hb][e] = (short)Q1[(q8 + e) * HID + 16 * hb + l16];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      qb[hb / 2][4 * (hb & 1) + e] = l16 < cout ? (short)Q2[(16 * hb + q4 + e) * cout + l16] : (short)0;
+  }
+  for (int i = tid; i < HID; i += 256) B1s[i] = b1[i];  // read after the first row's barrier
+  const int tj = tid >> 3, tc0 = (tid & 7) * 4;  // this thread's piece of T2[b][y]
+  short8_t a2n[2];
+  uint2 t2n = {0u, 0u};
+  if (blockIdx.x < rows) {
+    const bf16* hp = h + (long long)blockIdx.x * (W * C);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) a2n[s] = *(const short8_t*)(hp + (32 * w + 16 * s + l16) * C + q8);
+    t2n = *(const uint2*)(T2 + (long long)blockIdx.x * (J * C) + tj * C + tc0);
+  }
+  bf16* Ow = Os[w];
+  const int sr = lane >> 1, sh = (lane & 1) * 16;  // store: tile row, first channel
+  for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+    short8_t a2[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) a2[s] = a2n[s];
+    const uint2 v = t2n;
+    const long long rn = row + gridDim.x;
+    if (rn < rows) {  // the next row's operands, loaded while this row is worked on
+      const bf16* hp = h + rn * (W * C);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) a2n[s] = *(const short8_t*)(hp + (32 * w + 16 * s + l16) * C + q8);
+      t2n = *(const uint2*)(T2 + rn * (J * C) + tj * C + tc0);
+    }
+    {  // T2[b][y] (J x C) into LDS as [c][j]
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Ts[(tc0 + q) * kLDK + tj] = e[q];
+    }
+    __syncthreads();
+    // acc[s][t][e] = out[x = 32 w + 16 s + q4 + e][c = 16 t + l16]
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const short8_t b1v = *(const short8_t*)(Ts + (16 * t + l16) * kLDK + q8);
+        float4_t acc = mfma32(ax[s], b1v, float4_t{0.f, 0.f, 0.f, 0.f});
+        acc = mfma32(a2[s], wl[t], acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ow[(16 * s + q4 + e) * kLDK + 16 * t + l16] = f2bf(acc[e] + bc[t]);
+      }
+    wave_lds_sync();
+    if (hn) {
+      bf16* hrow = hn + row * (W * C) + 32 * w * C;
+      *(uint4*)(hrow + sr * C + sh) = *(const uint4*)(Ow + sr * kLDK + sh);
+      *(uint4*)(hrow + sr * C + sh + 8) = *(const uint4*)(Ow + sr * kLDK + sh + 8);
+    }
+    short8_t hv[2];
+#pragma unroll
+    for (int gp = 0; gp < 2; ++gp) hv[gp] = *(const short8_t*)(Ow + (16 * gp + l16) * kLDK + q8);
+    float4_t acc2[2] = {float4_t{0.f, 0.f, 0.f, 0.f}, float4_t{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int hp = 0; hp < HB / 2; ++hp) {
+#pragma unroll
+      for (int gp = 0; gp < 2; ++gp) {
+        short4_t av[2];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int hb = 2 * hp + hh;
+          const float4_t u = mfma32(qa[hb], hv[gp], float4_t{0.f, 0.f, 0.f, 0.f});
+          const float4 bb = *(const float4*)(B1s + 16 * hb + q4);
+          av[hh] = pack4(gelu(u[0] + bb.x), gelu(u[1] + bb.y), gelu(u[2] + bb.z), gelu(u[3] + bb.w));
+        }
+        acc2[gp] = mfma32(qb[hp], cat8(av[0], av[1]), acc2[gp]);
+      }
+    }
+#pragma unroll
+    for (int gp = 0; gp < 2; ++gp) {
+      const long long p = row * W + 32 * w + 16 * gp + l16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = q4 + e;
+        if (o < cout) {
+          float r = acc2[gp][e] + b2[o];
+          if (skip) r += skip[p * skip_r + o];
+          y[p * ys + o] = r;
+        }
+      }
+    }
+    __syncthreads();  // Ts and the tiles are overwritten by the next row
+  }
+}
+
 // The k_y step of the truncated transform for C = 32, 2m = 32 and H = 128,
 // one (sample b, k_x) pair per workgroup iteration.  With the real and
 // imaginary k_x rows R = T1[b][kx], I = T1[b][m + kx] (H x C each),
@@ -701,12 +846,13 @@ __global__ void __launch_bounds__(256) k_yanalysis(const bf16* __restrict__ T1, 
   constexpr int C = 32, H = 128, m = 16, Q = 4 * m, LD = H + 8;
   __shared__ __align__(16) bf16 Rs[2][C * LD];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int q8 = (lane >> 4) * 8;
   const int tid = threadIdx.x;
-  short4_t aR[H / 16], aI[H / 16];
+  short8_t aR[H / 32], aI[H / 32];  // k slots: y = 32 kk + q8 .. + 7
 #pragma unroll
-  for (int kk = 0; kk < H / 16; ++kk) {
-    aR[kk] = *(const short4_t*)(DyRe + (16 * w + l16) * H + 16 * kk + q4);
-    aI[kk] = *(const short4_t*)(DyIm + (16 * w + l16) * H + 16 * kk + q4);
+  for (int kk = 0; kk < H / 32; ++kk) {
+    aR[kk] = *(const short8_t*)(DyRe + (16 * w + l16) * H + 32 * kk + q8);
+    aI[kk] = *(const short8_t*)(DyIm + (16 * w + l16) * H + 32 * kk + q8);
   }
   for (long long it = blockIdx.x; it < items; it += gridDim.x) {
     const int kx = (int)(it % m);
@@ -731,11 +877,11 @@ __global__ void __launch_bounds__(256) k_yanalysis(const bf16* __restrict__ T1, 
     for (int t = 0; t < 2; ++t) {
       float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < H / 16; ++kk) {
-        const short4_t bR = *(const short4_t*)(Rs[0] + (16 * t + l16) * LD + 16 * kk + q4);
-        const short4_t bI = *(const short4_t*)(Rs[1] + (16 * t + l16) * LD + 16 * kk + q4);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bR, aR[kk], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bI, aI[kk], acc, 0, 0, 0);
+      for (int kk = 0; kk < H / 32; ++kk) {
+        const short8_t bR = *(const short8_t*)(Rs[0] + (16 * t + l16) * LD + 32 * kk + q8);
+        const short8_t bI = *(const short8_t*)(Rs[1] + (16 * t + l16) * LD + 32 * kk + q8);
+        acc = mfma32(bR, aR[kk], acc);
+        acc = mfma32(bI, aI[kk], acc);
       }
       // lane: row q = 16 w + l16, channels 16 t + q4 .. + 3
       *(short4_t*)(G + (((long long)kx * Q + 16 * w + l16) * B + b) * C + 16 * t + q4) =
@@ -757,17 +903,16 @@ __global__ void __launch_bounds__(256) k_ysynth(const bf16* __restrict__ O, cons
   constexpr int C = 32, H = 128, m = 16, K = 2 * m;
   __shared__ __align__(16) bf16 Os[2][C * kLDK];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int q8 = (lane >> 4) * 8;
   const int tid = threadIdx.x;
-  short4_t ac[2][2], as[2][2], an[2][2];
+  short8_t ac[2], as[2], an[2];  // k slots: ky = q8 .. q8 + 7
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int off = (32 * w + 16 * s + l16) * K + 16 * kk + q4;
-      ac[s][kk] = *(const short4_t*)(Ec + off);
-      as[s][kk] = *(const short4_t*)(Es + off);
-      an[s][kk] = *(const short4_t*)(Esn + off);
-    }
+  for (int s = 0; s < 2; ++s) {
+    const int off = (32 * w + 16 * s + l16) * K + q8;
+    ac[s] = *(const short8_t*)(Ec + off);
+    as[s] = *(const short8_t*)(Es + off);
+    an[s] = *(const short8_t*)(Esn + off);
+  }
   for (long long it = blockIdx.x; it < items; it += gridDim.x) {
     const int kx = (int)(it % m);
     const long long b = it / m;
@@ -786,26 +931,21 @@ __global__ void __launch_bounds__(256) k_ysynth(const bf16* __restrict__ O, cons
       }
     }
     __syncthreads();
-    short4_t br[2][2], bi[2][2];
+    short8_t br[2], bi[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        br[t][kk] = *(const short4_t*)(Os[0] + (16 * t + l16) * kLDK + 16 * kk + q4);
-        bi[t][kk] = *(const short4_t*)(Os[1] + (16 * t + l16) * kLDK + 16 * kk + q4);
-      }
+    for (int t = 0; t < 2; ++t) {
+      br[t] = *(const short8_t*)(Os[0] + (16 * t + l16) * kLDK + q8);
+      bi[t] = *(const short8_t*)(Os[1] + (16 * t + l16) * kLDK + q8);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         float4_t fr = {0.f, 0.f, 0.f, 0.f}, fi = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          fr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[t][kk], ac[s][kk], fr, 0, 0, 0);
-          fr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[t][kk], an[s][kk], fr, 0, 0, 0);
-          fi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[t][kk], as[s][kk], fi, 0, 0, 0);
-          fi = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[t][kk], ac[s][kk], fi, 0, 0, 0);
-        }
+        fr = mfma32(br[t], ac[s], fr);
+        fr = mfma32(bi[t], an[s], fr);
+        fi = mfma32(br[t], as[s], fi);
+        fi = mfma32(bi[t], ac[s], fi);
         // lane: y = 32 w + 16 s + l16, channels 16 t + q4 .. + 3
         bf16* row = T2 + ((b * H + 32 * w + 16 * s + l16) * K) * C + 16 * t + q4;
         *(short4_t*)(row + kx * C) = pack4(fr[0], fr[1], fr[2], fr[3]);
@@ -827,6 +967,7 @@ __global__ void __launch_bounds__(256) k_mix(const bf16* __restrict__ G, const b
                                              bf16* __restrict__ out, int B, int m) {
   constexpr int C = 32, C2 = 64;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int q8 = (lane >> 4) * 8;  // k slots: 32 kk + q8 .. + 7 (kk = 0: G_r, 1: G_i)
   const long long mode = blockIdx.x;  // kx * 2m + q
   const int kx = (int)(mode / (2 * m)), q = (int)(mode % (2 * m));
   const bf16* Gr = G + ((long long)kx * 4 * m + q) * B * C;
@@ -836,19 +977,19 @@ __global__ void __launch_bounds__(256) k_mix(const bf16* __restrict__ G, const b
   const int tiles = (B + 31) / 32 * 2;
   for (int tile = w; tile < tiles; tile += 4) {
     const int i0 = (tile >> 1) * 32, j0 = (tile & 1) * 32;
-    short4_t a[2][4], v[2][4];
+    short8_t a[2][2], v[2][2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int row = i0 + 16 * s + l16;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        a[s][kk] = row < B ? *(const short4_t*)((kk < 2 ? Gr : Gi) + (long long)row * C + 16 * (kk & 1) + q4)
-                           : short4_t{0, 0, 0, 0};
+      for (int kk = 0; kk < 2; ++kk)
+        a[s][kk] = row < B ? *(const short8_t*)((kk == 0 ? Gr : Gi) + (long long)row * C + q8)
+                           : short8_t{0, 0, 0, 0, 0, 0, 0, 0};
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) v[t][kk] = *(const short4_t*)(V + (j0 + 16 * t + l16) * C2 + 16 * kk + q4);
+      for (int kk = 0; kk < 2; ++kk) v[t][kk] = *(const short8_t*)(V + (j0 + 16 * t + l16) * C2 + 32 * kk + q8);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int row = i0 + 16 * s + l16;
@@ -856,7 +997,7 @@ __global__ void __launch_bounds__(256) k_mix(const bf16* __restrict__ G, const b
       for (int t = 0; t < 2; ++t) {
         float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(v[t][kk], a[s][kk], acc, 0, 0, 0);
+        for (int kk = 0; kk < 2; ++kk) acc = mfma32(v[t][kk], a[s][kk], acc);
         if (row < B) *(short4_t*)(o + (long long)row * C2 + j0 + 16 * t + q4) = pack4(acc[0], acc[1], acc[2], acc[3]);
       }
     }
@@ -880,8 +1021,10 @@ __global__ void __launch_bounds__(256, 2) k_proj_back(const bf16* __restrict__ h
                                                       const float* __restrict__ b1, const bf16* __restrict__ Q2,
                                                       const bf16* __restrict__ dy, int cout, bf16* __restrict__ dh,
                                                       float* __restrict__ part, long long npts) {
+  static_assert(C == 32 && HID % 32 == 0, "k in steps of 32");
   constexpr int HB = HID / 16, KB = C / 16, LDJ = HID + 8, LDC = C + 8, MO = kProjBackMaxCout;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q4 = (lane >> 4) * 4;
+  const int q8 = (lane >> 4) * 8;  // k slots of the 32-deep products: q8 .. q8 + 7
   const long long wave = (long long)blockIdx.x * 4 + w, nwave = (long long)gridDim.x * 4;
   __shared__ float Q2s[HID][MO], B1s[HID];
   __shared__ __align__(16) bf16 Q1s[C * LDJ], Q1t[HID * LDC];  // Q1 [c][j] and Q1^T [j][c]
@@ -914,23 +1057,16 @@ __global__ void __launch_bounds__(256, 2) k_proj_back(const bf16* __restrict__ h
   for (long long t = wave; t * 16 < npts; t += nwave) {
     const long long p = t * 16 + l16;
     const bool ok = p < npts;
-    short4_t hv[KB];
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) hv[kb] = ok ? *(const short4_t*)(h + p * C + 16 * kb + q4) : short4_t{0, 0, 0, 0};
+    const short8_t hv = ok ? *(const short8_t*)(h + p * C + q8) : short8_t{0, 0, 0, 0, 0, 0, 0, 0};
     float dyv[MO];  // this lane's point
 #pragma unroll
     for (int o = 0; o < MO; ++o) dyv[o] = (ok && o < cout) ? bf2f(dy[p * cout + o]) : 0.f;
 #pragma unroll
     for (int e = 0; e < 4; ++e) dy_s[l16 * 16 + q4 + e] = (ok && q4 + e < cout) ? dy[p * cout + q4 + e] : (bf16)0;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) *(short4_t*)(h_s + l16 * LDC + 16 * kb + q4) = hv[kb];
+    *(short8_t*)(h_s + l16 * LDC + q8) = hv;
 #pragma unroll
     for (int hb = 0; hb < HB; ++hb) {
-      float4_t u = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb)
-        u = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(*(const short4_t*)(Q1t + (16 * hb + l16) * LDC + 16 * kb + q4),
-                                                       hv[kb], u, 0, 0, 0);
+      const float4_t u = mfma32(*(const short8_t*)(Q1t + (16 * hb + l16) * LDC + q8), hv, float4_t{0.f, 0.f, 0.f, 0.f});
       float a4[4], d4[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -957,12 +1093,12 @@ __global__ void __launch_bounds__(256, 2) k_proj_back(const bf16* __restrict__ h
     for (int cb = 0; cb < KB; ++cb) {
       float4_t d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int hb = 0; hb < HB; ++hb)
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(*(const short4_t*)(Q1s + (16 * cb + l16) * LDJ + 16 * hb + q4),
-                                                       *(const short4_t*)(du_s + l16 * LDJ + 16 * hb + q4), d, 0, 0, 0);
+      for (int hp = 0; hp < HID / 32; ++hp)
+        d = mfma32(*(const short8_t*)(Q1s + (16 * cb + l16) * LDJ + 32 * hp + q8),
+                   *(const short8_t*)(du_s + l16 * LDJ + 32 * hp + q8), d);
       if (ok) *(short4_t*)(dh + p * C + 16 * cb + q4) = pack4(d[0], d[1], d[2], d[3]);
     }
-    // weight gradients: contraction over the group's 16 points
+    // weight gradients: contraction over the group's 16 points (16 deep)
     short4_t hT[KB], dyb;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
@@ -979,8 +1115,8 @@ __global__ void __launch_bounds__(256, 2) k_proj_back(const bf16* __restrict__ h
         aT[e] = (short)a_s[(q4 + e) * LDJ + 16 * jb + l16];
       }
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) g1[jb][kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(duT, hT[kb], g1[jb][kb], 0, 0, 0);
-      g2[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aT, dyb, g2[jb], 0, 0, 0);
+      for (int kb = 0; kb < KB; ++kb) g1[jb][kb] = mfma16(duT, hT[kb], g1[jb][kb]);
+      g2[jb] = mfma16(aT, dyb, g2[jb]);
     }
     // db2: this lane adds points q4 .. q4 + 3 of output l16 (the four lane groups are added at the end)
 #pragma unroll
@@ -1363,6 +1499,7 @@ struct fno_ctx {
   // stage capture (FNO_OPT_CAPTURE, for stage-level tests): per layer, the
   // intermediates that later layers overwrite, copied as they are produced
   bool capture = false;
+  bool tail_proj = true;  // FNO_OPT_TAIL_PROJ
   bf16 *capT1[16] = {}, *capO[16] = {}, *capT2[16] = {};                       // forward
   bf16 *capDZ[16] = {}, *capBT1[16] = {}, *capGG[16] = {}, *capGF[16] = {}, *capBT2[16] = {}, *capDH[16] = {};
   bf16* capDHL = nullptr;                                                      // dl/dh_L from the projection
@@ -1644,6 +1781,27 @@ int layer_tail(fno_ctx* c, int l, int B, bool train) {
   return TTSH_OK;
 }
 
+// The last layer's tail fused with the projection into y (pixel stride ys,
+// skip: the residual input or null).  h_L is written only where something
+// reads it: the training backward, or the stage capture.
+int last_tail_proj(fno_ctx* c, int B, bool train, float* y, long long ys, const float* skip) {
+  const int l = c->L - 1;
+  const long long rows = (long long)B * c->H, P = rows * c->W;
+  const std::pair<const char*, size_t>* none = nullptr;
+  bf16* hn = (train || c->capture) ? c->h[l + 1] : nullptr;
+  if (!inside(c, c->h[l], P * 32 - 1, 2, none, 0) || !inside(c, hn, P * 32 - 1, 2, none, 0) ||
+      !inside(c, c->T2, rows * 32 * 32 - 1, 2, none, 0) || !inside(c, c->Ax, 128 * 32 - 1, 2, none, 0) ||
+      !inside(c, c->Wl[l], 32 * 32 - 1, 2, none, 0) || !inside(c, c->Q1, 32LL * 128 - 1, 2, none, 0) ||
+      !inside(c, c->Q2, 128LL * c->cout - 1, 2, none, 0))
+    return ffail(TTSH_EINVAL, "tail projection operand out of bounds (internal layout error)");
+  const unsigned blocks = (unsigned)std::min<long long>(rows, 1280);
+  hipLaunchKernelGGL((k_tail_proj<128>), dim3(blocks), dim3(256), 0, c->s, c->h[l], c->T2, c->Ax, c->Wl[l],
+                     c->theta + c->ob[l], hn, c->Q1, c->theta + c->oQ1b, c->Q2, c->theta + c->oQ2b, c->cout, y, ys,
+                     skip, (long long)c->cin, rows);
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
 // Inverse along y of the mode array src [m][2m][B][2C] (real, imaginary halves
 // of each channel block) into T2 [B][H][2m][C] (k_x real at kx, imaginary at m+kx).
 int spectral_synth_y(fno_ctx* c, const bf16* src, int B) {
@@ -1912,6 +2070,7 @@ int fno_set_option(fno_ctx* c, int option, int value) {
   if (!c) return ffail(TTSH_EINVAL, "null context");
   if (option == FNO_OPT_STAGED_GEMM) c->staged_gemm = value != 0;
   else if (option == FNO_OPT_SPECIALIZED) c->specialized = value != 0;
+  else if (option == FNO_OPT_TAIL_PROJ) c->tail_proj = value != 0;
   else if (option == FNO_OPT_CAPTURE) {
     if (value && !c->capT1[0]) {  // buffers are allocated once, on first use
       int rc;
@@ -1998,6 +2157,11 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     hipLaunchKernelGGL(k_lift, dim3(nb(P * C)), dim3(256), 0, c->s, c->xb, c->Pw, c->theta + c->oPb, c->h[0], P,
                        c->cin, C);
   FCHK(hipGetLastError());
+  // the fused projection: always for inference; in training too with the
+  // specialized kernels, whose fused backward recomputes the hidden layer
+  const bool proj_fused = C == 32 && c->hid == 128 && c->cout <= 16 &&
+                          (!train || (c->specialized && c->cout <= kProjBackMaxCout));
+  c->proj_train_fused = train && proj_fused;
   for (int l = 0; l < c->L; ++l) {
     const bool last = l == c->L - 1;
     // with the fused tail (and lift), the previous step already left T1 (the k_x step of h_l)
@@ -2010,6 +2174,8 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     if ((rc = spectral_synth_y(c, c->O, B))) return rc;
     if ((rc = cap_copy(c, c->capT2[l], c->T2, (long long)B * H * 2 * m * C))) return rc;
     if (fuse) {
+      if (last && proj_fused && c->tail_proj)
+        return last_tail_proj(c, B, train != 0, y, (long long)ys, residual ? x : nullptr);
       if ((rc = layer_tail(c, l, B, train != 0))) return rc;
       continue;
     }
@@ -2030,11 +2196,6 @@ int fno_forward_ex(fno_ctx* c, const float* x, float* y, int64_t ys, int residua
     }
     if ((rc = cgemm(c, g))) return rc;
   }
-  // the fused projection: always for inference; in training too with the
-  // specialized kernels, whose fused backward recomputes the hidden layer
-  const bool proj_fused = C == 32 && c->hid == 128 && c->cout <= 16 &&
-                          (!train || (c->specialized && c->cout <= kProjBackMaxCout));
-  c->proj_train_fused = train && proj_fused;
   if (proj_fused) {
     // h_L is [P][C] (inside h[L]), y and skip were range-checked above
     const long long tiles = (P + 15) / 16;

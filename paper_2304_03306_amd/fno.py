@@ -14,6 +14,7 @@ _sig_done = False
 FNO_OPT_STAGED_GEMM = 1
 FNO_OPT_SPECIALIZED = 2
 FNO_OPT_CAPTURE = 3
+FNO_OPT_TAIL_PROJ = 4
 (FNO_CAP_XB, FNO_CAP_H, FNO_CAP_Z, FNO_CAP_T1, FNO_CAP_G, FNO_CAP_O, FNO_CAP_T2) = range(7)
 (FNO_CAP_DZ, FNO_CAP_BT1, FNO_CAP_GG, FNO_CAP_GF, FNO_CAP_BT2, FNO_CAP_DH, FNO_CAP_DHL, FNO_CAP_DY) = range(10, 18)
 

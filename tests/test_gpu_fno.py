@@ -298,6 +298,55 @@ def test_specialized_kernels_match_oracle_and_general_path(gpu):
         assert e < 1.6e-2 and d < 3e-3, (k, e, d)  # measured <= 7.8e-3 and 1.0e-3
 
 
+def test_last_tail_fused_with_projection_gives_the_same_bits(gpu):
+    """With the specialized kernels the last layer's tail (1x1 convolution,
+    inverse k_x transform, bias) runs inside the projection kernel, h_L formed
+    on chip (FNO_OPT_TAIL_PROJ).  It must give the unfused pair's bits: the
+    inference output, the residual in-place output, the training output, the
+    h_L it stores for the backward pass, and the gradients; and an inference
+    forward must leave the stored h_L untouched.  The batch of 5 leaves the
+    row loop's grid partly idle; cout = 3 exercises a lane count the 16-wide
+    output fragment does not fill."""
+    import torch
+    from paper_2304_03306_amd import fno
+    say("fno last tail fused with the projection")
+    cfg = F.Config(H=128, W=128, cin=4, cout=3, width=32, modes=16, layers=2, hidden=128)
+    B = 5
+    net, p = make_net(gpu, cfg, B, seed=31)
+    rng = np.random.default_rng(32)
+    x = rng.standard_normal((B, cfg.H, cfg.W, cfg.cin)).astype(np.float32)
+    x2 = rng.standard_normal((B, cfg.H, cfg.W, cfg.cin)).astype(np.float32)
+    t = rng.standard_normal((B, cfg.H, cfg.W, cfg.cout)).astype(np.float32)
+    xd, x2d, td = torch.from_numpy(x).cuda(), torch.from_numpy(x2).cuda(), torch.from_numpy(t).cuda()
+    P = B * cfg.H * cfg.W
+    out = {}
+    for fused in (1, 0):
+        net.set_option(fno.FNO_OPT_TAIL_PROJ, fused)
+        yt = torch.empty((B, cfg.H, cfg.W, cfg.cout), dtype=torch.float32, device="cuda")
+        net.forward(xd, yt, train=True)
+        net.set_option(fno.FNO_OPT_CAPTURE, 1)
+        hL = net.capture(fno.FNO_CAP_H, cfg.layers, P * cfg.width)
+        net.set_option(fno.FNO_OPT_CAPTURE, 0)
+        net.loss(yt, td)
+        net.backward(B)
+        g = net.grads().copy()
+        y = torch.empty_like(yt)
+        net.forward(x2d, y, train=False)  # another input: h_L would change if it were written
+        net.set_option(fno.FNO_OPT_CAPTURE, 1)
+        hL_after = net.capture(fno.FNO_CAP_H, cfg.layers, P * cfg.width)
+        net.set_option(fno.FNO_OPT_CAPTURE, 0)
+        xr = xd.clone()
+        net.forward_ex(xr, xr, cfg.cin, True, B)
+        out[fused] = (y.cpu().numpy(), yt.cpu().numpy(), hL, g, xr.cpu().numpy(), hL_after)
+    net.set_option(fno.FNO_OPT_TAIL_PROJ, 1)
+    for name, a, b in zip(("inference", "training", "h_L", "gradients", "residual"), out[1][:5], out[0][:5]):
+        assert np.array_equal(a, b), name
+    assert np.array_equal(out[1][5], out[1][2])  # the fused inference forward wrote no h_L
+    assert not np.array_equal(out[0][5], out[0][2])  # the unfused one did
+    yo = F.forward(p, x2.astype(np.float64), cfg)
+    assert rel(out[1][0].astype(np.float64), yo) < 1.6e-2
+
+
 def test_increment_loss_and_its_gradient(gpu):
     """fno_loss_ex normalises each sample's error by ||t - ref|| (ref: the
     input's first channels, pixel stride cin); its value is that mean, and
