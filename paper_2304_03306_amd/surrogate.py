@@ -51,6 +51,12 @@ class SurrogateConfig:
     increment_loss: bool = False  # normalise the loss by the change over the step (fno_loss_ex)
     input_noise: float = 0.0      # uniform perturbation of the input velocity in training
     augment: bool = True          # a random symmetry of the square per training sample (fno_gather_d4)
+    # pushforward training: this fraction of the batches, from pushforward_start of the
+    # schedule on, takes as input the network's own prediction of the snapshot from the
+    # one before it (no gradient through that prediction), so that the network learns to
+    # correct the errors its rollouts feed back to it
+    pushforward: float = 0.0
+    pushforward_start: float = 0.25
 
 
 def _torch():
@@ -157,20 +163,28 @@ class Trainer:
         n_snap, I = D.shape[0], D.shape[1]
         return np.array([t * I + i for t in range(n_snap - 1) for i in ids], dtype=np.int64)
 
-    def batch_step(self, D, idx: np.ndarray, lr: float) -> float:
+    def batch_step(self, D, idx: np.ndarray, lr: float, pushforward: bool = False) -> float:
+        """One Adam step on the pairs idx -> idx + I.  With pushforward every
+        idx must have a predecessor (idx >= I): the input is then the
+        network's one-step prediction from snapshot idx - I, formed in place
+        by an inference forward (the mask and spacing channels are those of
+        the snapshot, which do not change along a trajectory)."""
         c = self.cfg
         I = D.shape[1]
         npix = c.Nc * c.Nc
         B = len(idx)
         dch = D.shape[-1]
+        src = idx - I if pushforward else idx
         if c.augment:
             # the same rotation or reflection for a sample's input and target
             sym = self.rng.integers(0, 8, B)
-            self.net.gather_d4(self.xb, c.cin, D, dch, c.cin, c.Nc, idx, sym)
+            self.net.gather_d4(self.xb, c.cin, D, dch, c.cin, c.Nc, src, sym)
             self.net.gather_d4(self.tb, c.cout, D, dch, c.cout, c.Nc, idx + I, sym)
         else:
-            self.net.gather(self.xb, c.cin, D, dch, c.cin, npix, idx)
+            self.net.gather(self.xb, c.cin, D, dch, c.cin, npix, src)
             self.net.gather(self.tb, c.cout, D, dch, c.cout, npix, idx + I)
+        if pushforward:
+            self.net.forward_ex(self.xb, self.xb, c.cin, True, B)
         if c.input_noise > 0:
             self.net.perturb(self.xb, c.cin, c.cout, B * npix, c.input_noise, self.step_count + 1)
         self.net.forward_ex(self.xb, self.yb, c.cout, True, B, train=True)
@@ -188,6 +202,9 @@ class Trainer:
         Returns the list of (epoch, mean loss, seconds)."""
         c = self.cfg
         pairs = self.pairs(D, ids)
+        I = D.shape[1]
+        if c.pushforward > 0 and D.shape[0] < 3:
+            raise ValueError("pushforward training needs at least three snapshots")
         rng = np.random.default_rng(seed)
         nb = max(1, len(pairs) // c.batch)
         total = epochs * nb
@@ -199,7 +216,11 @@ class Trainer:
             acc = 0.0
             for b in range(nb):
                 lr = 0.5 * c.lr * (1.0 + math.cos(math.pi * k / total))
-                acc += self.batch_step(D, perm[b * c.batch:(b + 1) * c.batch], lr)
+                idx = perm[b * c.batch:(b + 1) * c.batch]
+                pf = c.pushforward > 0 and k >= c.pushforward_start * total and rng.random() < c.pushforward
+                if pf:  # inputs at the first snapshot have no predecessor: take the next pair instead
+                    idx = np.where(idx < I, idx + I, idx)
+                acc += self.batch_step(D, idx, lr, pushforward=pf)
                 k += 1
             hist.append((ep, acc / nb, time.time() - t0))
             if log and (ep % 10 == 0 or ep == epochs - 1):
@@ -405,6 +426,9 @@ def main(argv=None):
                     help="train without the random rotation or reflection of the square per sample (by default "
                          "each training sample takes one: the circles sit on the grid centre, and the equation "
                          "has no preferred direction or handedness)")
+    ap.add_argument("--pushforward", type=float, default=0.0,
+                    help="fraction of the training batches (after the first quarter of the schedule) whose input "
+                         "is the network's own one-step prediction from the previous snapshot")
     ap.add_argument("--threshold", type=float, default=0.1)
     ap.add_argument("--check-every", type=int, default=25)
     ap.add_argument("--report", default="surrogate_report.json")
@@ -417,7 +441,7 @@ def main(argv=None):
     inst = wl.instances
     params = Wl.workload_coefficients()
     cfg = SurrogateConfig(batch=a.batch, lr=a.lr, modes=a.modes, input_noise=a.input_noise,
-                          cin=4 if a.scale_channel else 3, augment=not a.no_augment)
+                          cin=4 if a.scale_channel else 3, augment=not a.no_augment, pushforward=a.pushforward)
     I, Nc = len(inst), cfg.Nc
     spacing = [i.L / Nc for i in inst] if a.scale_channel else None
     masks = coarse_masks(inst, Nc, params)
@@ -464,7 +488,7 @@ def main(argv=None):
         "instances": I, "coarse_grid": Nc, "solver_steps_per_surrogate_step": cfg.every,
         "network": dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, hidden=cfg.hidden,
                         params=int(tr.net.n), dtype="bf16 storage, fp32 accumulation",
-                        input_noise=cfg.input_noise, augment=cfg.augment,
+                        input_noise=cfg.input_noise, augment=cfg.augment, pushforward=cfg.pushforward,
                         inputs="v_x, v_y, K" + (", dx" if a.scale_channel else "")),
         "data": dict(transient=a.transient, snapshots=a.snapshots, train_pairs=len(tr.pairs(Dtrain, train_ids)),
                      train_instances=train_ids, test_instances=test_ids),

@@ -141,3 +141,34 @@ def test_scale_channel_pipeline(data):
     ro = S.Rollout(tr.net, cfg, inst, data["p"], s, check_every=0, envelope=float("inf"))
     res = ro.run(D4[0], 3, judge=lambda k: D4[k] if k < D4.shape[0] else None)
     assert np.isfinite(res.err).all()
+
+
+def test_pushforward_batch_trains_on_the_networks_own_prediction(data, gpu):
+    """A pushforward batch's input is the network's one-step prediction of
+    snapshot t from snapshot t - 1 (velocity channels; the mask channel is the
+    snapshot's), made with the weights before the step, and its target is
+    snapshot t + 1; the step is then an ordinary Adam step (the loss is finite
+    and the weights change).  Inputs at the first snapshot are moved to the
+    second by the schedule, so every index has a predecessor."""
+    import torch
+    from paper_2304_03306_amd import surrogate as S
+    say("surrogate pushforward batch")
+    D = data["D"]
+    I = D.shape[1]
+    cfg = S.SurrogateConfig(batch=8, lr=1e-3, augment=False, pushforward=1.0, pushforward_start=0.0)
+    tr = S.Trainer(cfg, seed=3)
+    idx = np.array([5 * I + 0, 7 * I + 3, 1 * I + 4, 40 * I + 11], dtype=np.int64)
+    B = len(idx)
+    x = torch.empty((B, 128, 128, 3), dtype=torch.float32, device="cuda")
+    tr.net.gather(x, 3, D, D.shape[-1], 3, 128 * 128, idx - I)
+    want = x.clone()
+    tr.net.forward_ex(want, want, 3, True, B)
+    p0 = tr.net.params().copy()
+    loss = tr.batch_step(D, idx, 1e-3, pushforward=True)
+    assert np.isfinite(loss)
+    assert torch.equal(tr.xb[:B], want)
+    assert torch.equal(tr.xb[:B, ..., 2], D.view(-1, 128, 128, 3)[torch.from_numpy(idx).cuda()][..., 2])
+    assert torch.equal(tr.tb[:B], D.view(-1, 128, 128, 3)[torch.from_numpy(idx + I).cuda()][..., :2])
+    assert not np.array_equal(tr.net.params(), p0)
+    hist = tr.train(D[:4], [0, 1], epochs=2, seed=5)  # every batch pushforward, first-snapshot inputs moved
+    assert all(np.isfinite(h[1]) for h in hist)
