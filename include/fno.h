@@ -56,11 +56,12 @@ void fno_destroy(fno_ctx* ctx);
  * Returns TTSH_EINVAL for an unknown option. */
 #define FNO_OPT_STAGED_GEMM 1
 #define FNO_OPT_SPECIALIZED 2
-/* FNO_OPT_TAIL_PROJ: with the specialized kernels, the last Fourier layer's
- * tail (1x1 convolution, inverse k_x transform, bias) fused with the
- * projection, so that h_layers is formed on chip and written to memory only
- * for the training backward or the stage capture.  On by default; the same
- * bits as the unfused pair. */
+/* FNO_OPT_TAIL_PROJ: with the specialized kernels (and hidden 128, at most 16
+ * outputs, at most 4 in a training forward), the last Fourier layer's tail
+ * (1x1 convolution, inverse k_x transform, bias) fused with the projection,
+ * so that h_layers is formed on chip and written to memory only for the
+ * training backward or the stage capture.  On by default; the same bits as
+ * the unfused pair. */
 #define FNO_OPT_TAIL_PROJ 4
 /* FNO_OPT_CAPTURE: keep each stage's BF16 intermediates per layer (for
  * stage-level tests; buffers of a few times the activations, allocated on
