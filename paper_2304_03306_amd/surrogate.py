@@ -1,7 +1,7 @@
 """Coarse-field surrogate of the solver: training data from solver
 trajectories, training of the Fourier neural operator (libttsh's fno_* entry
 points), and rollout with acceptance checks, solver fallback and the solver
-as the judge of its error.
+as the reference for its error.
 
 Every arithmetic step runs in the HIP library: the solver (ttsh_*), the
 coarsening and its inverse (ttsh_get_field_coarse / ttsh_set_field_coarse),
@@ -260,7 +260,7 @@ class Trainer:
 
 @dataclasses.dataclass
 class RolloutResult:
-    err: np.ndarray            # [steps][I] rel-L2 vs the judge (NaN where no judge)
+    err: np.ndarray            # [steps][I] rel-L2 vs the reference (NaN where none)
     fallback_step: np.ndarray  # [I] surrogate step at which the instance went to the solver (-1: never)
     reason: List[str]
     seconds: float             # wall time of the rollout (surrogate + checks + fallback)
@@ -289,9 +289,9 @@ class Rollout:
         self.checker = checker
         self.envelope, self.check_every, self.tol = envelope, check_every, tol
 
-    def run(self, x0, steps: int, judge=None, log=None) -> RolloutResult:
+    def run(self, x0, steps: int, reference=None, log=None) -> RolloutResult:
         """x0: device [I][Nc][Nc][cin] (v_x, v_y, K[, dx]) at surrogate step 0.
-        judge(s) -> device [I][Nc][Nc][>=2] solver fields at step s, or None."""
+        reference(s) -> device [I][Nc][Nc][>=2] solver fields at step s, or None."""
         torch = _torch()
         c = self.cfg
         I = x0.shape[0]
@@ -353,8 +353,8 @@ class Rollout:
                 for q, i in enumerate(ids):
                     sol.field_coarse(q, c.Nc, x[i], ch)
             prev = nrm if prev is None else np.where(active[:, None], nrm, prev)
-            if judge is not None:
-                tgt = judge(s + 1)
+            if reference is not None:
+                tgt = reference(s + 1)
                 if tgt is not None:
                     err[s] = F.fno_sample_errors(x, ch, tgt, tgt.shape[-1], 2, npix, I)
             if log and (s + 1) % 50 == 0:
@@ -405,7 +405,7 @@ def first_exceeding(curve: np.ndarray, thr: float) -> int:
 
 
 def main(argv=None):
-    """Radius-sweep surrogate: collect, train, roll out, judge; one JSON report."""
+    """Radius-sweep surrogate: collect, train, roll out, compare with the solver; one JSON report."""
     import argparse
     import json
     from . import workloads as Wl
@@ -469,12 +469,12 @@ def main(argv=None):
            "train_radii_later_times": tr.eval_one_step(Deval, train_ids, project=solver)}
     log(f"one-step errors after the training window: {one}")
     steps = min(a.rollout, D.shape[0] - 1 - t0)
-    judge = lambda s: D[t0 + s] if t0 + s < D.shape[0] else None
+    reference = lambda s: D[t0 + s] if t0 + s < D.shape[0] else None
     # pure network (no checks), then with acceptance checks and fallback
     ro_free = Rollout(tr.net, cfg, inst, params, solver, envelope=float("inf"), check_every=0)
-    free = ro_free.run(D[t0], steps, judge=judge, log=log)
+    free = ro_free.run(D[t0], steps, reference=reference, log=log)
     ro = Rollout(tr.net, cfg, inst, params, solver, check_every=a.check_every, tol=a.threshold)
-    guarded = ro.run(D[t0], steps, judge=judge, log=log)
+    guarded = ro.run(D[t0], steps, reference=reference, log=log)
     # persistence for reference
     npix = Nc * Nc
     dch = D.shape[-1]

@@ -87,7 +87,7 @@ def test_trained_network_beats_persistence(data, trained):
     assert ev["network_projected"] < 0.7 * ev["persistence"], ev
 
 
-def test_rollout_is_judged_and_falls_back(data, trained):
+def test_rollout_is_checked_and_falls_back(data, trained):
     """A rollout over all instances: per-step errors against the recorded
     solver trajectory are finite; with corrupted weights every instance fails
     acceptance at the first step and continues on the solver, so its error
@@ -98,9 +98,9 @@ def test_rollout_is_judged_and_falls_back(data, trained):
     tr, _ = trained
     D = data["D"]
     t0, steps = 40, 20
-    judge = lambda s: D[t0 + s] if t0 + s < D.shape[0] else None
+    reference = lambda s: D[t0 + s] if t0 + s < D.shape[0] else None
     ro = S.Rollout(tr.net, tr.cfg, data["inst"], data["p"], data["solver"], check_every=10, tol=0.2)
-    res = ro.run(D[t0], steps, judge=judge, log=lambda m: print(m, flush=True))
+    res = ro.run(D[t0], steps, reference=reference, log=lambda m: print(m, flush=True))
     print("rollout mean err per step", np.nanmean(res.err, axis=1), "fallbacks", res.fallback_step, flush=True)
     assert np.isfinite(res.err).all()
     # corrupted weights -> non-finite output -> all instances on the solver
@@ -109,7 +109,7 @@ def test_rollout_is_judged_and_falls_back(data, trained):
     bad[: bad.size // 2] = np.nan
     tr.net.set_params(bad)
     try:
-        res2 = ro.run(D[t0], 5, judge=judge)
+        res2 = ro.run(D[t0], 5, reference=reference)
     finally:
         tr.net.set_params(good)
     assert (res2.fallback_step == 0).all(), res2.fallback_step
@@ -139,7 +139,7 @@ def test_scale_channel_pipeline(data):
     hist = tr.train(D4, [0, 1, 2, 3], epochs=2, seed=1)
     assert np.isfinite(hist[-1][1])
     ro = S.Rollout(tr.net, cfg, inst, data["p"], s, check_every=0, envelope=float("inf"))
-    res = ro.run(D4[0], 3, judge=lambda k: D4[k] if k < D4.shape[0] else None)
+    res = ro.run(D4[0], 3, reference=lambda k: D4[k] if k < D4.shape[0] else None)
     assert np.isfinite(res.err).all()
 
 
