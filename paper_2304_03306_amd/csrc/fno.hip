@@ -1427,6 +1427,32 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const float* __restrict__ 
   }
 }
 
+// The same sums in two passes that keep every CU busy: kRedChunk consecutive
+// partial vectors added in part order (one thread per element, consecutive
+// threads on consecutive elements, so each part row is read coalesced), then
+// the chunk sums added in chunk order.  The order is fixed, so the result is
+// the same run to run.
+constexpr int kRedChunk = 32;
+__global__ void __launch_bounds__(256) k_reduce_chunks(const float* __restrict__ part, int nparts, long long n,
+                                                       float* __restrict__ sums) {
+  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const int c0 = (int)blockIdx.y * kRedChunk, c1 = min(nparts, c0 + kRedChunk);
+  float s = 0.f;
+#pragma unroll 8
+  for (int c = c0; c < c1; ++c) s += part[(long long)c * n + j];
+  sums[(long long)blockIdx.y * n + j] = s;
+}
+__global__ void __launch_bounds__(256) k_reduce_sums(const float* __restrict__ sums, int nchunks, long long n,
+                                                     float* __restrict__ out) {
+  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.f;
+#pragma unroll 8
+  for (int c = 0; c < nchunks; ++c) s += sums[(long long)c * n + j];
+  out[j] = s;
+}
+
 __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
                        float c1, float c2) {
@@ -1490,6 +1516,8 @@ struct fno_ctx {
   bf16 *dh0, *dh1, *dz, *gG, *gF, *du, *xt;
   float *part = nullptr;
   size_t part_n = 0;
+  float* red2 = nullptr;  // chunk sums of the two-pass reduction of part
+  size_t red2_n = 0;
   double* lsum = nullptr;
   long long* gidx = nullptr;  // sample indices of fno_gather [max_batch]
   int* gsym = nullptr;        // symmetry elements of fno_gather_d4 [max_batch]
@@ -1873,6 +1901,22 @@ int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, const bf16* WbT, boo
 
 long long pts(const fno_ctx* c, int B) { return (long long)B * c->H * c->W; }
 
+// out[0:n] = sum over the nparts vectors part[c][0:n] in a fixed order: two
+// passes (k_reduce_chunks, k_reduce_sums) when the chunk sums fit their
+// buffer, else the one-pass k_reduce_parts
+int reduce_parts(fno_ctx* c, const float* part, long long nparts, long long n, float* out) {
+  const long long nch = (nparts + kRedChunk - 1) / kRedChunk;
+  if (nparts > kRedChunk && nch <= 65535 && (size_t)(nch * n) <= c->red2_n) {
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n), (unsigned)nch), dim3(256), 0, c->s, part, (int)nparts, n,
+                       c->red2);
+    hipLaunchKernelGGL(k_reduce_sums, dim3(nb(n)), dim3(256), 0, c->s, c->red2, (int)nch, n, out);
+  } else {
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nb(n, 16)), dim3(256), 0, c->s, part, (int)nparts, n, out);
+  }
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
 // element counts of the captured buffers at the maximum batch
 long long cap_len_T(const fno_ctx* c) { return (long long)c->maxB * 2 * c->m * c->H * c->C; }  // T1, T2
 long long cap_len_O(const fno_ctx* c) { return (long long)c->m * 2 * c->m * c->maxB * 2 * c->C; }  // O, gF, gG
@@ -1918,10 +1962,7 @@ int wgrad(fno_ctx* c, int M, int N, long long P, const bf16* A, long long rA, lo
     t.C = c->part + (nchunk - 1) * M * N;
     if ((rc = cgemm(c, t))) return rc;
   }
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nb((long long)M * N, 16)), dim3(256), 0, c->s, c->part, (int)nchunk,
-                     (long long)M * N, out);
-  FCHK(hipGetLastError());
-  return TTSH_OK;
+  return reduce_parts(c, c->part, nchunk, (long long)M * N, out);
 }
 
 int colsum(fno_ctx* c, const bf16* a, long long rows, int ncol, float* out) {
@@ -1936,10 +1977,8 @@ int colsum(fno_ctx* c, const bf16* a, long long rows, int ncol, float* out) {
     hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)nchunk), dim3(lanes * ncol), 0, c->s, a, rows, ncol, chunk,
                        c->part);
   }
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nb(ncol, 16)), dim3(256), 0, c->s, c->part, (int)nchunk, (long long)ncol,
-                     out);
   FCHK(hipGetLastError());
-  return TTSH_OK;
+  return reduce_parts(c, c->part, nchunk, (long long)ncol, out);
 }
 
 void free_fno(fno_ctx* c) {
@@ -2009,6 +2048,8 @@ int fno_create(fno_ctx** out, int width, int modes, int layers, int cin, int cou
   // (and 2048 wavefront slots of the fused projection backward: two workgroups per CU)
   c->part_n = std::max<size_t>(c->part_n, (size_t)2048 * (size_t)(C * hidden + hidden + (long long)hidden * cout + cout));
   if ((rc = alloc(c, &c->part, c->part_n))) return bail(rc);
+  c->red2_n = c->part_n / kRedChunk + 65536;
+  if ((rc = alloc(c, &c->red2, c->red2_n))) return bail(rc);
   if ((rc = make_dft(c))) return bail(rc);
   // seeded initial parameters (same distributions as the oracle's)
   std::vector<float> th(o, 0.f);
@@ -2272,9 +2313,8 @@ int fno_backward(fno_ctx* c, int B) {
       return ffail(TTSH_EINVAL, "projection backward operand out of bounds (internal layout error)");
     hipLaunchKernelGGL((k_proj_back<32, 128>), dim3((unsigned)blocks), dim3(256), 0, c->s, c->h[c->L], c->Q1,
                        c->theta + c->oQ1b, c->Q2, c->dy, co, c->dh0, c->part, P);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nb(S, 16)), dim3(256), 0, c->s, c->part, (int)(blocks * 4), S,
-                       c->grad + c->oQ1);
     FCHK(hipGetLastError());
+    if ((rc = reduce_parts(c, c->part, blocks * 4, S, c->grad + c->oQ1))) return rc;
   } else {
   if ((rc = wgrad(c, hid, co, P, c->a, 1, hid, c->dy, co, 1, c->grad + c->oQ2))) return rc;
   if ((rc = colsum(c, c->dy, P, co, c->grad + c->oQ2b))) return rc;
@@ -2377,9 +2417,8 @@ int fno_backward(fno_ctx* c, int B) {
       case 3: hipLaunchKernelGGL(k_lift_wgrad_part<3>, g, t, 0, c->s, xb, (const bf16*)dh, P, kWgradChunk, c->part); break;
       default: hipLaunchKernelGGL(k_lift_wgrad_part<4>, g, t, 0, c->s, xb, (const bf16*)dh, P, kWgradChunk, c->part); break;
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nb((long long)c->cin * C, 16)), dim3(256), 0, c->s, c->part,
-                       (int)nchunk, (long long)c->cin * C, c->grad + c->oPw);
     FCHK(hipGetLastError());
+    if ((rc = reduce_parts(c, c->part, nchunk, (long long)c->cin * C, c->grad + c->oPw))) return rc;
   } else if ((rc = wgrad(c, c->cin, C, P, c->xb, 1, c->cin, dh, C, 1, c->grad + c->oPw))) {
     return rc;
   }
