@@ -537,13 +537,14 @@ __global__ void __launch_bounds__(256) k_proj_fused(const bf16* __restrict__ h, 
 // pre-activation: the next gradient dz, stored to hn, whose k_x transform
 // with DxG (passed as Dx) is formed as above.
 constexpr int kMaxLiftCin = 16;
-template <bool ACT, bool NEXT, bool LIFT, bool DGRAD = false>
-__global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, const bf16* __restrict__ T2,
+template <bool ACT, bool NEXT, bool LIFT, bool DGRAD = false, bool CSUM = false>
+__global__ void __launch_bounds__(256, CSUM ? 4 : 1) k_layer_tail(const bf16* __restrict__ h, const bf16* __restrict__ T2,
                                                     const bf16* __restrict__ Ax, const bf16* __restrict__ Wl,
                                                     const float* __restrict__ bias, const bf16* __restrict__ Dx,
                                                     bf16* __restrict__ hn, bf16* __restrict__ z,
                                                     bf16* __restrict__ T1, int H, long long rows, int cin,
-                                                    const bf16* __restrict__ zin = nullptr) {
+                                                    const bf16* __restrict__ zin = nullptr,
+                                                    float* __restrict__ csum = nullptr) {
   constexpr int C = 32, J = 32, W = 128;
   __shared__ __align__(16) bf16 Ts[C * kLDK];      // T2 block transposed: [c][j]
   __shared__ __align__(16) bf16 Os[4][32 * kLDK];  // per wavefront output tile [x][c]
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
       a3[s] = cat8(*(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + q4),
                    *(const short4_t*)(Dx + (16 * s + l16) * W + 32 * w + 16 + q4));
   }
-  float bc[2];
+  float bc[2], cs[2] = {0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     bc[t] = (DGRAD || !bias) ? 0.f : bias[16 * t + l16];
@@ -669,6 +670,14 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
           b3[s][t][e] = (short)f2bf(v);
         }
     if constexpr (DGRAD) wave_lds_sync();  // zin read before the tile is overwritten
+    if constexpr (CSUM) {  // this lane's channels 16 t + l16, the stored (rounded) values in point order
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) cs[t] += bf2f((bf16)b3[s][t][e]);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -702,6 +711,23 @@ __global__ void __launch_bounds__(256) k_layer_tail(const bf16* __restrict__ h, 
       __syncthreads();  // Ts is overwritten by the next row
     }
     wave_lds_sync();  // Os is overwritten by the next row
+  }
+  if constexpr (CSUM) {
+    // column sums of everything this workgroup stored: the four lane groups of a
+    // wavefront, then the four wavefronts in order, into csum[blockIdx.x][C]
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      cs[t] += __shfl_xor(cs[t], 16);
+      cs[t] += __shfl_xor(cs[t], 32);
+    }
+    __syncthreads();  // every wavefront is done with Rs
+    float* cw = &Rs[0][0][0];
+    if (lane < 16) {
+      cw[w * C + l16] = cs[0];
+      cw[w * C + 16 + l16] = cs[1];
+    }
+    __syncthreads();
+    if (tid < C) csum[(long long)blockIdx.x * C + tid] = ((cw[tid] + cw[C + tid]) + cw[2 * C + tid]) + cw[3 * C + tid];
   }
 }
 
@@ -1745,10 +1771,28 @@ int spectral_analysis(fno_ctx* c, const bf16* src, const bf16* Dxm, bf16* dst, i
 
 bool tail_fusable(const fno_ctx* c) { return c->specialized && c->C == 32 && c->m == 16 && c->W == 128; }
 
+// out[0:n] = sum over the nparts vectors part[c][0:n] in a fixed order: two
+// passes (k_reduce_chunks, k_reduce_sums) when the chunk sums fit their
+// buffer, else the one-pass k_reduce_parts
+int reduce_parts(fno_ctx* c, const float* part, long long nparts, long long n, float* out) {
+  const long long nch = (nparts + kRedChunk - 1) / kRedChunk;
+  if (nparts > kRedChunk && nch <= 65535 && (size_t)(nch * n) <= c->red2_n) {
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n), (unsigned)nch), dim3(256), 0, c->s, part, (int)nparts, n,
+                       c->red2);
+    hipLaunchKernelGGL(k_reduce_sums, dim3(nb(n)), dim3(256), 0, c->s, c->red2, (int)nch, n, out);
+  } else {
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nb(n, 16)), dim3(256), 0, c->s, part, (int)nparts, n, out);
+  }
+  FCHK(hipGetLastError());
+  return TTSH_OK;
+}
+
 // Backward tail of layer l: dh_l = Ax1 T2 + dz W_l^T into `out`; for l > 0
 // multiplied by GELU'(z[l-1]) (the next gradient dz) with its k_x transform
-// (DxG) into T1.
-int layer_tail_back(fno_ctx* c, int l, int B, const bf16* dz, bf16* out) {
+// (DxG) into T1.  With bias_grad, the column sums of what it stores (the bias
+// gradient of layer l - 1, or of the lift for l = 0) go there: per-workgroup
+// partial sums, then reduce_parts.
+int layer_tail_back(fno_ctx* c, int l, int B, const bf16* dz, bf16* out, float* bias_grad) {
   const long long rows = (long long)B * c->H, P = rows * c->W;
   const std::pair<const char*, size_t>* none = nullptr;
   const bf16* zin = l > 0 ? c->z[l - 1] : nullptr;
@@ -1758,13 +1802,21 @@ int layer_tail_back(fno_ctx* c, int l, int B, const bf16* dz, bf16* out) {
       !inside(c, c->DxG, 32 * 128 - 1, 2, none, 0) || !inside(c, c->WlT[l], 32 * 32 - 1, 2, none, 0))
     return ffail(TTSH_EINVAL, "layer tail (backward) operand out of bounds (internal layout error)");
   const unsigned blocks = (unsigned)std::min<long long>(rows, 1280);
-  if (l > 0)
+  if (bias_grad && (size_t)blocks * 32 > c->part_n) return ffail(TTSH_ENOMEM, "fno partials buffer too small");
+  if (l > 0 && bias_grad)
+    hipLaunchKernelGGL((k_layer_tail<false, true, false, true, true>), dim3(blocks), dim3(256), 0, c->s, dz, c->T2,
+                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, zin, c->part);
+  else if (l > 0)
     hipLaunchKernelGGL((k_layer_tail<false, true, false, true>), dim3(blocks), dim3(256), 0, c->s, dz, c->T2,
-                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, zin);
+                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, zin, nullptr);
+  else if (bias_grad)
+    hipLaunchKernelGGL((k_layer_tail<false, false, false, false, true>), dim3(blocks), dim3(256), 0, c->s, dz,
+                       c->T2, c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, nullptr, c->part);
   else
     hipLaunchKernelGGL((k_layer_tail<false, false, false, false>), dim3(blocks), dim3(256), 0, c->s, dz, c->T2,
-                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, nullptr);
+                       c->Ax1, c->WlT[l], nullptr, c->DxG, out, nullptr, c->T1, c->H, rows, 0, nullptr, nullptr);
   FCHK(hipGetLastError());
+  if (bias_grad) return reduce_parts(c, c->part, blocks, 32, bias_grad);
   return TTSH_OK;
 }
 
@@ -1901,21 +1953,6 @@ int spectral_mix(fno_ctx* c, const bf16* G, const bf16* Wb, const bf16* WbT, boo
 
 long long pts(const fno_ctx* c, int B) { return (long long)B * c->H * c->W; }
 
-// out[0:n] = sum over the nparts vectors part[c][0:n] in a fixed order: two
-// passes (k_reduce_chunks, k_reduce_sums) when the chunk sums fit their
-// buffer, else the one-pass k_reduce_parts
-int reduce_parts(fno_ctx* c, const float* part, long long nparts, long long n, float* out) {
-  const long long nch = (nparts + kRedChunk - 1) / kRedChunk;
-  if (nparts > kRedChunk && nch <= 65535 && (size_t)(nch * n) <= c->red2_n) {
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb(n), (unsigned)nch), dim3(256), 0, c->s, part, (int)nparts, n,
-                       c->red2);
-    hipLaunchKernelGGL(k_reduce_sums, dim3(nb(n)), dim3(256), 0, c->s, c->red2, (int)nch, n, out);
-  } else {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nb(n, 16)), dim3(256), 0, c->s, part, (int)nparts, n, out);
-  }
-  FCHK(hipGetLastError());
-  return TTSH_OK;
-}
 
 // element counts of the captured buffers at the maximum batch
 long long cap_len_T(const fno_ctx* c) { return (long long)c->maxB * 2 * c->m * c->H * c->C; }  // T1, T2
@@ -2352,7 +2389,9 @@ int fno_backward(fno_ctx* c, int B) {
     }
     if ((rc = cap_copy(c, c->capDZ[l], dz, P * C))) return rc;
     if ((rc = wgrad(c, C, C, P, c->h[l], 1, C, dz, C, 1, c->grad + c->oW[l]))) return rc;
-    if ((rc = colsum(c, dz, P, C, c->grad + c->ob[l]))) return rc;
+    // (with the fused backward tails, layer l + 1's tail summed dz already)
+    if (!(fuse_b && l < c->L - 1))
+      if ((rc = colsum(c, dz, P, C, c->grad + c->ob[l]))) return rc;
     // g_G = (w/(HW)) trunc rfft2(dz)
     if (!fuse_b || l == c->L - 1)
       if ((rc = spectral_analysis_x(c, dz, c->DxG, B))) return rc;
@@ -2386,7 +2425,7 @@ int fno_backward(fno_ctx* c, int B) {
     if ((rc = spectral_synth_y(c, c->gF, B))) return rc;
     if ((rc = cap_copy(c, c->capBT2[l], c->T2, (long long)B * H * 2 * m * C))) return rc;
     if (fuse_b) {
-      if ((rc = layer_tail_back(c, l, B, dz, dh_next))) return rc;
+      if ((rc = layer_tail_back(c, l, B, dz, dh_next, c->grad + (l > 0 ? c->ob[l - 1] : c->oPb)))) return rc;
       if ((rc = cap_copy(c, c->capDH[l], dh_next, P * C))) return rc;
       std::swap(dh, dh_next);
       continue;
@@ -2422,7 +2461,8 @@ int fno_backward(fno_ctx* c, int B) {
   } else if ((rc = wgrad(c, c->cin, C, P, c->xb, 1, c->cin, dh, C, 1, c->grad + c->oPw))) {
     return rc;
   }
-  if ((rc = colsum(c, dh, P, C, c->grad + c->oPb))) return rc;
+  if (!fuse_b)  // else layer 0's backward tail summed dh already
+    if ((rc = colsum(c, dh, P, C, c->grad + c->oPb))) return rc;
   return TTSH_OK;
 }
 
