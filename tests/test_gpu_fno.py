@@ -347,6 +347,42 @@ def test_last_tail_fused_with_projection_gives_the_same_bits(gpu):
     assert rel(out[1][0].astype(np.float64), yo) < 1.6e-2
 
 
+def test_gradients_are_reproducible_bit_for_bit(gpu):
+    """The weight-gradient partials are summed in a fixed order (32-part chunks,
+    then the chunk sums in order), and the backward tails sum the bias
+    gradients of the layers below per workgroup in a fixed order too, so two
+    backward passes over the same input give the same bits.  Batch 11 gives
+    1408 image rows over the tails' 1280 workgroups (some take two rows) and
+    176 partial chunks per 1 x 1 weight gradient; the bias gradients stay
+    within FP32 rounding of the FP64 column sums of the stored gradients."""
+    import torch
+    from paper_2304_03306_amd import fno
+    say("fno gradient reproducibility")
+    cfg = F.Config(H=128, W=128, cin=3, cout=2, width=32, modes=16, layers=3, hidden=128)
+    B = 11
+    net, p = make_net(gpu, cfg, B, seed=41)
+    rng = np.random.default_rng(42)
+    x = torch.from_numpy(rng.standard_normal((B, cfg.H, cfg.W, cfg.cin)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((B, cfg.H, cfg.W, cfg.cout)).astype(np.float32)).cuda()
+    y = torch.empty((B, cfg.H, cfg.W, cfg.cout), dtype=torch.float32, device="cuda")
+    net.set_option(fno.FNO_OPT_CAPTURE, 1)
+    grads = []
+    for _ in range(2):
+        net.forward(x, y, train=True)
+        net.loss(y, t)
+        net.backward(B)
+        grads.append(net.grads().copy())
+    assert np.array_equal(grads[0], grads[1])
+    g = fno.unflatten(grads[0], p, cfg.layers)
+    P, C = B * cfg.H * cfg.W, cfg.width
+    sums = {f"b{l}": net.capture(fno.FNO_CAP_DZ, l, P * C).reshape(P, C) for l in range(cfg.layers)}
+    sums["P_b"] = net.capture(fno.FNO_CAP_DH, 0, P * C).reshape(P, C)
+    net.set_option(fno.FNO_OPT_CAPTURE, 0)
+    for k, dz in sums.items():
+        want, scale = dz.sum(axis=0), np.abs(dz).sum(axis=0)
+        assert np.all(np.abs(g[k] - want) <= 1e-5 * scale + 1e-30), k
+
+
 def test_increment_loss_and_its_gradient(gpu):
     """fno_loss_ex normalises each sample's error by ||t - ref|| (ref: the
     input's first channels, pixel stride cin); its value is that mean, and
